@@ -1,0 +1,174 @@
+/*
+ * holo.h -- C ABI of the MI355X (gfx950) hot path for LUT-based phase
+ * randomisation in hologram generation, after Christopher & Wilkinson,
+ * "Lookup tables for phase randomisation in hardware generated holograms"
+ * (arXiv:2004.04049).
+ *
+ * The paper poses hologram generation as finding the aperture f whose
+ * far-field DFT (Eq. (1)) matches a target; algorithms back-propagate the
+ * target with Eq. (2), quantise each pixel to the nearest value the SLM
+ * allows, and judge the replay R' = F{H'} (Section 2).  Targets are amplitudes
+ * only, so a random phase is attached to them (Section 3), drawn here from a
+ * small table read cyclically (Sections 4 and 5) instead of a PRNG plus
+ * sin/cos.
+ *
+ * Conventions for every call:
+ *   - Images are row-major [ny][nx] (x fastest), raster index p = y*nx + x.
+ *   - "device" buffers live in the GPU's memory and are owned by the caller
+ *     (e.g. torch tensors passed by data_ptr()); the library never frees them.
+ *     "host" buffers are ordinary process memory.
+ *   - Complex fields are interleaved float pairs (re, im), 8 bytes per pixel.
+ *   - nx and ny must be powers of two in [16, 2048] (HOLO_EUNSUPPORTED
+ *     otherwise).
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream).  Device
+ *     outputs are written in stream order; the call returns after enqueueing,
+ *     except that host outputs (NMSE values) are complete on return, which
+ *     synchronises the stream.  With HOLO_F_NMSE_DEVICE the NMSE pointers are
+ *     device pointers written in stream order and nothing synchronises.
+ *   - Calls made concurrently on different host threads are safe; calls that
+ *     overlap on the same stream are ordered by it.  The library keeps one
+ *     scratch workspace per (device, stream).
+ *   - Every call returns a holo_status; no exception or abort crosses the ABI.
+ *     holo_last_error() gives this thread's text for the last failure.
+ */
+#ifndef HOLO_H_
+#define HOLO_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HOLO_API __attribute__((visibility("default")))
+
+typedef int32_t holo_status;
+enum {
+    HOLO_OK = 0,
+    HOLO_EINVAL = -1,       /* null required pointer or out-of-range count   */
+    HOLO_EUNSUPPORTED = -2, /* size or precision this build does not handle  */
+    HOLO_ENOMEM = -3,       /* workspace or table allocation failed          */
+    HOLO_EDEVICE = -4       /* a HIP call failed; text in holo_last_error()  */
+};
+
+/* Arithmetic of the transform stages. */
+enum { HOLO_FP32 = 0, HOLO_BF16 = 1, HOLO_FP16 = 2 };
+
+/* Flags. */
+enum { HOLO_F_NMSE_DEVICE = 1 };
+
+/* holo_lut_check() warning bits (Section 5.1 hard limits, Section 8 rules). */
+enum {
+    HOLO_LUT_FLAT = 1,           /* n_lut == 0: no randomisation at all          */
+    HOLO_LUT_NOT_PRIME = 2,      /* length not prime (Section 8, first rule)     */
+    HOLO_LUT_LE_NSF = 4,         /* n_lut <= n_sf: sub-frames not independent   */
+    HOLO_LUT_LE_MAXDIM = 8,      /* n_lut <= max(nx, ny) (Section 8, third rule) */
+    HOLO_LUT_DIVIDES_FRAME = 16, /* n_lut divides nx*ny: identical sub-frames    */
+    HOLO_LUT_LT_FULL = 32        /* n_lut < nx*ny*n_sf: not PRNG-equivalent     */
+};
+
+typedef struct holo_lut holo_lut; /* opaque, library-owned, immutable once built */
+
+HOLO_API const char* holo_last_error(void);
+HOLO_API int32_t holo_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Phase LUT (Section 4: a pool of random phases fixed ahead of time).
+ *
+ * holo_lut_build: n_lut phases phi_j = 2*pi*u_j, u_j = (x_j >> 11) * 2^-53 from
+ * SplitMix64 seeded with `seed` (uniform on [0, 2*pi)); the device holds them
+ * as FP32 unit phasors (cos phi_j, sin phi_j) so no trigonometry runs per
+ * pixel.  n_lut = 0 builds the flat-phase table (phasor 1).  n_lut must be
+ * < 2^31.  The table lives on the current device.  *out receives the handle.
+ * holo_lut_from_phases: the same from caller phases (host, FP64, n_lut).
+ * holo_lut_phases: copies min(n, n_lut) FP64 phases to host `out`.
+ * holo_lut_check: bitmask of HOLO_LUT_* warnings; never an error, because the
+ * paper's own sweeps break these rules on purpose.
+ * ------------------------------------------------------------------------- */
+HOLO_API holo_status holo_lut_build(uint64_t n_lut, uint64_t seed, holo_lut** out);
+HOLO_API holo_status holo_lut_from_phases(const double* phases, uint64_t n_lut, holo_lut** out);
+HOLO_API holo_status holo_lut_phases(const holo_lut* lut, double* out, uint64_t n);
+HOLO_API uint64_t holo_lut_size(const holo_lut* lut);
+HOLO_API void holo_lut_free(holo_lut* lut);
+HOLO_API uint32_t holo_lut_check(uint64_t n_lut, int64_t nx, int64_t ny, int32_t n_sf);
+
+/* ---------------------------------------------------------------------------
+ * holo_ospr_generate -- One-Step Phase-Retrieval frame (Section 2, 3).
+ *
+ * For sub-frames k = 0..n_sf-1: R_k = T * exp(i*phi), with phi read from the
+ * LUT at (c + k*nx*ny + p) mod n_lut, c = *cursor (Section 5, Fig. 3);
+ * H_k = F^{-1}{R_k} (Eq. (2)); each pixel set to the nearest of {+1, -1}, i.e.
+ * bit = (Re H_k < 0), tie Re H = 0 -> +1 (bit 0); replay I_k = |F{H'_k}|^2
+ * (Eq. (1), unitary); time average I = (1/n_sf) sum_k I_k (Section 3).
+ *   target     device float[ny][nx], amplitudes (any non-negative scale)
+ *   cursor     host in/out; advanced by n_sf*nx*ny on success
+ *   holo_bits  device uint32[n_sf][nx*ny/32]: bit p%32 of word p/32 is pixel
+ *              p (LSB first); 1 means phase pi
+ *   recon      device float[ny][nx] time-averaged intensity, or NULL
+ *   nmse2      {NMSE vs T^2, NMSE vs the point-symmetrised T^2} or NULL, where
+ *              NMSE(I, W) = 1 - (sum I W)^2 / (sum I^2 * sum W^2), the
+ *              optimal-scale normalised MSE, accumulated in FP64
+ *   precision  HOLO_FP32 (BF16/FP16 through holo_ospr_generate_batched)
+ * Errors: HOLO_EINVAL for null target/lut/cursor/holo_bits or n_sf < 1.
+ * ------------------------------------------------------------------------- */
+HOLO_API holo_status holo_ospr_generate(const float* target, int64_t nx, int64_t ny, int32_t n_sf,
+                                        const holo_lut* lut, uint64_t* cursor, uint32_t* holo_bits,
+                                        float* recon, double* nmse2, int32_t precision, uint32_t flags,
+                                        void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * holo_gs_iterate -- Gerchberg-Saxton (Section 2), phase-only hologram,
+ * amplitude-only replay constraint.
+ *   R_0 = T * phasor, phasor = init_phasor/|init_phasor| (0 -> 1) if given,
+ *         else the LUT at (c + p) mod n_lut, c = *cursor (then *cursor += N);
+ *   iteration i = 1..n_iter: H_i = F^{-1}{R_{i-1}}, H'_i = H_i/|H_i|
+ *         (0 -> 1), R'_i = F{H'_i}, NMSE_i = NMSE(|R'_i|^2, T^2),
+ *         E_i = sum (|R'_i| - Te)^2 with Te = T*sqrt(N/sum T^2),
+ *         R_i = T * R'_i/|R'_i| (0 -> T);
+ *   then the final H_n is quantised to 8 levels m = round(8 arg H/(2 pi)) mod 8
+ *   and its replay is reconstructed.
+ *   target       device float[ny][nx]
+ *   init_phasor  device float2[ny][nx] or NULL (LUT).  Passing a previous
+ *                call's `field` resumes the iteration exactly.
+ *   field        device float2[ny][nx] out: unitary replay field R'_n, or NULL
+ *   codes        device uint8[ny][nx] out: 8-level codes of H_n, or NULL
+ *   nmse_per_iter, err_per_iter   [n_iter] or NULL (host, or device with
+ *                HOLO_F_NMSE_DEVICE)
+ *   nmse_final2  NMSE pair of the 8-level replay, or NULL (needs codes)
+ *   recon        device float[ny][nx] 8-level replay intensity, or NULL
+ * Errors: HOLO_EINVAL for null target/cursor, null lut without init_phasor,
+ * n_iter < 1, nmse_final2/recon without codes.
+ * ------------------------------------------------------------------------- */
+HOLO_API holo_status holo_gs_iterate(const float* target, int64_t nx, int64_t ny, int32_t n_iter,
+                                     const holo_lut* lut, uint64_t* cursor, const float* init_phasor,
+                                     float* field, uint8_t* codes, double* nmse_per_iter, double* err_per_iter,
+                                     double* nmse_final2, float* recon, int32_t precision, uint32_t flags,
+                                     void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * holo_reconstruct_nmse -- replay of quantised holograms, R' = F{H'}
+ * (Section 2), intensity time-averaged over n_sf holograms (Section 3).
+ *   holo    device: levels == 2 -> packed bits as holo_ospr_generate writes
+ *           them, [n_sf][nx*ny/32]; levels == 8 -> uint8 codes [n_sf][ny][nx]
+ *           meaning exp(i*2*pi*m/8)
+ *   recon   device float[ny][nx] or NULL;  nmse2 as in holo_ospr_generate
+ * Errors: HOLO_EINVAL for null holo/target, levels not 2 or 8, n_sf < 1.
+ * ------------------------------------------------------------------------- */
+HOLO_API holo_status holo_reconstruct_nmse(const void* holo, int32_t levels, int64_t nx, int64_t ny,
+                                           int32_t n_sf, const float* target, float* recon, double* nmse2,
+                                           uint32_t flags, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * holo_fft2 -- the unitary transform pair itself: Eq. (1) for sign = -1,
+ * Eq. (2) for sign = +1, complex [ny][nx] device in -> device out (may alias).
+ * ------------------------------------------------------------------------- */
+HOLO_API holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t ny, int32_t sign,
+                               void* hip_stream);
+
+/* Releases every workspace and twiddle table on every device. */
+HOLO_API void holo_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOLO_H_ */

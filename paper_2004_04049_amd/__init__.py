@@ -1,0 +1,236 @@
+"""Python binding of libholo.so, the MI355X (gfx950) hot path for LUT phase
+randomisation in OSPR / Gerchberg-Saxton hologram generation (Christopher &
+Wilkinson, arXiv:2004.04049).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch provides device memory and streams.  Function names follow
+the C ABI in include/holo.h (holo_<name>).  There is no fallback: if the
+library is missing, importing the binding's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libholo.so")
+
+HOLO_OK, HOLO_EINVAL, HOLO_EUNSUPPORTED, HOLO_ENOMEM, HOLO_EDEVICE = 0, -1, -2, -3, -4
+FP32, BF16, FP16 = 0, 1, 2
+F_NMSE_DEVICE = 1
+LUT_FLAT, LUT_NOT_PRIME, LUT_LE_NSF, LUT_LE_MAXDIM, LUT_DIVIDES_FRAME, LUT_LT_FULL = 1, 2, 4, 8, 16, 32
+
+_lib = None
+
+# name -> (restype, argtypes)
+_P, _U64, _I64, _I32, _U32 = C.c_void_p, C.c_uint64, C.c_int64, C.c_int32, C.c_uint32
+SIGNATURES = {
+    "holo_last_error": (C.c_char_p, []),
+    "holo_version": (_I32, []),
+    "holo_lut_build": (_I32, [_U64, _U64, C.POINTER(_P)]),
+    "holo_lut_from_phases": (_I32, [_P, _U64, C.POINTER(_P)]),
+    "holo_lut_phases": (_I32, [_P, _P, _U64]),
+    "holo_lut_size": (_U64, [_P]),
+    "holo_lut_free": (None, [_P]),
+    "holo_lut_check": (_U32, [_U64, _I64, _I64, _I32]),
+    "holo_ospr_generate": (_I32, [_P, _I64, _I64, _I32, _P, C.POINTER(_U64), _P, _P, _P, _I32, _U32, _P]),
+    "holo_gs_iterate": (_I32, [_P, _I64, _I64, _I32, _P, C.POINTER(_U64), _P, _P, _P, _P, _P, _P, _P, _I32,
+                               _U32, _P]),
+    "holo_reconstruct_nmse": (_I32, [_P, _I32, _I64, _I64, _I32, _P, _P, _P, _U32, _P]),
+    "holo_fft2": (_I32, [_P, _P, _I64, _I64, _I32, _P]),
+    "holo_shutdown": (None, []),
+}
+
+
+class HoloError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"holo status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Loads libholo.so (built by paper_2004_04049_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2004_04049_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != HOLO_OK:
+        raise HoloError(status, lib().holo_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Lut:
+    """Phase LUT handle (holo_lut_build / holo_lut_from_phases)."""
+
+    def __init__(self, n_lut: int, seed: int = 1, phases=None):
+        h = C.c_void_p()
+        if phases is not None:
+            import numpy as np
+            ph = np.ascontiguousarray(phases, dtype=np.float64)
+            _check(lib().holo_lut_from_phases(ph.ctypes.data_as(C.c_void_p), len(ph), C.byref(h)))
+        else:
+            _check(lib().holo_lut_build(n_lut, seed, C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __len__(self):
+        return int(lib().holo_lut_size(self._h))
+
+    def phases(self):
+        import numpy as np
+        n = len(self)
+        out = np.zeros(max(n, 1), dtype=np.float64)
+        _check(lib().holo_lut_phases(self._h, out.ctypes.data_as(C.c_void_p), n))
+        return out[:n]
+
+    def close(self):
+        if self._h:
+            lib().holo_lut_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lut_build(n_lut: int, seed: int = 1) -> Lut:
+    return Lut(n_lut, seed)
+
+
+def lut_check(n_lut: int, nx: int, ny: int, n_sf: int) -> int:
+    return int(lib().holo_lut_check(n_lut, nx, ny, n_sf))
+
+
+def _nmse_buf(n, device_out):
+    import numpy as np
+    if device_out is not None:
+        return device_out, C.c_void_p(device_out.data_ptr()), F_NMSE_DEVICE
+    a = np.zeros(n)
+    return a, a.ctypes.data_as(C.c_void_p), 0
+
+
+def ospr_generate(target, n_sf: int, lut: Lut, cursor: int, bits=None, recon=None, want_nmse=True,
+                  nmse_out=None, stream=None):
+    """holo_ospr_generate.  Returns (bits, nmse2 or None, new_cursor).
+    target: cuda float32 [ny, nx]; bits: cuda int32 [n_sf, nx*ny/32] (allocated
+    if None); recon: cuda float32 [ny, nx] or None; nmse_out: cuda float64 [2]
+    to keep the NMSE on the device (no synchronisation)."""
+    ny, nx = target.shape
+    _dev(target, torch.float32, None, "target")
+    if bits is None:
+        bits = torch.empty((n_sf, nx * ny // 32), dtype=torch.int32, device=target.device)
+    _dev(bits, torch.int32, (n_sf, nx * ny // 32), "bits")
+    if recon is not None:
+        _dev(recon, torch.float32, (ny, nx), "recon")
+    nm, nm_p, flags = (None, None, 0)
+    if want_nmse or nmse_out is not None:
+        nm, nm_p, flags = _nmse_buf(2, nmse_out)
+    cur = C.c_uint64(cursor)
+    _check(lib().holo_ospr_generate(_ptr(target), nx, ny, n_sf, lut.handle, C.byref(cur), _ptr(bits),
+                                    _ptr(recon), nm_p, FP32, flags, _stream(stream)))
+    return bits, nm, int(cur.value)
+
+
+def gs_iterate(target, n_iter: int, lut: Lut | None, cursor: int, init_phasor=None, field=None, codes=None,
+               want_nmse=True, want_err=False, want_final=True, recon=None, stream=None):
+    """holo_gs_iterate.  Returns dict(nmse, err, nmse_final2, field, codes,
+    cursor).  Tensors: target float32 [ny, nx]; init_phasor/field complex64
+    [ny, nx]; codes uint8 [ny, nx]."""
+    import numpy as np
+    ny, nx = target.shape
+    _dev(target, torch.float32, None, "target")
+    if init_phasor is not None:
+        _dev(init_phasor, torch.complex64, (ny, nx), "init_phasor")
+    if field is None:
+        field = torch.empty((ny, nx), dtype=torch.complex64, device=target.device)
+    _dev(field, torch.complex64, (ny, nx), "field")
+    if codes is None and (want_final or recon is not None):
+        codes = torch.empty((ny, nx), dtype=torch.uint8, device=target.device)
+    if codes is not None:
+        _dev(codes, torch.uint8, (ny, nx), "codes")
+    nm = np.zeros(n_iter) if want_nmse else None
+    er = np.zeros(n_iter) if want_err else None
+    fin = np.zeros(2) if want_final else None
+    cur = C.c_uint64(cursor)
+    _check(lib().holo_gs_iterate(
+        _ptr(target), nx, ny, n_iter, lut.handle if lut is not None else None, C.byref(cur), _ptr(init_phasor),
+        _ptr(field), _ptr(codes),
+        nm.ctypes.data_as(C.c_void_p) if nm is not None else None,
+        er.ctypes.data_as(C.c_void_p) if er is not None else None,
+        fin.ctypes.data_as(C.c_void_p) if fin is not None else None,
+        _ptr(recon), FP32, 0, _stream(stream)))
+    return {"nmse": nm, "err": er, "nmse_final2": fin, "field": field, "codes": codes, "cursor": int(cur.value)}
+
+
+def reconstruct_nmse(holo, levels: int, nx: int, ny: int, n_sf: int, target, recon=None, stream=None):
+    """holo_reconstruct_nmse.  holo: int32 [n_sf, nx*ny/32] bits (levels 2) or
+    uint8 [n_sf, ny, nx] codes (levels 8).  Returns the NMSE pair."""
+    import numpy as np
+    _dev(target, torch.float32, (ny, nx), "target")
+    if levels == 2:
+        _dev(holo, torch.int32, (n_sf, nx * ny // 32), "holo")
+    else:
+        _dev(holo, torch.uint8, None, "holo")
+        if holo.numel() != n_sf * nx * ny:
+            raise ValueError("codes must hold n_sf*ny*nx bytes")
+    if recon is not None:
+        _dev(recon, torch.float32, (ny, nx), "recon")
+    nm = np.zeros(2)
+    _check(lib().holo_reconstruct_nmse(_ptr(holo), levels, nx, ny, n_sf, _ptr(target), _ptr(recon),
+                                       nm.ctypes.data_as(C.c_void_p), 0, _stream(stream)))
+    return nm
+
+
+def fft2(x, sign: int, out=None, stream=None):
+    """holo_fft2: unitary Eq. (1) (sign -1) or Eq. (2) (sign +1) of a complex64 [ny, nx] tensor."""
+    _dev(x, torch.complex64, None, "x")
+    ny, nx = x.shape
+    if out is None:
+        out = torch.empty_like(x)
+    _dev(out, torch.complex64, (ny, nx), "out")
+    _check(lib().holo_fft2(_ptr(x), _ptr(out), nx, ny, sign, _stream(stream)))
+    return out
+
+
+def unpack_bits(bits: torch.Tensor, n: int):
+    """int32 words (LSB-first raster order) -> numpy uint8 bits [..., n] (host)."""
+    import numpy as np
+    a = bits.detach().cpu().numpy().view(np.uint8)
+    return np.unpackbits(a, axis=-1, bitorder="little")[..., :n]

@@ -1,0 +1,255 @@
+// fft_engine.hpp -- register/LDS Stockham FFT engine for gfx950 (wave64).
+//
+// Evaluates the 1D factors of the unitary DFT pair of Eq. (1)/(2) (without the
+// 1/sqrt(N) scale, which callers fold in where it matters) along one axis of a
+// 2D field.  A length-N transform (N = 2^k, 16 <= N <= 2048) is computed by
+// T = N/16 cooperating threads that each hold P = 16 points in registers.
+//
+// Register layout: thread t holds element e = t + T*m in slot m (m < 16) at the
+// start of every stage and after the last stage, so:
+//   * the first stage reads straight from memory with lane-contiguous addresses
+//     (coalesced along rows, or 16 columns at a time along columns);
+//   * the last stage leaves results where the next pointwise step (binarise,
+//     normalise, |.|^2, amplitude replacement) and a following transform of the
+//     same axis expect them -- no shuffle between chained transforms;
+//   * only the stage-to-stage exchange goes through LDS.
+// Stages (Stockham autosort, natural order in and out): radix 16 as often as
+// 16 divides the remaining length, then one radix-2/4/8 stage.  Stage with
+// radix R after Ns points have been combined: butterfly j = t + b*T (b < 16/R)
+// reads elements j + r*N/R, multiplies by W_{Ns*R}^{(j mod Ns)*r}, does an
+// R-point DFT in registers, and writes element (j/Ns)*Ns*R + (j mod Ns) + r*Ns.
+//
+// Twiddles come from a table W_N^k = exp(-2*pi*i*k/N), k < N, generated once
+// per length in FP64 on the device and rounded to FP32 (never by recurrence);
+// the inverse direction uses its conjugate.  Radix-16 internal constants are
+// the FP32 roundings of cos/sin(2*pi*k/16).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace holo {
+
+constexpr int kP = 16;  // points per thread
+
+template <int N>
+struct ilog2 { static constexpr int v = 1 + ilog2<N / 2>::v; };
+template <>
+struct ilog2<1> { static constexpr int v = 0; };
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
+}
+
+// cos/sin(2*pi*k/16), k = 0..4 (the rest follow by symmetry).
+__device__ __forceinline__ float c16(int k)
+{
+    switch (k & 15) {
+        case 0: return 1.0f;
+        case 1: return 0.923879532511286756f;
+        case 2: return 0.707106781186547524f;
+        case 3: return 0.382683432365089772f;
+        case 4: return 0.0f;
+        case 5: return -0.382683432365089772f;
+        case 6: return -0.707106781186547524f;
+        case 7: return -0.923879532511286756f;
+        case 8: return -1.0f;
+        case 9: return -0.923879532511286756f;
+        case 10: return -0.707106781186547524f;
+        case 11: return -0.382683432365089772f;
+        case 12: return 0.0f;
+        case 13: return 0.382683432365089772f;
+        case 14: return 0.707106781186547524f;
+        default: return 0.923879532511286756f;
+    }
+}
+__device__ __forceinline__ float s16(int k) { return c16(k - 4); }
+
+// x * exp(SIGN * 2*pi*i*k/16) with k a compile-time constant after unrolling;
+// exact cases (multiples of pi/2) avoid multiplications.
+template <int SIGN>
+__device__ __forceinline__ float2 rot16(float2 x, int k)
+{
+    k &= 15;
+    if (k == 0) return x;
+    if (k == 8) return make_float2(-x.x, -x.y);
+    if (k == 4) return SIGN > 0 ? make_float2(-x.y, x.x) : make_float2(x.y, -x.x);
+    if (k == 12) return SIGN > 0 ? make_float2(x.y, -x.x) : make_float2(-x.y, x.x);
+    const float c = c16(k), s = SIGN > 0 ? s16(k) : -s16(k);
+    if (k == 2 || k == 6 || k == 10 || k == 14) {
+        // |c| == |s| == sqrt(1/2): (x.x*c - x.y*s, x.x*s + x.y*c) with one scale
+        const float h = 0.707106781186547524f;
+        float sc = c > 0 ? 1.0f : -1.0f, ss = s > 0 ? 1.0f : -1.0f;
+        return make_float2(h * (sc * x.x - ss * x.y), h * (ss * x.x + sc * x.y));
+    }
+    return make_float2(fmaf(x.x, c, -x.y * s), fmaf(x.x, s, x.y * c));
+}
+
+// R-point DFT (R = 2, 4, 8, 16) of u[0..R) in registers, natural order in and
+// out, kernel exp(SIGN*2*pi*i*q*r/R): radix-2 decimation in time.
+template <int R, int SIGN>
+__device__ __forceinline__ void dft_small(float2 (&u)[R])
+{
+    constexpr int LR = ilog2<R>::v;
+    float2 a[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        int r = 0;
+#pragma unroll
+        for (int b = 0; b < LR; ++b) r |= ((i >> b) & 1) << (LR - 1 - b);
+        a[r] = u[i];
+    }
+#pragma unroll
+    for (int len = 2; len <= R; len <<= 1) {
+        const int half = len >> 1;
+#pragma unroll
+        for (int j = 0; j < half; ++j) {
+#pragma unroll
+            for (int i = 0; i < R; i += len) {
+                float2 e = a[i + j];
+                float2 o = rot16<SIGN>(a[i + j + half], j * (16 / len));
+                a[i + j] = cadd(e, o);
+                a[i + j + half] = csub(e, o);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) u[i] = a[i];
+}
+
+// Padded LDS element offset: one spare slot every 16 elements keeps the
+// stride-16 writes of a radix-16 stage off a single bank group.
+__device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
+template <int N>
+struct PadLen { static constexpr int v = N + N / 16; };
+__host__ __device__ constexpr int pad_len(int n) { return n + n / 16; }
+// Threads per column-transform block: 512 keeps up to 256 VGPRs per lane for
+// the two chained transforms; 2048-point columns need 1024 to hold 8 columns.
+__host__ __device__ constexpr int col_bound(int n) { return n >= 2048 ? 1024 : 512; }
+
+// One transform of length N on T = N/16 threads.  `v` holds slot m = element
+// t + T*m on entry and on exit.  LDS addressing is abstracted by `addr(e)` so
+// row (one transform per LDS row) and column (C interleaved transforms) layouts
+// share the engine.  `tw` is the FP32 table W_N^k; SIGN = -1 for Eq. (1),
+// +1 for Eq. (2).  Contains __syncthreads(): every thread of the block must
+// call it the same number of times.
+template <int N, int SIGN, typename Addr>
+__device__ __forceinline__ void fft_stages(float2 (&v)[kP], int t, float2* lds, Addr addr,
+                                           const float2* __restrict__ tw)
+{
+    constexpr int T = N / kP;
+    constexpr int L = ilog2<N>::v;
+    constexpr int NS16 = L / 4;          // radix-16 stages
+    constexpr int REM = L % 4;           // bits left for the last small stage
+    constexpr int NSTAGE = NS16 + (REM ? 1 : 0);
+    int Ns = 1;
+#pragma unroll
+    for (int s = 0; s < NSTAGE; ++s) {
+        const bool last = (s == NSTAGE - 1);
+        const int R = (s < NS16) ? 16 : (1 << REM);
+        const int nb = kP / R;
+        // butterflies
+#pragma unroll
+        for (int b = 0; b < nb; ++b) {
+            const int j = t + b * T;
+            const int jm = j & (Ns - 1);
+            if (R == 16) {
+                float2 u[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) u[r] = v[b + r * nb];
+                if (Ns > 1) {
+                    const int step = jm * (N / (Ns * 16));
+#pragma unroll
+                    for (int r = 1; r < 16; ++r) {
+                        float2 w = tw[step * r];
+                        u[r] = SIGN < 0 ? cmul(u[r], w) : cmulc(u[r], w);
+                    }
+                }
+                dft_small<16, SIGN>(u);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) v[b + r * nb] = u[r];
+            } else if (R == 8) {
+                float2 u[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) u[r] = v[b + r * nb];
+                if (Ns > 1) {
+                    const int step = jm * (N / (Ns * 8));
+#pragma unroll
+                    for (int r = 1; r < 8; ++r) {
+                        float2 w = tw[step * r];
+                        u[r] = SIGN < 0 ? cmul(u[r], w) : cmulc(u[r], w);
+                    }
+                }
+                dft_small<8, SIGN>(u);
+#pragma unroll
+                for (int r = 0; r < 8; ++r) v[b + r * nb] = u[r];
+            } else if (R == 4) {
+                float2 u[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) u[r] = v[b + r * nb];
+                if (Ns > 1) {
+                    const int step = jm * (N / (Ns * 4));
+#pragma unroll
+                    for (int r = 1; r < 4; ++r) {
+                        float2 w = tw[step * r];
+                        u[r] = SIGN < 0 ? cmul(u[r], w) : cmulc(u[r], w);
+                    }
+                }
+                dft_small<4, SIGN>(u);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[b + r * nb] = u[r];
+            } else {
+                float2 u[2];
+#pragma unroll
+                for (int r = 0; r < 2; ++r) u[r] = v[b + r * nb];
+                if (Ns > 1) {
+                    const int step = jm * (N / (Ns * 2));
+                    float2 w = tw[step];
+                    u[1] = SIGN < 0 ? cmul(u[1], w) : cmulc(u[1], w);
+                }
+                dft_small<2, SIGN>(u);
+                v[b] = u[0];
+                v[b + nb] = u[1];
+            }
+        }
+        if (!last) {
+            // exchange: write outputs at their Stockham positions, read back the
+            // t + T*m set for the next stage.
+#pragma unroll
+            for (int b = 0; b < nb; ++b) {
+                const int j = t + b * T;
+                const int base = (j / Ns) * Ns * R + (j & (Ns - 1));
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[addr(base + r * Ns)] = v[b + r * nb];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < kP; ++m) v[m] = lds[addr(t + T * m)];
+            __syncthreads();
+        }
+        Ns *= R;
+    }
+}
+
+// LDS addressing for R_ROWS independent row transforms of length N, one per
+// padded LDS row.
+template <int N>
+struct RowAddr {
+    int row;
+    __device__ __forceinline__ int operator()(int e) const { return row * PadLen<N>::v + lds_pad(e); }
+};
+// LDS addressing for C interleaved column transforms: element e of column c.
+template <int C>
+struct ColAddr {
+    int c;
+    __device__ __forceinline__ int operator()(int e) const { return lds_pad(e) * C + c; }
+};
+
+}  // namespace holo

@@ -1,0 +1,339 @@
+// gs_kernels.hip -- Gerchberg-Saxton passes (FP32 transforms, FP64 sums).
+//
+// GS (Section 2; Gerchberg & Saxton 1972) alternates between the hologram
+// plane, where the SLM allows phase only, and the replay plane, where only the
+// target amplitude is prescribed.  One iteration is two passes over the field:
+//   cols pass: inverse transform along y (completing H = F^{-1}{R}, Eq. (2)),
+//              optional 8-level codes of H, H' = H/|H| (H = 0 -> 1), forward
+//              transform along y (first half of R' = F{H'}, Eq. (1)).
+//   rows pass: forward transform along x (R'), FP64 partial sums of the
+//              per-iteration NMSE and amplitude error, amplitude replacement
+//              R = T * R'/|R'| (R' = 0 -> T), inverse transform along x.
+// The first rows pass forms R_0 = T * phasor from the LUT (cyclic address
+// (c + p) mod N_LUT, Section 5) or from a caller phasor field, and the last one
+// writes the unitary replay field R'_n instead of replacing amplitudes.
+#include "fft_engine.hpp"
+#include "kernels.hpp"
+
+namespace holo {
+
+#define HOLO_SWITCH_N(n, ...)                              \
+    switch (n) {                                           \
+        case 16: { constexpr int N_ = 16; __VA_ARGS__; } break;     \
+        case 32: { constexpr int N_ = 32; __VA_ARGS__; } break;     \
+        case 64: { constexpr int N_ = 64; __VA_ARGS__; } break;     \
+        case 128: { constexpr int N_ = 128; __VA_ARGS__; } break;   \
+        case 256: { constexpr int N_ = 256; __VA_ARGS__; } break;   \
+        case 512: { constexpr int N_ = 512; __VA_ARGS__; } break;   \
+        case 1024: { constexpr int N_ = 1024; __VA_ARGS__; } break; \
+        case 2048: { constexpr int N_ = 2048; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue;              \
+    }
+
+namespace {
+struct RowAddrG {
+    int base;
+    __device__ __forceinline__ int operator()(int e) const { return base + lds_pad(e); }
+};
+struct ColAddrG {
+    int c, C;
+    __device__ __forceinline__ int operator()(int e) const { return lds_pad(e) * C + c; }
+};
+
+template <typename K>
+void allow_lds_g(K kernel, size_t bytes)
+{
+    if (bytes > 64 * 1024) hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// fixed-order block reduction of NV doubles per thread; result valid in thread 0
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&a)[NV], double* red, double (&out)[NV])
+{
+    const int n = blockDim.x;
+    for (int i = 0; i < NV; ++i) red[i * n + threadIdx.x] = a[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < NV; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < n; ++j) s += red[i * n + j];
+            out[i] = s;
+        }
+    }
+}
+}  // namespace
+
+// Nearest of the 8 phase levels exp(i*2*pi*m/8) to h, m = round(8*arg(h)/(2*pi))
+// mod 8, decided by comparing |Im| and |Re| against tan(pi/8) without atan2.
+__device__ __forceinline__ uint8_t quant8(float2 h)
+{
+    if (h.x == 0.0f && h.y == 0.0f) return 0;
+    const float t8 = 0.414213562373095049f;   // tan(pi/8)
+    const float ax = fabsf(h.x), ay = fabsf(h.y);
+    int d;                                     // 0: along Re axis, 1: diagonal, 2: along Im axis
+    if (ay < ax * t8) d = 0;
+    else if (ax < ay * t8) d = 2;
+    else d = 1;
+    const bool re_neg = h.x < 0.0f, im_neg = h.y < 0.0f;
+    int m;
+    if (!re_neg && !im_neg) m = d;             // [0, pi/2]
+    else if (re_neg && !im_neg) m = 4 - d;     // (pi/2, pi]
+    else if (re_neg && im_neg) m = 4 + d;      // (pi, 3pi/2)
+    else m = (8 - d) & 7;                      // (3pi/2, 2pi)
+    return (uint8_t)m;
+}
+
+// -------------------------------------------------------------------------
+// Rows pass.  partials layout: [ny][3] = {S_II, S_IT, E} for ITER/FINAL,
+// [ny][2] = {sum T^2, sum T^4} for INIT.
+// -------------------------------------------------------------------------
+template <int NX, int MODE>
+__global__ __launch_bounds__(1024) void k_gs_rows(const float* __restrict__ target, int ny,
+                                                  const float2* __restrict__ lut, uint32_t n_lut, uint64_t c0,
+                                                  const float2* __restrict__ init, float2* __restrict__ state,
+                                                  float2* __restrict__ field_out, double* __restrict__ partials,
+                                                  const GsConsts* __restrict__ consts, const float2* __restrict__ tw)
+{
+    extern __shared__ float2 lds[];
+    constexpr int T = NX / kP;
+    const int rows = blockDim.x / T;
+    const int row = threadIdx.x / T, t = threadIdx.x % T;
+    const int y = blockIdx.x * rows + row;
+    const float* trow = target + (size_t)y * NX;
+    float2* srow = state + (size_t)y * NX;
+    float2 v[kP];
+    float ta[kP];
+#pragma unroll
+    for (int m = 0; m < kP; ++m) ta[m] = trow[t + T * m];
+
+    if (MODE == GS_INIT) {
+        double s2 = 0.0, s4 = 0.0;
+        if (init) {
+            const float2* irow = init + (size_t)y * NX;
+#pragma unroll
+            for (int m = 0; m < kP; ++m) {
+                const float2 p = irow[t + T * m];
+                const float mag = sqrtf(p.x * p.x + p.y * p.y);
+                v[m] = mag > 0.0f ? make_float2(ta[m] * (p.x / mag), ta[m] * (p.y / mag)) : make_float2(ta[m], 0.0f);
+            }
+        } else {
+            uint32_t idx = (uint32_t)((c0 + (uint64_t)y * NX + (uint64_t)t) % n_lut);
+            const uint32_t step = (uint32_t)(T % n_lut);
+#pragma unroll
+            for (int m = 0; m < kP; ++m) {
+                const float2 p = lut[idx];
+                v[m] = make_float2(ta[m] * p.x, ta[m] * p.y);
+                idx += step;
+                if (idx >= n_lut) idx -= n_lut;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < kP; ++m) {
+            const double q = (double)ta[m] * (double)ta[m];
+            s2 += q;
+            s4 += q * q;
+        }
+        fft_stages<NX, 1>(v, t, lds, RowAddrG{row * PadLen<NX>::v}, tw);
+#pragma unroll
+        for (int m = 0; m < kP; ++m) srow[t + T * m] = v[m];
+        __syncthreads();
+        double a[2] = {s2, s4}, out[2];
+        // one partial per row: reduce each row's T threads (rows of a block
+        // reduce one after another through the same scratch)
+        double* red = reinterpret_cast<double*>(lds);
+        red[2 * threadIdx.x] = a[0];
+        red[2 * threadIdx.x + 1] = a[1];
+        __syncthreads();
+        if (t == 0) {
+            out[0] = out[1] = 0.0;
+            for (int j = 0; j < T; ++j) {
+                out[0] += red[2 * (row * T + j)];
+                out[1] += red[2 * (row * T + j) + 1];
+            }
+            partials[(size_t)y * 2] = out[0];
+            partials[(size_t)y * 2 + 1] = out[1];
+        }
+        return;
+    }
+
+#pragma unroll
+    for (int m = 0; m < kP; ++m) v[m] = srow[t + T * m];
+    fft_stages<NX, -1>(v, t, lds, RowAddrG{row * PadLen<NX>::v}, tw);
+    // R' (unscaled) = sqrt(N) * R'_unitary; intensity in unitary units
+    const float inv_n = 1.0f / (float)((size_t)NX * (size_t)ny);
+    const float inv_sqrt_n = (float)(1.0 / sqrt((double)NX * (double)ny));
+    const double te = consts->te_scale;
+    double s_ii = 0.0, s_it = 0.0, e = 0.0;
+#pragma unroll
+    for (int m = 0; m < kP; ++m) {
+        const float i_u = (v[m].x * v[m].x + v[m].y * v[m].y) * inv_n;
+        const double ib = (double)i_u;
+        const double t2 = (double)ta[m] * (double)ta[m];
+        s_ii += ib * ib;
+        s_it += ib * t2;
+        const double d = sqrt(ib) - (double)ta[m] * te;
+        e += d * d;
+    }
+    if (MODE == GS_FINAL) {
+        float2* frow = field_out + (size_t)y * NX;
+#pragma unroll
+        for (int m = 0; m < kP; ++m) frow[t + T * m] = make_float2(v[m].x * inv_sqrt_n, v[m].y * inv_sqrt_n);
+    } else {
+#pragma unroll
+        for (int m = 0; m < kP; ++m) {
+            const float mag = sqrtf(v[m].x * v[m].x + v[m].y * v[m].y);
+            v[m] = mag > 0.0f ? make_float2(ta[m] * (v[m].x / mag), ta[m] * (v[m].y / mag)) : make_float2(ta[m], 0.0f);
+        }
+        fft_stages<NX, 1>(v, t, lds, RowAddrG{row * PadLen<NX>::v}, tw);
+#pragma unroll
+        for (int m = 0; m < kP; ++m) srow[t + T * m] = v[m];
+    }
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(lds);
+    red[3 * threadIdx.x] = s_ii;
+    red[3 * threadIdx.x + 1] = s_it;
+    red[3 * threadIdx.x + 2] = e;
+    __syncthreads();
+    if (t == 0) {
+        double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+        for (int j = 0; j < T; ++j) {
+            o0 += red[3 * (row * T + j)];
+            o1 += red[3 * (row * T + j) + 1];
+            o2 += red[3 * (row * T + j) + 2];
+        }
+        partials[(size_t)y * 3] = o0;
+        partials[(size_t)y * 3 + 1] = o1;
+        partials[(size_t)y * 3 + 2] = o2;
+    }
+}
+
+hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const float2* lut, uint32_t n_lut,
+                          uint64_t c0, const float2* init, float2* state, float2* field_out,
+                          double* partials, const GsConsts* consts, const float2* tw_x,
+                          const LaunchCfg& cfg, hipStream_t s)
+{
+    const int T = nx / kP;
+    int rows = cfg.rows_per_block > 0 ? cfg.rows_per_block : (256 / T > 0 ? 256 / T : 1);
+    while (rows > 1 && (ny % rows)) rows >>= 1;
+    if (rows > ny) rows = ny;
+    HOLO_SWITCH_N(nx, {
+        size_t fft_lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
+        size_t red_lds = (size_t)3 * rows * T * sizeof(double);
+        size_t lds = fft_lds > red_lds ? fft_lds : red_lds;
+        if (mode == GS_INIT) {
+            allow_lds_g(k_gs_rows<N_, GS_INIT>, lds);
+            hipLaunchKernelGGL((k_gs_rows<N_, GS_INIT>), dim3(ny / rows), dim3(rows * T), lds, s, target, ny, lut,
+                               n_lut, c0, init, state, field_out, partials, consts, tw_x);
+        } else if (mode == GS_ITER) {
+            allow_lds_g(k_gs_rows<N_, GS_ITER>, lds);
+            hipLaunchKernelGGL((k_gs_rows<N_, GS_ITER>), dim3(ny / rows), dim3(rows * T), lds, s, target, ny, lut,
+                               n_lut, c0, init, state, field_out, partials, consts, tw_x);
+        } else {
+            allow_lds_g(k_gs_rows<N_, GS_FINAL>, lds);
+            hipLaunchKernelGGL((k_gs_rows<N_, GS_FINAL>), dim3(ny / rows), dim3(rows * T), lds, s, target, ny, lut,
+                               n_lut, c0, init, state, field_out, partials, consts, tw_x);
+        }
+    });
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------
+// Columns pass (in place on `state`).
+// -------------------------------------------------------------------------
+template <int NY>
+__global__ __launch_bounds__(col_bound(NY)) void k_gs_cols(float2* __restrict__ state, int nx, uint8_t* __restrict__ codes,
+                                                  const float2* __restrict__ tw)
+{
+    extern __shared__ float2 lds[];
+    constexpr int T = NY / kP;
+    const int C = blockDim.x / T;
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int x = blockIdx.x * C + c;
+    float2 v[kP];
+#pragma unroll
+    for (int m = 0; m < kP; ++m) v[m] = state[(size_t)(t + T * m) * nx + x];
+    fft_stages<NY, 1>(v, t, lds, ColAddrG{c, C}, tw);
+    if (codes) {
+#pragma unroll
+        for (int m = 0; m < kP; ++m) codes[(size_t)(t + T * m) * nx + x] = quant8(v[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < kP; ++m) {
+        const float mag = sqrtf(v[m].x * v[m].x + v[m].y * v[m].y);
+        v[m] = mag > 0.0f ? make_float2(v[m].x / mag, v[m].y / mag) : make_float2(1.0f, 0.0f);
+    }
+    fft_stages<NY, -1>(v, t, lds, ColAddrG{c, C}, tw);
+#pragma unroll
+    for (int m = 0; m < kP; ++m) state[(size_t)(t + T * m) * nx + x] = v[m];
+}
+
+hipError_t launch_gs_cols(float2* state, int nx, int ny, uint8_t* codes, const float2* tw_y,
+                          const LaunchCfg& cfg, hipStream_t s)
+{
+    const int T = ny / kP;
+    int C = cfg.cols_per_block;
+    while (C > 1 && (C * T > col_bound(ny) || (size_t)C * pad_len(ny) * sizeof(float2) > 160 * 1024)) C >>= 1;
+    if (C > nx) C = nx;
+    HOLO_SWITCH_N(ny, {
+        size_t lds = (size_t)C * PadLen<N_>::v * sizeof(float2);
+        allow_lds_g(k_gs_cols<N_>, lds);
+        hipLaunchKernelGGL((k_gs_cols<N_>), dim3(nx / C), dim3(C * T), lds, s, state, nx, codes, tw_y);
+    });
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------
+// Frame constants from the INIT partials: sum T^2, sum T^4 and the amplitude
+// scale Te = T * sqrt(N / sum T^2) that matches a unit-modulus hologram's
+// replay energy (Parseval).
+// -------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gs_consts(const double* __restrict__ part, int ny, int nx,
+                                                   GsConsts* __restrict__ consts)
+{
+    __shared__ double red[2 * 256];
+    double a[2] = {0.0, 0.0}, out[2];
+    for (int r = threadIdx.x; r < ny; r += 256) {
+        a[0] += part[(size_t)r * 2];
+        a[1] += part[(size_t)r * 2 + 1];
+    }
+    block_sum<2>(a, red, out);
+    if (threadIdx.x == 0) {
+        consts->sum_t2 = out[0];
+        consts->sum_t4 = out[1];
+        consts->te_scale = out[0] > 0.0 ? sqrt((double)nx * (double)ny / out[0]) : 0.0;
+    }
+}
+
+hipError_t launch_gs_consts(const double* init_partials, int ny, int nx, GsConsts* consts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gs_consts, dim3(1), dim3(256), 0, s, init_partials, ny, nx, consts);
+    return hipGetLastError();
+}
+
+// One block per iteration: NMSE_i = 1 - S_IT^2 / (S_II * S_TT), E_i.
+__global__ __launch_bounds__(256) void k_gs_finalize(const double* __restrict__ part, int ny,
+                                                     const GsConsts* __restrict__ consts, double* __restrict__ nmse,
+                                                     double* __restrict__ err)
+{
+    __shared__ double red[3 * 256];
+    const int it = blockIdx.x;
+    const double* p = part + (size_t)it * ny * 3;
+    double a[3] = {0.0, 0.0, 0.0}, out[3];
+    for (int r = threadIdx.x; r < ny; r += 256)
+        for (int i = 0; i < 3; ++i) a[i] += p[(size_t)r * 3 + i];
+    block_sum<3>(a, red, out);
+    if (threadIdx.x == 0) {
+        const double s_tt = consts->sum_t4;
+        if (nmse) nmse[it] = (out[0] > 0.0 && s_tt > 0.0) ? 1.0 - out[1] * out[1] / (out[0] * s_tt) : 1.0;
+        if (err) err[it] = out[2];
+    }
+}
+
+hipError_t launch_gs_finalize(const double* partials, int n_iter, int ny, const GsConsts* consts,
+                              double* nmse_out, double* err_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gs_finalize, dim3(n_iter), dim3(256), 0, s, partials, ny, consts, nmse_out, err_out);
+    return hipGetLastError();
+}
+
+}  // namespace holo

@@ -1,0 +1,59 @@
+// kernels.hpp -- internal launch interface between the C-ABI host code and the
+// HIP kernels.  Not part of the public boundary (include/holo.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace holo {
+
+// Per-kernel launch shape, chosen by the plan (default or autotuned).
+struct LaunchCfg {
+    int cols_per_block = 16;   // C: interleaved column transforms per block
+    int rows_per_block = 0;    // row transforms per block (0 = fill 256 threads)
+    int ksplit = 4;            // sub-frame groups per reconstruction-row block
+};
+
+// FP64 twiddle generation on the device: tw[k] = fp32(exp(-2*pi*i*k/n)).
+hipError_t launch_twiddle_gen(float2* tw, int n, hipStream_t s);
+
+// Plain unitary 2D transform (Eq. (1) for sign < 0, Eq. (2) for sign > 0):
+// rows of `in` into `tmp`, columns of `tmp` into `out` (1/sqrt(N) applied).
+hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int ny, int sign,
+                       const float2* tw_x, const float2* tw_y, const LaunchCfg& cfg, hipStream_t s);
+
+// OSPR K1: R = T * LUT phasor, inverse row transform, all n_sf sub-frames.
+hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const float2* lut,
+                            uint32_t n_lut, uint64_t c0, float2* x1, const float2* tw_x,
+                            const LaunchCfg& cfg, hipStream_t s);
+// OSPR K2: inverse column transform, binarise + pack, forward column transform
+// of the +-1 column, half spectrum (rows 0..ny/2) out.
+hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
+                            const float2* tw_y, const LaunchCfg& cfg, hipStream_t s);
+// Reconstruction column transform straight from a quantised hologram:
+// levels 2 (packed bits -> half spectrum) or 8 (codes -> full spectrum).
+hipError_t launch_recon_cols(const void* holo, int levels, int nx, int ny, int n_sf, float2* x2,
+                             const float2* tw_y, const LaunchCfg& cfg, hipStream_t s);
+// K3: row transform, |.|^2, mean over sub-frames, NMSE partial sums (FP64).
+// half: x2 holds rows 0..ny/2 of a Hermitian-symmetric spectrum.
+hipError_t launch_recon_rows(const float2* x2, int nx, int ny, int n_sf, bool half, const float* target,
+                             float* recon, double* partials, const float2* tw_x, const LaunchCfg& cfg,
+                             hipStream_t s);
+// K4: deterministic reduction of `nrows` x 5 partials -> {NMSE, NMSE_sym}.
+hipError_t launch_nmse_finalize(const double* partials, int nrows, double* out2, hipStream_t s);
+
+// Gerchberg-Saxton passes.
+enum GsRowMode { GS_INIT = 0, GS_ITER = 1, GS_FINAL = 2 };
+struct GsConsts {
+    double sum_t2, sum_t4, te_scale;
+};
+hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const float2* lut, uint32_t n_lut,
+                          uint64_t c0, const float2* init, float2* state, float2* field_out,
+                          double* partials, const GsConsts* consts, const float2* tw_x,
+                          const LaunchCfg& cfg, hipStream_t s);
+hipError_t launch_gs_cols(float2* state, int nx, int ny, uint8_t* codes, const float2* tw_y,
+                          const LaunchCfg& cfg, hipStream_t s);
+hipError_t launch_gs_consts(const double* init_partials, int ny, int nx, GsConsts* consts, hipStream_t s);
+hipError_t launch_gs_finalize(const double* partials, int n_iter, int ny, const GsConsts* consts,
+                              double* nmse_out, double* err_out, hipStream_t s);
+
+}  // namespace holo

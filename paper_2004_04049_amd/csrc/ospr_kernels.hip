@@ -1,0 +1,502 @@
+// ospr_kernels.hip -- OSPR generation, reconstruction and NMSE kernels (FP32
+// transforms, FP64 sums) for gfx950.
+//
+// Data path of one OSPR frame of n_sf sub-frames (Section 2, Section 3):
+//   K1 ospr_rows : R_k = T * LUT[(c + k*N + p) mod N_LUT]  (Section 5, Fig. 3)
+//                  and the inverse transform along x                (Eq. (2))
+//   K2 ospr_cols : inverse transform along y -> H_k; nearest binary value
+//                  b = (Re H_k < 0) packed LSB-first; forward transform along y
+//                  of the real +-1 column B_k = 1 - 2b                 (Eq. (1))
+//                  written for rows v = 0..ny/2 only (B_k is real, so its
+//                  spectrum is Hermitian and the other half is redundant)
+//   K3 recon_rows: forward transform along x, I_k = |.|^2, the time average
+//                  over sub-frames in registers, FP64 NMSE partial sums
+//   K4 finalize  : fixed-order FP64 reduction -> {NMSE, NMSE_sym}
+// Transforms are unscaled; the unitary 1/sqrt(N) factors of Eq. (1)/(2) are
+// folded into the intensity (1/N), since binarisation is invariant to a
+// positive scale.
+#include "fft_engine.hpp"
+#include "kernels.hpp"
+
+namespace holo {
+
+#define HOLO_SWITCH_N(n, ...)                              \
+    switch (n) {                                           \
+        case 16: { constexpr int N_ = 16; __VA_ARGS__; } break;     \
+        case 32: { constexpr int N_ = 32; __VA_ARGS__; } break;     \
+        case 64: { constexpr int N_ = 64; __VA_ARGS__; } break;     \
+        case 128: { constexpr int N_ = 128; __VA_ARGS__; } break;   \
+        case 256: { constexpr int N_ = 256; __VA_ARGS__; } break;   \
+        case 512: { constexpr int N_ = 512; __VA_ARGS__; } break;   \
+        case 1024: { constexpr int N_ = 1024; __VA_ARGS__; } break; \
+        case 2048: { constexpr int N_ = 2048; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue;              \
+    }
+
+// Runtime LDS addressing (block shape chosen at launch).
+struct RowAddrR {
+    int base;
+    __device__ __forceinline__ int operator()(int e) const { return base + lds_pad(e); }
+};
+struct ColAddrR {
+    int c, C;
+    __device__ __forceinline__ int operator()(int e) const { return lds_pad(e) * C + c; }
+};
+
+static int row_block_rows(int n, int nrows, const LaunchCfg& cfg)
+{
+    const int T = n / kP;
+    int rows = cfg.rows_per_block > 0 ? cfg.rows_per_block : (256 / T > 0 ? 256 / T : 1);
+    if (rows < 1) rows = 1;
+    while (rows > 1 && (nrows % rows)) rows >>= 1;
+    if (rows > nrows) rows = nrows;
+    return rows;
+}
+
+static int col_block_cols(int n, int ncols, const LaunchCfg& cfg)
+{
+    const int T = n / kP;
+    int C = cfg.cols_per_block;
+    while (C > 1 && (C * T > col_bound(n) || (size_t)C * pad_len(n) * sizeof(float2) > 160 * 1024)) C >>= 1;
+    if (C > ncols) C = ncols;
+    return C;
+}
+
+// -------------------------------------------------------------------------
+// Twiddles: FP64 evaluation on the device, rounded once to FP32.
+// -------------------------------------------------------------------------
+__global__ void k_twiddle_gen(float2* tw, int n)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double two_pi = 6.283185307179586476925286766559;
+    double a = two_pi * ((double)k / (double)n);
+    tw[k] = make_float2((float)cos(a), (float)(-sin(a)));
+}
+
+hipError_t launch_twiddle_gen(float2* tw, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_twiddle_gen, dim3((n + 255) / 256), dim3(256), 0, s, tw, n);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------
+// Plain 2D transform (used by the unitary holo_fft2 entry point and tests).
+// -------------------------------------------------------------------------
+template <int N, int SIGN>
+__global__ __launch_bounds__(1024) void k_fft_rows(const float2* __restrict__ in, float2* __restrict__ out,
+                                                   int nrows, const float2* __restrict__ tw)
+{
+    extern __shared__ float2 lds[];
+    constexpr int T = N / kP;
+    const int row = threadIdx.x / T, t = threadIdx.x % T;
+    const int rows = blockDim.x / T;
+    const size_t y = (size_t)blockIdx.x * rows + row;
+    float2 v[kP];
+    const float2* src = in + y * N;
+#pragma unroll
+    for (int m = 0; m < kP; ++m) v[m] = src[t + T * m];
+    fft_stages<N, SIGN>(v, t, lds, RowAddrR{row * PadLen<N>::v}, tw);
+    float2* dst = out + y * N;
+#pragma unroll
+    for (int m = 0; m < kP; ++m) dst[t + T * m] = v[m];
+}
+
+template <int N, int SIGN>
+__global__ __launch_bounds__(col_bound(N)) void k_fft_cols(const float2* __restrict__ in, float2* __restrict__ out,
+                                                   int nx, float scale, const float2* __restrict__ tw)
+{
+    extern __shared__ float2 lds[];
+    constexpr int T = N / kP;
+    const int C = blockDim.x / T;
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int x = blockIdx.x * C + c;
+    float2 v[kP];
+#pragma unroll
+    for (int m = 0; m < kP; ++m) v[m] = in[(size_t)(t + T * m) * nx + x];
+    fft_stages<N, SIGN>(v, t, lds, ColAddrR{c, C}, tw);
+#pragma unroll
+    for (int m = 0; m < kP; ++m) out[(size_t)(t + T * m) * nx + x] = make_float2(v[m].x * scale, v[m].y * scale);
+}
+
+template <typename K>
+static void allow_lds(K kernel, size_t bytes)
+{
+    if (bytes > 64 * 1024) hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int ny, int sign,
+                       const float2* tw_x, const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
+{
+    {
+        const int rows = row_block_rows(nx, ny, cfg);
+        HOLO_SWITCH_N(nx, {
+            constexpr int T = N_ / kP;
+            size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
+            if (sign < 0) {
+                allow_lds(k_fft_rows<N_, -1>, lds);
+                hipLaunchKernelGGL((k_fft_rows<N_, -1>), dim3(ny / rows), dim3(rows * T), lds, s, in, tmp, ny, tw_x);
+            } else {
+                allow_lds(k_fft_rows<N_, 1>, lds);
+                hipLaunchKernelGGL((k_fft_rows<N_, 1>), dim3(ny / rows), dim3(rows * T), lds, s, in, tmp, ny, tw_x);
+            }
+        });
+    }
+    {
+        const int C = col_block_cols(ny, nx, cfg);
+        const float scale = (float)(1.0 / sqrt((double)nx * (double)ny));
+        HOLO_SWITCH_N(ny, {
+            constexpr int T = N_ / kP;
+            size_t lds = (size_t)C * PadLen<N_>::v * sizeof(float2);
+            if (sign < 0) {
+                allow_lds(k_fft_cols<N_, -1>, lds);
+                hipLaunchKernelGGL((k_fft_cols<N_, -1>), dim3(nx / C), dim3(C * T), lds, s, tmp, out, nx, scale, tw_y);
+            } else {
+                allow_lds(k_fft_cols<N_, 1>, lds);
+                hipLaunchKernelGGL((k_fft_cols<N_, 1>), dim3(nx / C), dim3(C * T), lds, s, tmp, out, nx, scale, tw_y);
+            }
+        });
+    }
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------
+// K1: LUT phase randomisation fused with the inverse row transform.
+// Grid: (ny / rows) * n_sf blocks of rows * (nx/16) threads.
+// -------------------------------------------------------------------------
+template <int NX>
+__global__ __launch_bounds__(1024) void k_ospr_rows(const float* __restrict__ target, int ny,
+                                                    const float2* __restrict__ lut, uint32_t n_lut, uint64_t c0,
+                                                    float2* __restrict__ x1, const float2* __restrict__ tw)
+{
+    extern __shared__ float2 lds[];
+    constexpr int T = NX / kP;
+    const int rows = blockDim.x / T;
+    const int row = threadIdx.x / T, t = threadIdx.x % T;
+    const int blocks_per_sf = ny / rows;
+    const int k = blockIdx.x / blocks_per_sf;
+    const int y = (blockIdx.x % blocks_per_sf) * rows + row;
+    const uint64_t npix = (uint64_t)NX * (uint64_t)ny;
+    // Cyclic LUT address of pixel (t, y) in sub-frame k; then +T per slot.
+    uint32_t idx = (uint32_t)((c0 + (uint64_t)k * npix + (uint64_t)y * NX + (uint64_t)t) % n_lut);
+    const uint32_t step = (uint32_t)(T % n_lut);
+    const float* trow = target + (size_t)y * NX;
+    float2 v[kP];
+#pragma unroll
+    for (int m = 0; m < kP; ++m) {
+        const float a = trow[t + T * m];
+        const float2 ph = lut[idx];
+        v[m] = make_float2(a * ph.x, a * ph.y);
+        idx += step;
+        if (idx >= n_lut) idx -= n_lut;
+    }
+    fft_stages<NX, 1>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, tw);
+    float2* dst = x1 + (size_t)k * npix + (size_t)y * NX;
+#pragma unroll
+    for (int m = 0; m < kP; ++m) dst[t + T * m] = v[m];
+}
+
+hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const float2* lut,
+                            uint32_t n_lut, uint64_t c0, float2* x1, const float2* tw_x,
+                            const LaunchCfg& cfg, hipStream_t s)
+{
+    const int rows = row_block_rows(nx, ny, cfg);
+    HOLO_SWITCH_N(nx, {
+        constexpr int T = N_ / kP;
+        size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
+        allow_lds(k_ospr_rows<N_>, lds);
+        hipLaunchKernelGGL((k_ospr_rows<N_>), dim3((ny / rows) * n_sf), dim3(rows * T), lds, s, target, ny, lut,
+                           n_lut, c0, x1, tw_x);
+    });
+    return hipGetLastError();
+}
+
+// Store one wave's binarised row chunks: lanes c = 0..C-1 of each C-lane group
+// hold consecutive pixels of one row; the ballot gives their bits in lane order,
+// which is raster order, LSB first.
+__device__ __forceinline__ void store_bit_chunk(uint8_t* bits8, uint64_t mask, int lane, int C, size_t p0)
+{
+    const int g = lane / C;
+    const uint32_t chunk = (uint32_t)(mask >> (g * C));
+    if (C == 32) reinterpret_cast<uint32_t*>(bits8)[p0 >> 5] = chunk;
+    else if (C == 16) reinterpret_cast<uint16_t*>(bits8)[p0 >> 4] = (uint16_t)chunk;
+    else reinterpret_cast<uint8_t*>(bits8)[p0 >> 3] = (uint8_t)chunk;
+}
+
+// -------------------------------------------------------------------------
+// K2: inverse column transform, binarise + pack, forward column transform of
+// the +-1 column; writes the half spectrum rows 0..ny/2.
+// Grid: (nx / C) * n_sf blocks of C * (ny/16) threads, C in {8, 16, 32}.
+// -------------------------------------------------------------------------
+template <int NY>
+__global__ __launch_bounds__(col_bound(NY)) void k_ospr_cols(const float2* __restrict__ x1, int nx,
+                                                    uint32_t* __restrict__ bits, float2* __restrict__ x2,
+                                                    const float2* __restrict__ tw)
+{
+    extern __shared__ float2 lds[];
+    constexpr int T = NY / kP;
+    const int C = blockDim.x / T;
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int lane = threadIdx.x & 63;
+    const int ncb = nx / C;
+    const int k = blockIdx.x / ncb;
+    const int x0 = (blockIdx.x % ncb) * C;
+    const int x = x0 + c;
+    const size_t npix = (size_t)nx * NY;
+    const float2* src = x1 + (size_t)k * npix;
+    float2 v[kP];
+#pragma unroll
+    for (int m = 0; m < kP; ++m) v[m] = src[(size_t)(t + T * m) * nx + x];
+    fft_stages<NY, 1>(v, t, lds, ColAddrR{c, C}, tw);
+    uint8_t* bits8 = reinterpret_cast<uint8_t*>(bits + (size_t)k * (npix / 32));
+#pragma unroll
+    for (int m = 0; m < kP; ++m) {
+        const bool neg = v[m].x < 0.0f;   // nearest of {+1, -1}; Re H = 0 -> +1
+        const uint64_t mask = __ballot(neg);
+        if (c == 0) store_bit_chunk(bits8, mask, lane, C, (size_t)(t + T * m) * nx + x0);
+        v[m] = make_float2(neg ? -1.0f : 1.0f, 0.0f);
+    }
+    fft_stages<NY, -1>(v, t, lds, ColAddrR{c, C}, tw);
+    float2* dst = x2 + (size_t)k * (NY / 2 + 1) * nx;
+#pragma unroll
+    for (int m = 0; m < kP; ++m) {
+        const int vv = t + T * m;
+        if (vv <= NY / 2) dst[(size_t)vv * nx + x] = v[m];
+    }
+}
+
+hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
+                            const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
+{
+    int C = col_block_cols(ny, nx, cfg);
+    if (C < 8) return hipErrorInvalidValue;   // bit chunks are at least a byte
+    HOLO_SWITCH_N(ny, {
+        constexpr int T = N_ / kP;
+        size_t lds = (size_t)C * PadLen<N_>::v * sizeof(float2);
+        allow_lds(k_ospr_cols<N_>, lds);
+        hipLaunchKernelGGL((k_ospr_cols<N_>), dim3((nx / C) * n_sf), dim3(C * T), lds, s, x1, nx, bits, x2, tw_y);
+    });
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------
+// Reconstruction column transform from a quantised hologram.
+//   levels 2: packed bits -> B = +-1 -> rows 0..ny/2 of its column spectrum
+//   levels 8: codes m -> exp(i*2*pi*m/8) -> full column spectrum
+// -------------------------------------------------------------------------
+__device__ __forceinline__ float2 level8_phasor(int m)
+{
+    const float h = 0.707106781186547524f;
+    switch (m & 7) {
+        case 0: return make_float2(1.0f, 0.0f);
+        case 1: return make_float2(h, h);
+        case 2: return make_float2(0.0f, 1.0f);
+        case 3: return make_float2(-h, h);
+        case 4: return make_float2(-1.0f, 0.0f);
+        case 5: return make_float2(-h, -h);
+        case 6: return make_float2(0.0f, -1.0f);
+        default: return make_float2(h, -h);
+    }
+}
+
+template <int NY>
+__global__ __launch_bounds__(col_bound(NY)) void k_recon_cols(const void* __restrict__ holo, int levels, int nx,
+                                                     float2* __restrict__ x2, const float2* __restrict__ tw)
+{
+    extern __shared__ float2 lds[];
+    constexpr int T = NY / kP;
+    const int C = blockDim.x / T;
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int ncb = nx / C;
+    const int k = blockIdx.x / ncb;
+    const int x = (blockIdx.x % ncb) * C + c;
+    const size_t npix = (size_t)nx * NY;
+    float2 v[kP];
+    if (levels == 2) {
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(holo) + (size_t)k * (npix / 32);
+#pragma unroll
+        for (int m = 0; m < kP; ++m) {
+            const size_t p = (size_t)(t + T * m) * nx + x;
+            const uint32_t b = (w[p >> 5] >> (p & 31)) & 1u;
+            v[m] = make_float2(b ? -1.0f : 1.0f, 0.0f);
+        }
+    } else {
+        const uint8_t* cd = reinterpret_cast<const uint8_t*>(holo) + (size_t)k * npix;
+#pragma unroll
+        for (int m = 0; m < kP; ++m) v[m] = level8_phasor(cd[(size_t)(t + T * m) * nx + x]);
+    }
+    fft_stages<NY, -1>(v, t, lds, ColAddrR{c, C}, tw);
+    const int vmax = levels == 2 ? NY / 2 : NY - 1;
+    float2* dst = x2 + (size_t)k * (vmax + 1) * nx;
+#pragma unroll
+    for (int m = 0; m < kP; ++m) {
+        const int vv = t + T * m;
+        if (vv <= vmax) dst[(size_t)vv * nx + x] = v[m];
+    }
+}
+
+hipError_t launch_recon_cols(const void* holo, int levels, int nx, int ny, int n_sf, float2* x2,
+                             const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
+{
+    const int C = col_block_cols(ny, nx, cfg);
+    HOLO_SWITCH_N(ny, {
+        constexpr int T = N_ / kP;
+        size_t lds = (size_t)C * PadLen<N_>::v * sizeof(float2);
+        allow_lds(k_recon_cols<N_>, lds);
+        hipLaunchKernelGGL((k_recon_cols<N_>), dim3((nx / C) * n_sf), dim3(C * T), lds, s, holo, levels, nx, x2,
+                           tw_y);
+    });
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------
+// K3: row transform of each sub-frame's column spectrum, intensity, time
+// average and FP64 NMSE partial sums.  One block per spectrum row v; its
+// G = blockDim/(nx/16) thread groups take sub-frames g, g+G, ... and their
+// sums are combined through LDS in a fixed order.
+// partials[v*5 + {0..4}] = {S_II, S_IT, S_ITs, S_TT, S_TsTs} over the pixels
+// this row stands for (itself and, for the half spectrum, its point mirror).
+// -------------------------------------------------------------------------
+__device__ __forceinline__ void block_sum5(double (&a)[5], double* red, int nthreads, double* out)
+{
+    // fixed-order reduction: every thread parks its 5 sums, thread 0 adds them
+    // in thread order (nthreads <= 1024, done once per block).
+    for (int i = 0; i < 5; ++i) red[i * nthreads + threadIdx.x] = a[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 5; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < nthreads; ++j) s += red[i * nthreads + j];
+            out[i] = s;
+        }
+    }
+}
+
+template <int NX>
+__global__ __launch_bounds__(512) void k_recon_rows(const float2* __restrict__ x2, int ny, int n_sf, int half,
+                                                     const float* __restrict__ target, float* __restrict__ recon,
+                                                     double* __restrict__ partials, const float2* __restrict__ tw,
+                                                     float inv_scale)
+{
+    extern __shared__ float2 lds[];
+    constexpr int T = NX / kP;
+    const int G = blockDim.x / T;
+    const int g = threadIdx.x / T, t = threadIdx.x % T;
+    const int v_row = blockIdx.x;
+    const int nrows_spec = half ? (ny / 2 + 1) : ny;
+    const size_t sf_stride = (size_t)nrows_spec * NX;
+    float acc[kP];
+#pragma unroll
+    for (int m = 0; m < kP; ++m) acc[m] = 0.0f;
+    const int rounds = (n_sf + G - 1) / G;
+    for (int r = 0; r < rounds; ++r) {
+        const int k = r * G + g;
+        const bool valid = k < n_sf;
+        const float2* src = x2 + (size_t)(valid ? k : 0) * sf_stride + (size_t)v_row * NX;
+        float2 v[kP];
+#pragma unroll
+        for (int m = 0; m < kP; ++m) v[m] = valid ? src[t + T * m] : make_float2(0.0f, 0.0f);
+        fft_stages<NX, -1>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, tw);
+#pragma unroll
+        for (int m = 0; m < kP; ++m) acc[m] = fmaf(v[m].x, v[m].x, fmaf(v[m].y, v[m].y, acc[m]));
+    }
+    // combine the G groups' sums (group order fixed)
+    float* ldsf = reinterpret_cast<float*>(lds);
+    if (G > 1) {
+#pragma unroll
+        for (int m = 0; m < kP; ++m) ldsf[g * NX + t + T * m] = acc[m];
+        __syncthreads();
+        if (g == 0) {
+#pragma unroll
+            for (int m = 0; m < kP; ++m) {
+                float s = ldsf[t + T * m];
+                for (int gg = 1; gg < G; ++gg) s += ldsf[gg * NX + t + T * m];
+                acc[m] = s;
+            }
+        }
+        __syncthreads();
+    }
+    double sums[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (g == 0) {
+        const int vm = (ny - v_row) % ny;
+        const bool self_mirror = !half || v_row == 0 || v_row == ny / 2;
+        const float* trow = target + (size_t)v_row * NX;
+        const float* mrow = target + (size_t)vm * NX;
+#pragma unroll
+        for (int m = 0; m < kP; ++m) {
+            const int u = t + T * m;
+            const int um = (NX - u) & (NX - 1);
+            const double ib = (double)(acc[m] * inv_scale);
+            const double ta = (double)trow[u], tb = (double)mrow[um];
+            const double t2a = ta * ta, t2b = tb * tb, ts = 0.5 * (t2a + t2b);
+            if (half && !self_mirror) {
+                sums[0] += 2.0 * ib * ib;
+                sums[1] += ib * (t2a + t2b);
+                sums[2] += 2.0 * ib * ts;
+                sums[3] += t2a * t2a + t2b * t2b;
+                sums[4] += 2.0 * ts * ts;
+            } else {
+                sums[0] += ib * ib;
+                sums[1] += ib * t2a;
+                sums[2] += ib * ts;
+                sums[3] += t2a * t2a;
+                sums[4] += ts * ts;
+            }
+            if (recon) {
+                recon[(size_t)v_row * NX + u] = (float)ib;
+                if (half && !self_mirror) recon[(size_t)vm * NX + um] = (float)ib;
+            }
+        }
+    }
+    __syncthreads();
+    block_sum5(sums, reinterpret_cast<double*>(lds), blockDim.x, partials + (size_t)v_row * 5);
+}
+
+hipError_t launch_recon_rows(const float2* x2, int nx, int ny, int n_sf, bool half, const float* target,
+                             float* recon, double* partials, const float2* tw_x, const LaunchCfg& cfg,
+                             hipStream_t s)
+{
+    const int nrows_spec = half ? ny / 2 + 1 : ny;
+    HOLO_SWITCH_N(nx, {
+        constexpr int T = N_ / kP;
+        int G = cfg.ksplit > 0 ? cfg.ksplit : 1;
+        while (G > 1 && (G * T > 512 || G > n_sf)) G >>= 1;
+        if (G * T < 5) G = 1;
+        size_t fft_lds = (size_t)G * PadLen<N_>::v * sizeof(float2);
+        size_t red_lds = (size_t)5 * G * T * sizeof(double);
+        size_t lds = fft_lds > red_lds ? fft_lds : red_lds;
+        const float inv_scale = (float)(1.0 / ((double)n_sf * (double)nx * (double)ny));
+        allow_lds(k_recon_rows<N_>, lds);
+        hipLaunchKernelGGL((k_recon_rows<N_>), dim3(nrows_spec), dim3(G * T), lds, s, x2, ny, n_sf, half ? 1 : 0,
+                           target, recon, partials, tw_x, inv_scale);
+    });
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------
+// K4: {NMSE, NMSE_sym} = 1 - S_IW^2 / (S_II * S_WW) from the row partials,
+// reduced in a fixed order (deterministic run to run).
+// -------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_nmse_finalize(const double* __restrict__ partials, int nrows,
+                                                       double* __restrict__ out2)
+{
+    __shared__ double red[5 * 256];
+    double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int r = threadIdx.x; r < nrows; r += 256)
+        for (int i = 0; i < 5; ++i) a[i] += partials[(size_t)r * 5 + i];
+    double s[5];
+    block_sum5(a, red, 256, s);
+    if (threadIdx.x == 0) {
+        const double s_ii = s[0], s_it = s[1], s_its = s[2], s_tt = s[3], s_tsts = s[4];
+        out2[0] = (s_ii > 0.0 && s_tt > 0.0) ? 1.0 - s_it * s_it / (s_ii * s_tt) : 1.0;
+        out2[1] = (s_ii > 0.0 && s_tsts > 0.0) ? 1.0 - s_its * s_its / (s_ii * s_tsts) : 1.0;
+    }
+}
+
+hipError_t launch_nmse_finalize(const double* partials, int nrows, double* out2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nmse_finalize, dim3(1), dim3(256), 0, s, partials, nrows, out2);
+    return hipGetLastError();
+}
+
+}  // namespace holo

@@ -1,0 +1,73 @@
+"""The C-ABI library: it loads, exports every symbol include/holo.h declares,
+and rejects invalid arguments with the documented status codes before
+touching a device.  CPU only (no compute calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    syms = []
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            syms += re.findall(r"HOLO_API\s+[\w\s\*]+?\b(holo_\w+)\s*\(", txt)
+    return sorted(set(syms))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2004_04049_amd as h
+    if not os.path.exists(h.LIB_PATH):
+        pytest.fail("libholo.so is not built (run __graft_entry__.build())")
+    return h.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = _declared_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(lib, s), s
+    import paper_2004_04049_amd as h
+    assert set(h.SIGNATURES) >= set(syms)
+
+
+def test_lut_check_rules(lib):
+    import paper_2004_04049_amd as h
+    assert h.lut_check(10007, 1024, 1024, 24) == h.LUT_LT_FULL
+    w = h.lut_check(256, 256, 256, 24)
+    assert w & h.LUT_NOT_PRIME and w & h.LUT_LE_MAXDIM and w & h.LUT_DIVIDES_FRAME
+    assert h.lut_check(23, 64, 64, 24) & h.LUT_LE_NSF
+    assert h.lut_check(0, 64, 64, 8) & h.LUT_FLAT
+    assert h.lut_check(1024 * 1024 * 24 + 7, 1024, 1024, 24) & h.LUT_LT_FULL == 0
+
+
+def test_invalid_arguments_rejected_before_device_work(lib):
+    import paper_2004_04049_amd as h
+    cur = C.c_uint64(0)
+    P = C.c_void_p
+    fake = P(16)
+    st = lib.holo_ospr_generate(None, 64, 64, 8, fake, C.byref(cur), fake, None, None, 0, 0, None)
+    assert st == h.HOLO_EINVAL
+    st = lib.holo_ospr_generate(fake, 64, 64, 0, fake, C.byref(cur), fake, None, None, 0, 0, None)
+    assert st == h.HOLO_EINVAL
+    assert b"n_sf" in lib.holo_last_error()
+    st = lib.holo_ospr_generate(fake, 100, 64, 8, fake, C.byref(cur), fake, None, None, 0, 0, None)
+    assert st == h.HOLO_EUNSUPPORTED
+    st = lib.holo_ospr_generate(fake, 4096, 64, 8, fake, C.byref(cur), fake, None, None, 0, 0, None)
+    assert st == h.HOLO_EUNSUPPORTED
+    st = lib.holo_gs_iterate(fake, 64, 64, 0, fake, C.byref(cur), None, None, None, None, None, None, None, 0, 0,
+                             None)
+    assert st == h.HOLO_EINVAL
+    st = lib.holo_gs_iterate(fake, 64, 64, 5, fake, C.byref(cur), None, None, None, None, None, fake, None, 0, 0,
+                             None)
+    assert st == h.HOLO_EINVAL   # nmse_final2 without codes
+    st = lib.holo_reconstruct_nmse(fake, 4, 64, 64, 1, fake, None, None, 0, None)
+    assert st == h.HOLO_EINVAL
+    st = lib.holo_fft2(fake, fake, 64, 64, 2, None)
+    assert st == h.HOLO_EINVAL
+    assert cur.value == 0

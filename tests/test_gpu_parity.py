@@ -1,0 +1,179 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+identical seeded inputs.
+
+Tolerances (in unitary units of Eq. (1)/(2), targets in [0, 1]):
+  * binary holograms: bit-exact except pixels with |Re H_oracle| < 1e-5;
+  * NMSE values: 1e-4 relative;
+  * transforms / time-averaged intensities: relative L2 error < 1e-5
+    (FP32 radix-16 transforms: about log2(N) * 2^-24 per element).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TIE = 1e-5
+NMSE_RTOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def holo():
+    import paper_2004_04049_amd as h
+    h.lib()
+    assert torch.cuda.is_available()
+    return h
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _check_bits(h, orc, bits_gpu, ref, n):
+    got = h.unpack_bits(bits_gpu, n)
+    want = orc.unpack_bits(ref["bits"], n)
+    reh = ref["reH"].reshape(got.shape[0], -1)
+    decided = np.abs(reh) >= TIE
+    mism = (got != want) & decided
+    assert int(mism.sum()) == 0, f"{int(mism.sum())} decided pixels differ"
+    return int((~decided).sum())
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 16), (64, 32), (32, 128), (256, 256), (1024, 1024), (2048, 64), (64, 2048)])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_fft2_matches_oracle(holo, orc, nx, ny, sign):
+    rng = np.random.default_rng(nx + 7 * ny)
+    f = (rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))).astype(np.complex64)
+    print(f"fft2 {nx}x{ny} sign {sign}", flush=True)
+    got = holo.fft2(torch.from_numpy(f).cuda(), sign).cpu().numpy()
+    want = orc.fft2(f.astype(np.complex128), sign)
+    assert _rel_l2(got, want) < 1e-6
+
+
+def _ospr_case(holo, orc, nx, ny, nsf, n_lut, cursor, target, want_recon=True):
+    print(f"ospr {nx}x{ny} nsf={nsf} lut={n_lut} cursor={cursor}", flush=True)
+    lut = holo.Lut(n_lut, 1)
+    phi = orc.lut_phases(n_lut, 1)
+    assert np.array_equal(lut.phases(), phi)           # bit-exact FP64 phases
+    t = torch.from_numpy(target).cuda()
+    recon = torch.empty((ny, nx), dtype=torch.float32, device="cuda") if want_recon else None
+    bits, nm, cur = holo.ospr_generate(t, nsf, lut, cursor, recon=recon)
+    torch.cuda.synchronize()
+    ref = orc.ospr(target, nsf, phi, n_lut, cursor)
+    assert cur == cursor + nsf * nx * ny
+    ties = _check_bits(holo, orc, bits, ref, nx * ny)
+    np.testing.assert_allclose(nm, ref["nmse2"], rtol=NMSE_RTOL)
+    if want_recon:
+        assert _rel_l2(recon.cpu().numpy().astype(np.float64), ref["ibar"]) < 1e-5
+    return bits, ref, ties
+
+
+def test_ospr_uniform_64_lut256(holo, orc):
+    # 64x64 uniform target, 8 sub-frames, 256-entry LUT (which divides the
+    # frame, so every sub-frame is the same hologram)
+    t = synth.uniform_target(64, 64, synth.SEED_UNIFORM_64)
+    bits, ref, _ = _ospr_case(holo, orc, 64, 64, 8, 256, 0, t)
+    b = bits.cpu().numpy()
+    assert all(np.array_equal(b[k], b[0]) for k in range(8))
+
+
+@pytest.mark.parametrize("nx,ny,nsf,n_lut,cursor", [
+    (128, 32, 5, 10007, 123456789012),      # ragged sub-frame count, non-square
+    (32, 256, 3, 1, 7),                     # single-entry LUT
+    (64, 64, 2, 0, 0),                      # flat phase
+    (16, 16, 1, 17, 2 ** 63 + 5),           # smallest size, huge cursor
+    (512, 512, 9, 65537, 3),
+])
+def test_ospr_small_cases(holo, orc, nx, ny, nsf, n_lut, cursor):
+    t = synth.blob_target(nx, ny, 5)
+    _ospr_case(holo, orc, nx, ny, nsf, n_lut, cursor, t)
+
+
+@pytest.mark.parametrize("n_lut", [2 ** 16, 10007])
+def test_ospr_1024_full_size(holo, orc, n_lut):
+    t = synth.blob_target(1024, 1024, synth.SEED_OSPR_1024)
+    _, _, ties = _ospr_case(holo, orc, 1024, 1024, 24, n_lut, 0, t, want_recon=True)
+    assert ties < 24 * 1024 * 1024 * 1e-3
+
+
+def test_ospr_2048_tall_and_wide(holo, orc):
+    t = synth.blob_target(2048, 128, 21)
+    _ospr_case(holo, orc, 2048, 128, 3, 10007, 11, t)
+    t = synth.blob_target(128, 2048, 22)
+    _ospr_case(holo, orc, 128, 2048, 3, 10007, 11, t)
+
+
+def test_ospr_cursor_chaining_bit_exact(holo):
+    t = torch.from_numpy(synth.blob_target(256, 256, 3)).cuda()
+    lut = holo.Lut(10007, 1)
+    b8, _, c8 = holo.ospr_generate(t, 8, lut, 99)
+    b4a, _, c4 = holo.ospr_generate(t, 4, lut, 99)
+    b4b, _, c4b = holo.ospr_generate(t, 4, lut, c4)
+    assert c8 == c4b
+    assert torch.equal(b8, torch.cat([b4a, b4b]))
+
+
+def test_reconstruct_from_oracle_holograms(holo, orc):
+    nx, ny, nsf = 256, 128, 6
+    t = synth.blob_target(nx, ny, 9)
+    phi = orc.lut_phases(10007, 1)
+    ref = orc.ospr(t, nsf, phi, 10007, 0)
+    bits = torch.from_numpy(ref["bits"].view(np.int32)).cuda()
+    nm = holo.reconstruct_nmse(bits, 2, nx, ny, nsf, torch.from_numpy(t).cuda())
+    np.testing.assert_allclose(nm, ref["nmse2"], rtol=NMSE_RTOL)
+    # 8-level codes
+    codes = np.random.default_rng(1).integers(0, 8, (2, ny, nx), dtype=np.uint8)
+    recon = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
+    nm8 = holo.reconstruct_nmse(torch.from_numpy(codes).cuda(), 8, nx, ny, 2, torch.from_numpy(t).cuda(), recon)
+    iv = orc.reconstruct(codes.reshape(2, -1), 8, nx, ny, 2)
+    np.testing.assert_allclose(nm8, orc.nmse_pair(iv, t), rtol=NMSE_RTOL)
+    assert _rel_l2(recon.cpu().numpy().astype(np.float64), iv) < 1e-5
+
+
+def _gs_case(holo, orc, nx, ny, n_iter, n_lut, seed):
+    print(f"gs {nx}x{ny} iters={n_iter} lut={n_lut}", flush=True)
+    t = synth.blob_target(nx, ny, seed)
+    lut = holo.Lut(n_lut, 1)
+    r = holo.gs_iterate(torch.from_numpy(t).cuda(), n_iter, lut, 0, want_err=True)
+    phi = orc.lut_phases(n_lut, 1)
+    init = orc.lut_phasor_field(phi, n_lut, 0, 0, nx, ny)
+    ref = orc.gs(t, n_iter, init)
+    assert r["cursor"] == nx * ny
+    np.testing.assert_allclose(r["nmse"], ref["nmse"], rtol=NMSE_RTOL)
+    np.testing.assert_allclose(r["err"], ref["err"], rtol=1e-3)
+    return t, r, ref
+
+
+def test_gs_512_50_iterations(holo, orc):
+    t, r, ref = _gs_case(holo, orc, 512, 512, 50, 4096, synth.SEED_GS_512)
+    codes = r["codes"].cpu().numpy()
+    mism = np.mean(codes != ref["codes"])
+    assert mism < 1e-3, mism
+    np.testing.assert_allclose(r["nmse_final2"], ref["nmse_final2"], rtol=1e-3)
+    fld = r["field"].cpu().numpy()
+    assert _rel_l2(fld, ref["field"]) < 1e-3
+
+
+@pytest.mark.parametrize("nx,ny", [(16, 64), (128, 32), (1024, 1024)])
+def test_gs_other_sizes(holo, orc, nx, ny):
+    _gs_case(holo, orc, nx, ny, 6, 10007, 4)
+
+
+def test_gs_fixed_point_and_resume(holo, orc):
+    nx, ny = 64, 32
+    rng = np.random.default_rng(3)
+    hs = np.exp(1j * rng.uniform(0, 2 * np.pi, (ny, nx)))
+    F = np.fft.fft2(hs, norm="ortho")
+    t = torch.from_numpy(np.abs(F).astype(np.float32)).cuda()
+    init = torch.from_numpy((F / np.abs(F)).astype(np.complex64)).cuda()
+    r = holo.gs_iterate(t, 1, None, 0, init_phasor=init)
+    assert r["nmse"][0] < 1e-10
+    # resume: 3 iterations == 2, then 1 more seeded with the returned field
+    tb = torch.from_numpy(synth.blob_target(nx, ny, 2)).cuda()
+    lut = holo.Lut(101, 1)
+    a = holo.gs_iterate(tb, 3, lut, 0)
+    b = holo.gs_iterate(tb, 2, lut, 0)
+    c = holo.gs_iterate(tb, 1, None, 0, init_phasor=b["field"].clone())
+    np.testing.assert_allclose(c["nmse"][0], a["nmse"][2], rtol=1e-5)
