@@ -1,0 +1,225 @@
+"""Throughput of the hot path on one MI355X.
+
+One step = one OSPR frame at 1024x1024 with 24 binary sub-frames: LUT phase
+randomisation, inverse 2D transform, binarisation, reconstruction transforms,
+time-averaged intensity and FP64 NMSE, all in the library's HIP kernels,
+inputs resident in HBM.  Reported: sub-frames/s (value), the HBM roofline of
+the dominant kernel (from HIP events recorded inside the library on the launch
+stream), the FP64 CPU oracle on a bounded sample of the same workload, GS
+iterations/s at 512x512 and 1024x1024, and a LUT-length sweep with NMSE.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+METRIC = "OSPR 1024² sub-frames/s + GS iter/s at matched NMSE; % HBM roofline"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--lut", type=int, default=65536)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip GS and the LUT sweep")
+    return ap.parse_args()
+
+
+def ospr_kernel_bytes(nx, ny, n_sf, n_lut):
+    """Algorithmic HBM bytes per launch of each OSPR kernel, from the per-pixel
+    byte model of the three-pass design (per sub-frame: K1 writes the complex
+    field, 8 B/px; K2 reads it, 8 B/px, writes the packed bits, 1/8 B/px, and the
+    complex reconstruction column spectrum, 8 B/px; K3 reads that, 8 B/px; the
+    target, 4 B/px, is read once per frame by K1 and once by K3).  A LUT of more
+    than 2^16 entries cannot stay cache-resident, so its unique entries read
+    (8 B each) are charged to K1."""
+    n = nx * ny
+    lut_bytes = 8 * min(n_lut, n * n_sf) if n_lut > 65536 else 0
+    return {
+        "ospr_rows": n_sf * n * 8 + n * 4 + lut_bytes,
+        "ospr_cols": n_sf * n * (8 + 0.125 + 8),
+        "recon_rows": n_sf * n * 8 + n * 4,
+    }
+
+
+def source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2004_04049_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they
+    were taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        with open(p) as f:
+            rec = json.load(f)
+        e = rec.get(workload, {}).get(kernel)
+        if not e or e.get("source_hash") != source_hash():
+            return None
+        return e["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(frames and sub-frames would shard by cursor range; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2004_04049_amd as h
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    nx = ny = 1024
+    n_sf = 24
+    n_lut = args.lut
+    target = torch.from_numpy(synth.blob_target(nx, ny, synth.SEED_OSPR_1024)).to(dev)
+    lut = h.Lut(n_lut, synth.SEED_LUT)
+    bits = torch.empty((n_sf, nx * ny // 32), dtype=torch.int32, device=dev)
+    nmse_dev = torch.zeros(2, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    cursor = 0
+    for _ in range(args.warmup):
+        _, _, cursor = h.ospr_generate(target, n_sf, lut, cursor, bits=bits, want_nmse=False, nmse_out=nmse_dev)
+    torch.cuda.synchronize()
+    h.prof_reset()
+    h.prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, cursor = h.ospr_generate(target, n_sf, lut, cursor, bits=bits, want_nmse=False, nmse_out=nmse_dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h.prof_enable(False)
+    elapsed = t1 - t0
+    value = args.steps * n_sf / elapsed
+    nmse = nmse_dev.cpu().numpy().tolist()
+
+    kbytes = ospr_kernel_bytes(nx, ny, n_sf, n_lut)
+    kern = {}
+    for k in ("ospr_rows", "ospr_cols", "recon_rows", "nmse_finalize"):
+        ms, cnt = h.prof_read(k)
+        if cnt:
+            kern[k] = {"avg_us": 1e3 * ms / cnt, "launches": cnt}
+    dom = max((k for k in kbytes if k in kern), key=lambda k: kern[k]["avg_us"])
+    avg_s = kern[dom]["avg_us"] * 1e-6
+    achieved = kbytes[dom] / avg_s / 1e9
+    for k in kbytes:
+        if k in kern:
+            kern[k]["algorithmic_GBps"] = kbytes[k] / (kern[k]["avg_us"] * 1e-6) / 1e9
+    workload = f"ospr_{nx}x{ny}_sf{n_sf}_lut{n_lut}"
+    traffic = measured_traffic(dom, workload)
+    step_bytes = sum(kbytes.values())
+    roofline = {
+        "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "step_frac": round(step_bytes / (elapsed / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "sub-frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"OSPR binary {nx}x{ny}, {n_sf} sub-frames, LUT {n_lut} entries, "
+                               f"seeded 20-blob + 10-rectangle target", "nx": nx, "ny": ny, "n_sf": n_sf,
+                   "n_lut": n_lut},
+        "nmse": nmse, "roofline": roofline, "kernels": kern,
+    }
+
+    if not args.no_extras:
+        out["gs"] = bench_gs(h, synth, torch, dev)
+        out["lut_sweep"] = bench_lut_sweep(h, synth, torch, dev, target, nx, ny, n_sf)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(synth, nx, ny, n_lut)
+    print(json.dumps(out), flush=True)
+
+
+def bench_gs(h, synth, torch, dev):
+    res = {}
+    for n, reps in ((512, 20), (1024, 10)):
+        t = torch.from_numpy(synth.blob_target(n, n, synth.SEED_GS_512)).to(dev)
+        lut = h.Lut(4096, synth.SEED_LUT)
+        field = torch.empty((n, n), dtype=torch.complex64, device=dev)
+        codes = torch.empty((n, n), dtype=torch.uint8, device=dev)
+        r = h.gs_iterate(t, 50, lut, 0, field=field, codes=codes)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = h.gs_iterate(t, 50, lut, 0, field=field, codes=codes)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res[f"{n}x{n}"] = {"iters": 50, "iter_per_s": round(50 / dt, 1), "ms_per_run": round(1e3 * dt, 3),
+                           "nmse_iter1": float(r["nmse"][0]), "nmse_iter50": float(r["nmse"][-1]),
+                           "nmse_8level": float(r["nmse_final2"][0]),
+                           "hbm_frac_36Bpx": round(36 * n * n * 50 / dt / 1e9 / HBM_PEAK_GBS, 4)}
+    return res
+
+
+def bench_lut_sweep(h, synth, torch, dev, target, nx, ny, n_sf):
+    res = []
+    sizes = [2 ** 8, 2 ** 12, 2 ** 16, 2 ** 20, nx * ny * n_sf, 10007, 65537, 1048573]
+    bits = torch.empty((n_sf, nx * ny // 32), dtype=torch.int32, device=dev)
+    for L in sizes:
+        lut = h.Lut(L, synth.SEED_LUT)
+        _, nm, c = h.ospr_generate(target, n_sf, lut, 0, bits=bits)
+        torch.cuda.synchronize()
+        steps = 20
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, _, c = h.ospr_generate(target, n_sf, lut, c, bits=bits, want_nmse=False,
+                                      nmse_out=torch.empty(2, dtype=torch.float64, device=dev))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res.append({"n_lut": L, "subframes_per_s": round(n_sf / dt, 1), "nmse": float(nm[0]),
+                    "nmse_sym": float(nm[1]), "warnings": h.lut_check(L, nx, ny, n_sf)})
+        lut.close()
+    return res
+
+
+def cpu_baseline(synth, nx, ny, n_lut):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload: the
+    same target, LUT and frame size, 4 frames of 24 sub-frames."""
+    import oracle
+    t = synth.blob_target(nx, ny, synth.SEED_OSPR_1024)
+    phi = oracle.lut_phases(n_lut, synth.SEED_LUT)
+    frames, n_sf = 4, 24
+    cursor = 0
+    t0 = time.perf_counter()
+    for _ in range(frames):
+        oracle.ospr(t, n_sf, phi, n_lut, cursor, want_reh=False, want_ibar=False)
+        cursor += n_sf * nx * ny
+    dt = time.perf_counter() - t0
+    return {"value": round(frames * n_sf / dt, 3), "unit": "sub-frames/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": f"{frames} frames x {n_sf} sub-frames at {nx}x{ny}, LUT {n_lut}, "
+                                        f"{dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -165,6 +165,19 @@ HOLO_API holo_status holo_reconstruct_nmse(const void* holo, int32_t levels, int
 HOLO_API holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t ny, int32_t sign,
                                void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Kernel timing (measurement support, not part of the method).
+ * holo_prof_enable(1) makes every subsequent launch record a pair of HIP
+ * events on its stream; holo_prof_read waits for the recorded events and
+ * returns the accumulated duration (ms) and launch count of one kernel:
+ * "ospr_rows", "ospr_cols", "recon_cols", "recon_rows", "nmse_finalize",
+ * "gs_rows", "gs_cols", "gs_consts", "gs_finalize", "fft2".  Unknown names
+ * read as zero.  holo_prof_reset clears the totals.
+ * ------------------------------------------------------------------------- */
+HOLO_API holo_status holo_prof_enable(int32_t on);
+HOLO_API holo_status holo_prof_read(const char* kernel, double* total_ms, int64_t* count);
+HOLO_API void holo_prof_reset(void);
+
 /* Releases every workspace and twiddle table on every device. */
 HOLO_API void holo_shutdown(void);
 

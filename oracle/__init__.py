@@ -59,6 +59,7 @@ def _load():
         "orc_reconstruct": (None, [P, i32, i64, i64, i32, P]),
         "orc_ospr": (None, [P, i64, i64, i32, P, u64, u64, P, P, P, P]),
         "orc_gs": (None, [P, i64, i64, i32, P, P, P, P, P, P]),
+        "orc_num_threads": (i32, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -66,6 +67,10 @@ def _load():
         f.argtypes = args
     _lib = lib
     return lib
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
 
 
 def _p(a):

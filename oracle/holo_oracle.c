@@ -383,3 +383,11 @@ void orc_gs(const float *T, int64_t nx, int64_t ny, int n_iter, const double *in
     }
     free(r); free(h); free(t2); free(iv);
 }
+
+/* Threads the OpenMP loops above use (reported with CPU timings). */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_num_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_num_threads(void) { return 1; }
+#endif

@@ -41,6 +41,9 @@ SIGNATURES = {
     "holo_reconstruct_nmse": (_I32, [_P, _I32, _I64, _I64, _I32, _P, _P, _P, _U32, _P]),
     "holo_fft2": (_I32, [_P, _P, _I64, _I64, _I32, _P]),
     "holo_shutdown": (None, []),
+    "holo_prof_enable": (_I32, [_I32]),
+    "holo_prof_read": (_I32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(_I64)]),
+    "holo_prof_reset": (None, []),
 }
 
 
@@ -234,3 +237,20 @@ def unpack_bits(bits: torch.Tensor, n: int):
     import numpy as np
     a = bits.detach().cpu().numpy().view(np.uint8)
     return np.unpackbits(a, axis=-1, bitorder="little")[..., :n]
+
+
+def prof_enable(on: bool = True):
+    """Start/stop per-launch HIP-event timing inside the library."""
+    _check(lib().holo_prof_enable(1 if on else 0))
+
+
+def prof_read(kernel: str):
+    """(total_ms, launches) recorded for `kernel` since the last reset."""
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(lib().holo_prof_read(kernel.encode(), C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+def prof_reset():
+    lib().holo_prof_reset()

@@ -129,6 +129,73 @@ struct Carver {
     }
 };
 
+// Kernel timing: when enabled, each launch is bracketed by a pair of HIP
+// events recorded on the launch stream; durations are folded into per-kernel
+// totals when read.  Off by default (no events are recorded).
+struct ProfPending {
+    const char* name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfPending> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+std::map<std::string, std::pair<double, int64_t>> g_prof_tot;
+
+hipEvent_t prof_event()
+{
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct ProfScope {
+    const char* name;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(const char* n, hipStream_t st) : name(n), s(st)
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (!g_prof_on) return;
+        a = prof_event();
+        b = prof_event();
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    ~ProfScope()
+    {
+        if (!a || !b) return;
+        (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_pending.push_back({name, a, b});
+    }
+};
+
+void prof_drain()
+{
+    for (auto& p : g_prof_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            auto& t = g_prof_tot[p.name];
+            t.first += ms;
+            t.second += 1;
+        }
+        g_prof_pool.push_back(p.a);
+        g_prof_pool.push_back(p.b);
+    }
+    g_prof_pending.clear();
+}
+
+#define LAUNCH(name, s, expr)           \
+    do {                                \
+        ProfScope ps_(name, s);         \
+        HIP_TRY(expr);                  \
+    } while (0)
+
 holo_status check_lut(const holo_lut* lut, int device)
 {
     if (!lut) return fail(HOLO_EINVAL, "lut is NULL");
@@ -280,10 +347,10 @@ holo_status holo_ospr_generate(const float* target, int64_t nx, int64_t ny, int3
     const uint32_t L = lut->n_dev;
     const uint64_t c0 = *cursor % L;
     const LaunchCfg cfg = default_cfg();
-    HIP_TRY(launch_ospr_rows(target, (int)nx, (int)ny, n_sf, lut->dev, L, c0, x1, tw_x, cfg, s));
-    HIP_TRY(launch_ospr_cols(x1, (int)nx, (int)ny, n_sf, holo_bits, x2, tw_y, cfg, s));
-    HIP_TRY(launch_recon_rows(x2, (int)nx, (int)ny, n_sf, true, target, recon, part, tw_x, cfg, s));
-    HIP_TRY(launch_nmse_finalize(part, (int)(ny / 2 + 1), nm, s));
+    LAUNCH("ospr_rows", s, launch_ospr_rows(target, (int)nx, (int)ny, n_sf, lut->dev, L, c0, x1, tw_x, cfg, s));
+    LAUNCH("ospr_cols", s, launch_ospr_cols(x1, (int)nx, (int)ny, n_sf, holo_bits, x2, tw_y, cfg, s));
+    LAUNCH("recon_rows", s, launch_recon_rows(x2, (int)nx, (int)ny, n_sf, true, target, recon, part, tw_x, cfg, s));
+    LAUNCH("nmse_finalize", s, launch_nmse_finalize(part, (int)(ny / 2 + 1), nm, s));
     if ((st = copy_out(nmse2, nm, 2, flags, s))) return st;
     *cursor += (uint64_t)n_sf * (uint64_t)npix;
     return HOLO_OK;
@@ -318,9 +385,9 @@ holo_status holo_reconstruct_nmse(const void* holo, int32_t levels, int64_t nx, 
     double* part = (double*)(b + o_part);
     double* nm = (double*)(b + o_nm);
     const LaunchCfg cfg = default_cfg();
-    HIP_TRY(launch_recon_cols(holo, levels, (int)nx, (int)ny, n_sf, x2, tw_y, cfg, s));
-    HIP_TRY(launch_recon_rows(x2, (int)nx, (int)ny, n_sf, half, target, recon, part, tw_x, cfg, s));
-    HIP_TRY(launch_nmse_finalize(part, nrows, nm, s));
+    LAUNCH("recon_cols", s, launch_recon_cols(holo, levels, (int)nx, (int)ny, n_sf, x2, tw_y, cfg, s));
+    LAUNCH("recon_rows", s, launch_recon_rows(x2, (int)nx, (int)ny, n_sf, half, target, recon, part, tw_x, cfg, s));
+    LAUNCH("nmse_finalize", s, launch_nmse_finalize(part, nrows, nm, s));
     return copy_out(nmse2, nm, 2, flags, s);
 }
 
@@ -373,23 +440,23 @@ holo_status holo_gs_iterate(const float* target, int64_t nx, int64_t ny, int32_t
     const float2* lutp = use_lut ? lut->dev : nullptr;
     const LaunchCfg cfg = default_cfg();
     const int inx = (int)nx, iny = (int)ny;
-    HIP_TRY(launch_gs_rows(GS_INIT, target, inx, iny, lutp, L, c0, (const float2*)init_phasor, state, nullptr,
+    LAUNCH("gs_rows", s, launch_gs_rows(GS_INIT, target, inx, iny, lutp, L, c0, (const float2*)init_phasor, state, nullptr,
                            pinit, consts, tw_x, cfg, s));
-    HIP_TRY(launch_gs_consts(pinit, iny, inx, consts, s));
+    LAUNCH("gs_consts", s, launch_gs_consts(pinit, iny, inx, consts, s));
     for (int it = 0; it < n_iter; ++it) {
         const bool last = it == n_iter - 1;
-        HIP_TRY(launch_gs_cols(state, inx, iny, last ? codes : nullptr, tw_y, cfg, s));
-        HIP_TRY(launch_gs_rows(last ? GS_FINAL : GS_ITER, target, inx, iny, lutp, L, c0, nullptr, state, fout,
+        LAUNCH("gs_cols", s, launch_gs_cols(state, inx, iny, last ? codes : nullptr, tw_y, cfg, s));
+        LAUNCH("gs_rows", s, launch_gs_rows(last ? GS_FINAL : GS_ITER, target, inx, iny, lutp, L, c0, nullptr, state, fout,
                                piter + (size_t)it * 3 * ny, consts, tw_x, cfg, s));
     }
-    HIP_TRY(launch_gs_finalize(piter, n_iter, iny, consts, nm, er, s));
+    LAUNCH("gs_finalize", s, launch_gs_finalize(piter, n_iter, iny, consts, nm, er, s));
     if (codes && (nmse_final2 || recon)) {
         float2* x2 = (float2*)(b + o_x2);
         double* p5 = (double*)(b + o_p5);
         double* f2 = (double*)(b + o_f2);
-        HIP_TRY(launch_recon_cols(codes, 8, inx, iny, 1, x2, tw_y, cfg, s));
-        HIP_TRY(launch_recon_rows(x2, inx, iny, 1, false, target, recon, p5, tw_x, cfg, s));
-        HIP_TRY(launch_nmse_finalize(p5, iny, f2, s));
+        LAUNCH("recon_cols", s, launch_recon_cols(codes, 8, inx, iny, 1, x2, tw_y, cfg, s));
+        LAUNCH("recon_rows", s, launch_recon_rows(x2, inx, iny, 1, false, target, recon, p5, tw_x, cfg, s));
+        LAUNCH("nmse_finalize", s, launch_nmse_finalize(p5, iny, f2, s));
         if ((st = copy_out(nmse_final2, f2, 2, flags, s))) return st;
     }
     if ((st = copy_out(nmse_per_iter, nm, n_iter, flags, s))) return st;
@@ -413,9 +480,34 @@ holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t ny, int32
     if ((st = get_twiddles(device, (int)ny, s, &tw_y))) return st;
     void* ws;
     if ((st = get_workspace(device, s, sizeof(float2) * (size_t)nx * ny, &ws))) return st;
-    HIP_TRY(launch_fft2((const float2*)in, (float2*)ws, (float2*)out, (int)nx, (int)ny, sign, tw_x, tw_y,
+    LAUNCH("fft2", s, launch_fft2((const float2*)in, (float2*)ws, (float2*)out, (int)nx, (int)ny, sign, tw_x, tw_y,
                         default_cfg(), s));
     return HOLO_OK;
+}
+
+holo_status holo_prof_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return HOLO_OK;
+}
+
+holo_status holo_prof_read(const char* kernel, double* total_ms, int64_t* count)
+{
+    if (!kernel || !total_ms || !count) return fail(HOLO_EINVAL, "kernel, total_ms and count are required");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_drain();
+    auto it = g_prof_tot.find(kernel);
+    *total_ms = it == g_prof_tot.end() ? 0.0 : it->second.first;
+    *count = it == g_prof_tot.end() ? 0 : it->second.second;
+    return HOLO_OK;
+}
+
+void holo_prof_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_drain();
+    g_prof_tot.clear();
 }
 
 void holo_shutdown(void)

@@ -65,8 +65,14 @@ def _ospr_case(holo, orc, nx, ny, nsf, n_lut, cursor, target, want_recon=True):
     assert cur == cursor + nsf * nx * ny
     ties = _check_bits(holo, orc, bits, ref, nx * ny)
     np.testing.assert_allclose(nm, ref["nmse2"], rtol=NMSE_RTOL)
+    # A pixel with |Re H| below the tie threshold may legitimately binarise
+    # either way, and one flipped pixel moves every replay value by ~2/sqrt(N);
+    # so the reconstruction is checked against the oracle's replay of the
+    # GPU's own holograms (unique given the bits).
+    own = orc.reconstruct(bits.cpu().numpy().view(np.uint32), 2, nx, ny, nsf)
+    np.testing.assert_allclose(nm, orc.nmse_pair(own, target), rtol=NMSE_RTOL)
     if want_recon:
-        assert _rel_l2(recon.cpu().numpy().astype(np.float64), ref["ibar"]) < 1e-5
+        assert _rel_l2(recon.cpu().numpy().astype(np.float64), own) < 1e-5
     return bits, ref, ties
 
 
