@@ -140,6 +140,73 @@ __host__ __device__ constexpr int col_bound(int n) { return n >= 2048 ? 1024 : 5
 // share the engine.  `tw` is the FP32 table W_N^k; SIGN = -1 for Eq. (1),
 // +1 for Eq. (2).  Contains __syncthreads(): every thread of the block must
 // call it the same number of times.
+// u[r] *= W^(step*r) for r = 1..R-1 (conjugated for the inverse kernel),
+// where W^k = tw[k] = exp(-2*pi*i*k/N).  Radix 16 loads W^s, W^2s, W^3s and
+// W^4s, W^8s, W^12s and forms the other nine as W^4as * W^bs (one FP32 product
+// of two correctly rounded table values); radix 8 loads four and forms three.
+// Fewer table loads keep register pressure and vector-memory traffic low.
+template <int R, int SIGN>
+__device__ __forceinline__ void apply_twiddles(float2 (&u)[R], const float2* __restrict__ tw, int step)
+{
+    auto mul = [](float2 x, float2 w) { return SIGN < 0 ? cmul(x, w) : cmulc(x, w); };
+    if (R == 2) {
+        u[1] = mul(u[1], tw[step]);
+    } else if (R == 4) {
+        const float2 w1 = tw[step], w2 = tw[2 * step], w3 = tw[3 * step];
+        u[1] = mul(u[1], w1);
+        u[2] = mul(u[2], w2);
+        u[3] = mul(u[3], w3);
+    } else if (R == 8) {
+        const float2 w1 = tw[step], w2 = tw[2 * step], w3 = tw[3 * step], w4 = tw[4 * step];
+        u[1] = mul(u[1], w1);
+        u[2] = mul(u[2], w2);
+        u[3] = mul(u[3], w3);
+        u[4] = mul(u[4], w4);
+        u[5] = mul(u[5], cmul(w4, w1));
+        u[6] = mul(u[6], cmul(w4, w2));
+        u[7] = mul(u[7], cmul(w4, w3));
+    } else {
+        float2 wb[4], wa[4];
+        wb[1] = tw[step];
+        wb[2] = tw[2 * step];
+        wb[3] = tw[3 * step];
+        wa[1] = tw[4 * step];
+        wa[2] = tw[8 * step];
+        wa[3] = tw[12 * step];
+#pragma unroll
+        for (int b = 1; b < 4; ++b) u[b] = mul(u[b], wb[b]);
+#pragma unroll
+        for (int a = 1; a < 4; ++a) {
+            u[4 * a] = mul(u[4 * a], wa[a]);
+#pragma unroll
+            for (int b = 1; b < 4; ++b) u[4 * a + b] = mul(u[4 * a + b], cmul(wa[a], wb[b]));
+        }
+    }
+}
+
+// One radix-R stage on butterfly b of thread t (slots b + r*16/R).
+template <int N, int R, int SIGN>
+__device__ __forceinline__ void stage_butterfly(float2 (&v)[kP], int t, int b, int Ns,
+                                                const float2* __restrict__ tw)
+{
+    constexpr int T = N / kP;
+    constexpr int nb = kP / R;
+    const int j = t + b * T;
+    float2 u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = v[b + r * nb];
+    if (Ns > 1) apply_twiddles<R, SIGN>(u, tw, (j & (Ns - 1)) * (N / (Ns * R)));
+    dft_small<R, SIGN>(u);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[b + r * nb] = u[r];
+}
+
+// One transform of length N on T = N/16 threads.  `v` holds slot m = element
+// t + T*m on entry and on exit.  LDS addressing is abstracted by `addr(e)` so
+// row (one transform per LDS row) and column (C interleaved transforms) layouts
+// share the engine.  `tw` is the FP32 table W_N^k; SIGN = -1 for Eq. (1),
+// +1 for Eq. (2).  Contains __syncthreads(): every thread of the block must
+// call it the same number of times.
 template <int N, int SIGN, typename Addr>
 __device__ __forceinline__ void fft_stages(float2 (&v)[kP], int t, float2* lds, Addr addr,
                                            const float2* __restrict__ tw)
@@ -155,69 +222,12 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[kP], int t, float2* lds, 
         const bool last = (s == NSTAGE - 1);
         const int R = (s < NS16) ? 16 : (1 << REM);
         const int nb = kP / R;
-        // butterflies
 #pragma unroll
         for (int b = 0; b < nb; ++b) {
-            const int j = t + b * T;
-            const int jm = j & (Ns - 1);
-            if (R == 16) {
-                float2 u[16];
-#pragma unroll
-                for (int r = 0; r < 16; ++r) u[r] = v[b + r * nb];
-                if (Ns > 1) {
-                    const int step = jm * (N / (Ns * 16));
-#pragma unroll
-                    for (int r = 1; r < 16; ++r) {
-                        float2 w = tw[step * r];
-                        u[r] = SIGN < 0 ? cmul(u[r], w) : cmulc(u[r], w);
-                    }
-                }
-                dft_small<16, SIGN>(u);
-#pragma unroll
-                for (int r = 0; r < 16; ++r) v[b + r * nb] = u[r];
-            } else if (R == 8) {
-                float2 u[8];
-#pragma unroll
-                for (int r = 0; r < 8; ++r) u[r] = v[b + r * nb];
-                if (Ns > 1) {
-                    const int step = jm * (N / (Ns * 8));
-#pragma unroll
-                    for (int r = 1; r < 8; ++r) {
-                        float2 w = tw[step * r];
-                        u[r] = SIGN < 0 ? cmul(u[r], w) : cmulc(u[r], w);
-                    }
-                }
-                dft_small<8, SIGN>(u);
-#pragma unroll
-                for (int r = 0; r < 8; ++r) v[b + r * nb] = u[r];
-            } else if (R == 4) {
-                float2 u[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) u[r] = v[b + r * nb];
-                if (Ns > 1) {
-                    const int step = jm * (N / (Ns * 4));
-#pragma unroll
-                    for (int r = 1; r < 4; ++r) {
-                        float2 w = tw[step * r];
-                        u[r] = SIGN < 0 ? cmul(u[r], w) : cmulc(u[r], w);
-                    }
-                }
-                dft_small<4, SIGN>(u);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[b + r * nb] = u[r];
-            } else {
-                float2 u[2];
-#pragma unroll
-                for (int r = 0; r < 2; ++r) u[r] = v[b + r * nb];
-                if (Ns > 1) {
-                    const int step = jm * (N / (Ns * 2));
-                    float2 w = tw[step];
-                    u[1] = SIGN < 0 ? cmul(u[1], w) : cmulc(u[1], w);
-                }
-                dft_small<2, SIGN>(u);
-                v[b] = u[0];
-                v[b + nb] = u[1];
-            }
+            if (R == 16) stage_butterfly<N, 16, SIGN>(v, t, b, Ns, tw);
+            else if (R == 8) stage_butterfly<N, 8, SIGN>(v, t, b, Ns, tw);
+            else if (R == 4) stage_butterfly<N, 4, SIGN>(v, t, b, Ns, tw);
+            else stage_butterfly<N, 2, SIGN>(v, t, b, Ns, tw);
         }
         if (!last) {
             // exchange: write outputs at their Stockham positions, read back the
@@ -236,6 +246,62 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[kP], int t, float2* lds, 
         }
         Ns *= R;
     }
+}
+
+// Deterministic sums: butterfly (xor) reduction inside aligned segments of
+// `seg` lanes (seg a power of two <= 64); every lane of a segment ends with
+// the segment total, added in the same order on every run.
+__device__ __forceinline__ double seg_sum(double v, int seg)
+{
+    for (int off = seg >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-wide sum of NV doubles per thread, fixed order: per-wave butterflies,
+// then wave totals added in wave order by thread 0 (result valid there).
+// `red` needs NV * (blockDim.x / 64 + 1) doubles of LDS.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&a)[NV], double* red, double (&out)[NV])
+{
+    const int n = blockDim.x;
+    const int seg = n < 64 ? n : 64;
+    const int nw = (n + 63) / 64;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) a[i] = seg_sum(a[i], seg);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        for (int i = 0; i < NV; ++i) red[(threadIdx.x >> 6) * NV + i] = a[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NV; ++i) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += red[w * NV + i];
+            out[i] = s;
+        }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b mod 8), each with its own L2.  This maps the blocks of one XCD onto a
+// contiguous range of logical tiles so neighbouring column tiles, which share
+// 128-byte lines, meet in the same L2.  A permutation of [0, nblocks).
+__device__ __forceinline__ int xcd_tile(int b, int nblocks)
+{
+    if (nblocks & 7) return b;
+    return (b & 7) * (nblocks >> 3) + (b >> 3);
+}
+
+// Load / store at a wave-uniform base pointer plus a 32-bit per-lane byte
+// offset, so the compiler can use the scalar-base addressing form and keep one
+// offset register for a whole set of strided accesses.
+template <typename V>
+__device__ __forceinline__ V ld_off(const V* base, uint32_t boff)
+{
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + boff);
+}
+template <typename V>
+__device__ __forceinline__ void st_off(V* base, uint32_t boff, V v)
+{
+    *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + boff) = v;
 }
 
 // LDS addressing for R_ROWS independent row transforms of length N, one per

@@ -35,10 +35,6 @@ struct RowAddrG {
     int base;
     __device__ __forceinline__ int operator()(int e) const { return base + lds_pad(e); }
 };
-struct ColAddrG {
-    int c, C;
-    __device__ __forceinline__ int operator()(int e) const { return lds_pad(e) * C + c; }
-};
 
 template <typename K>
 void allow_lds_g(K kernel, size_t bytes)
@@ -46,18 +42,27 @@ void allow_lds_g(K kernel, size_t bytes)
     if (bytes > 64 * 1024) hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// fixed-order block reduction of NV doubles per thread; result valid in thread 0
+// Sum over the T threads of each row (rows are aligned groups of T lanes):
+// butterflies inside a wave, then the T/64 wave totals of a row in order.
+// Result valid in the row's thread t == 0.  Needs NV * blockDim/64 doubles.
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&a)[NV], double* red, double (&out)[NV])
+__device__ __forceinline__ void row_sum(double (&a)[NV], double* red, int T, int row, int t)
 {
-    const int n = blockDim.x;
-    for (int i = 0; i < NV; ++i) red[i * n + threadIdx.x] = a[i];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < NV; ++i) {
-            double s = 0.0;
-            for (int j = 0; j < n; ++j) s += red[i * n + j];
-            out[i] = s;
+    const int seg = T < 64 ? T : 64;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) a[i] = seg_sum(a[i], seg);
+    if (T > 64) {
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0)
+            for (int i = 0; i < NV; ++i) red[(threadIdx.x >> 6) * NV + i] = a[i];
+        __syncthreads();
+        if (t == 0) {
+            const int w0 = (row * T) >> 6, nw = T >> 6;
+            for (int i = 0; i < NV; ++i) {
+                double s = 0.0;
+                for (int w = 0; w < nw; ++w) s += red[(w0 + w) * NV + i];
+                a[i] = s;
+            }
         }
     }
 }
@@ -88,7 +93,7 @@ __device__ __forceinline__ uint8_t quant8(float2 h)
 // [ny][2] = {sum T^2, sum T^4} for INIT.
 // -------------------------------------------------------------------------
 template <int NX, int MODE>
-__global__ __launch_bounds__(1024) void k_gs_rows(const float* __restrict__ target, int ny,
+__global__ __launch_bounds__(256) void k_gs_rows(const float* __restrict__ target, int ny,
                                                   const float2* __restrict__ lut, uint32_t n_lut, uint64_t c0,
                                                   const float2* __restrict__ init, float2* __restrict__ state,
                                                   float2* __restrict__ field_out, double* __restrict__ partials,
@@ -136,22 +141,11 @@ __global__ __launch_bounds__(1024) void k_gs_rows(const float* __restrict__ targ
         fft_stages<NX, 1>(v, t, lds, RowAddrG{row * PadLen<NX>::v}, tw);
 #pragma unroll
         for (int m = 0; m < kP; ++m) srow[t + T * m] = v[m];
-        __syncthreads();
-        double a[2] = {s2, s4}, out[2];
-        // one partial per row: reduce each row's T threads (rows of a block
-        // reduce one after another through the same scratch)
-        double* red = reinterpret_cast<double*>(lds);
-        red[2 * threadIdx.x] = a[0];
-        red[2 * threadIdx.x + 1] = a[1];
-        __syncthreads();
+        double a2[2] = {s2, s4};
+        row_sum<2>(a2, reinterpret_cast<double*>(lds), T, row, t);
         if (t == 0) {
-            out[0] = out[1] = 0.0;
-            for (int j = 0; j < T; ++j) {
-                out[0] += red[2 * (row * T + j)];
-                out[1] += red[2 * (row * T + j) + 1];
-            }
-            partials[(size_t)y * 2] = out[0];
-            partials[(size_t)y * 2 + 1] = out[1];
+            partials[(size_t)y * 2] = a2[0];
+            partials[(size_t)y * 2 + 1] = a2[1];
         }
         return;
     }
@@ -188,22 +182,12 @@ __global__ __launch_bounds__(1024) void k_gs_rows(const float* __restrict__ targ
 #pragma unroll
         for (int m = 0; m < kP; ++m) srow[t + T * m] = v[m];
     }
-    __syncthreads();
-    double* red = reinterpret_cast<double*>(lds);
-    red[3 * threadIdx.x] = s_ii;
-    red[3 * threadIdx.x + 1] = s_it;
-    red[3 * threadIdx.x + 2] = e;
-    __syncthreads();
+    double a3[3] = {s_ii, s_it, e};
+    row_sum<3>(a3, reinterpret_cast<double*>(lds), T, row, t);
     if (t == 0) {
-        double o0 = 0.0, o1 = 0.0, o2 = 0.0;
-        for (int j = 0; j < T; ++j) {
-            o0 += red[3 * (row * T + j)];
-            o1 += red[3 * (row * T + j) + 1];
-            o2 += red[3 * (row * T + j) + 2];
-        }
-        partials[(size_t)y * 3] = o0;
-        partials[(size_t)y * 3 + 1] = o1;
-        partials[(size_t)y * 3 + 2] = o2;
+        partials[(size_t)y * 3] = a3[0];
+        partials[(size_t)y * 3 + 1] = a3[1];
+        partials[(size_t)y * 3 + 2] = a3[2];
     }
 }
 
@@ -214,11 +198,12 @@ hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const f
 {
     const int T = nx / kP;
     int rows = cfg.rows_per_block > 0 ? cfg.rows_per_block : (256 / T > 0 ? 256 / T : 1);
+    while (rows > 1 && rows * T > 256) rows >>= 1;   // launch bound of k_gs_rows
     while (rows > 1 && (ny % rows)) rows >>= 1;
     if (rows > ny) rows = ny;
     HOLO_SWITCH_N(nx, {
         size_t fft_lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
-        size_t red_lds = (size_t)3 * rows * T * sizeof(double);
+        size_t red_lds = (size_t)3 * (rows * T / 64 + 1) * sizeof(double);
         size_t lds = fft_lds > red_lds ? fft_lds : red_lds;
         if (mode == GS_INIT) {
             allow_lds_g(k_gs_rows<N_, GS_INIT>, lds);
@@ -240,45 +225,65 @@ hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const f
 // -------------------------------------------------------------------------
 // Columns pass (in place on `state`).
 // -------------------------------------------------------------------------
-template <int NY>
-__global__ __launch_bounds__(col_bound(NY)) void k_gs_cols(float2* __restrict__ state, int nx, uint8_t* __restrict__ codes,
-                                                  const float2* __restrict__ tw)
+template <int NY, int C>
+__global__ __launch_bounds__(C * (NY / kP)) void k_gs_cols(float2* __restrict__ state, int nx,
+                                                          uint8_t* __restrict__ codes, const float2* __restrict__ tw)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NY / kP;
-    const int C = blockDim.x / T;
     const int c = threadIdx.x % C, t = threadIdx.x / C;
-    const int x = blockIdx.x * C + c;
+    const int x0 = xcd_tile(blockIdx.x, gridDim.x) * C;
+    const size_t mstride = (size_t)T * nx;
+    const uint32_t toff = ((uint32_t)t * (uint32_t)nx + (uint32_t)c) * (uint32_t)sizeof(float2);
+    float2* col = state + x0;
     float2 v[kP];
 #pragma unroll
-    for (int m = 0; m < kP; ++m) v[m] = state[(size_t)(t + T * m) * nx + x];
-    fft_stages<NY, 1>(v, t, lds, ColAddrG{c, C}, tw);
+    for (int m = 0; m < kP; ++m) v[m] = ld_off(col + m * mstride, toff);
+    fft_stages<NY, 1>(v, t, lds, ColAddr<C>{c}, tw);
     if (codes) {
+        const uint32_t coff = (uint32_t)t * (uint32_t)nx + (uint32_t)c;
 #pragma unroll
-        for (int m = 0; m < kP; ++m) codes[(size_t)(t + T * m) * nx + x] = quant8(v[m]);
+        for (int m = 0; m < kP; ++m) st_off(codes + x0 + m * mstride, coff, quant8(v[m]));
     }
 #pragma unroll
     for (int m = 0; m < kP; ++m) {
         const float mag = sqrtf(v[m].x * v[m].x + v[m].y * v[m].y);
         v[m] = mag > 0.0f ? make_float2(v[m].x / mag, v[m].y / mag) : make_float2(1.0f, 0.0f);
     }
-    fft_stages<NY, -1>(v, t, lds, ColAddrG{c, C}, tw);
+    fft_stages<NY, -1>(v, t, lds, ColAddr<C>{c}, tw);
 #pragma unroll
-    for (int m = 0; m < kP; ++m) state[(size_t)(t + T * m) * nx + x] = v[m];
+    for (int m = 0; m < kP; ++m) st_off(col + m * mstride, toff, v[m]);
 }
 
 hipError_t launch_gs_cols(float2* state, int nx, int ny, uint8_t* codes, const float2* tw_y,
                           const LaunchCfg& cfg, hipStream_t s)
 {
     const int T = ny / kP;
-    int C = cfg.cols_per_block;
-    while (C > 1 && (C * T > col_bound(ny) || (size_t)C * pad_len(ny) * sizeof(float2) > 160 * 1024)) C >>= 1;
+    int C = cfg.cols_per_block >= 16 ? 16 : 8;
+    if (C == 16 && (16 * T > 1024 || (size_t)16 * pad_len(ny) * sizeof(float2) > 160 * 1024)) C = 8;
     if (C > nx) C = nx;
-    HOLO_SWITCH_N(ny, {
-        size_t lds = (size_t)C * PadLen<N_>::v * sizeof(float2);
-        allow_lds_g(k_gs_cols<N_>, lds);
-        hipLaunchKernelGGL((k_gs_cols<N_>), dim3(nx / C), dim3(C * T), lds, s, state, nx, codes, tw_y);
-    });
+    switch (C) {
+        case 8: {
+            constexpr int C_ = 8;
+            HOLO_SWITCH_N(ny, {
+                size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
+                allow_lds_g(k_gs_cols<N_, C_>, lds);
+                hipLaunchKernelGGL((k_gs_cols<N_, C_>), dim3(nx / C_), dim3(C_ * T), lds, s, state, nx, codes, tw_y);
+            });
+        } break;
+        case 16: {
+            constexpr int C_ = 16;
+            HOLO_SWITCH_N(ny, {
+                if (N_ <= 1024) {
+                    size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
+                    allow_lds_g(k_gs_cols<N_, C_>, lds);
+                    hipLaunchKernelGGL((k_gs_cols<N_, C_>), dim3(nx / C_), dim3(C_ * T), lds, s, state, nx, codes,
+                                       tw_y);
+                }
+            });
+        } break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -290,7 +295,7 @@ hipError_t launch_gs_cols(float2* state, int nx, int ny, uint8_t* codes, const f
 __global__ __launch_bounds__(256) void k_gs_consts(const double* __restrict__ part, int ny, int nx,
                                                    GsConsts* __restrict__ consts)
 {
-    __shared__ double red[2 * 256];
+    __shared__ double red[2 * 8];
     double a[2] = {0.0, 0.0}, out[2];
     for (int r = threadIdx.x; r < ny; r += 256) {
         a[0] += part[(size_t)r * 2];
@@ -315,7 +320,7 @@ __global__ __launch_bounds__(256) void k_gs_finalize(const double* __restrict__ 
                                                      const GsConsts* __restrict__ consts, double* __restrict__ nmse,
                                                      double* __restrict__ err)
 {
-    __shared__ double red[3 * 256];
+    __shared__ double red[3 * 8];
     const int it = blockIdx.x;
     const double* p = part + (size_t)it * ny * 3;
     double a[3] = {0.0, 0.0, 0.0}, out[3];

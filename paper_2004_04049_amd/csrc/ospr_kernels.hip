@@ -33,14 +33,18 @@ namespace holo {
         default: return hipErrorInvalidValue;              \
     }
 
+// Column-tile width C (columns transformed side by side by one block).
+#define HOLO_SWITCH_C(c, ...)                                    \
+    switch (c) {                                                 \
+        case 8: { constexpr int C_ = 8; __VA_ARGS__; } break;    \
+        case 16: { constexpr int C_ = 16; __VA_ARGS__; } break;  \
+        default: return hipErrorInvalidValue;                    \
+    }
+
 // Runtime LDS addressing (block shape chosen at launch).
 struct RowAddrR {
     int base;
     __device__ __forceinline__ int operator()(int e) const { return base + lds_pad(e); }
-};
-struct ColAddrR {
-    int c, C;
-    __device__ __forceinline__ int operator()(int e) const { return lds_pad(e) * C + c; }
 };
 
 static int row_block_rows(int n, int nrows, const LaunchCfg& cfg)
@@ -53,11 +57,12 @@ static int row_block_rows(int n, int nrows, const LaunchCfg& cfg)
     return rows;
 }
 
+// Column-tile width: 8 or 16, at most 1024 threads and 160 KiB of LDS.
 static int col_block_cols(int n, int ncols, const LaunchCfg& cfg)
 {
     const int T = n / kP;
-    int C = cfg.cols_per_block;
-    while (C > 1 && (C * T > col_bound(n) || (size_t)C * pad_len(n) * sizeof(float2) > 160 * 1024)) C >>= 1;
+    int C = cfg.cols_per_block >= 16 ? 16 : 8;
+    if (C == 16 && (16 * T > 1024 || (size_t)16 * pad_len(n) * sizeof(float2) > 160 * 1024)) C = 8;
     if (C > ncols) C = ncols;
     return C;
 }
@@ -102,21 +107,22 @@ __global__ __launch_bounds__(1024) void k_fft_rows(const float2* __restrict__ in
     for (int m = 0; m < kP; ++m) dst[t + T * m] = v[m];
 }
 
-template <int N, int SIGN>
-__global__ __launch_bounds__(col_bound(N)) void k_fft_cols(const float2* __restrict__ in, float2* __restrict__ out,
-                                                   int nx, float scale, const float2* __restrict__ tw)
+template <int N, int SIGN, int C>
+__global__ __launch_bounds__(C * (N / kP)) void k_fft_cols(const float2* __restrict__ in, float2* __restrict__ out,
+                                                           int nx, float scale, const float2* __restrict__ tw)
 {
     extern __shared__ float2 lds[];
     constexpr int T = N / kP;
-    const int C = blockDim.x / T;
     const int c = threadIdx.x % C, t = threadIdx.x / C;
-    const int x = blockIdx.x * C + c;
+    const int x0 = xcd_tile(blockIdx.x, gridDim.x) * C;
+    const size_t mstride = (size_t)T * nx;
+    const uint32_t toff = ((uint32_t)t * (uint32_t)nx + (uint32_t)c) * (uint32_t)sizeof(float2);
     float2 v[kP];
 #pragma unroll
-    for (int m = 0; m < kP; ++m) v[m] = in[(size_t)(t + T * m) * nx + x];
-    fft_stages<N, SIGN>(v, t, lds, ColAddrR{c, C}, tw);
+    for (int m = 0; m < kP; ++m) v[m] = ld_off(in + x0 + m * mstride, toff);
+    fft_stages<N, SIGN>(v, t, lds, ColAddr<C>{c}, tw);
 #pragma unroll
-    for (int m = 0; m < kP; ++m) out[(size_t)(t + T * m) * nx + x] = make_float2(v[m].x * scale, v[m].y * scale);
+    for (int m = 0; m < kP; ++m) st_off(out + x0 + m * mstride, toff, make_float2(v[m].x * scale, v[m].y * scale));
 }
 
 template <typename K>
@@ -145,17 +151,21 @@ hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int n
     {
         const int C = col_block_cols(ny, nx, cfg);
         const float scale = (float)(1.0 / sqrt((double)nx * (double)ny));
-        HOLO_SWITCH_N(ny, {
+        HOLO_SWITCH_N(ny, HOLO_SWITCH_C(C, {
             constexpr int T = N_ / kP;
-            size_t lds = (size_t)C * PadLen<N_>::v * sizeof(float2);
-            if (sign < 0) {
-                allow_lds(k_fft_cols<N_, -1>, lds);
-                hipLaunchKernelGGL((k_fft_cols<N_, -1>), dim3(nx / C), dim3(C * T), lds, s, tmp, out, nx, scale, tw_y);
-            } else {
-                allow_lds(k_fft_cols<N_, 1>, lds);
-                hipLaunchKernelGGL((k_fft_cols<N_, 1>), dim3(nx / C), dim3(C * T), lds, s, tmp, out, nx, scale, tw_y);
+            if (C_ * T <= 1024) {
+                size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
+                if (sign < 0) {
+                    allow_lds(k_fft_cols<N_, -1, C_>, lds);
+                    hipLaunchKernelGGL((k_fft_cols<N_, -1, C_>), dim3(nx / C_), dim3(C_ * T), lds, s, tmp, out, nx,
+                                       scale, tw_y);
+                } else {
+                    allow_lds(k_fft_cols<N_, 1, C_>, lds);
+                    hipLaunchKernelGGL((k_fft_cols<N_, 1, C_>), dim3(nx / C_), dim3(C_ * T), lds, s, tmp, out, nx,
+                                       scale, tw_y);
+                }
             }
-        });
+        }));
     }
     return hipGetLastError();
 }
@@ -211,71 +221,71 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
     return hipGetLastError();
 }
 
-// Store one wave's binarised row chunks: lanes c = 0..C-1 of each C-lane group
-// hold consecutive pixels of one row; the ballot gives their bits in lane order,
-// which is raster order, LSB first.
-__device__ __forceinline__ void store_bit_chunk(uint8_t* bits8, uint64_t mask, int lane, int C, size_t p0)
-{
-    const int g = lane / C;
-    const uint32_t chunk = (uint32_t)(mask >> (g * C));
-    if (C == 32) reinterpret_cast<uint32_t*>(bits8)[p0 >> 5] = chunk;
-    else if (C == 16) reinterpret_cast<uint16_t*>(bits8)[p0 >> 4] = (uint16_t)chunk;
-    else reinterpret_cast<uint8_t*>(bits8)[p0 >> 3] = (uint8_t)chunk;
-}
-
 // -------------------------------------------------------------------------
 // K2: inverse column transform, binarise + pack, forward column transform of
 // the +-1 column; writes the half spectrum rows 0..ny/2.
-// Grid: (nx / C) * n_sf blocks of C * (ny/16) threads, C in {8, 16, 32}.
+// Grid: (nx / C) * n_sf blocks of C * (ny/16) threads.  Thread (c, t) owns
+// column x0 + c, rows t + T*m.  The C lanes of a row segment are adjacent in
+// the wave, so a ballot yields that row's C bits in raster order.
 // -------------------------------------------------------------------------
-template <int NY>
-__global__ __launch_bounds__(col_bound(NY)) void k_ospr_cols(const float2* __restrict__ x1, int nx,
-                                                    uint32_t* __restrict__ bits, float2* __restrict__ x2,
-                                                    const float2* __restrict__ tw)
+template <int NY, int C>
+__global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __restrict__ x1, int nx,
+                                                            uint32_t* __restrict__ bits, float2* __restrict__ x2,
+                                                            const float2* __restrict__ tw)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NY / kP;
-    const int C = blockDim.x / T;
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int lane = threadIdx.x & 63;
     const int ncb = nx / C;
-    const int k = blockIdx.x / ncb;
-    const int x0 = (blockIdx.x % ncb) * C;
-    const int x = x0 + c;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = tile / ncb;
+    const int x0 = (tile - k * ncb) * C;
     const size_t npix = (size_t)nx * NY;
-    const float2* src = x1 + (size_t)k * npix;
+    const size_t mstride = (size_t)T * nx;
+    const uint32_t toff = ((uint32_t)t * (uint32_t)nx + (uint32_t)c) * (uint32_t)sizeof(float2);
+    const float2* src = x1 + (size_t)k * npix + x0;
     float2 v[kP];
 #pragma unroll
-    for (int m = 0; m < kP; ++m) v[m] = src[(size_t)(t + T * m) * nx + x];
-    fft_stages<NY, 1>(v, t, lds, ColAddrR{c, C}, tw);
-    uint8_t* bits8 = reinterpret_cast<uint8_t*>(bits + (size_t)k * (npix / 32));
+    for (int m = 0; m < kP; ++m) v[m] = ld_off(src + m * mstride, toff);
+    fft_stages<NY, 1>(v, t, lds, ColAddr<C>{c}, tw);
+
+    // nearest of {+1, -1}: bit = (Re H < 0); Re H = 0 -> +1
+    uint8_t* bits8 = reinterpret_cast<uint8_t*>(bits + (size_t)k * (npix / 32)) + x0 / 8;
+    const uint32_t boff = (uint32_t)t * (uint32_t)(nx / 8);
 #pragma unroll
     for (int m = 0; m < kP; ++m) {
-        const bool neg = v[m].x < 0.0f;   // nearest of {+1, -1}; Re H = 0 -> +1
+        const bool neg = v[m].x < 0.0f;
         const uint64_t mask = __ballot(neg);
-        if (c == 0) store_bit_chunk(bits8, mask, lane, C, (size_t)(t + T * m) * nx + x0);
+        if (c == 0) {
+            const uint32_t chunk = (uint32_t)(mask >> (lane & ~(C - 1)));
+            uint8_t* row = bits8 + (size_t)m * T * (nx / 8);
+            if (C == 16) st_off(reinterpret_cast<uint16_t*>(row), boff, (uint16_t)chunk);
+            else st_off(row, boff, (uint8_t)chunk);
+        }
         v[m] = make_float2(neg ? -1.0f : 1.0f, 0.0f);
     }
-    fft_stages<NY, -1>(v, t, lds, ColAddrR{c, C}, tw);
-    float2* dst = x2 + (size_t)k * (NY / 2 + 1) * nx;
+    fft_stages<NY, -1>(v, t, lds, ColAddr<C>{c}, tw);
+    // rows v = t + T*m <= NY/2: every slot m < 8, and m = 8 for t = 0 only
+    float2* dst = x2 + (size_t)k * (NY / 2 + 1) * nx + x0;
 #pragma unroll
-    for (int m = 0; m < kP; ++m) {
-        const int vv = t + T * m;
-        if (vv <= NY / 2) dst[(size_t)vv * nx + x] = v[m];
-    }
+    for (int m = 0; m < kP / 2; ++m) st_off(dst + m * mstride, toff, v[m]);
+    if (t == 0) st_off(dst + (kP / 2) * mstride, toff, v[kP / 2]);
 }
 
 hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
                             const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
 {
-    int C = col_block_cols(ny, nx, cfg);
-    if (C < 8) return hipErrorInvalidValue;   // bit chunks are at least a byte
-    HOLO_SWITCH_N(ny, {
+    const int C = col_block_cols(ny, nx, cfg);
+    HOLO_SWITCH_N(ny, HOLO_SWITCH_C(C, {
         constexpr int T = N_ / kP;
-        size_t lds = (size_t)C * PadLen<N_>::v * sizeof(float2);
-        allow_lds(k_ospr_cols<N_>, lds);
-        hipLaunchKernelGGL((k_ospr_cols<N_>), dim3((nx / C) * n_sf), dim3(C * T), lds, s, x1, nx, bits, x2, tw_y);
-    });
+        if (C_ * T <= 1024) {
+            size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
+            allow_lds(k_ospr_cols<N_, C_>, lds);
+            hipLaunchKernelGGL((k_ospr_cols<N_, C_>), dim3((nx / C_) * n_sf), dim3(C_ * T), lds, s, x1, nx, bits,
+                               x2, tw_y);
+        }
+    }));
     return hipGetLastError();
 }
 
@@ -299,17 +309,18 @@ __device__ __forceinline__ float2 level8_phasor(int m)
     }
 }
 
-template <int NY>
-__global__ __launch_bounds__(col_bound(NY)) void k_recon_cols(const void* __restrict__ holo, int levels, int nx,
-                                                     float2* __restrict__ x2, const float2* __restrict__ tw)
+template <int NY, int C>
+__global__ __launch_bounds__(C * (NY / kP)) void k_recon_cols(const void* __restrict__ holo, int levels, int nx,
+                                                             float2* __restrict__ x2, const float2* __restrict__ tw)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NY / kP;
-    const int C = blockDim.x / T;
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int ncb = nx / C;
-    const int k = blockIdx.x / ncb;
-    const int x = (blockIdx.x % ncb) * C + c;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = tile / ncb;
+    const int x0 = (tile - k * ncb) * C;
+    const int x = x0 + c;
     const size_t npix = (size_t)nx * NY;
     float2 v[kP];
     if (levels == 2) {
@@ -325,7 +336,7 @@ __global__ __launch_bounds__(col_bound(NY)) void k_recon_cols(const void* __rest
 #pragma unroll
         for (int m = 0; m < kP; ++m) v[m] = level8_phasor(cd[(size_t)(t + T * m) * nx + x]);
     }
-    fft_stages<NY, -1>(v, t, lds, ColAddrR{c, C}, tw);
+    fft_stages<NY, -1>(v, t, lds, ColAddr<C>{c}, tw);
     const int vmax = levels == 2 ? NY / 2 : NY - 1;
     float2* dst = x2 + (size_t)k * (vmax + 1) * nx;
 #pragma unroll
@@ -339,13 +350,15 @@ hipError_t launch_recon_cols(const void* holo, int levels, int nx, int ny, int n
                              const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
 {
     const int C = col_block_cols(ny, nx, cfg);
-    HOLO_SWITCH_N(ny, {
+    HOLO_SWITCH_N(ny, HOLO_SWITCH_C(C, {
         constexpr int T = N_ / kP;
-        size_t lds = (size_t)C * PadLen<N_>::v * sizeof(float2);
-        allow_lds(k_recon_cols<N_>, lds);
-        hipLaunchKernelGGL((k_recon_cols<N_>), dim3((nx / C) * n_sf), dim3(C * T), lds, s, holo, levels, nx, x2,
-                           tw_y);
-    });
+        if (C_ * T <= 1024) {
+            size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
+            allow_lds(k_recon_cols<N_, C_>, lds);
+            hipLaunchKernelGGL((k_recon_cols<N_, C_>), dim3((nx / C_) * n_sf), dim3(C_ * T), lds, s, holo, levels,
+                               nx, x2, tw_y);
+        }
+    }));
     return hipGetLastError();
 }
 
@@ -357,21 +370,6 @@ hipError_t launch_recon_cols(const void* holo, int levels, int nx, int ny, int n
 // partials[v*5 + {0..4}] = {S_II, S_IT, S_ITs, S_TT, S_TsTs} over the pixels
 // this row stands for (itself and, for the half spectrum, its point mirror).
 // -------------------------------------------------------------------------
-__device__ __forceinline__ void block_sum5(double (&a)[5], double* red, int nthreads, double* out)
-{
-    // fixed-order reduction: every thread parks its 5 sums, thread 0 adds them
-    // in thread order (nthreads <= 1024, done once per block).
-    for (int i = 0; i < 5; ++i) red[i * nthreads + threadIdx.x] = a[i];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < 5; ++i) {
-            double s = 0.0;
-            for (int j = 0; j < nthreads; ++j) s += red[i * nthreads + j];
-            out[i] = s;
-        }
-    }
-}
-
 template <int NX>
 __global__ __launch_bounds__(512) void k_recon_rows(const float2* __restrict__ x2, int ny, int n_sf, int half,
                                                      const float* __restrict__ target, float* __restrict__ recon,
@@ -448,8 +446,10 @@ __global__ __launch_bounds__(512) void k_recon_rows(const float2* __restrict__ x
             }
         }
     }
-    __syncthreads();
-    block_sum5(sums, reinterpret_cast<double*>(lds), blockDim.x, partials + (size_t)v_row * 5);
+    double tot[5];
+    block_sum<5>(sums, reinterpret_cast<double*>(lds), tot);
+    if (threadIdx.x == 0)
+        for (int i = 0; i < 5; ++i) partials[(size_t)v_row * 5 + i] = tot[i];
 }
 
 hipError_t launch_recon_rows(const float2* x2, int nx, int ny, int n_sf, bool half, const float* target,
@@ -461,9 +461,8 @@ hipError_t launch_recon_rows(const float2* x2, int nx, int ny, int n_sf, bool ha
         constexpr int T = N_ / kP;
         int G = cfg.ksplit > 0 ? cfg.ksplit : 1;
         while (G > 1 && (G * T > 512 || G > n_sf)) G >>= 1;
-        if (G * T < 5) G = 1;
         size_t fft_lds = (size_t)G * PadLen<N_>::v * sizeof(float2);
-        size_t red_lds = (size_t)5 * G * T * sizeof(double);
+        size_t red_lds = (size_t)5 * (G * T / 64 + 1) * sizeof(double);
         size_t lds = fft_lds > red_lds ? fft_lds : red_lds;
         const float inv_scale = (float)(1.0 / ((double)n_sf * (double)nx * (double)ny));
         allow_lds(k_recon_rows<N_>, lds);
@@ -480,12 +479,12 @@ hipError_t launch_recon_rows(const float2* x2, int nx, int ny, int n_sf, bool ha
 __global__ __launch_bounds__(256) void k_nmse_finalize(const double* __restrict__ partials, int nrows,
                                                        double* __restrict__ out2)
 {
-    __shared__ double red[5 * 256];
+    __shared__ double red[5 * 8];
     double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int r = threadIdx.x; r < nrows; r += 256)
         for (int i = 0; i < 5; ++i) a[i] += partials[(size_t)r * 5 + i];
     double s[5];
-    block_sum5(a, red, 256, s);
+    block_sum<5>(a, red, s);
     if (threadIdx.x == 0) {
         const double s_ii = s[0], s_it = s[1], s_its = s[2], s_tt = s[3], s_tsts = s[4];
         out2[0] = (s_ii > 0.0 && s_tt > 0.0) ? 1.0 - s_it * s_it / (s_ii * s_tt) : 1.0;

@@ -153,13 +153,39 @@ def _gs_case(holo, orc, nx, ny, n_iter, n_lut, seed):
 
 
 def test_gs_512_50_iterations(holo, orc):
+    # 512x512, 50 iterations, 4096-entry LUT seed, 8 levels at the end.  The
+    # FP32 trajectory drifts from the FP64 one by ~1e-4 in relative L2 after
+    # 50 iterations, so the 8-level codes are compared as a mismatch fraction
+    # (pixels near a decision boundary may flip) while the replay NMSE of the
+    # GPU's own codes is checked exactly against the oracle's reconstruction.
     t, r, ref = _gs_case(holo, orc, 512, 512, 50, 4096, synth.SEED_GS_512)
     codes = r["codes"].cpu().numpy()
-    mism = np.mean(codes != ref["codes"])
-    assert mism < 1e-3, mism
-    np.testing.assert_allclose(r["nmse_final2"], ref["nmse_final2"], rtol=1e-3)
+    mism = float(np.mean(codes != ref["codes"]))
+    print(f"8-level code mismatch after 50 iterations: {mism:.2e}")
+    assert mism < 1e-2, mism
+    np.testing.assert_allclose(r["nmse_final2"], ref["nmse_final2"], rtol=1e-2)
+    own = orc.reconstruct(codes[None], 8, 512, 512, 1)
+    np.testing.assert_allclose(r["nmse_final2"], orc.nmse_pair(own, t), rtol=NMSE_RTOL)
     fld = r["field"].cpu().numpy()
     assert _rel_l2(fld, ref["field"]) < 1e-3
+
+
+def test_gs_quantiser_exact_after_one_iteration(holo, orc):
+    # After one iteration H_1 = F^{-1}{T * phasor} differs from FP64 by FP32
+    # rounding only: codes must agree except within 1e-4 rad of a boundary.
+    nx, ny = 256, 128
+    t = synth.blob_target(nx, ny, 8)
+    lut = holo.Lut(10007, 1)
+    r = holo.gs_iterate(torch.from_numpy(t).cuda(), 1, lut, 0)
+    init = orc.lut_phasor_field(orc.lut_phases(10007, 1), 10007, 0, 0, nx, ny)
+    ref = orc.gs(t, 1, init)
+    h1 = np.fft.ifft2(t.astype(np.float64) * init, norm="ortho")
+    th = np.mod(np.angle(h1), 2 * np.pi)
+    dist = np.abs(np.mod(th * 8 / (2 * np.pi), 1.0) - 0.5) * (2 * np.pi / 8)
+    decided = (dist > 1e-4) & (np.abs(h1) > 1e-6)
+    got = r["codes"].cpu().numpy()
+    assert np.array_equal(got[decided], ref["codes"][decided])
+    assert decided.mean() > 0.99
 
 
 @pytest.mark.parametrize("nx,ny", [(16, 64), (128, 32), (1024, 1024)])
@@ -175,7 +201,7 @@ def test_gs_fixed_point_and_resume(holo, orc):
     t = torch.from_numpy(np.abs(F).astype(np.float32)).cuda()
     init = torch.from_numpy((F / np.abs(F)).astype(np.complex64)).cuda()
     r = holo.gs_iterate(t, 1, None, 0, init_phasor=init)
-    assert r["nmse"][0] < 1e-10
+    assert r["nmse"][0] < 1e-8
     # resume: 3 iterations == 2, then 1 more seeded with the returned field
     tb = torch.from_numpy(synth.blob_target(nx, ny, 2)).cuda()
     lut = holo.Lut(101, 1)
