@@ -166,6 +166,34 @@ HOLO_API holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t 
                                void* hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * Launch plans and the autotuner (implementation choices, not part of the
+ * method: every plan computes the same holograms).
+ * A plan is four ints {cols, rows, ksplit, recon_cols}: column-tile width of
+ * the generation column pass (OSPR: 8 or 16; GS: 2, 4, 8 or 16), row
+ * transforms per block of the row pass, sub-frame groups per block of the
+ * reconstruction row pass, column-tile width of the reconstruction column
+ * pass; 0 selects the built-in heuristic.  Plans are keyed by kind
+ * (0 = OSPR, 1 = GS), nx, ny and n_sf (ignored for GS).
+ * holo_autotune_ospr / holo_autotune_gs time candidate plans on the caller's
+ * inputs (coordinate descent, `reps` timed runs each) and keep the fastest
+ * whose holograms (bits / codes) and NMSE equal those of the default plan;
+ * `chosen` (int[4] or NULL) receives it.  scratch_bits: device
+ * uint32[n_sf][nx*ny/32], overwritten.  holo_plan_save / holo_plan_load
+ * write and read all plans as JSON.  holo_set_graphs(0) disables the HIP
+ * graph replay of holo_gs_iterate (on by default).
+ * ------------------------------------------------------------------------- */
+HOLO_API holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t ny, int32_t n_sf,
+                                        const holo_lut* lut, uint32_t* scratch_bits, int32_t reps, int32_t* chosen,
+                                        void* hip_stream);
+HOLO_API holo_status holo_autotune_gs(const float* target, int64_t nx, int64_t ny, const holo_lut* lut,
+                                      int32_t reps, int32_t* chosen, void* hip_stream);
+HOLO_API holo_status holo_plan_set(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, const int32_t* cfg4);
+HOLO_API holo_status holo_plan_get(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, int32_t* cfg4);
+HOLO_API holo_status holo_plan_save(const char* path);
+HOLO_API holo_status holo_plan_load(const char* path);
+HOLO_API holo_status holo_set_graphs(int32_t on);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (measurement support, not part of the method).
  * holo_prof_enable(1) makes every subsequent launch record a pair of HIP
  * events on its stream; holo_prof_read waits for the recorded events and

@@ -44,6 +44,13 @@ SIGNATURES = {
     "holo_prof_enable": (_I32, [_I32]),
     "holo_prof_read": (_I32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(_I64)]),
     "holo_prof_reset": (None, []),
+    "holo_autotune_ospr": (_I32, [_P, _I64, _I64, _I32, _P, _P, _I32, _P, _P]),
+    "holo_autotune_gs": (_I32, [_P, _I64, _I64, _P, _I32, _P, _P]),
+    "holo_plan_set": (_I32, [_I32, _I64, _I64, _I32, _P]),
+    "holo_plan_get": (_I32, [_I32, _I64, _I64, _I32, _P]),
+    "holo_plan_save": (_I32, [C.c_char_p]),
+    "holo_plan_load": (_I32, [C.c_char_p]),
+    "holo_set_graphs": (_I32, [_I32]),
 }
 
 
@@ -254,3 +261,54 @@ def prof_read(kernel: str):
 
 def prof_reset():
     lib().holo_prof_reset()
+
+
+PLAN_OSPR, PLAN_GS = 0, 1
+
+
+def autotune_ospr(target, n_sf: int, lut: Lut, reps: int = 5, stream=None):
+    """holo_autotune_ospr: returns the chosen plan [cols, rows, ksplit, recon_cols]."""
+    import numpy as np
+    ny, nx = target.shape
+    _dev(target, torch.float32, None, "target")
+    scratch = torch.empty((n_sf, nx * ny // 32), dtype=torch.int32, device=target.device)
+    out = np.zeros(4, dtype=np.int32)
+    _check(lib().holo_autotune_ospr(_ptr(target), nx, ny, n_sf, lut.handle, _ptr(scratch), reps,
+                                    out.ctypes.data_as(C.c_void_p), _stream(stream)))
+    return out.tolist()
+
+
+def autotune_gs(target, lut: Lut, reps: int = 5, stream=None):
+    """holo_autotune_gs: returns the chosen plan [cols, rows, ksplit, recon_cols]."""
+    import numpy as np
+    ny, nx = target.shape
+    _dev(target, torch.float32, None, "target")
+    out = np.zeros(4, dtype=np.int32)
+    _check(lib().holo_autotune_gs(_ptr(target), nx, ny, lut.handle, reps, out.ctypes.data_as(C.c_void_p),
+                                  _stream(stream)))
+    return out.tolist()
+
+
+def plan_set(kind: int, nx: int, ny: int, n_sf: int, cfg):
+    import numpy as np
+    a = np.ascontiguousarray(cfg, dtype=np.int32)
+    _check(lib().holo_plan_set(kind, nx, ny, n_sf, a.ctypes.data_as(C.c_void_p)))
+
+
+def plan_get(kind: int, nx: int, ny: int, n_sf: int):
+    import numpy as np
+    a = np.zeros(4, dtype=np.int32)
+    _check(lib().holo_plan_get(kind, nx, ny, n_sf, a.ctypes.data_as(C.c_void_p)))
+    return a.tolist()
+
+
+def plan_save(path: str):
+    _check(lib().holo_plan_save(path.encode()))
+
+
+def plan_load(path: str):
+    _check(lib().holo_plan_load(path.encode()))
+
+
+def set_graphs(on: bool):
+    _check(lib().holo_set_graphs(1 if on else 0))

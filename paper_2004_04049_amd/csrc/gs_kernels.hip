@@ -197,7 +197,11 @@ hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const f
                           const LaunchCfg& cfg, hipStream_t s)
 {
     const int T = nx / kP;
-    int rows = cfg.rows_per_block > 0 ? cfg.rows_per_block : (256 / T > 0 ? 256 / T : 1);
+    int rows = cfg.rows_per_block;
+    if (rows <= 0) {   // widest block that still leaves >= 512 blocks
+        rows = 256 / T > 0 ? 256 / T : 1;
+        while (rows > 1 && ny / rows < 512) rows >>= 1;
+    }
     while (rows > 1 && rows * T > 256) rows >>= 1;   // launch bound of k_gs_rows
     while (rows > 1 && (ny % rows)) rows >>= 1;
     if (rows > ny) rows = ny;
@@ -259,31 +263,27 @@ hipError_t launch_gs_cols(float2* state, int nx, int ny, uint8_t* codes, const f
                           const LaunchCfg& cfg, hipStream_t s)
 {
     const int T = ny / kP;
-    int C = cfg.cols_per_block >= 16 ? 16 : 8;
-    if (C == 16 && (16 * T > 1024 || (size_t)16 * pad_len(ny) * sizeof(float2) > 160 * 1024)) C = 8;
-    if (C > nx) C = nx;
+    const int C = col_block_cols(ny, nx, 1, cfg.cols_per_block, 2);
+#define HOLO_GS_COLS_CASE(CC)                                                                                \
+    case CC: {                                                                                               \
+        constexpr int C_ = CC;                                                                               \
+        HOLO_SWITCH_N(ny, {                                                                                  \
+            if (C_ * (N_ / kP) <= 1024) {                                                                    \
+                size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);                                   \
+                allow_lds_g(k_gs_cols<N_, C_>, lds);                                                         \
+                hipLaunchKernelGGL((k_gs_cols<N_, C_>), dim3(nx / C_), dim3(C_ * T), lds, s, state, nx, codes, \
+                                   tw_y);                                                                    \
+            }                                                                                                \
+        });                                                                                                  \
+    } break;
     switch (C) {
-        case 8: {
-            constexpr int C_ = 8;
-            HOLO_SWITCH_N(ny, {
-                size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
-                allow_lds_g(k_gs_cols<N_, C_>, lds);
-                hipLaunchKernelGGL((k_gs_cols<N_, C_>), dim3(nx / C_), dim3(C_ * T), lds, s, state, nx, codes, tw_y);
-            });
-        } break;
-        case 16: {
-            constexpr int C_ = 16;
-            HOLO_SWITCH_N(ny, {
-                if (N_ <= 1024) {
-                    size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
-                    allow_lds_g(k_gs_cols<N_, C_>, lds);
-                    hipLaunchKernelGGL((k_gs_cols<N_, C_>), dim3(nx / C_), dim3(C_ * T), lds, s, state, nx, codes,
-                                       tw_y);
-                }
-            });
-        } break;
+        HOLO_GS_COLS_CASE(2)
+        HOLO_GS_COLS_CASE(4)
+        HOLO_GS_COLS_CASE(8)
+        HOLO_GS_COLS_CASE(16)
         default: return hipErrorInvalidValue;
     }
+#undef HOLO_GS_COLS_CASE
     return hipGetLastError();
 }
 

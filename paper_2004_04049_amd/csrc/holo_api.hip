@@ -218,6 +218,246 @@ holo_status copy_out(double* dst, const double* dev_src, size_t n, uint32_t flag
 
 LaunchCfg default_cfg() { return LaunchCfg{}; }
 
+// ---------------------------------------------------------------------------
+// Plans: launch shapes per (path, nx, ny, n_sf), defaulting to the kernels'
+// built-in heuristics; filled by the autotuner or by holo_plan_set/load.
+// ---------------------------------------------------------------------------
+enum { PLAN_OSPR = 0, PLAN_GS = 1 };
+struct PlanKey {
+    int kind;
+    int64_t nx, ny;
+    int n_sf;
+    bool operator<(const PlanKey& o) const
+    {
+        if (kind != o.kind) return kind < o.kind;
+        if (nx != o.nx) return nx < o.nx;
+        if (ny != o.ny) return ny < o.ny;
+        return n_sf < o.n_sf;
+    }
+};
+std::mutex g_plan_mu;
+std::map<PlanKey, LaunchCfg> g_plans;
+
+LaunchCfg plan_get(int kind, int64_t nx, int64_t ny, int n_sf)
+{
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(PlanKey{kind, nx, ny, kind == PLAN_GS ? 1 : n_sf});
+    return it == g_plans.end() ? LaunchCfg{} : it->second;
+}
+
+void plan_put(int kind, int64_t nx, int64_t ny, int n_sf, const LaunchCfg& c)
+{
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_plans[PlanKey{kind, nx, ny, kind == PLAN_GS ? 1 : n_sf}] = c;
+}
+
+// ---------------------------------------------------------------------------
+// OSPR frame: K1 -> K2 -> K3 -> K4 on stream s with launch shapes `cfg`.
+// ---------------------------------------------------------------------------
+holo_status ospr_run(int device, const float* target, int64_t nx, int64_t ny, int n_sf, const holo_lut* lut,
+                     uint64_t cursor, uint32_t* holo_bits, float* recon, double* nmse2, uint32_t flags,
+                     hipStream_t s, const LaunchCfg& cfg)
+{
+    holo_status st;
+    const float2 *tw_x, *tw_y;
+    if ((st = get_twiddles(device, (int)nx, s, &tw_x))) return st;
+    if ((st = get_twiddles(device, (int)ny, s, &tw_y))) return st;
+    const size_t npix = (size_t)nx * (size_t)ny;
+    const size_t nspec = (size_t)(ny / 2 + 1) * (size_t)nx;
+    Carver cv;
+    const size_t o_x1 = cv.take(sizeof(float2) * npix * n_sf);
+    const size_t o_x2 = cv.take(sizeof(float2) * nspec * n_sf);
+    const size_t o_part = cv.take(sizeof(double) * 5 * (size_t)(ny / 2 + 1));
+    const size_t o_nm = cv.take(sizeof(double) * 2);
+    void* ws;
+    if ((st = get_workspace(device, s, cv.off, &ws))) return st;
+    char* b = (char*)ws;
+    float2* x1 = (float2*)(b + o_x1);
+    float2* x2 = (float2*)(b + o_x2);
+    double* part = (double*)(b + o_part);
+    double* nm = (double*)(b + o_nm);
+    const uint32_t L = lut->n_dev;
+    const uint64_t c0 = cursor % L;
+    LAUNCH("ospr_rows", s, launch_ospr_rows(target, (int)nx, (int)ny, n_sf, lut->dev, L, c0, x1, tw_x, cfg, s));
+    LAUNCH("ospr_cols", s, launch_ospr_cols(x1, (int)nx, (int)ny, n_sf, holo_bits, x2, tw_y, cfg, s));
+    LAUNCH("recon_rows", s, launch_recon_rows(x2, (int)nx, (int)ny, n_sf, true, target, recon, part, tw_x, cfg, s));
+    LAUNCH("nmse_finalize", s, launch_nmse_finalize(part, (int)(ny / 2 + 1), nm, s));
+    return copy_out(nmse2, nm, 2, flags, s);
+}
+
+// ---------------------------------------------------------------------------
+// GS: the device work of one call is a fixed sequence of 2*n_iter + 4..7
+// launches.  Unless kernel timing is on, it is captured once into a HIP graph
+// per (stream, arguments, workspace, plan) and replayed, which removes the
+// per-launch host cost from the iteration loop.
+// ---------------------------------------------------------------------------
+struct GsArgs {
+    const float* target;
+    int64_t nx, ny;
+    int n_iter;
+    const holo_lut* lut;
+    uint64_t cursor;
+    const float* init;
+    float* field;
+    uint8_t* codes;
+    double *nmse, *err, *final2;
+    float* recon;
+    uint32_t flags;
+};
+
+struct GraphKey {
+    std::vector<uintptr_t> k;
+    bool operator<(const GraphKey& o) const { return k < o.k; }
+};
+std::mutex g_graph_mu;
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+std::vector<GraphKey> g_graph_order;
+bool g_use_graphs = true;
+
+holo_status gs_enqueue(const GsArgs& a, hipStream_t s, const LaunchCfg& cfg, const float2* tw_x, const float2* tw_y,
+                       char* b, size_t o_state, size_t o_field, size_t o_pinit, size_t o_piter, size_t o_consts,
+                       size_t o_nm, size_t o_er, size_t o_x2, size_t o_p5, size_t o_f2)
+{
+    const int inx = (int)a.nx, iny = (int)a.ny;
+    float2* state = (float2*)(b + o_state);
+    float2* fout = a.field ? (float2*)a.field : (float2*)(b + o_field);
+    double* pinit = (double*)(b + o_pinit);
+    double* piter = (double*)(b + o_piter);
+    GsConsts* consts = (GsConsts*)(b + o_consts);
+    double* nm = (double*)(b + o_nm);
+    double* er = (double*)(b + o_er);
+    const bool use_lut = a.init == nullptr;
+    const uint32_t L = use_lut ? a.lut->n_dev : 1u;
+    const uint64_t c0 = use_lut ? a.cursor % L : 0;
+    const float2* lutp = use_lut ? a.lut->dev : nullptr;
+    LAUNCH("gs_rows", s, launch_gs_rows(GS_INIT, a.target, inx, iny, lutp, L, c0, (const float2*)a.init, state,
+                                        nullptr, pinit, consts, tw_x, cfg, s));
+    LAUNCH("gs_consts", s, launch_gs_consts(pinit, iny, inx, consts, s));
+    for (int it = 0; it < a.n_iter; ++it) {
+        const bool last = it == a.n_iter - 1;
+        LAUNCH("gs_cols", s, launch_gs_cols(state, inx, iny, last ? a.codes : nullptr, tw_y, cfg, s));
+        LAUNCH("gs_rows", s, launch_gs_rows(last ? GS_FINAL : GS_ITER, a.target, inx, iny, lutp, L, c0, nullptr,
+                                            state, fout, piter + (size_t)it * 3 * iny, consts, tw_x, cfg, s));
+    }
+    LAUNCH("gs_finalize", s, launch_gs_finalize(piter, a.n_iter, iny, consts, nm, er, s));
+    if (a.codes && (a.final2 || a.recon)) {
+        float2* x2 = (float2*)(b + o_x2);
+        double* p5 = (double*)(b + o_p5);
+        double* f2 = (double*)(b + o_f2);
+        LAUNCH("recon_cols", s, launch_recon_cols(a.codes, 8, inx, iny, 1, x2, tw_y, cfg, s));
+        LAUNCH("recon_rows", s, launch_recon_rows(x2, inx, iny, 1, false, a.target, a.recon, p5, tw_x, cfg, s));
+        LAUNCH("nmse_finalize", s, launch_nmse_finalize(p5, iny, f2, s));
+    }
+    return HOLO_OK;
+}
+
+holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& cfg)
+{
+    holo_status st;
+    const float2 *tw_x, *tw_y;
+    if ((st = get_twiddles(device, (int)a.nx, s, &tw_x))) return st;
+    if ((st = get_twiddles(device, (int)a.ny, s, &tw_y))) return st;
+    const size_t npix = (size_t)a.nx * (size_t)a.ny;
+    const int n_iter = a.n_iter, ny = (int)a.ny;
+    Carver cv;
+    const size_t o_state = cv.take(sizeof(float2) * npix);
+    const size_t o_field = cv.take(a.field ? 0 : sizeof(float2) * npix);
+    const size_t o_pinit = cv.take(sizeof(double) * 2 * ny);
+    const size_t o_piter = cv.take(sizeof(double) * 3 * ny * (size_t)n_iter);
+    const size_t o_consts = cv.take(sizeof(GsConsts));
+    const size_t o_nm = cv.take(sizeof(double) * n_iter);
+    const size_t o_er = cv.take(sizeof(double) * n_iter);
+    const size_t o_x2 = cv.take(a.codes ? sizeof(float2) * npix : 0);
+    const size_t o_p5 = cv.take(sizeof(double) * 5 * ny);
+    const size_t o_f2 = cv.take(sizeof(double) * 2);
+    void* ws;
+    if ((st = get_workspace(device, s, cv.off, &ws))) return st;
+    char* b = (char*)ws;
+
+    bool prof_on;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        prof_on = g_prof_on;
+    }
+    // the legacy default stream cannot be captured: launch directly there
+    if (!g_use_graphs || prof_on || s == nullptr) {
+        if ((st = gs_enqueue(a, s, cfg, tw_x, tw_y, b, o_state, o_field, o_pinit, o_piter, o_consts, o_nm, o_er,
+                             o_x2, o_p5, o_f2)))
+            return st;
+    } else {
+        const uint32_t L = a.init ? 1u : a.lut->n_dev;
+        GraphKey key{{(uintptr_t)device, (uintptr_t)s, (uintptr_t)a.target, (uintptr_t)a.nx, (uintptr_t)a.ny,
+                      (uintptr_t)a.n_iter, (uintptr_t)(a.init ? nullptr : a.lut->dev), (uintptr_t)L,
+                      (uintptr_t)(a.init ? 0 : a.cursor % L), (uintptr_t)a.init, (uintptr_t)a.field,
+                      (uintptr_t)a.codes, (uintptr_t)(a.final2 != nullptr), (uintptr_t)a.recon, (uintptr_t)ws,
+                      (uintptr_t)cfg.cols_per_block, (uintptr_t)cfg.rows_per_block, (uintptr_t)cfg.ksplit,
+                      (uintptr_t)cfg.recon_cols_per_block}};
+        hipGraphExec_t exec = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_graph_mu);
+            auto it = g_graphs.find(key);
+            if (it != g_graphs.end()) exec = it->second;
+        }
+        if (!exec) {
+            hipGraph_t graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            holo_status est = gs_enqueue(a, s, cfg, tw_x, tw_y, b, o_state, o_field, o_pinit, o_piter, o_consts,
+                                         o_nm, o_er, o_x2, o_p5, o_f2);
+            hipError_t ce = hipStreamEndCapture(s, &graph);
+            if (est) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return est;
+            }
+            if (ce != hipSuccess) return fail(HOLO_EDEVICE, "GS graph capture: %s", hipGetErrorString(ce));
+            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) return fail(HOLO_EDEVICE, "GS graph instantiate: %s", hipGetErrorString(ie));
+            std::lock_guard<std::mutex> lk(g_graph_mu);
+            g_graphs[key] = exec;
+            g_graph_order.push_back(key);
+            if (g_graph_order.size() > 32) {
+                auto old = g_graphs.find(g_graph_order.front());
+                if (old != g_graphs.end()) {
+                    (void)hipStreamSynchronize(s);
+                    (void)hipGraphExecDestroy(old->second);
+                    g_graphs.erase(old);
+                }
+                g_graph_order.erase(g_graph_order.begin());
+            }
+        }
+        HIP_TRY(hipGraphLaunch(exec, s));
+    }
+    if (a.codes && a.final2) {
+        if ((st = copy_out(a.final2, (double*)(b + o_f2), 2, a.flags, s))) return st;
+    }
+    if ((st = copy_out(a.nmse, (double*)(b + o_nm), n_iter, a.flags, s))) return st;
+    if ((st = copy_out(a.err, (double*)(b + o_er), n_iter, a.flags, s))) return st;
+    return HOLO_OK;
+}
+
+// Median-free timing of `reps` back-to-back runs of f on stream s (ms per run).
+template <typename F>
+holo_status time_runs(hipStream_t s, int reps, F f, double* ms_out)
+{
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    holo_status st = f();   // warm-up (and first-use allocations)
+    if (!st) {
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipEventRecord(e0, s));
+        for (int r = 0; r < reps && !st; ++r) st = f();
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        *ms_out = ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
 }  // namespace
 }  // namespace holo
 
@@ -324,35 +564,11 @@ holo_status holo_ospr_generate(const float* target, int64_t nx, int64_t ny, int3
     HIP_TRY(hipGetDevice(&device));
     holo_status st = check_lut(lut, device);
     if (st) return st;
-    hipStream_t s = (hipStream_t)hip_stream;
-    const float2 *tw_x, *tw_y;
-    if ((st = get_twiddles(device, (int)nx, s, &tw_x))) return st;
-    if ((st = get_twiddles(device, (int)ny, s, &tw_y))) return st;
-
-    const size_t npix = (size_t)nx * (size_t)ny;
-    const size_t nspec = (size_t)(ny / 2 + 1) * (size_t)nx;
-    Carver cv;
-    const size_t o_x1 = cv.take(sizeof(float2) * npix * n_sf);
-    const size_t o_x2 = cv.take(sizeof(float2) * nspec * n_sf);
-    const size_t o_part = cv.take(sizeof(double) * 5 * (size_t)(ny / 2 + 1));
-    const size_t o_nm = cv.take(sizeof(double) * 2);
-    void* ws;
-    if ((st = get_workspace(device, s, cv.off, &ws))) return st;
-    char* b = (char*)ws;
-    float2* x1 = (float2*)(b + o_x1);
-    float2* x2 = (float2*)(b + o_x2);
-    double* part = (double*)(b + o_part);
-    double* nm = (double*)(b + o_nm);
-
-    const uint32_t L = lut->n_dev;
-    const uint64_t c0 = *cursor % L;
-    const LaunchCfg cfg = default_cfg();
-    LAUNCH("ospr_rows", s, launch_ospr_rows(target, (int)nx, (int)ny, n_sf, lut->dev, L, c0, x1, tw_x, cfg, s));
-    LAUNCH("ospr_cols", s, launch_ospr_cols(x1, (int)nx, (int)ny, n_sf, holo_bits, x2, tw_y, cfg, s));
-    LAUNCH("recon_rows", s, launch_recon_rows(x2, (int)nx, (int)ny, n_sf, true, target, recon, part, tw_x, cfg, s));
-    LAUNCH("nmse_finalize", s, launch_nmse_finalize(part, (int)(ny / 2 + 1), nm, s));
-    if ((st = copy_out(nmse2, nm, 2, flags, s))) return st;
-    *cursor += (uint64_t)n_sf * (uint64_t)npix;
+    const LaunchCfg cfg = plan_get(PLAN_OSPR, nx, ny, n_sf);
+    if ((st = ospr_run(device, target, nx, ny, n_sf, lut, *cursor, holo_bits, recon, nmse2, flags,
+                       (hipStream_t)hip_stream, cfg)))
+        return st;
+    *cursor += (uint64_t)n_sf * (uint64_t)nx * (uint64_t)ny;
     return HOLO_OK;
 }
 
@@ -384,7 +600,7 @@ holo_status holo_reconstruct_nmse(const void* holo, int32_t levels, int64_t nx, 
     float2* x2 = (float2*)(b + o_x2);
     double* part = (double*)(b + o_part);
     double* nm = (double*)(b + o_nm);
-    const LaunchCfg cfg = default_cfg();
+    const LaunchCfg cfg = plan_get(PLAN_OSPR, nx, ny, n_sf);
     LAUNCH("recon_cols", s, launch_recon_cols(holo, levels, (int)nx, (int)ny, n_sf, x2, tw_y, cfg, s));
     LAUNCH("recon_rows", s, launch_recon_rows(x2, (int)nx, (int)ny, n_sf, half, target, recon, part, tw_x, cfg, s));
     LAUNCH("nmse_finalize", s, launch_nmse_finalize(part, nrows, nm, s));
@@ -406,62 +622,11 @@ holo_status holo_gs_iterate(const float* target, int64_t nx, int64_t ny, int32_t
     HIP_TRY(hipGetDevice(&device));
     holo_status st;
     if (!init_phasor && (st = check_lut(lut, device))) return st;
-    hipStream_t s = (hipStream_t)hip_stream;
-    const float2 *tw_x, *tw_y;
-    if ((st = get_twiddles(device, (int)nx, s, &tw_x))) return st;
-    if ((st = get_twiddles(device, (int)ny, s, &tw_y))) return st;
-
-    const size_t npix = (size_t)nx * (size_t)ny;
-    Carver cv;
-    const size_t o_state = cv.take(sizeof(float2) * npix);
-    const size_t o_field = cv.take(field ? 0 : sizeof(float2) * npix);
-    const size_t o_pinit = cv.take(sizeof(double) * 2 * ny);
-    const size_t o_piter = cv.take(sizeof(double) * 3 * ny * (size_t)n_iter);
-    const size_t o_consts = cv.take(sizeof(GsConsts));
-    const size_t o_nm = cv.take(sizeof(double) * n_iter);
-    const size_t o_er = cv.take(sizeof(double) * n_iter);
-    const size_t o_x2 = cv.take(codes ? sizeof(float2) * npix : 0);
-    const size_t o_p5 = cv.take(sizeof(double) * 5 * ny);
-    const size_t o_f2 = cv.take(sizeof(double) * 2);
-    void* ws;
-    if ((st = get_workspace(device, s, cv.off, &ws))) return st;
-    char* b = (char*)ws;
-    float2* state = (float2*)(b + o_state);
-    float2* fout = field ? (float2*)field : (float2*)(b + o_field);
-    double* pinit = (double*)(b + o_pinit);
-    double* piter = (double*)(b + o_piter);
-    GsConsts* consts = (GsConsts*)(b + o_consts);
-    double* nm = (double*)(b + o_nm);
-    double* er = (double*)(b + o_er);
-
-    const bool use_lut = init_phasor == nullptr;
-    const uint32_t L = use_lut ? lut->n_dev : 1u;
-    const uint64_t c0 = use_lut ? *cursor % L : 0;
-    const float2* lutp = use_lut ? lut->dev : nullptr;
-    const LaunchCfg cfg = default_cfg();
-    const int inx = (int)nx, iny = (int)ny;
-    LAUNCH("gs_rows", s, launch_gs_rows(GS_INIT, target, inx, iny, lutp, L, c0, (const float2*)init_phasor, state, nullptr,
-                           pinit, consts, tw_x, cfg, s));
-    LAUNCH("gs_consts", s, launch_gs_consts(pinit, iny, inx, consts, s));
-    for (int it = 0; it < n_iter; ++it) {
-        const bool last = it == n_iter - 1;
-        LAUNCH("gs_cols", s, launch_gs_cols(state, inx, iny, last ? codes : nullptr, tw_y, cfg, s));
-        LAUNCH("gs_rows", s, launch_gs_rows(last ? GS_FINAL : GS_ITER, target, inx, iny, lutp, L, c0, nullptr, state, fout,
-                               piter + (size_t)it * 3 * ny, consts, tw_x, cfg, s));
-    }
-    LAUNCH("gs_finalize", s, launch_gs_finalize(piter, n_iter, iny, consts, nm, er, s));
-    if (codes && (nmse_final2 || recon)) {
-        float2* x2 = (float2*)(b + o_x2);
-        double* p5 = (double*)(b + o_p5);
-        double* f2 = (double*)(b + o_f2);
-        LAUNCH("recon_cols", s, launch_recon_cols(codes, 8, inx, iny, 1, x2, tw_y, cfg, s));
-        LAUNCH("recon_rows", s, launch_recon_rows(x2, inx, iny, 1, false, target, recon, p5, tw_x, cfg, s));
-        LAUNCH("nmse_finalize", s, launch_nmse_finalize(p5, iny, f2, s));
-        if ((st = copy_out(nmse_final2, f2, 2, flags, s))) return st;
-    }
-    if ((st = copy_out(nmse_per_iter, nm, n_iter, flags, s))) return st;
-    if ((st = copy_out(err_per_iter, er, n_iter, flags, s))) return st;
-    if (use_lut) *cursor += npix;
+    GsArgs a{target, nx, ny, n_iter, init_phasor ? nullptr : lut, init_phasor ? 0 : *cursor, init_phasor,
+             field, codes, nmse_per_iter, err_per_iter, nmse_final2, recon, flags};
+    const LaunchCfg cfg = plan_get(PLAN_GS, nx, ny, 1);
+    if ((st = gs_run(device, a, (hipStream_t)hip_stream, cfg))) return st;
+    if (!init_phasor) *cursor += (uint64_t)nx * (uint64_t)ny;
     return HOLO_OK;
 }
 
@@ -482,6 +647,214 @@ holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t ny, int32
     if ((st = get_workspace(device, s, sizeof(float2) * (size_t)nx * ny, &ws))) return st;
     LAUNCH("fft2", s, launch_fft2((const float2*)in, (float2*)ws, (float2*)out, (int)nx, (int)ny, sign, tw_x, tw_y,
                         default_cfg(), s));
+    return HOLO_OK;
+}
+
+holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t ny, int32_t n_sf, const holo_lut* lut,
+                               uint32_t* scratch_bits, int32_t reps, int32_t* chosen, void* hip_stream)
+{
+    if (!target || !scratch_bits) return fail(HOLO_EINVAL, "target and scratch_bits are required");
+    if (n_sf < 1 || reps < 1) return fail(HOLO_EINVAL, "n_sf and reps must be >= 1");
+    if (!pow2_in_range(nx) || !pow2_in_range(ny))
+        return fail(HOLO_EUNSUPPORTED, "nx, ny must be powers of two in [16, 2048]");
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    holo_status st = check_lut(lut, device);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t nwords = (size_t)n_sf * (size_t)nx * (size_t)ny / 32;
+    std::vector<uint32_t> ref_bits(nwords), bits(nwords);
+    double ref_nm[2], nm[2];
+    // reference: built-in heuristic shapes
+    LaunchCfg best{};
+    if ((st = ospr_run(device, target, nx, ny, n_sf, lut, 0, scratch_bits, nullptr, ref_nm, 0, s, best))) return st;
+    HIP_TRY(hipMemcpy(ref_bits.data(), scratch_bits, nwords * 4, hipMemcpyDeviceToHost));
+    double best_ms = 0.0;
+    auto run = [&](const LaunchCfg& c) {
+        return ospr_run(device, target, nx, ny, n_sf, lut, 0, scratch_bits, nullptr, nullptr, 0, s, c);
+    };
+    if ((st = time_runs(s, reps, [&] { return run(best); }, &best_ms))) return st;
+    // coordinate descent over each kernel's shape; a candidate counts only if
+    // it reproduces the reference holograms bit for bit and its NMSE
+    const int cols_opts[] = {8, 16};
+    const int rows_opts[] = {1, 2, 4, 8, 16};
+    const int ks_opts[] = {1, 2, 4, 8};
+    for (int dim = 0; dim < 3; ++dim) {
+        const int* opts = dim == 0 ? cols_opts : dim == 1 ? rows_opts : ks_opts;
+        const int nopt = dim == 0 ? 2 : dim == 1 ? 5 : 4;
+        for (int i = 0; i < nopt; ++i) {
+            LaunchCfg c = best;
+            (dim == 0 ? c.cols_per_block : dim == 1 ? c.rows_per_block : c.ksplit) = opts[i];
+            double ms = 0.0;
+            if (run(c) != HOLO_OK) continue;
+            if ((st = ospr_run(device, target, nx, ny, n_sf, lut, 0, scratch_bits, nullptr, nm, 0, s, c))) continue;
+            HIP_TRY(hipMemcpy(bits.data(), scratch_bits, nwords * 4, hipMemcpyDeviceToHost));
+            if (bits != ref_bits || std::fabs(nm[0] - ref_nm[0]) > 1e-9 * std::fabs(ref_nm[0]) ||
+                std::fabs(nm[1] - ref_nm[1]) > 1e-9 * std::fabs(ref_nm[1]))
+                continue;
+            if (time_runs(s, reps, [&] { return run(c); }, &ms)) continue;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    }
+    plan_put(PLAN_OSPR, nx, ny, n_sf, best);
+    if (chosen) {
+        chosen[0] = best.cols_per_block;
+        chosen[1] = best.rows_per_block;
+        chosen[2] = best.ksplit;
+        chosen[3] = best.recon_cols_per_block;
+    }
+    g_err.clear();
+    return HOLO_OK;
+}
+
+holo_status holo_autotune_gs(const float* target, int64_t nx, int64_t ny, const holo_lut* lut, int32_t reps,
+                             int32_t* chosen, void* hip_stream)
+{
+    if (!target) return fail(HOLO_EINVAL, "target is required");
+    if (reps < 1) return fail(HOLO_EINVAL, "reps must be >= 1");
+    if (!pow2_in_range(nx) || !pow2_in_range(ny))
+        return fail(HOLO_EUNSUPPORTED, "nx, ny must be powers of two in [16, 2048]");
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    holo_status st = check_lut(lut, device);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int n_iter = 4;
+    const size_t npix = (size_t)nx * (size_t)ny;
+    uint8_t* codes = nullptr;
+    if (hipMalloc(&codes, npix) != hipSuccess) return fail(HOLO_ENOMEM, "autotune scratch");
+    std::vector<uint8_t> ref_codes(npix), cd(npix);
+    double ref_nm[n_iter], nm[n_iter];
+    GsArgs a{target, nx, ny, n_iter, lut, 0, nullptr, nullptr, codes, ref_nm, nullptr, nullptr, nullptr, 0};
+    LaunchCfg best{};
+    double best_ms = 0.0;
+    st = gs_run(device, a, s, best);
+    if (!st) {
+        (void)hipMemcpy(ref_codes.data(), codes, npix, hipMemcpyDeviceToHost);
+        GsArgs q = a;
+        q.nmse = nullptr;
+        auto run = [&](const LaunchCfg& c) { return gs_run(device, q, s, c); };
+        st = time_runs(s, reps, [&] { return run(best); }, &best_ms);
+        const int cols_opts[] = {2, 4, 8, 16};
+        const int rows_opts[] = {1, 2, 4, 8};
+        for (int dim = 0; dim < 2 && !st; ++dim) {
+            const int* opts = dim == 0 ? cols_opts : rows_opts;
+            for (int i = 0; i < 4; ++i) {
+                LaunchCfg c = best;
+                (dim == 0 ? c.cols_per_block : c.rows_per_block) = opts[i];
+                GsArgs v = a;
+                v.nmse = nm;
+                if (gs_run(device, v, s, c) != HOLO_OK) continue;
+                (void)hipMemcpy(cd.data(), codes, npix, hipMemcpyDeviceToHost);
+                bool same = cd == ref_codes;
+                for (int k = 0; k < n_iter; ++k) same = same && nm[k] == ref_nm[k];
+                if (!same) continue;
+                double ms = 0.0;
+                if (time_runs(s, reps, [&] { return run(c); }, &ms)) continue;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(codes);
+    if (st) return st;
+    plan_put(PLAN_GS, nx, ny, 1, best);
+    if (chosen) {
+        chosen[0] = best.cols_per_block;
+        chosen[1] = best.rows_per_block;
+        chosen[2] = best.ksplit;
+        chosen[3] = best.recon_cols_per_block;
+    }
+    g_err.clear();
+    return HOLO_OK;
+}
+
+holo_status holo_plan_set(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, const int32_t* cfg4)
+{
+    if ((kind != 0 && kind != 1) || !cfg4) return fail(HOLO_EINVAL, "kind must be 0 (OSPR) or 1 (GS), cfg4 set");
+    LaunchCfg c;
+    c.cols_per_block = cfg4[0];
+    c.rows_per_block = cfg4[1];
+    c.ksplit = cfg4[2];
+    c.recon_cols_per_block = cfg4[3];
+    plan_put(kind, nx, ny, n_sf, c);
+    return HOLO_OK;
+}
+
+holo_status holo_plan_get(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, int32_t* cfg4)
+{
+    if ((kind != 0 && kind != 1) || !cfg4) return fail(HOLO_EINVAL, "kind must be 0 (OSPR) or 1 (GS), cfg4 set");
+    const LaunchCfg c = plan_get(kind, nx, ny, n_sf);
+    cfg4[0] = c.cols_per_block;
+    cfg4[1] = c.rows_per_block;
+    cfg4[2] = c.ksplit;
+    cfg4[3] = c.recon_cols_per_block;
+    return HOLO_OK;
+}
+
+holo_status holo_plan_save(const char* path)
+{
+    if (!path) return fail(HOLO_EINVAL, "path is NULL");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(HOLO_EINVAL, "cannot write %s", path);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    std::fprintf(f, "{\"plans\": [");
+    bool first = true;
+    for (auto& kv : g_plans) {
+        std::fprintf(f, "%s\n  {\"kind\": %d, \"nx\": %lld, \"ny\": %lld, \"n_sf\": %d, \"cfg\": [%d, %d, %d, %d]}",
+                     first ? "" : ",", kv.first.kind, (long long)kv.first.nx, (long long)kv.first.ny, kv.first.n_sf,
+                     kv.second.cols_per_block, kv.second.rows_per_block, kv.second.ksplit,
+                     kv.second.recon_cols_per_block);
+        first = false;
+    }
+    std::fprintf(f, "\n]}\n");
+    std::fclose(f);
+    return HOLO_OK;
+}
+
+holo_status holo_plan_load(const char* path)
+{
+    if (!path) return fail(HOLO_EINVAL, "path is NULL");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(HOLO_EINVAL, "cannot read %s", path);
+    std::string txt;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+    std::fclose(f);
+    // entries written by holo_plan_save: {"kind": K, "nx": X, "ny": Y, "n_sf": S, "cfg": [a, b, c, d]}
+    size_t pos = 0;
+    int loaded = 0;
+    while ((pos = txt.find("{\"kind\"", pos)) != std::string::npos) {
+        int kind, sf, c0, c1, c2, c3;
+        long long nx, ny;
+        if (std::sscanf(txt.c_str() + pos,
+                        "{\"kind\": %d, \"nx\": %lld, \"ny\": %lld, \"n_sf\": %d, \"cfg\": [%d, %d, %d, %d]}", &kind,
+                        &nx, &ny, &sf, &c0, &c1, &c2, &c3) == 8) {
+            LaunchCfg c;
+            c.cols_per_block = c0;
+            c.rows_per_block = c1;
+            c.ksplit = c2;
+            c.recon_cols_per_block = c3;
+            plan_put(kind, nx, ny, sf, c);
+            ++loaded;
+        } else {
+            return fail(HOLO_EINVAL, "malformed plan entry in %s", path);
+        }
+        ++pos;
+    }
+    return HOLO_OK;
+}
+
+holo_status holo_set_graphs(int32_t on)
+{
+    g_use_graphs = on != 0;
     return HOLO_OK;
 }
 
@@ -523,6 +896,12 @@ void holo_shutdown(void)
             if (w.second.base) (void)hipFree(w.second.base);
     }
     g_dev.clear();
+    {
+        std::lock_guard<std::mutex> gl(g_graph_mu);
+        for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+        g_graphs.clear();
+        g_graph_order.clear();
+    }
     (void)hipSetDevice(cur);
 }
 

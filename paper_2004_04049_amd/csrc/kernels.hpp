@@ -6,12 +6,18 @@
 
 namespace holo {
 
-// Per-kernel launch shape, chosen by the plan (default or autotuned).
+// Launch shapes of one plan (0 = built-in heuristic).  Chosen per
+// (path, nx, ny, n_sf) by the autotuner or left at the defaults.
 struct LaunchCfg {
-    int cols_per_block = 16;   // C: interleaved column transforms per block
-    int rows_per_block = 0;    // row transforms per block (0 = fill 256 threads)
-    int ksplit = 4;            // sub-frame groups per reconstruction-row block
+    int cols_per_block = 0;        // C of the generation column pass (OSPR K2, GS cols)
+    int rows_per_block = 0;        // row transforms per block (OSPR K1, GS rows)
+    int ksplit = 0;                // sub-frame groups per reconstruction-row block
+    int recon_cols_per_block = 0;  // C of the reconstruction column pass
 };
+
+// Column-tile width for a column pass of length n over ncols columns and
+// nbatch independent fields (see the definition for the rule).
+int col_block_cols(int n, int ncols, int nbatch, int planned, int cmin);
 
 // FP64 twiddle generation on the device: tw[k] = fp32(exp(-2*pi*i*k/n)).
 hipError_t launch_twiddle_gen(float2* tw, int n, hipStream_t s);

@@ -36,6 +36,14 @@ namespace holo {
 // Column-tile width C (columns transformed side by side by one block).
 #define HOLO_SWITCH_C(c, ...)                                    \
     switch (c) {                                                 \
+        case 2: { constexpr int C_ = 2; __VA_ARGS__; } break;    \
+        case 4: { constexpr int C_ = 4; __VA_ARGS__; } break;    \
+        case 8: { constexpr int C_ = 8; __VA_ARGS__; } break;    \
+        case 16: { constexpr int C_ = 16; __VA_ARGS__; } break;  \
+        default: return hipErrorInvalidValue;                    \
+    }
+#define HOLO_SWITCH_C816(c, ...)                                 \
+    switch (c) {                                                 \
         case 8: { constexpr int C_ = 8; __VA_ARGS__; } break;    \
         case 16: { constexpr int C_ = 16; __VA_ARGS__; } break;  \
         default: return hipErrorInvalidValue;                    \
@@ -47,22 +55,31 @@ struct RowAddrR {
     __device__ __forceinline__ int operator()(int e) const { return base + lds_pad(e); }
 };
 
-static int row_block_rows(int n, int nrows, const LaunchCfg& cfg)
+static int row_block_rows(int n, int nrows, int planned)
 {
     const int T = n / kP;
-    int rows = cfg.rows_per_block > 0 ? cfg.rows_per_block : (256 / T > 0 ? 256 / T : 1);
+    int rows = planned > 0 ? planned : (256 / T > 0 ? 256 / T : 1);
+    if (rows * T > 1024) rows = 1024 / T;
     if (rows < 1) rows = 1;
     while (rows > 1 && (nrows % rows)) rows >>= 1;
     if (rows > nrows) rows = nrows;
     return rows;
 }
 
-// Column-tile width: 8 or 16, at most 1024 threads and 160 KiB of LDS.
-static int col_block_cols(int n, int ncols, const LaunchCfg& cfg)
+// Column-tile width C in {2, 4, 8, 16} (at least `cmin`): the plan's value, or
+// else the widest tile that still gives >= 512 blocks over the whole launch;
+// capped by 1024 threads and 160 KiB of LDS per block.
+int col_block_cols(int n, int ncols, int nbatch, int planned, int cmin)
 {
     const int T = n / kP;
-    int C = cfg.cols_per_block >= 16 ? 16 : 8;
-    if (C == 16 && (16 * T > 1024 || (size_t)16 * pad_len(n) * sizeof(float2) > 160 * 1024)) C = 8;
+    int C = planned;
+    if (C <= 0) {
+        C = 16;
+        while (C > cmin && (long)(ncols / C) * nbatch < 512) C >>= 1;
+    }
+    if (C < cmin) C = cmin;
+    if (C > 16) C = 16;
+    while (C > cmin && (C * T > 1024 || (size_t)C * pad_len(n) * sizeof(float2) > 160 * 1024)) C >>= 1;
     if (C > ncols) C = ncols;
     return C;
 }
@@ -135,7 +152,7 @@ hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int n
                        const float2* tw_x, const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
 {
     {
-        const int rows = row_block_rows(nx, ny, cfg);
+        const int rows = row_block_rows(nx, ny, cfg.rows_per_block);
         HOLO_SWITCH_N(nx, {
             constexpr int T = N_ / kP;
             size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
@@ -149,7 +166,7 @@ hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int n
         });
     }
     {
-        const int C = col_block_cols(ny, nx, cfg);
+        const int C = col_block_cols(ny, nx, 1, cfg.cols_per_block, 2);
         const float scale = (float)(1.0 / sqrt((double)nx * (double)ny));
         HOLO_SWITCH_N(ny, HOLO_SWITCH_C(C, {
             constexpr int T = N_ / kP;
@@ -210,7 +227,7 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
                             uint32_t n_lut, uint64_t c0, float2* x1, const float2* tw_x,
                             const LaunchCfg& cfg, hipStream_t s)
 {
-    const int rows = row_block_rows(nx, ny, cfg);
+    const int rows = row_block_rows(nx, ny, cfg.rows_per_block);
     HOLO_SWITCH_N(nx, {
         constexpr int T = N_ / kP;
         size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
@@ -276,8 +293,8 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __res
 hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
                             const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
 {
-    const int C = col_block_cols(ny, nx, cfg);
-    HOLO_SWITCH_N(ny, HOLO_SWITCH_C(C, {
+    const int C = col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8);
+    HOLO_SWITCH_N(ny, HOLO_SWITCH_C816(C, {
         constexpr int T = N_ / kP;
         if (C_ * T <= 1024) {
             size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
@@ -349,7 +366,7 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_recon_cols(const void* __rest
 hipError_t launch_recon_cols(const void* holo, int levels, int nx, int ny, int n_sf, float2* x2,
                              const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
 {
-    const int C = col_block_cols(ny, nx, cfg);
+    const int C = col_block_cols(ny, nx, n_sf, cfg.recon_cols_per_block, 2);
     HOLO_SWITCH_N(ny, HOLO_SWITCH_C(C, {
         constexpr int T = N_ / kP;
         if (C_ * T <= 1024) {
@@ -387,16 +404,33 @@ __global__ __launch_bounds__(512) void k_recon_rows(const float2* __restrict__ x
 #pragma unroll
     for (int m = 0; m < kP; ++m) acc[m] = 0.0f;
     const int rounds = (n_sf + G - 1) / G;
+    // software pipeline: the next sub-frame's row is in flight while the
+    // current one is transformed (LDS barriers do not wait on global loads)
+    float2 nxt[kP];
+    {
+        const bool valid = g < n_sf;
+        const float2* src = x2 + (size_t)(valid ? g : 0) * sf_stride + (size_t)v_row * NX;
+#pragma unroll
+        for (int m = 0; m < kP; ++m) nxt[m] = valid ? src[t + T * m] : make_float2(0.0f, 0.0f);
+    }
     for (int r = 0; r < rounds; ++r) {
         const int k = r * G + g;
         const bool valid = k < n_sf;
-        const float2* src = x2 + (size_t)(valid ? k : 0) * sf_stride + (size_t)v_row * NX;
         float2 v[kP];
 #pragma unroll
-        for (int m = 0; m < kP; ++m) v[m] = valid ? src[t + T * m] : make_float2(0.0f, 0.0f);
-        fft_stages<NX, -1>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, tw);
+        for (int m = 0; m < kP; ++m) v[m] = nxt[m];
+        if (r + 1 < rounds) {
+            const int kn = k + G;
+            const bool vn = kn < n_sf;
+            const float2* src = x2 + (size_t)(vn ? kn : 0) * sf_stride + (size_t)v_row * NX;
 #pragma unroll
-        for (int m = 0; m < kP; ++m) acc[m] = fmaf(v[m].x, v[m].x, fmaf(v[m].y, v[m].y, acc[m]));
+            for (int m = 0; m < kP; ++m) nxt[m] = vn ? src[t + T * m] : make_float2(0.0f, 0.0f);
+        }
+        fft_stages<NX, -1>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, tw);
+        if (valid) {
+#pragma unroll
+            for (int m = 0; m < kP; ++m) acc[m] = fmaf(v[m].x, v[m].x, fmaf(v[m].y, v[m].y, acc[m]));
+        }
     }
     // combine the G groups' sums (group order fixed)
     float* ldsf = reinterpret_cast<float*>(lds);
@@ -459,7 +493,7 @@ hipError_t launch_recon_rows(const float2* x2, int nx, int ny, int n_sf, bool ha
     const int nrows_spec = half ? ny / 2 + 1 : ny;
     HOLO_SWITCH_N(nx, {
         constexpr int T = N_ / kP;
-        int G = cfg.ksplit > 0 ? cfg.ksplit : 1;
+        int G = cfg.ksplit > 0 ? cfg.ksplit : 4;
         while (G > 1 && (G * T > 512 || G > n_sf)) G >>= 1;
         size_t fft_lds = (size_t)G * PadLen<N_>::v * sizeof(float2);
         size_t red_lds = (size_t)5 * (G * T / 64 + 1) * sizeof(double);
