@@ -35,7 +35,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip GS and the LUT sweep")
     ap.add_argument("--plan", default=None,
-                    help="OSPR launch plan 'cols,rows,ksplit,recon_cols' to use instead of autotuning")
+                    help="OSPR launch plan 'cols,rows,ksplit,recon_cols,pad' to use instead of autotuning")
+    ap.add_argument("--calib", action="store_true",
+                    help="finish with a plain 256 MiB copy kernel (reference for memory counters)")
     return ap.parse_args()
 
 
@@ -177,6 +179,12 @@ def main():
         out["lut_sweep"] = bench_lut_sweep(h, synth, torch, dev, target, nx, ny, n_sf)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(synth, nx, ny, n_lut)
+    if args.calib:
+        # known traffic: reads 2^28 bytes and writes 2^28 bytes
+        x = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+        y = x.mul(1.0)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
     print(json.dumps(out), flush=True)
 
 

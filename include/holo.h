@@ -168,16 +168,20 @@ HOLO_API holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t 
 /* ---------------------------------------------------------------------------
  * Launch plans and the autotuner (implementation choices, not part of the
  * method: every plan computes the same holograms).
- * A plan is four ints {cols, rows, ksplit, recon_cols}: column-tile width of
- * the generation column pass (OSPR: 8 or 16; GS: 2, 4, 8 or 16), row
- * transforms per block of the row pass, sub-frame groups per block of the
- * reconstruction row pass, column-tile width of the reconstruction column
- * pass; 0 selects the built-in heuristic.  Plans are keyed by kind
+ * A plan is six ints {cols, rows, ksplit, recon_cols, pad, chunk}:
+ * column-tile width of the generation column pass (OSPR: 8 or 16; GS: 2, 4, 8
+ * or 16), row transforms per block of the row pass, sub-frame groups per
+ * block of the reconstruction row pass, column-tile width of the
+ * reconstruction column pass (0 selects the built-in heuristic for these
+ * four); extra elements per row of the library's internal fields (-1:
+ * heuristic); and OSPR sub-frames generated per chunk (0: all; a chunk's
+ * intermediate planes are reused, so they can stay in the last-level cache).  Plans are keyed by kind
  * (0 = OSPR, 1 = GS), nx, ny and n_sf (ignored for GS).
  * holo_autotune_ospr / holo_autotune_gs time candidate plans on the caller's
  * inputs (coordinate descent, `reps` timed runs each) and keep the fastest
- * whose holograms (bits / codes) and NMSE equal those of the default plan;
- * `chosen` (int[4] or NULL) receives it.  scratch_bits: device
+ * whose holograms (bits / codes) equal those of the default plan exactly and
+ * whose NMSE agrees to 1e-6 relative (FP32 summation order of the average);
+ * `chosen` (int[6] or NULL) receives it.  scratch_bits: device
  * uint32[n_sf][nx*ny/32], overwritten.  holo_plan_save / holo_plan_load
  * write and read all plans as JSON.  holo_set_graphs(0) disables the HIP
  * graph replay of holo_gs_iterate (on by default).

@@ -264,40 +264,46 @@ def prof_reset():
 
 
 PLAN_OSPR, PLAN_GS = 0, 1
+PLAN_INTS = 6
+DEFAULT_PLAN = [0, 0, 0, 0, -1, 0]
 
 
 def autotune_ospr(target, n_sf: int, lut: Lut, reps: int = 5, stream=None):
-    """holo_autotune_ospr: returns the chosen plan [cols, rows, ksplit, recon_cols]."""
+    """holo_autotune_ospr: returns the chosen plan [cols, rows, ksplit, recon_cols, pad, chunk]."""
     import numpy as np
     ny, nx = target.shape
     _dev(target, torch.float32, None, "target")
     scratch = torch.empty((n_sf, nx * ny // 32), dtype=torch.int32, device=target.device)
-    out = np.zeros(4, dtype=np.int32)
+    out = np.zeros(PLAN_INTS, dtype=np.int32)
     _check(lib().holo_autotune_ospr(_ptr(target), nx, ny, n_sf, lut.handle, _ptr(scratch), reps,
                                     out.ctypes.data_as(C.c_void_p), _stream(stream)))
     return out.tolist()
 
 
 def autotune_gs(target, lut: Lut, reps: int = 5, stream=None):
-    """holo_autotune_gs: returns the chosen plan [cols, rows, ksplit, recon_cols]."""
+    """holo_autotune_gs: returns the chosen plan [cols, rows, ksplit, recon_cols, pad, chunk]."""
     import numpy as np
     ny, nx = target.shape
     _dev(target, torch.float32, None, "target")
-    out = np.zeros(4, dtype=np.int32)
+    out = np.zeros(PLAN_INTS, dtype=np.int32)
     _check(lib().holo_autotune_gs(_ptr(target), nx, ny, lut.handle, reps, out.ctypes.data_as(C.c_void_p),
                                   _stream(stream)))
     return out.tolist()
 
 
 def plan_set(kind: int, nx: int, ny: int, n_sf: int, cfg):
+    """cfg: [cols, rows, ksplit, recon_cols, pad, chunk]; DEFAULT_PLAN
+    selects the built-in heuristics."""
     import numpy as np
     a = np.ascontiguousarray(cfg, dtype=np.int32)
+    if a.size != PLAN_INTS:
+        raise ValueError("a plan is 6 ints: cols, rows, ksplit, recon_cols, pad, chunk")
     _check(lib().holo_plan_set(kind, nx, ny, n_sf, a.ctypes.data_as(C.c_void_p)))
 
 
 def plan_get(kind: int, nx: int, ny: int, n_sf: int):
     import numpy as np
-    a = np.zeros(4, dtype=np.int32)
+    a = np.zeros(PLAN_INTS, dtype=np.int32)
     _check(lib().holo_plan_get(kind, nx, ny, n_sf, a.ctypes.data_as(C.c_void_p)))
     return a.tolist()
 

@@ -231,17 +231,28 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[kP], int t, float2* lds, 
         }
         if (!last) {
             // exchange: write outputs at their Stockham positions, read back the
-            // t + T*m set for the next stage.
+            // t + T*m set for the next stage.  Addresses are padded indices
+            // p = e + e/16.  Radix-16 stages run first, so Ns is 1 or a multiple
+            // of 16 here and element base + r*Ns pads to pad(base) + r*ps with a
+            // compile-time ps; likewise t + T*m pads to pad(t) + m*T*17/16 when
+            // 16 divides T.  The addr functor gets padded indices.
+            const int ps = Ns == 1 ? 1 : (Ns / 16) * 17;
 #pragma unroll
             for (int b = 0; b < nb; ++b) {
                 const int j = t + b * T;
-                const int base = (j / Ns) * Ns * R + (j & (Ns - 1));
+                const int pb = lds_pad((j / Ns) * Ns * R + (j & (Ns - 1)));
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[addr(base + r * Ns)] = v[b + r * nb];
+                for (int r = 0; r < R; ++r) lds[addr(pb + r * ps)] = v[b + r * nb];
             }
             __syncthreads();
+            if (T % 16 == 0) {
+                const int pt = lds_pad(t);
 #pragma unroll
-            for (int m = 0; m < kP; ++m) v[m] = lds[addr(t + T * m)];
+                for (int m = 0; m < kP; ++m) v[m] = lds[addr(pt + m * (T / 16) * 17)];
+            } else {
+#pragma unroll
+                for (int m = 0; m < kP; ++m) v[m] = lds[addr(lds_pad(t + T * m))];
+            }
             __syncthreads();
         }
         Ns *= R;
@@ -306,16 +317,39 @@ __device__ __forceinline__ void st_off(V* base, uint32_t boff, V v)
 
 // LDS addressing for R_ROWS independent row transforms of length N, one per
 // padded LDS row.
+// (Both take the padded element index p = e + e/16.)
 template <int N>
 struct RowAddr {
     int row;
-    __device__ __forceinline__ int operator()(int e) const { return row * PadLen<N>::v + lds_pad(e); }
+    __device__ __forceinline__ int operator()(int p) const { return row * PadLen<N>::v + p; }
 };
 // LDS addressing for C interleaved column transforms: element e of column c.
 template <int C>
 struct ColAddr {
     int c;
-    __device__ __forceinline__ int operator()(int e) const { return lds_pad(e) * C + c; }
+    __device__ __forceinline__ int operator()(int p) const { return p * C + c; }
 };
+
+// Raw buffer access: a descriptor over `bytes` bytes from a wave-uniform base
+// (hardware range-checked: loads past the end read 0, stores are dropped),
+// a per-lane byte offset and a wave-uniform byte offset, so a strided set of
+// accesses needs one offset register and scalar increments.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float2 buf_ld2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_st2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float2 x)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x), r, voff, soff, 0);
+}
+__device__ __forceinline__ float buf_ld1(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
 
 }  // namespace holo

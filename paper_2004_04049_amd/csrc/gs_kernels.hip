@@ -33,7 +33,7 @@ namespace holo {
 namespace {
 struct RowAddrG {
     int base;
-    __device__ __forceinline__ int operator()(int e) const { return base + lds_pad(e); }
+    __device__ __forceinline__ int operator()(int p) const { return base + p; }
 };
 
 template <typename K>
@@ -97,7 +97,8 @@ __global__ __launch_bounds__(256) void k_gs_rows(const float* __restrict__ targe
                                                   const float2* __restrict__ lut, uint32_t n_lut, uint64_t c0,
                                                   const float2* __restrict__ init, float2* __restrict__ state,
                                                   float2* __restrict__ field_out, double* __restrict__ partials,
-                                                  const GsConsts* __restrict__ consts, const float2* __restrict__ tw)
+                                                  const GsConsts* __restrict__ consts, const float2* __restrict__ tw,
+                                                  int pitch)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NX / kP;
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(256) void k_gs_rows(const float* __restrict__ targe
     const int row = threadIdx.x / T, t = threadIdx.x % T;
     const int y = blockIdx.x * rows + row;
     const float* trow = target + (size_t)y * NX;
-    float2* srow = state + (size_t)y * NX;
+    float2* srow = state + (size_t)y * pitch;
     float2 v[kP];
     float ta[kP];
 #pragma unroll
@@ -212,15 +213,18 @@ hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const f
         if (mode == GS_INIT) {
             allow_lds_g(k_gs_rows<N_, GS_INIT>, lds);
             hipLaunchKernelGGL((k_gs_rows<N_, GS_INIT>), dim3(ny / rows), dim3(rows * T), lds, s, target, ny, lut,
-                               n_lut, c0, init, state, field_out, partials, consts, tw_x);
+                               n_lut, c0, init, state, field_out, partials, consts, tw_x,
+                               row_pitch(nx, cfg));
         } else if (mode == GS_ITER) {
             allow_lds_g(k_gs_rows<N_, GS_ITER>, lds);
             hipLaunchKernelGGL((k_gs_rows<N_, GS_ITER>), dim3(ny / rows), dim3(rows * T), lds, s, target, ny, lut,
-                               n_lut, c0, init, state, field_out, partials, consts, tw_x);
+                               n_lut, c0, init, state, field_out, partials, consts, tw_x,
+                               row_pitch(nx, cfg));
         } else {
             allow_lds_g(k_gs_rows<N_, GS_FINAL>, lds);
             hipLaunchKernelGGL((k_gs_rows<N_, GS_FINAL>), dim3(ny / rows), dim3(rows * T), lds, s, target, ny, lut,
-                               n_lut, c0, init, state, field_out, partials, consts, tw_x);
+                               n_lut, c0, init, state, field_out, partials, consts, tw_x,
+                               row_pitch(nx, cfg));
         }
     });
     return hipGetLastError();
@@ -231,14 +235,15 @@ hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const f
 // -------------------------------------------------------------------------
 template <int NY, int C>
 __global__ __launch_bounds__(C * (NY / kP)) void k_gs_cols(float2* __restrict__ state, int nx,
-                                                          uint8_t* __restrict__ codes, const float2* __restrict__ tw)
+                                                          uint8_t* __restrict__ codes, const float2* __restrict__ tw,
+                                                          int pitch)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NY / kP;
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int x0 = xcd_tile(blockIdx.x, gridDim.x) * C;
-    const size_t mstride = (size_t)T * nx;
-    const uint32_t toff = ((uint32_t)t * (uint32_t)nx + (uint32_t)c) * (uint32_t)sizeof(float2);
+    const size_t mstride = (size_t)T * pitch;
+    const uint32_t toff = ((uint32_t)t * (uint32_t)pitch + (uint32_t)c) * (uint32_t)sizeof(float2);
     float2* col = state + x0;
     float2 v[kP];
 #pragma unroll
@@ -246,8 +251,9 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_gs_cols(float2* __restrict__ 
     fft_stages<NY, 1>(v, t, lds, ColAddr<C>{c}, tw);
     if (codes) {
         const uint32_t coff = (uint32_t)t * (uint32_t)nx + (uint32_t)c;
+        const size_t cstride = (size_t)T * nx;
 #pragma unroll
-        for (int m = 0; m < kP; ++m) st_off(codes + x0 + m * mstride, coff, quant8(v[m]));
+        for (int m = 0; m < kP; ++m) st_off(codes + x0 + m * cstride, coff, quant8(v[m]));
     }
 #pragma unroll
     for (int m = 0; m < kP; ++m) {
@@ -272,7 +278,7 @@ hipError_t launch_gs_cols(float2* state, int nx, int ny, uint8_t* codes, const f
                 size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);                                   \
                 allow_lds_g(k_gs_cols<N_, C_>, lds);                                                         \
                 hipLaunchKernelGGL((k_gs_cols<N_, C_>), dim3(nx / C_), dim3(C_ * T), lds, s, state, nx, codes, \
-                                   tw_y);                                                                    \
+                                   tw_y, row_pitch(nx, cfg));                                                \
             }                                                                                                \
         });                                                                                                  \
     } break;

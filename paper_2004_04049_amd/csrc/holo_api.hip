@@ -262,10 +262,14 @@ holo_status ospr_run(int device, const float* target, int64_t nx, int64_t ny, in
     const float2 *tw_x, *tw_y;
     if ((st = get_twiddles(device, (int)nx, s, &tw_x))) return st;
     if ((st = get_twiddles(device, (int)ny, s, &tw_y))) return st;
-    const size_t npix = (size_t)nx * (size_t)ny;
-    const size_t nspec = (size_t)(ny / 2 + 1) * (size_t)nx;
+    const size_t pitch = (size_t)row_pitch((int)nx, cfg);
+    const size_t plane = (size_t)ny * pitch;
+    const size_t nspec = (size_t)(ny / 2 + 1) * pitch;
+    // sub-frames generated per chunk: the chunk's complex planes are reused,
+    // so a chunk's intermediates can stay in the device's last-level cache
+    const int chunk = (cfg.chunk > 0 && cfg.chunk < n_sf) ? cfg.chunk : n_sf;
     Carver cv;
-    const size_t o_x1 = cv.take(sizeof(float2) * npix * n_sf);
+    const size_t o_x1 = cv.take(sizeof(float2) * plane * chunk);
     const size_t o_x2 = cv.take(sizeof(float2) * nspec * n_sf);
     const size_t o_part = cv.take(sizeof(double) * 5 * (size_t)(ny / 2 + 1));
     const size_t o_nm = cv.take(sizeof(double) * 2);
@@ -277,9 +281,14 @@ holo_status ospr_run(int device, const float* target, int64_t nx, int64_t ny, in
     double* part = (double*)(b + o_part);
     double* nm = (double*)(b + o_nm);
     const uint32_t L = lut->n_dev;
-    const uint64_t c0 = cursor % L;
-    LAUNCH("ospr_rows", s, launch_ospr_rows(target, (int)nx, (int)ny, n_sf, lut->dev, L, c0, x1, tw_x, cfg, s));
-    LAUNCH("ospr_cols", s, launch_ospr_cols(x1, (int)nx, (int)ny, n_sf, holo_bits, x2, tw_y, cfg, s));
+    const size_t words = (size_t)nx * (size_t)ny / 32;
+    for (int k0 = 0; k0 < n_sf; k0 += chunk) {
+        const int ns = n_sf - k0 < chunk ? n_sf - k0 : chunk;
+        const uint64_t c0 = (uint64_t)(((unsigned __int128)cursor + (unsigned __int128)k0 * (uint64_t)(nx * ny)) % L);
+        LAUNCH("ospr_rows", s, launch_ospr_rows(target, (int)nx, (int)ny, ns, lut->dev, L, c0, x1, tw_x, cfg, s));
+        LAUNCH("ospr_cols", s, launch_ospr_cols(x1, (int)nx, (int)ny, ns, holo_bits + (size_t)k0 * words,
+                                                x2 + (size_t)k0 * nspec, tw_y, cfg, s));
+    }
     LAUNCH("recon_rows", s, launch_recon_rows(x2, (int)nx, (int)ny, n_sf, true, target, recon, part, tw_x, cfg, s));
     LAUNCH("nmse_finalize", s, launch_nmse_finalize(part, (int)(ny / 2 + 1), nm, s));
     return copy_out(nmse2, nm, 2, flags, s);
@@ -358,16 +367,17 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
     if ((st = get_twiddles(device, (int)a.nx, s, &tw_x))) return st;
     if ((st = get_twiddles(device, (int)a.ny, s, &tw_y))) return st;
     const size_t npix = (size_t)a.nx * (size_t)a.ny;
+    const size_t pitched = (size_t)a.ny * (size_t)row_pitch((int)a.nx, cfg);
     const int n_iter = a.n_iter, ny = (int)a.ny;
     Carver cv;
-    const size_t o_state = cv.take(sizeof(float2) * npix);
+    const size_t o_state = cv.take(sizeof(float2) * pitched);
     const size_t o_field = cv.take(a.field ? 0 : sizeof(float2) * npix);
     const size_t o_pinit = cv.take(sizeof(double) * 2 * ny);
     const size_t o_piter = cv.take(sizeof(double) * 3 * ny * (size_t)n_iter);
     const size_t o_consts = cv.take(sizeof(GsConsts));
     const size_t o_nm = cv.take(sizeof(double) * n_iter);
     const size_t o_er = cv.take(sizeof(double) * n_iter);
-    const size_t o_x2 = cv.take(a.codes ? sizeof(float2) * npix : 0);
+    const size_t o_x2 = cv.take(a.codes ? sizeof(float2) * pitched : 0);
     const size_t o_p5 = cv.take(sizeof(double) * 5 * ny);
     const size_t o_f2 = cv.take(sizeof(double) * 2);
     void* ws;
@@ -391,7 +401,8 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
                       (uintptr_t)(a.init ? 0 : a.cursor % L), (uintptr_t)a.init, (uintptr_t)a.field,
                       (uintptr_t)a.codes, (uintptr_t)(a.final2 != nullptr), (uintptr_t)a.recon, (uintptr_t)ws,
                       (uintptr_t)cfg.cols_per_block, (uintptr_t)cfg.rows_per_block, (uintptr_t)cfg.ksplit,
-                      (uintptr_t)cfg.recon_cols_per_block}};
+                      (uintptr_t)cfg.recon_cols_per_block, (uintptr_t)(intptr_t)cfg.pad,
+                      (uintptr_t)(intptr_t)cfg.chunk}};
         hipGraphExec_t exec = nullptr;
         {
             std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -591,7 +602,8 @@ holo_status holo_reconstruct_nmse(const void* holo, int32_t levels, int64_t nx, 
     const bool half = levels == 2;
     const int nrows = half ? (int)(ny / 2 + 1) : (int)ny;
     Carver cv;
-    const size_t o_x2 = cv.take(sizeof(float2) * (size_t)nrows * nx * n_sf);
+    const LaunchCfg cfg = plan_get(PLAN_OSPR, nx, ny, n_sf);
+    const size_t o_x2 = cv.take(sizeof(float2) * (size_t)nrows * (size_t)row_pitch((int)nx, cfg) * n_sf);
     const size_t o_part = cv.take(sizeof(double) * 5 * (size_t)nrows);
     const size_t o_nm = cv.take(sizeof(double) * 2);
     void* ws;
@@ -600,7 +612,6 @@ holo_status holo_reconstruct_nmse(const void* holo, int32_t levels, int64_t nx, 
     float2* x2 = (float2*)(b + o_x2);
     double* part = (double*)(b + o_part);
     double* nm = (double*)(b + o_nm);
-    const LaunchCfg cfg = plan_get(PLAN_OSPR, nx, ny, n_sf);
     LAUNCH("recon_cols", s, launch_recon_cols(holo, levels, (int)nx, (int)ny, n_sf, x2, tw_y, cfg, s));
     LAUNCH("recon_rows", s, launch_recon_rows(x2, (int)nx, (int)ny, n_sf, half, target, recon, part, tw_x, cfg, s));
     LAUNCH("nmse_finalize", s, launch_nmse_finalize(part, nrows, nm, s));
@@ -679,18 +690,27 @@ holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t ny, int3
     const int cols_opts[] = {8, 16};
     const int rows_opts[] = {1, 2, 4, 8, 16};
     const int ks_opts[] = {1, 2, 4, 8};
-    for (int dim = 0; dim < 3; ++dim) {
-        const int* opts = dim == 0 ? cols_opts : dim == 1 ? rows_opts : ks_opts;
-        const int nopt = dim == 0 ? 2 : dim == 1 ? 5 : 4;
+    const int pad_opts[] = {0, 16, 64};
+    const int chunk_opts[] = {0, 8, 12};
+    // the column pass first (largest), then its neighbours
+    const int order[5] = {0, 4, 1, 2, 3};
+    for (int oi = 0; oi < 5; ++oi) {
+        const int dim = order[oi];
+        const int* opts = dim == 0 ? cols_opts : dim == 1 ? rows_opts : dim == 2 ? ks_opts : dim == 3 ? pad_opts
+                          : chunk_opts;
+        const int nopt = dim == 0 ? 2 : dim == 1 ? 5 : dim == 2 ? 4 : 3;
         for (int i = 0; i < nopt; ++i) {
             LaunchCfg c = best;
-            (dim == 0 ? c.cols_per_block : dim == 1 ? c.rows_per_block : c.ksplit) = opts[i];
+            (dim == 0 ? c.cols_per_block : dim == 1 ? c.rows_per_block : dim == 2 ? c.ksplit : dim == 3 ? c.pad
+             : c.chunk) = opts[i];
             double ms = 0.0;
             if (run(c) != HOLO_OK) continue;
             if ((st = ospr_run(device, target, nx, ny, n_sf, lut, 0, scratch_bits, nullptr, nm, 0, s, c))) continue;
             HIP_TRY(hipMemcpy(bits.data(), scratch_bits, nwords * 4, hipMemcpyDeviceToHost));
-            if (bits != ref_bits || std::fabs(nm[0] - ref_nm[0]) > 1e-9 * std::fabs(ref_nm[0]) ||
-                std::fabs(nm[1] - ref_nm[1]) > 1e-9 * std::fabs(ref_nm[1]))
+            // bits must match exactly; the NMSE may differ by the FP32
+            // summation order of the time average (sub-frame grouping)
+            if (bits != ref_bits || std::fabs(nm[0] - ref_nm[0]) > 1e-6 * std::fabs(ref_nm[0]) ||
+                std::fabs(nm[1] - ref_nm[1]) > 1e-6 * std::fabs(ref_nm[1]))
                 continue;
             if (time_runs(s, reps, [&] { return run(c); }, &ms)) continue;
             if (ms < best_ms) {
@@ -705,6 +725,8 @@ holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t ny, int3
         chosen[1] = best.rows_per_block;
         chosen[2] = best.ksplit;
         chosen[3] = best.recon_cols_per_block;
+        chosen[4] = best.pad;
+        chosen[5] = best.chunk;
     }
     g_err.clear();
     return HOLO_OK;
@@ -740,11 +762,12 @@ holo_status holo_autotune_gs(const float* target, int64_t nx, int64_t ny, const 
         st = time_runs(s, reps, [&] { return run(best); }, &best_ms);
         const int cols_opts[] = {2, 4, 8, 16};
         const int rows_opts[] = {1, 2, 4, 8};
-        for (int dim = 0; dim < 2 && !st; ++dim) {
-            const int* opts = dim == 0 ? cols_opts : rows_opts;
+        const int pad_opts[] = {0, 16, 64, 64};
+        for (int dim = 0; dim < 3 && !st; ++dim) {
+            const int* opts = dim == 0 ? cols_opts : dim == 1 ? rows_opts : pad_opts;
             for (int i = 0; i < 4; ++i) {
                 LaunchCfg c = best;
-                (dim == 0 ? c.cols_per_block : c.rows_per_block) = opts[i];
+                (dim == 0 ? c.cols_per_block : dim == 1 ? c.rows_per_block : c.pad) = opts[i];
                 GsArgs v = a;
                 v.nmse = nm;
                 if (gs_run(device, v, s, c) != HOLO_OK) continue;
@@ -770,6 +793,8 @@ holo_status holo_autotune_gs(const float* target, int64_t nx, int64_t ny, const 
         chosen[1] = best.rows_per_block;
         chosen[2] = best.ksplit;
         chosen[3] = best.recon_cols_per_block;
+        chosen[4] = best.pad;
+        chosen[5] = best.chunk;
     }
     g_err.clear();
     return HOLO_OK;
@@ -783,6 +808,8 @@ holo_status holo_plan_set(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, co
     c.rows_per_block = cfg4[1];
     c.ksplit = cfg4[2];
     c.recon_cols_per_block = cfg4[3];
+    c.pad = cfg4[4];
+    c.chunk = cfg4[5];
     plan_put(kind, nx, ny, n_sf, c);
     return HOLO_OK;
 }
@@ -795,6 +822,8 @@ holo_status holo_plan_get(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, in
     cfg4[1] = c.rows_per_block;
     cfg4[2] = c.ksplit;
     cfg4[3] = c.recon_cols_per_block;
+    cfg4[4] = c.pad;
+    cfg4[5] = c.chunk;
     return HOLO_OK;
 }
 
@@ -807,10 +836,11 @@ holo_status holo_plan_save(const char* path)
     std::fprintf(f, "{\"plans\": [");
     bool first = true;
     for (auto& kv : g_plans) {
-        std::fprintf(f, "%s\n  {\"kind\": %d, \"nx\": %lld, \"ny\": %lld, \"n_sf\": %d, \"cfg\": [%d, %d, %d, %d]}",
+        std::fprintf(f,
+                     "%s\n  {\"kind\": %d, \"nx\": %lld, \"ny\": %lld, \"n_sf\": %d, \"cfg\": [%d, %d, %d, %d, %d, %d]}",
                      first ? "" : ",", kv.first.kind, (long long)kv.first.nx, (long long)kv.first.ny, kv.first.n_sf,
                      kv.second.cols_per_block, kv.second.rows_per_block, kv.second.ksplit,
-                     kv.second.recon_cols_per_block);
+                     kv.second.recon_cols_per_block, kv.second.pad, kv.second.chunk);
         first = false;
     }
     std::fprintf(f, "\n]}\n");
@@ -832,16 +862,18 @@ holo_status holo_plan_load(const char* path)
     size_t pos = 0;
     int loaded = 0;
     while ((pos = txt.find("{\"kind\"", pos)) != std::string::npos) {
-        int kind, sf, c0, c1, c2, c3;
+        int kind, sf, c0, c1, c2, c3, c4, c5;
         long long nx, ny;
         if (std::sscanf(txt.c_str() + pos,
-                        "{\"kind\": %d, \"nx\": %lld, \"ny\": %lld, \"n_sf\": %d, \"cfg\": [%d, %d, %d, %d]}", &kind,
-                        &nx, &ny, &sf, &c0, &c1, &c2, &c3) == 8) {
+                        "{\"kind\": %d, \"nx\": %lld, \"ny\": %lld, \"n_sf\": %d, \"cfg\": [%d, %d, %d, %d, %d, %d]}",
+                        &kind, &nx, &ny, &sf, &c0, &c1, &c2, &c3, &c4, &c5) == 10) {
             LaunchCfg c;
             c.cols_per_block = c0;
             c.rows_per_block = c1;
             c.ksplit = c2;
             c.recon_cols_per_block = c3;
+            c.pad = c4;
+            c.chunk = c5;
             plan_put(kind, nx, ny, sf, c);
             ++loaded;
         } else {

@@ -13,7 +13,18 @@ struct LaunchCfg {
     int rows_per_block = 0;        // row transforms per block (OSPR K1, GS rows)
     int ksplit = 0;                // sub-frame groups per reconstruction-row block
     int recon_cols_per_block = 0;  // C of the reconstruction column pass
+    int pad = -1;                  // extra elements per row of internal fields (-1 = heuristic)
+    int chunk = 0;                 // OSPR sub-frames per generation chunk (0 = all at once)
 };
+
+// Row pitch (complex elements) of the library's internal [rows][nx] fields:
+// power-of-two row strides make column passes hit few memory channels, so a
+// small pad is added (planned, or 16 elements for nx >= 256).
+inline int row_pitch(int nx, const LaunchCfg& c)
+{
+    const int pad = c.pad >= 0 ? c.pad : (nx >= 256 ? 16 : 0);
+    return nx + pad;
+}
 
 // Column-tile width for a column pass of length n over ncols columns and
 // nbatch independent fields (see the definition for the rule).

@@ -52,7 +52,7 @@ namespace holo {
 // Runtime LDS addressing (block shape chosen at launch).
 struct RowAddrR {
     int base;
-    __device__ __forceinline__ int operator()(int e) const { return base + lds_pad(e); }
+    __device__ __forceinline__ int operator()(int p) const { return base + p; }
 };
 
 static int row_block_rows(int n, int nrows, int planned)
@@ -194,7 +194,8 @@ hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int n
 template <int NX>
 __global__ __launch_bounds__(1024) void k_ospr_rows(const float* __restrict__ target, int ny,
                                                     const float2* __restrict__ lut, uint32_t n_lut, uint64_t c0,
-                                                    float2* __restrict__ x1, const float2* __restrict__ tw)
+                                                    float2* __restrict__ x1, const float2* __restrict__ tw,
+                                                    int pitch)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NX / kP;
@@ -207,20 +208,24 @@ __global__ __launch_bounds__(1024) void k_ospr_rows(const float* __restrict__ ta
     // Cyclic LUT address of pixel (t, y) in sub-frame k; then +T per slot.
     uint32_t idx = (uint32_t)((c0 + (uint64_t)k * npix + (uint64_t)y * NX + (uint64_t)t) % n_lut);
     const uint32_t step = (uint32_t)(T % n_lut);
-    const float* trow = target + (size_t)y * NX;
+    const auto rt = make_rsrc(target, (uint32_t)(npix * 4));
+    const auto rl = make_rsrc(lut, n_lut * 8u);
+    const uint32_t toff = ((uint32_t)y * NX + (uint32_t)t) * 4u;
     float2 v[kP];
 #pragma unroll
     for (int m = 0; m < kP; ++m) {
-        const float a = trow[t + T * m];
-        const float2 ph = lut[idx];
+        const float a = buf_ld1(rt, toff, (uint32_t)(m * T * 4));
+        const float2 ph = buf_ld2(rl, idx * 8u, 0);
         v[m] = make_float2(a * ph.x, a * ph.y);
         idx += step;
         if (idx >= n_lut) idx -= n_lut;
     }
     fft_stages<NX, 1>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, tw);
-    float2* dst = x1 + (size_t)k * npix + (size_t)y * NX;
+    const size_t plane = (size_t)ny * pitch;
+    const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
+    const uint32_t ooff = ((uint32_t)y * (uint32_t)pitch + (uint32_t)t) * 8u;
 #pragma unroll
-    for (int m = 0; m < kP; ++m) dst[t + T * m] = v[m];
+    for (int m = 0; m < kP; ++m) buf_st2(ro, ooff, (uint32_t)(m * T * 8), v[m]);
 }
 
 hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const float2* lut,
@@ -233,7 +238,7 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
         size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
         allow_lds(k_ospr_rows<N_>, lds);
         hipLaunchKernelGGL((k_ospr_rows<N_>), dim3((ny / rows) * n_sf), dim3(rows * T), lds, s, target, ny, lut,
-                           n_lut, c0, x1, tw_x);
+                           n_lut, c0, x1, tw_x, row_pitch(nx, cfg));
     });
     return hipGetLastError();
 }
@@ -248,7 +253,7 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
 template <int NY, int C>
 __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __restrict__ x1, int nx,
                                                             uint32_t* __restrict__ bits, float2* __restrict__ x2,
-                                                            const float2* __restrict__ tw)
+                                                            const float2* __restrict__ tw, int pitch)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NY / kP;
@@ -259,35 +264,39 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __res
     const int k = tile / ncb;
     const int x0 = (tile - k * ncb) * C;
     const size_t npix = (size_t)nx * NY;
-    const size_t mstride = (size_t)T * nx;
-    const uint32_t toff = ((uint32_t)t * (uint32_t)nx + (uint32_t)c) * (uint32_t)sizeof(float2);
-    const float2* src = x1 + (size_t)k * npix + x0;
+    // one descriptor per sub-frame plane; lane offset (t*pitch + x0 + c)*8
+    // bytes, slot m adds the uniform m*T*pitch*8
+    const size_t plane = (size_t)NY * pitch;
+    const uint32_t voff = ((uint32_t)t * (uint32_t)pitch + (uint32_t)(x0 + c)) * 8u;
+    const uint32_t mst = (uint32_t)T * (uint32_t)pitch * 8u;
+    const auto rin = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
     float2 v[kP];
 #pragma unroll
-    for (int m = 0; m < kP; ++m) v[m] = ld_off(src + m * mstride, toff);
+    for (int m = 0; m < kP; ++m) v[m] = buf_ld2(rin, voff, m * mst);
     fft_stages<NY, 1>(v, t, lds, ColAddr<C>{c}, tw);
 
     // nearest of {+1, -1}: bit = (Re H < 0); Re H = 0 -> +1
-    uint8_t* bits8 = reinterpret_cast<uint8_t*>(bits + (size_t)k * (npix / 32)) + x0 / 8;
-    const uint32_t boff = (uint32_t)t * (uint32_t)(nx / 8);
+    const auto rbits = make_rsrc(bits + (size_t)k * (npix / 32), (uint32_t)(npix / 8));
+    const uint32_t boff = ((uint32_t)t * (uint32_t)nx + (uint32_t)x0) / 8u;
+    const uint32_t bst = (uint32_t)T * (uint32_t)nx / 8u;
 #pragma unroll
     for (int m = 0; m < kP; ++m) {
         const bool neg = v[m].x < 0.0f;
         const uint64_t mask = __ballot(neg);
         if (c == 0) {
             const uint32_t chunk = (uint32_t)(mask >> (lane & ~(C - 1)));
-            uint8_t* row = bits8 + (size_t)m * T * (nx / 8);
-            if (C == 16) st_off(reinterpret_cast<uint16_t*>(row), boff, (uint16_t)chunk);
-            else st_off(row, boff, (uint8_t)chunk);
+            if (C == 16) __builtin_amdgcn_raw_buffer_store_b16((unsigned short)chunk, rbits, boff, m * bst, 0);
+            else __builtin_amdgcn_raw_buffer_store_b8((unsigned char)chunk, rbits, boff, m * bst, 0);
         }
         v[m] = make_float2(neg ? -1.0f : 1.0f, 0.0f);
     }
     fft_stages<NY, -1>(v, t, lds, ColAddr<C>{c}, tw);
     // rows v = t + T*m <= NY/2: every slot m < 8, and m = 8 for t = 0 only
-    float2* dst = x2 + (size_t)k * (NY / 2 + 1) * nx + x0;
+    const size_t hplane = (size_t)(NY / 2 + 1) * pitch;
+    const auto rout = make_rsrc(x2 + (size_t)k * hplane, (uint32_t)(hplane * 8));
 #pragma unroll
-    for (int m = 0; m < kP / 2; ++m) st_off(dst + m * mstride, toff, v[m]);
-    if (t == 0) st_off(dst + (kP / 2) * mstride, toff, v[kP / 2]);
+    for (int m = 0; m < kP / 2; ++m) buf_st2(rout, voff, m * mst, v[m]);
+    if (t == 0) buf_st2(rout, voff, (kP / 2) * mst, v[kP / 2]);
 }
 
 hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
@@ -300,7 +309,7 @@ hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t
             size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
             allow_lds(k_ospr_cols<N_, C_>, lds);
             hipLaunchKernelGGL((k_ospr_cols<N_, C_>), dim3((nx / C_) * n_sf), dim3(C_ * T), lds, s, x1, nx, bits,
-                               x2, tw_y);
+                               x2, tw_y, row_pitch(nx, cfg));
         }
     }));
     return hipGetLastError();
@@ -328,7 +337,8 @@ __device__ __forceinline__ float2 level8_phasor(int m)
 
 template <int NY, int C>
 __global__ __launch_bounds__(C * (NY / kP)) void k_recon_cols(const void* __restrict__ holo, int levels, int nx,
-                                                             float2* __restrict__ x2, const float2* __restrict__ tw)
+                                                             float2* __restrict__ x2, const float2* __restrict__ tw,
+                                                             int pitch)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NY / kP;
@@ -355,11 +365,11 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_recon_cols(const void* __rest
     }
     fft_stages<NY, -1>(v, t, lds, ColAddr<C>{c}, tw);
     const int vmax = levels == 2 ? NY / 2 : NY - 1;
-    float2* dst = x2 + (size_t)k * (vmax + 1) * nx;
+    float2* dst = x2 + (size_t)k * (vmax + 1) * pitch;
 #pragma unroll
     for (int m = 0; m < kP; ++m) {
         const int vv = t + T * m;
-        if (vv <= vmax) dst[(size_t)vv * nx + x] = v[m];
+        if (vv <= vmax) dst[(size_t)vv * pitch + x] = v[m];
     }
 }
 
@@ -373,7 +383,7 @@ hipError_t launch_recon_cols(const void* holo, int levels, int nx, int ny, int n
             size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
             allow_lds(k_recon_cols<N_, C_>, lds);
             hipLaunchKernelGGL((k_recon_cols<N_, C_>), dim3((nx / C_) * n_sf), dim3(C_ * T), lds, s, holo, levels,
-                               nx, x2, tw_y);
+                               nx, x2, tw_y, row_pitch(nx, cfg));
         }
     }));
     return hipGetLastError();
@@ -391,7 +401,7 @@ template <int NX>
 __global__ __launch_bounds__(512) void k_recon_rows(const float2* __restrict__ x2, int ny, int n_sf, int half,
                                                      const float* __restrict__ target, float* __restrict__ recon,
                                                      double* __restrict__ partials, const float2* __restrict__ tw,
-                                                     float inv_scale)
+                                                     float inv_scale, int pitch)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NX / kP;
@@ -399,20 +409,21 @@ __global__ __launch_bounds__(512) void k_recon_rows(const float2* __restrict__ x
     const int g = threadIdx.x / T, t = threadIdx.x % T;
     const int v_row = blockIdx.x;
     const int nrows_spec = half ? (ny / 2 + 1) : ny;
-    const size_t sf_stride = (size_t)nrows_spec * NX;
+    const size_t sf_stride = (size_t)nrows_spec * pitch;
     float acc[kP];
 #pragma unroll
     for (int m = 0; m < kP; ++m) acc[m] = 0.0f;
     const int rounds = (n_sf + G - 1) / G;
     // software pipeline: the next sub-frame's row is in flight while the
     // current one is transformed (LDS barriers do not wait on global loads)
+    // descriptor over all sub-frames' spectra; loads of sub-frames k >= n_sf
+    // fall outside it and read as zero
+    const auto rx = make_rsrc(x2, (uint32_t)(sf_stride * (size_t)n_sf * 8));
+    const uint32_t roff = ((uint32_t)v_row * (uint32_t)pitch + (uint32_t)t) * 8u;
+    const uint32_t kst = (uint32_t)(sf_stride * 8);
     float2 nxt[kP];
-    {
-        const bool valid = g < n_sf;
-        const float2* src = x2 + (size_t)(valid ? g : 0) * sf_stride + (size_t)v_row * NX;
 #pragma unroll
-        for (int m = 0; m < kP; ++m) nxt[m] = valid ? src[t + T * m] : make_float2(0.0f, 0.0f);
-    }
+    for (int m = 0; m < kP; ++m) nxt[m] = buf_ld2(rx, roff + (uint32_t)g * kst, (uint32_t)(m * T * 8));
     for (int r = 0; r < rounds; ++r) {
         const int k = r * G + g;
         const bool valid = k < n_sf;
@@ -420,11 +431,9 @@ __global__ __launch_bounds__(512) void k_recon_rows(const float2* __restrict__ x
 #pragma unroll
         for (int m = 0; m < kP; ++m) v[m] = nxt[m];
         if (r + 1 < rounds) {
-            const int kn = k + G;
-            const bool vn = kn < n_sf;
-            const float2* src = x2 + (size_t)(vn ? kn : 0) * sf_stride + (size_t)v_row * NX;
+            const uint32_t ko = (uint32_t)(k + G) * kst;
 #pragma unroll
-            for (int m = 0; m < kP; ++m) nxt[m] = vn ? src[t + T * m] : make_float2(0.0f, 0.0f);
+            for (int m = 0; m < kP; ++m) nxt[m] = buf_ld2(rx, roff + ko, (uint32_t)(m * T * 8));
         }
         fft_stages<NX, -1>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, tw);
         if (valid) {
@@ -501,7 +510,7 @@ hipError_t launch_recon_rows(const float2* x2, int nx, int ny, int n_sf, bool ha
         const float inv_scale = (float)(1.0 / ((double)n_sf * (double)nx * (double)ny));
         allow_lds(k_recon_rows<N_>, lds);
         hipLaunchKernelGGL((k_recon_rows<N_>), dim3(nrows_spec), dim3(G * T), lds, s, x2, ny, n_sf, half ? 1 : 0,
-                           target, recon, partials, tw_x, inv_scale);
+                           target, recon, partials, tw_x, inv_scale, row_pitch(nx, cfg));
     });
     return hipGetLastError();
 }
