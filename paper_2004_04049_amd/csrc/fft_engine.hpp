@@ -207,7 +207,24 @@ __device__ __forceinline__ void stage_butterfly(float2 (&v)[kP], int t, int b, i
 // share the engine.  `tw` is the FP32 table W_N^k; SIGN = -1 for Eq. (1),
 // +1 for Eq. (2).  Contains __syncthreads(): every thread of the block must
 // call it the same number of times.
-template <int N, int SIGN, typename Addr>
+// Synchronisation of an LDS exchange.  When every transform lives inside one
+// wave (T <= 64 threads, aligned groups), the exchange is private to the wave:
+// a wave's LDS operations execute in order, so only the compiler must be kept
+// from moving them, and waves of a block stay free to run different phases.
+// Otherwise the block barrier is needed.
+template <bool WAVE_LOCAL>
+__device__ __forceinline__ void exchange_sync()
+{
+    if (WAVE_LOCAL) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <int N, int SIGN, typename Addr, bool WAVE_LOCAL = false>
 __device__ __forceinline__ void fft_stages(float2 (&v)[kP], int t, float2* lds, Addr addr,
                                            const float2* __restrict__ tw)
 {
@@ -244,7 +261,7 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[kP], int t, float2* lds, 
 #pragma unroll
                 for (int r = 0; r < R; ++r) lds[addr(pb + r * ps)] = v[b + r * nb];
             }
-            __syncthreads();
+            exchange_sync<WAVE_LOCAL>();
             if (T % 16 == 0) {
                 const int pt = lds_pad(t);
 #pragma unroll
@@ -253,7 +270,7 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[kP], int t, float2* lds, 
 #pragma unroll
                 for (int m = 0; m < kP; ++m) v[m] = lds[addr(lds_pad(t + T * m))];
             }
-            __syncthreads();
+            exchange_sync<WAVE_LOCAL>();
         }
         Ns *= R;
     }

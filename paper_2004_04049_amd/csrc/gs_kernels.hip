@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_gs_rows(const float* __restrict__ targe
             s2 += q;
             s4 += q * q;
         }
-        fft_stages<NX, 1>(v, t, lds, RowAddrG{row * PadLen<NX>::v}, tw);
+        fft_stages<NX, 1, RowAddrG, (NX / kP <= 64)>(v, t, lds, RowAddrG{row * PadLen<NX>::v}, tw);
 #pragma unroll
         for (int m = 0; m < kP; ++m) srow[t + T * m] = v[m];
         double a2[2] = {s2, s4};
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_gs_rows(const float* __restrict__ targe
 
 #pragma unroll
     for (int m = 0; m < kP; ++m) v[m] = srow[t + T * m];
-    fft_stages<NX, -1>(v, t, lds, RowAddrG{row * PadLen<NX>::v}, tw);
+    fft_stages<NX, -1, RowAddrG, (NX / kP <= 64)>(v, t, lds, RowAddrG{row * PadLen<NX>::v}, tw);
     // R' (unscaled) = sqrt(N) * R'_unitary; intensity in unitary units
     const float inv_n = 1.0f / (float)((size_t)NX * (size_t)ny);
     const float inv_sqrt_n = (float)(1.0 / sqrt((double)NX * (double)ny));
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_gs_rows(const float* __restrict__ targe
             const float mag = sqrtf(v[m].x * v[m].x + v[m].y * v[m].y);
             v[m] = mag > 0.0f ? make_float2(ta[m] * (v[m].x / mag), ta[m] * (v[m].y / mag)) : make_float2(ta[m], 0.0f);
         }
-        fft_stages<NX, 1>(v, t, lds, RowAddrG{row * PadLen<NX>::v}, tw);
+        fft_stages<NX, 1, RowAddrG, (NX / kP <= 64)>(v, t, lds, RowAddrG{row * PadLen<NX>::v}, tw);
 #pragma unroll
         for (int m = 0; m < kP; ++m) srow[t + T * m] = v[m];
     }

@@ -265,8 +265,11 @@ holo_status ospr_run(int device, const float* target, int64_t nx, int64_t ny, in
     const size_t pitch = (size_t)row_pitch((int)nx, cfg);
     const size_t plane = (size_t)ny * pitch;
     const size_t nspec = (size_t)(ny / 2 + 1) * pitch;
-    // sub-frames generated per chunk: the chunk's complex planes are reused,
-    // so a chunk's intermediates can stay in the device's last-level cache
+    // Sub-frames are generated in chunks that reuse one set of intermediate
+    // planes, so a chunk's planes can stay in the last-level cache between the
+    // row pass that writes them and the column pass that reads them.  (Running
+    // chunks concurrently on two streams was measured slower: the doubled
+    // working set no longer fits that cache.)
     const int chunk = (cfg.chunk > 0 && cfg.chunk < n_sf) ? cfg.chunk : n_sf;
     Carver cv;
     const size_t o_x1 = cv.take(sizeof(float2) * plane * chunk);
@@ -687,37 +690,51 @@ holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t ny, int3
     if ((st = time_runs(s, reps, [&] { return run(best); }, &best_ms))) return st;
     // coordinate descent over each kernel's shape; a candidate counts only if
     // it reproduces the reference holograms bit for bit and its NMSE
+    // a candidate counts only if it reproduces the reference holograms bit for
+    // bit; its NMSE may differ by the FP32 summation order of the average
+    auto try_plan = [&](const LaunchCfg& c) {
+        double ms = 0.0;
+        if (run(c) != HOLO_OK) return;
+        if (ospr_run(device, target, nx, ny, n_sf, lut, 0, scratch_bits, nullptr, nm, 0, s, c)) return;
+        if (hipMemcpy(bits.data(), scratch_bits, nwords * 4, hipMemcpyDeviceToHost) != hipSuccess) return;
+        if (bits != ref_bits || std::fabs(nm[0] - ref_nm[0]) > 1e-6 * std::fabs(ref_nm[0]) ||
+            std::fabs(nm[1] - ref_nm[1]) > 1e-6 * std::fabs(ref_nm[1]))
+            return;
+        if (time_runs(s, reps, [&] { return run(c); }, &ms)) return;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    };
+    // column-tile width and chunking interact (tile lines vs cache residency):
+    // search them jointly, then the remaining shapes one at a time
     const int cols_opts[] = {8, 16};
-    const int rows_opts[] = {1, 2, 4, 8, 16};
+    const int chunk_opts[] = {0, 4, 6, 8, 12};
+    const LaunchCfg base = best;
+    for (int ci : cols_opts)
+        for (int ch : chunk_opts) {
+            LaunchCfg c = base;
+            c.cols_per_block = ci;
+            c.chunk = ch;
+            try_plan(c);
+        }
+    const int rows_opts[] = {1, 2, 4, 8};
     const int ks_opts[] = {1, 2, 4, 8};
     const int pad_opts[] = {0, 16, 64};
-    const int chunk_opts[] = {0, 8, 12};
-    // the column pass first (largest), then its neighbours
-    const int order[5] = {0, 4, 1, 2, 3};
-    for (int oi = 0; oi < 5; ++oi) {
-        const int dim = order[oi];
-        const int* opts = dim == 0 ? cols_opts : dim == 1 ? rows_opts : dim == 2 ? ks_opts : dim == 3 ? pad_opts
-                          : chunk_opts;
-        const int nopt = dim == 0 ? 2 : dim == 1 ? 5 : dim == 2 ? 4 : 3;
-        for (int i = 0; i < nopt; ++i) {
-            LaunchCfg c = best;
-            (dim == 0 ? c.cols_per_block : dim == 1 ? c.rows_per_block : dim == 2 ? c.ksplit : dim == 3 ? c.pad
-             : c.chunk) = opts[i];
-            double ms = 0.0;
-            if (run(c) != HOLO_OK) continue;
-            if ((st = ospr_run(device, target, nx, ny, n_sf, lut, 0, scratch_bits, nullptr, nm, 0, s, c))) continue;
-            HIP_TRY(hipMemcpy(bits.data(), scratch_bits, nwords * 4, hipMemcpyDeviceToHost));
-            // bits must match exactly; the NMSE may differ by the FP32
-            // summation order of the time average (sub-frame grouping)
-            if (bits != ref_bits || std::fabs(nm[0] - ref_nm[0]) > 1e-6 * std::fabs(ref_nm[0]) ||
-                std::fabs(nm[1] - ref_nm[1]) > 1e-6 * std::fabs(ref_nm[1]))
-                continue;
-            if (time_runs(s, reps, [&] { return run(c); }, &ms)) continue;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = c;
-            }
-        }
+    for (int r : rows_opts) {
+        LaunchCfg c = best;
+        c.rows_per_block = r;
+        try_plan(c);
+    }
+    for (int k : ks_opts) {
+        LaunchCfg c = best;
+        c.ksplit = k;
+        try_plan(c);
+    }
+    for (int p : pad_opts) {
+        LaunchCfg c = best;
+        c.pad = p;
+        try_plan(c);
     }
     plan_put(PLAN_OSPR, nx, ny, n_sf, best);
     if (chosen) {

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(1024) void k_fft_rows(const float2* __restrict__ in
     const float2* src = in + y * N;
 #pragma unroll
     for (int m = 0; m < kP; ++m) v[m] = src[t + T * m];
-    fft_stages<N, SIGN>(v, t, lds, RowAddrR{row * PadLen<N>::v}, tw);
+    fft_stages<N, SIGN, RowAddrR, (N / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<N>::v}, tw);
     float2* dst = out + y * N;
 #pragma unroll
     for (int m = 0; m < kP; ++m) dst[t + T * m] = v[m];
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(1024) void k_ospr_rows(const float* __restrict__ ta
         idx += step;
         if (idx >= n_lut) idx -= n_lut;
     }
-    fft_stages<NX, 1>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, tw);
+    fft_stages<NX, 1, RowAddrR, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, tw);
     const size_t plane = (size_t)ny * pitch;
     const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
     const uint32_t ooff = ((uint32_t)y * (uint32_t)pitch + (uint32_t)t) * 8u;
@@ -435,15 +435,17 @@ __global__ __launch_bounds__(512) void k_recon_rows(const float2* __restrict__ x
 #pragma unroll
             for (int m = 0; m < kP; ++m) nxt[m] = buf_ld2(rx, roff + ko, (uint32_t)(m * T * 8));
         }
-        fft_stages<NX, -1>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, tw);
+        fft_stages<NX, -1, RowAddrR, (NX / kP <= 64)>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, tw);
         if (valid) {
 #pragma unroll
             for (int m = 0; m < kP; ++m) acc[m] = fmaf(v[m].x, v[m].x, fmaf(v[m].y, v[m].y, acc[m]));
         }
     }
-    // combine the G groups' sums (group order fixed)
+    // combine the G groups' sums (group order fixed); the groups' transforms
+    // synchronise per wave, so wait for all of them before reusing LDS
     float* ldsf = reinterpret_cast<float*>(lds);
     if (G > 1) {
+        __syncthreads();
 #pragma unroll
         for (int m = 0; m < kP; ++m) ldsf[g * NX + t + T * m] = acc[m];
         __syncthreads();
