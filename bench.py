@@ -41,19 +41,22 @@ def parse():
     return ap.parse_args()
 
 
-def ospr_kernel_bytes(nx, ny, n_sf, n_lut):
+def ospr_kernel_bytes(nx, ny, n_sf, n_lut, chunk=0):
     """Algorithmic HBM bytes per launch of each OSPR kernel, from the per-pixel
     byte model of the three-pass design (per sub-frame: K1 writes the complex
     field, 8 B/px; K2 reads it, 8 B/px, writes the packed bits, 1/8 B/px, and the
     complex reconstruction column spectrum, 8 B/px; K3 reads that, 8 B/px; the
     target, 4 B/px, is read once per frame by K1 and once by K3).  A LUT of more
     than 2^16 entries cannot stay cache-resident, so its unique entries read
-    (8 B each) are charged to K1."""
+    (8 B each) are charged to K1.  With a chunked plan, K1 and K2 launch once
+    per chunk of `chunk` sub-frames; the figures are per launch (per-frame
+    terms prorated over the chunks)."""
     n = nx * ny
+    per = chunk if 0 < chunk < n_sf else n_sf
     lut_bytes = 8 * min(n_lut, n * n_sf) if n_lut > 65536 else 0
     return {
-        "ospr_rows": n_sf * n * 8 + n * 4 + lut_bytes,
-        "ospr_cols": n_sf * n * (8 + 0.125 + 8),
+        "ospr_rows": per * n * 8 + (n * 4 + lut_bytes) * per / n_sf,
+        "ospr_cols": per * n * (8 + 0.125 + 8),
         "recon_rows": n_sf * n * 8 + n * 4,
     }
 
@@ -142,7 +145,7 @@ def main():
     t3 = time.perf_counter()
     h.prof_enable(False)
 
-    kbytes = ospr_kernel_bytes(nx, ny, n_sf, n_lut)
+    kbytes = ospr_kernel_bytes(nx, ny, n_sf, n_lut, plan[5])
     kern = {}
     for k in ("ospr_rows", "ospr_cols", "recon_rows", "nmse_finalize"):
         ms, cnt = h.prof_read(k)
@@ -156,7 +159,7 @@ def main():
             kern[k]["algorithmic_GBps"] = kbytes[k] / (kern[k]["avg_us"] * 1e-6) / 1e9
     workload = f"ospr_{nx}x{ny}_sf{n_sf}_lut{n_lut}"
     traffic = measured_traffic(dom, workload)
-    step_bytes = sum(kbytes.values())
+    step_bytes = sum(ospr_kernel_bytes(nx, ny, n_sf, n_lut).values())
     roofline = {
         "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -175,6 +178,7 @@ def main():
     }
 
     if not args.no_extras:
+        out["batched"] = bench_batched(h, synth, torch, dev)
         out["gs"] = bench_gs(h, synth, torch, dev)
         out["lut_sweep"] = bench_lut_sweep(h, synth, torch, dev, target, nx, ny, n_sf)
     if not args.no_cpu:
@@ -186,6 +190,33 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
     print(json.dumps(out), flush=True)
+
+
+def bench_batched(h, synth, torch, dev):
+    """64 frames, sizes uniform over {256, 512, 1024, 2048}^2, n_sf uniform in
+    8..24 (seed 14), targets seeds 1000+f, LUT 10007 chained across frames, one
+    graph launch per batch."""
+    layout = synth.batch_layout(64, synth.SEED_BATCH)
+    targets = [torch.from_numpy(synth.blob_target(n, n, synth.SEED_BATCH_TARGET0 + f)).to(dev)
+               for f, (n, _) in enumerate(layout)]
+    nsfs = [k for _, k in layout]
+    lut = h.Lut(10007, synth.SEED_LUT)
+    nm = torch.zeros((64, 2), dtype=torch.float64, device=dev)
+    bits, _, c = h.ospr_generate_batched(targets, nsfs, lut, 0, nmse_out=nm)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bits, _, c = h.ospr_generate_batched(targets, nsfs, lut, c, bits=bits, nmse_out=nm)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    pxsf = sum(n * n * k for n, k in layout)
+    canon = sum(n * n * (k * 32.125 + 8) for n, k in layout)
+    return {"frames": 64, "px_subframes": pxsf, "ms_per_batch": round(1e3 * dt, 3),
+            "px_subframes_per_s": round(pxsf / dt, 1), "canonical_GB": round(canon / 1e9, 3),
+            "hbm_frac": round(canon / dt / 1e9 / HBM_PEAK_GBS, 4), "dtype": "f32",
+            "sizes": {str(s_): sum(1 for n, _ in layout if n == s_) for s_ in (256, 512, 1024, 2048)},
+            "nmse_mean": float(nm[:, 0].mean().item())}
 
 
 def bench_gs(h, synth, torch, dev):

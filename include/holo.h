@@ -159,6 +159,37 @@ HOLO_API holo_status holo_reconstruct_nmse(const void* holo, int32_t levels, int
                                            uint32_t flags, void* hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * holo_ospr_generate_batched -- many OSPR frames of uneven size in one call,
+ * each exactly as holo_ospr_generate would compute it with the pool cursor
+ * continuing from frame to frame in array order (Section 5: frames continue
+ * where the previous left off): frame f starts at *cursor + sum over g < f of
+ * n_sf_g * nx_g * ny_g, and *cursor advances by the total.
+ *   frames    host array of n_frames (1..4096) descriptors; every pointer in
+ *             them is a device pointer owned by the caller
+ *   nmse_out  [n_frames][2] {NMSE, NMSE_sym} per frame, host (complete on
+ *             return) or device with HOLO_F_NMSE_DEVICE, or NULL
+ * The device work of a batch is captured once into a HIP graph whose frames
+ * run on four concurrent branches (longest frames first) and replayed with
+ * one graph launch per call while the frame list, plans and buffers are
+ * unchanged; the moving cursor is read from device memory, so replays need
+ * no re-capture.  On the legacy default stream, or while kernel timing is on,
+ * the frames are launched directly instead.
+ * Errors: HOLO_EINVAL (null frames/cursor/target/bits, n_sf < 1, n_frames out
+ * of range), HOLO_EUNSUPPORTED (sizes, precision not built).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t nx, ny;
+    int32_t n_sf;
+    const float* target;  /* device float[ny][nx]                        */
+    uint32_t* holo_bits;  /* device uint32[n_sf][nx*ny/32], as above     */
+    float* recon;         /* device float[ny][nx] time average, or NULL  */
+} holo_frame;
+
+HOLO_API holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frames, const holo_lut* lut,
+                                                uint64_t* cursor, double* nmse_out, int32_t precision,
+                                                uint32_t flags, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
  * holo_fft2 -- the unitary transform pair itself: Eq. (1) for sign = -1,
  * Eq. (2) for sign = +1, complex [ny][nx] device in -> device out (may alias).
  * ------------------------------------------------------------------------- */

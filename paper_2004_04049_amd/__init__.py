@@ -51,7 +51,14 @@ SIGNATURES = {
     "holo_plan_save": (_I32, [C.c_char_p]),
     "holo_plan_load": (_I32, [C.c_char_p]),
     "holo_set_graphs": (_I32, [_I32]),
+    "holo_ospr_generate_batched": (_I32, [_P, _I32, _P, C.POINTER(_U64), _P, _I32, _U32, _P]),
 }
+
+
+class HoloFrame(C.Structure):
+    """holo_frame: one frame of a batched OSPR call (device pointers)."""
+    _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("n_sf", C.c_int32), ("target", C.c_void_p),
+                ("holo_bits", C.c_void_p), ("recon", C.c_void_p)]
 
 
 class HoloError(RuntimeError):
@@ -318,3 +325,35 @@ def plan_load(path: str):
 
 def set_graphs(on: bool):
     _check(lib().holo_set_graphs(1 if on else 0))
+
+
+def ospr_generate_batched(targets, n_sfs, lut: Lut, cursor: int, bits=None, recons=None, nmse_out=None,
+                          stream=None):
+    """holo_ospr_generate_batched.  targets: list of cuda float32 [ny, nx];
+    n_sfs: list of sub-frame counts; bits: list of int32 [n_sf, nx*ny/32]
+    (allocated if None).  Returns (bits list, nmse [n, 2] or None, cursor).
+    nmse_out: cuda float64 [n, 2] keeps the NMSE on the device."""
+    import numpy as np
+    n = len(targets)
+    if bits is None:
+        bits = [torch.empty((k, t.shape[0] * t.shape[1] // 32), dtype=torch.int32, device=t.device)
+                for t, k in zip(targets, n_sfs)]
+    arr = (HoloFrame * n)()
+    for i, (t, k, b) in enumerate(zip(targets, n_sfs, bits)):
+        _dev(t, torch.float32, None, "target")
+        ny, nx = t.shape
+        _dev(b, torch.int32, (k, nx * ny // 32), "bits")
+        r = recons[i] if recons is not None else None
+        if r is not None:
+            _dev(r, torch.float32, (ny, nx), "recon")
+        arr[i] = HoloFrame(nx, ny, k, t.data_ptr(), b.data_ptr(), r.data_ptr() if r is not None else None)
+    if nmse_out is not None:
+        _dev(nmse_out, torch.float64, (n, 2), "nmse_out")
+        nm, nm_p, flags = nmse_out, C.c_void_p(nmse_out.data_ptr()), F_NMSE_DEVICE
+    else:
+        nm = np.zeros((n, 2))
+        nm_p, flags = nm.ctypes.data_as(C.c_void_p), 0
+    cur = C.c_uint64(cursor)
+    _check(lib().holo_ospr_generate_batched(C.cast(arr, C.c_void_p), n, lut.handle, C.byref(cur), nm_p, FP32,
+                                            flags, _stream(stream)))
+    return bits, nm, int(cur.value)

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -254,14 +255,15 @@ void plan_put(int kind, int64_t nx, int64_t ny, int n_sf, const LaunchCfg& c)
 // ---------------------------------------------------------------------------
 // OSPR frame: K1 -> K2 -> K3 -> K4 on stream s with launch shapes `cfg`.
 // ---------------------------------------------------------------------------
-holo_status ospr_run(int device, const float* target, int64_t nx, int64_t ny, int n_sf, const holo_lut* lut,
-                     uint64_t cursor, uint32_t* holo_bits, float* recon, double* nmse2, uint32_t flags,
-                     hipStream_t s, const LaunchCfg& cfg)
+// Workspace of one OSPR frame: intermediate planes and reduction scratch.
+struct OsprLayout {
+    size_t o_x1, o_x2, o_part, o_nm, bytes;
+    int chunk;
+};
+
+OsprLayout ospr_layout(int64_t nx, int64_t ny, int n_sf, const LaunchCfg& cfg)
 {
-    holo_status st;
-    const float2 *tw_x, *tw_y;
-    if ((st = get_twiddles(device, (int)nx, s, &tw_x))) return st;
-    if ((st = get_twiddles(device, (int)ny, s, &tw_y))) return st;
+    OsprLayout l;
     const size_t pitch = (size_t)row_pitch((int)nx, cfg);
     const size_t plane = (size_t)ny * pitch;
     const size_t nspec = (size_t)(ny / 2 + 1) * pitch;
@@ -270,30 +272,60 @@ holo_status ospr_run(int device, const float* target, int64_t nx, int64_t ny, in
     // row pass that writes them and the column pass that reads them.  (Running
     // chunks concurrently on two streams was measured slower: the doubled
     // working set no longer fits that cache.)
-    const int chunk = (cfg.chunk > 0 && cfg.chunk < n_sf) ? cfg.chunk : n_sf;
+    l.chunk = (cfg.chunk > 0 && cfg.chunk < n_sf) ? cfg.chunk : n_sf;
     Carver cv;
-    const size_t o_x1 = cv.take(sizeof(float2) * plane * chunk);
-    const size_t o_x2 = cv.take(sizeof(float2) * nspec * n_sf);
-    const size_t o_part = cv.take(sizeof(double) * 5 * (size_t)(ny / 2 + 1));
-    const size_t o_nm = cv.take(sizeof(double) * 2);
-    void* ws;
-    if ((st = get_workspace(device, s, cv.off, &ws))) return st;
-    char* b = (char*)ws;
-    float2* x1 = (float2*)(b + o_x1);
-    float2* x2 = (float2*)(b + o_x2);
-    double* part = (double*)(b + o_part);
-    double* nm = (double*)(b + o_nm);
+    l.o_x1 = cv.take(sizeof(float2) * plane * l.chunk);
+    l.o_x2 = cv.take(sizeof(float2) * nspec * n_sf);
+    l.o_part = cv.take(sizeof(double) * 5 * (size_t)(ny / 2 + 1));
+    l.o_nm = cv.take(sizeof(double) * 2);
+    l.bytes = cv.off;
+    return l;
+}
+
+// Device work of one OSPR frame on stream s, scratch at `b` (layout `l`),
+// {NMSE, NMSE_sym} to device `nm_out`.  The frame starts in the pool at
+// (c0 + *c0_base) mod L (c0 < L; c0_base may be NULL).
+holo_status ospr_enqueue(const float* target, int64_t nx, int64_t ny, int n_sf, const holo_lut* lut, uint64_t c0,
+                         const uint64_t* c0_base, uint32_t* holo_bits, float* recon, double* nm_out,
+                         const float2* tw_x, const float2* tw_y, char* b, const OsprLayout& l, hipStream_t s,
+                         const LaunchCfg& cfg)
+{
+    const size_t pitch = (size_t)row_pitch((int)nx, cfg);
+    const size_t nspec = (size_t)(ny / 2 + 1) * pitch;
+    float2* x1 = (float2*)(b + l.o_x1);
+    float2* x2 = (float2*)(b + l.o_x2);
+    double* part = (double*)(b + l.o_part);
     const uint32_t L = lut->n_dev;
     const size_t words = (size_t)nx * (size_t)ny / 32;
-    for (int k0 = 0; k0 < n_sf; k0 += chunk) {
-        const int ns = n_sf - k0 < chunk ? n_sf - k0 : chunk;
-        const uint64_t c0 = (uint64_t)(((unsigned __int128)cursor + (unsigned __int128)k0 * (uint64_t)(nx * ny)) % L);
-        LAUNCH("ospr_rows", s, launch_ospr_rows(target, (int)nx, (int)ny, ns, lut->dev, L, c0, x1, tw_x, cfg, s));
+    for (int k0 = 0; k0 < n_sf; k0 += l.chunk) {
+        const int ns = n_sf - k0 < l.chunk ? n_sf - k0 : l.chunk;
+        const uint64_t ck = (uint64_t)(((unsigned __int128)c0 + (unsigned __int128)k0 * (uint64_t)(nx * ny)) % L);
+        LAUNCH("ospr_rows", s, launch_ospr_rows(target, (int)nx, (int)ny, ns, lut->dev, L, ck, c0_base, x1, tw_x,
+                                                cfg, s));
         LAUNCH("ospr_cols", s, launch_ospr_cols(x1, (int)nx, (int)ny, ns, holo_bits + (size_t)k0 * words,
                                                 x2 + (size_t)k0 * nspec, tw_y, cfg, s));
     }
     LAUNCH("recon_rows", s, launch_recon_rows(x2, (int)nx, (int)ny, n_sf, true, target, recon, part, tw_x, cfg, s));
-    LAUNCH("nmse_finalize", s, launch_nmse_finalize(part, (int)(ny / 2 + 1), nm, s));
+    LAUNCH("nmse_finalize", s, launch_nmse_finalize(part, (int)(ny / 2 + 1), nm_out, s));
+    return HOLO_OK;
+}
+
+holo_status ospr_run(int device, const float* target, int64_t nx, int64_t ny, int n_sf, const holo_lut* lut,
+                     uint64_t cursor, uint32_t* holo_bits, float* recon, double* nmse2, uint32_t flags,
+                     hipStream_t s, const LaunchCfg& cfg)
+{
+    holo_status st;
+    const float2 *tw_x, *tw_y;
+    if ((st = get_twiddles(device, (int)nx, s, &tw_x))) return st;
+    if ((st = get_twiddles(device, (int)ny, s, &tw_y))) return st;
+    const OsprLayout l = ospr_layout(nx, ny, n_sf, cfg);
+    void* ws;
+    if ((st = get_workspace(device, s, l.bytes, &ws))) return st;
+    char* b = (char*)ws;
+    double* nm = (double*)(b + l.o_nm);
+    if ((st = ospr_enqueue(target, nx, ny, n_sf, lut, cursor % lut->n_dev, nullptr, holo_bits, recon, nm, tw_x,
+                           tw_y, b, l, s, cfg)))
+        return st;
     return copy_out(nmse2, nm, 2, flags, s);
 }
 
@@ -446,6 +478,31 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
     }
     if ((st = copy_out(a.nmse, (double*)(b + o_nm), n_iter, a.flags, s))) return st;
     if ((st = copy_out(a.err, (double*)(b + o_er), n_iter, a.flags, s))) return st;
+    return HOLO_OK;
+}
+
+// Stream-ordered store of one 64-bit value (kernel argument, so no host
+// buffer has to outlive the call).
+__global__ void k_set_u64(uint64_t* p, uint64_t v) { *p = v; }
+
+// Branch streams (default priority) for the batched graph's fork/join.
+constexpr int kBranches = 4;
+struct BatchSync {
+    hipStream_t br[kBranches] = {};
+    hipEvent_t fork = nullptr, join[kBranches] = {};
+};
+std::map<int, BatchSync> g_batch_sync;
+
+holo_status get_batch_sync(int device, BatchSync** out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    BatchSync& b = g_batch_sync[device];
+    for (int i = 0; i < kBranches; ++i) {
+        if (!b.br[i]) HIP_TRY(hipStreamCreateWithFlags(&b.br[i], hipStreamNonBlocking));
+        if (!b.join[i]) HIP_TRY(hipEventCreateWithFlags(&b.join[i], hipEventDisableTiming));
+    }
+    if (!b.fork) HIP_TRY(hipEventCreateWithFlags(&b.fork, hipEventDisableTiming));
+    *out = &b;
     return HOLO_OK;
 }
 
@@ -661,6 +718,162 @@ holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t ny, int32
     if ((st = get_workspace(device, s, sizeof(float2) * (size_t)nx * ny, &ws))) return st;
     LAUNCH("fft2", s, launch_fft2((const float2*)in, (float2*)ws, (float2*)out, (int)nx, (int)ny, sign, tw_x, tw_y,
                         default_cfg(), s));
+    return HOLO_OK;
+}
+
+holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frames, const holo_lut* lut,
+                                       uint64_t* cursor, double* nmse_out, int32_t precision, uint32_t flags,
+                                       void* hip_stream)
+{
+    if (!frames || !cursor) return fail(HOLO_EINVAL, "frames and cursor are required");
+    if (n_frames < 1 || n_frames > 4096) return fail(HOLO_EINVAL, "n_frames must be in [1, 4096] (got %d)", n_frames);
+    for (int f = 0; f < n_frames; ++f) {
+        const holo_frame& fr = frames[f];
+        if (!fr.target || !fr.holo_bits) return fail(HOLO_EINVAL, "frame %d: target and holo_bits are required", f);
+        if (fr.n_sf < 1) return fail(HOLO_EINVAL, "frame %d: n_sf must be >= 1", f);
+        if (!pow2_in_range(fr.nx) || !pow2_in_range(fr.ny))
+            return fail(HOLO_EUNSUPPORTED, "frame %d: nx, ny must be powers of two in [16, 2048]", f);
+    }
+    if (precision != HOLO_FP32) return fail(HOLO_EUNSUPPORTED, "precision %d is not available", precision);
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    holo_status st = check_lut(lut, device);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const uint32_t L = lut->n_dev;
+
+    // per-frame plans, layouts, pool offsets (exclusive prefix sum of n_sf*N)
+    std::vector<LaunchCfg> cfg(n_frames);
+    std::vector<OsprLayout> lay(n_frames);
+    std::vector<uint64_t> off(n_frames);
+    uint64_t total = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const holo_frame& fr = frames[f];
+        cfg[f] = plan_get(PLAN_OSPR, fr.nx, fr.ny, fr.n_sf);
+        lay[f] = ospr_layout(fr.nx, fr.ny, fr.n_sf, cfg[f]);
+        off[f] = total;
+        total += (uint64_t)fr.n_sf * (uint64_t)fr.nx * (uint64_t)fr.ny;
+    }
+    // frames to branches: longest first onto the least-loaded branch
+    const int nb = n_frames < kBranches ? n_frames : kBranches;
+    std::vector<int> order(n_frames), branch(n_frames);
+    for (int f = 0; f < n_frames; ++f) order[f] = f;
+    std::sort(order.begin(), order.end(), [&](int a, int b2) {
+        const double wa = (double)frames[a].n_sf * frames[a].nx * frames[a].ny;
+        const double wb = (double)frames[b2].n_sf * frames[b2].nx * frames[b2].ny;
+        return wa != wb ? wa > wb : a < b2;
+    });
+    std::vector<double> load(nb, 0.0);
+    std::vector<size_t> bbytes(nb, 0);
+    for (int f : order) {
+        int b = 0;
+        for (int i = 1; i < nb; ++i)
+            if (load[i] < load[b]) b = i;
+        branch[f] = b;
+        load[b] += (double)frames[f].n_sf * frames[f].nx * frames[f].ny;
+        if (lay[f].bytes > bbytes[b]) bbytes[b] = lay[f].bytes;
+    }
+    Carver cv;
+    std::vector<size_t> o_branch(nb);
+    for (int b = 0; b < nb; ++b) o_branch[b] = cv.take(bbytes[b]);
+    const size_t o_base = cv.take(sizeof(uint64_t));
+    const size_t o_nm = cv.take(sizeof(double) * 2 * n_frames);
+    // twiddle tables first: they synchronise, which capture forbids
+    std::map<int, const float2*> tw;
+    for (int f = 0; f < n_frames; ++f)
+        for (int n : {(int)frames[f].nx, (int)frames[f].ny})
+            if (!tw.count(n)) {
+                const float2* t = nullptr;
+                if ((st = get_twiddles(device, n, s, &t))) return st;
+                tw[n] = t;
+            }
+    void* ws;
+    if ((st = get_workspace(device, s, cv.off, &ws))) return st;
+    char* b = (char*)ws;
+    uint64_t* dbase = (uint64_t*)(b + o_base);
+    double* nm = (double*)(b + o_nm);
+
+    // the only per-call value inside the graph: the pool start, in device memory
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, dbase, *cursor % L);
+    HIP_TRY(hipGetLastError());
+
+    auto enqueue_all = [&](bool branches, BatchSync* bs) -> holo_status {
+        for (int f = 0; f < n_frames; ++f) {
+            const holo_frame& fr = frames[f];
+            hipStream_t fs = branches ? bs->br[branch[f]] : s;
+            holo_status e = ospr_enqueue(fr.target, fr.nx, fr.ny, fr.n_sf, lut, off[f] % L, dbase, fr.holo_bits,
+                                         fr.recon, nm + 2 * f, tw[(int)fr.nx], tw[(int)fr.ny],
+                                         b + o_branch[branch[f]], lay[f], fs, cfg[f]);
+            if (e) return e;
+        }
+        return HOLO_OK;
+    };
+    bool prof_on;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        prof_on = g_prof_on;
+    }
+    if (!g_use_graphs || prof_on || s == nullptr) {
+        if ((st = enqueue_all(false, nullptr))) return st;
+    } else {
+        BatchSync* bs = nullptr;
+        if ((st = get_batch_sync(device, &bs))) return st;
+        GraphKey key;
+        key.k = {(uintptr_t)0xBA7C, (uintptr_t)device, (uintptr_t)s, (uintptr_t)ws, (uintptr_t)lut->dev,
+                 (uintptr_t)L, (uintptr_t)n_frames};
+        for (int f = 0; f < n_frames; ++f) {
+            const holo_frame& fr = frames[f];
+            const LaunchCfg& c = cfg[f];
+            key.k.insert(key.k.end(), {(uintptr_t)fr.nx, (uintptr_t)fr.ny, (uintptr_t)fr.n_sf, (uintptr_t)fr.target,
+                                       (uintptr_t)fr.holo_bits, (uintptr_t)fr.recon, (uintptr_t)(off[f] % L),
+                                       (uintptr_t)c.cols_per_block, (uintptr_t)c.rows_per_block,
+                                       (uintptr_t)c.ksplit, (uintptr_t)c.recon_cols_per_block,
+                                       (uintptr_t)(intptr_t)c.pad, (uintptr_t)(intptr_t)c.chunk});
+        }
+        hipGraphExec_t exec = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_graph_mu);
+            auto it = g_graphs.find(key);
+            if (it != g_graphs.end()) exec = it->second;
+        }
+        if (!exec) {
+            hipGraph_t graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            holo_status est = HOLO_OK;
+            hipError_t he = hipEventRecord(bs->fork, s);
+            for (int i = 0; i < nb && he == hipSuccess; ++i) he = hipStreamWaitEvent(bs->br[i], bs->fork, 0);
+            if (he == hipSuccess) est = enqueue_all(true, bs);
+            for (int i = 0; i < nb && he == hipSuccess; ++i) {
+                he = hipEventRecord(bs->join[i], bs->br[i]);
+                if (he == hipSuccess) he = hipStreamWaitEvent(s, bs->join[i], 0);
+            }
+            hipError_t ce = hipStreamEndCapture(s, &graph);
+            if (est || he != hipSuccess || ce != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                if (est) return est;
+                return fail(HOLO_EDEVICE, "batch graph capture: %s",
+                            hipGetErrorString(he != hipSuccess ? he : ce));
+            }
+            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) return fail(HOLO_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(ie));
+            std::lock_guard<std::mutex> lk(g_graph_mu);
+            g_graphs[key] = exec;
+            g_graph_order.push_back(key);
+            if (g_graph_order.size() > 32) {
+                auto old = g_graphs.find(g_graph_order.front());
+                if (old != g_graphs.end()) {
+                    (void)hipStreamSynchronize(s);
+                    (void)hipGraphExecDestroy(old->second);
+                    g_graphs.erase(old);
+                }
+                g_graph_order.erase(g_graph_order.begin());
+            }
+        }
+        HIP_TRY(hipGraphLaunch(exec, s));
+    }
+    if ((st = copy_out(nmse_out, nm, 2 * (size_t)n_frames, flags, s))) return st;
+    *cursor += total;
     return HOLO_OK;
 }
 
@@ -945,6 +1158,14 @@ void holo_shutdown(void)
             if (w.second.base) (void)hipFree(w.second.base);
     }
     g_dev.clear();
+    for (auto& kv : g_batch_sync) {
+        for (int i = 0; i < kBranches; ++i) {
+            if (kv.second.br[i]) (void)hipStreamDestroy(kv.second.br[i]);
+            if (kv.second.join[i]) (void)hipEventDestroy(kv.second.join[i]);
+        }
+        if (kv.second.fork) (void)hipEventDestroy(kv.second.fork);
+    }
+    g_batch_sync.clear();
     {
         std::lock_guard<std::mutex> gl(g_graph_mu);
         for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);

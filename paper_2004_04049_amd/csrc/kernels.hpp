@@ -39,8 +39,10 @@ hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int n
                        const float2* tw_x, const float2* tw_y, const LaunchCfg& cfg, hipStream_t s);
 
 // OSPR K1: R = T * LUT phasor, inverse row transform, all n_sf sub-frames.
+// The pool position of the launch's first pixel is (c0 + *c0_base) mod n_lut
+// (c0_base may be NULL; both terms < n_lut).
 hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const float2* lut,
-                            uint32_t n_lut, uint64_t c0, float2* x1, const float2* tw_x,
+                            uint32_t n_lut, uint64_t c0, const uint64_t* c0_base, float2* x1, const float2* tw_x,
                             const LaunchCfg& cfg, hipStream_t s);
 // OSPR K2: inverse column transform, binarise + pack, forward column transform
 // of the +-1 column, half spectrum (rows 0..ny/2) out.

@@ -194,6 +194,7 @@ hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int n
 template <int NX>
 __global__ __launch_bounds__(1024) void k_ospr_rows(const float* __restrict__ target, int ny,
                                                     const float2* __restrict__ lut, uint32_t n_lut, uint64_t c0,
+                                                    const uint64_t* __restrict__ c0_base,
                                                     float2* __restrict__ x1, const float2* __restrict__ tw,
                                                     int pitch)
 {
@@ -206,7 +207,10 @@ __global__ __launch_bounds__(1024) void k_ospr_rows(const float* __restrict__ ta
     const int y = (blockIdx.x % blocks_per_sf) * rows + row;
     const uint64_t npix = (uint64_t)NX * (uint64_t)ny;
     // Cyclic LUT address of pixel (t, y) in sub-frame k; then +T per slot.
-    uint32_t idx = (uint32_t)((c0 + (uint64_t)k * npix + (uint64_t)y * NX + (uint64_t)t) % n_lut);
+    // start of this launch in the pool: c0, plus a base read from device memory
+    // when given (lets a replayed graph follow a cursor that moves per call)
+    const uint64_t cb = c0_base ? *c0_base : 0;
+    uint32_t idx = (uint32_t)((cb + c0 + (uint64_t)k * npix + (uint64_t)y * NX + (uint64_t)t) % n_lut);
     const uint32_t step = (uint32_t)(T % n_lut);
     const auto rt = make_rsrc(target, (uint32_t)(npix * 4));
     const auto rl = make_rsrc(lut, n_lut * 8u);
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(1024) void k_ospr_rows(const float* __restrict__ ta
 }
 
 hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const float2* lut,
-                            uint32_t n_lut, uint64_t c0, float2* x1, const float2* tw_x,
+                            uint32_t n_lut, uint64_t c0, const uint64_t* c0_base, float2* x1, const float2* tw_x,
                             const LaunchCfg& cfg, hipStream_t s)
 {
     const int rows = row_block_rows(nx, ny, cfg.rows_per_block);
@@ -238,7 +242,7 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
         size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
         allow_lds(k_ospr_rows<N_>, lds);
         hipLaunchKernelGGL((k_ospr_rows<N_>), dim3((ny / rows) * n_sf), dim3(rows * T), lds, s, target, ny, lut,
-                           n_lut, c0, x1, tw_x, row_pitch(nx, cfg));
+                           n_lut, c0, c0_base, x1, tw_x, row_pitch(nx, cfg));
     });
     return hipGetLastError();
 }

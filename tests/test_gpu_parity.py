@@ -276,3 +276,31 @@ def test_launch_plans_give_identical_holograms(holo, plan):
     # the sub-frame grouping of the reconstruction pass changes only the FP32
     # summation order of the time average
     np.testing.assert_allclose(nm1, nm0, rtol=1e-6)
+
+
+def test_batched_equals_sequential_calls(holo, orc):
+    # a seeded batch of uneven frames in one (graph-replayed) call equals one
+    # holo_ospr_generate call per frame with the cursor chained in batch order
+    layout = synth.batch_layout(10, synth.SEED_BATCH, sizes=(64, 128, 256, 512), n_sf_range=(3, 9))
+    targets = [torch.from_numpy(synth.blob_target(n, n, synth.SEED_BATCH_TARGET0 + f)).cuda()
+               for f, (n, _) in enumerate(layout)]
+    nsfs = [k for _, k in layout]
+    lut = holo.Lut(10007, 1)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for rep, cursor in enumerate((123, 10 ** 12 + 7, 5)):
+            bits, nm, cur = holo.ospr_generate_batched(targets, nsfs, lut, cursor)
+            c = cursor
+            for f, (t, k) in enumerate(zip(targets, nsfs)):
+                b1, nm1, c = holo.ospr_generate(t, k, lut, c)
+                assert torch.equal(bits[f], b1), (rep, f)
+                np.testing.assert_array_equal(nm[f], nm1)
+            assert cur == c
+    torch.cuda.synchronize()
+    # and one frame of the batch against the oracle
+    f = 1
+    n = layout[f][0]
+    t = targets[f].cpu().numpy()
+    ref = orc.ospr(t, nsfs[f], orc.lut_phases(10007, 1), 10007, 5 + sum(k * m * m for m, k in layout[:f]))
+    _check_bits(holo, orc, bits[f], ref, n * n)
+    np.testing.assert_allclose(nm[f], ref["nmse2"], rtol=NMSE_RTOL)
