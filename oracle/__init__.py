@@ -60,6 +60,12 @@ def _load():
         "orc_ospr": (None, [P, i64, i64, i32, P, u64, u64, P, P, P, P]),
         "orc_gs": (None, [P, i64, i64, i32, P, P, P, P, P, P]),
         "orc_num_threads": (i32, []),
+        "orc_conv3x3": (None, [P, i32, i32, i32, P, P, i32, P]),
+        "orc_cnn_nparams": (i32, [i32]),
+        "orc_cnn_forward": (None, [P, i32, P, i32, i32, P, P, P]),
+        "orc_cnn_loss": (dbl, [P, P, P, u64]),
+        "orc_cnn_backward": (dbl, [P, i32, P, P, i32, i32, P]),
+        "orc_adam": (None, [P, P, P, P, i32, i32, dbl, dbl, dbl, dbl]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -217,3 +223,61 @@ def unpack_bits(bits: np.ndarray, n: int) -> np.ndarray:
     b = np.unpackbits(np.ascontiguousarray(bits, dtype=np.uint32).view(np.uint8), axis=-1,
                       bitorder="little")
     return b[..., :n]
+
+
+# ----------------------------------------------------------------------------
+# Learned GS seed (small CNN; not part of the paper's method)
+# ----------------------------------------------------------------------------
+def conv3x3(x, w, b=None):
+    """x [cin, ny, nx], w [cout, cin, 3, 3] -> [cout, ny, nx] (circular)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    cin, ny, nx = x.shape
+    cout = w.shape[0]
+    out = np.zeros((cout, ny, nx))
+    bb = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
+    _load().orc_conv3x3(x.ctypes.data, cin, ny, nx, w.ctypes.data, _p(bb), cout, out.ctypes.data)
+    return out
+
+
+def cnn_nparams(C: int) -> int:
+    return int(_load().orc_cnn_nparams(C))
+
+
+def cnn_forward(params, C, target):
+    """Returns (acts [4, C, ny, nx], out2 [2, ny, nx], phasor complex [ny, nx])."""
+    pr = np.ascontiguousarray(params, dtype=np.float64)
+    t = _f32(target)
+    ny, nx = t.shape
+    acts = np.zeros((4, C, ny, nx))
+    out2 = np.zeros((2, ny, nx))
+    ph = np.zeros(2 * ny * nx)
+    _load().orc_cnn_forward(pr.ctypes.data, C, t.ctypes.data, ny, nx, acts.ctypes.data, out2.ctypes.data,
+                            ph.ctypes.data)
+    return acts, out2, ph.view(np.complex128).reshape(ny, nx)
+
+
+def cnn_loss(phasor, label, target) -> float:
+    p = _c128(phasor)
+    q = _c128(label)
+    t = _f32(target)
+    return float(_load().orc_cnn_loss(p.ctypes.data, q.ctypes.data, t.ctypes.data, t.size))
+
+
+def cnn_backward(params, C, target, label):
+    """Returns (loss, grad [nparams])."""
+    pr = np.ascontiguousarray(params, dtype=np.float64)
+    t = _f32(target)
+    ny, nx = t.shape
+    q = _c128(label)
+    g = np.zeros(pr.size)
+    loss = _load().orc_cnn_backward(pr.ctypes.data, C, t.ctypes.data, q.ctypes.data, ny, nx, g.ctypes.data)
+    return float(loss), g
+
+
+def adam(params, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays."""
+    for a in (params, grad, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    _load().orc_adam(params.ctypes.data, grad.ctypes.data, m.ctypes.data, v.ctypes.data, params.size, t, lr, b1,
+                     b2, eps)
