@@ -190,6 +190,44 @@ HOLO_API holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_
                                                 uint32_t flags, void* hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * Learned GS seed (not part of the paper's method: a learned replacement for
+ * the LUT seed of R_0, trained on the project's own GS output; the LUT seed of
+ * holo_gs_iterate remains the fallback).
+ * Network: five 3x3 convolutions with circular padding, 1 -> 32 -> 32 -> 32
+ * -> 32 -> 2 channels, ReLU after the first four, output phasor o/|o| per
+ * pixel.  BF16 weights and activations, FP32 accumulation (the 32->32 layers
+ * on MFMA); FP32 master parameters and Adam moments.
+ * Parameters: flat FP32 vector of holo_cnn_nparams() values, per layer
+ * w[co][ci][3][3] then b[co]; tap (dy, dx) multiplies input (y+dy, x+dx).
+ * Loss: L = 1 - |sum w p conj(q)| / sum w, w = T^2, q = label/|label| (any
+ * complex label field, e.g. holo_gs_iterate's `field`): the T^2-weighted
+ * phase error at the best global phase offset.
+ *   holo_cnn_create   He-uniform init from SplitMix64(seed), biases 0
+ *   holo_cnn_infer    target device float[ny][nx] -> phasor_out device
+ *                     float2[ny][nx] (stream-ordered)
+ *   holo_cnn_loss_grad  loss and parameter gradient (host outputs, sync)
+ *   holo_cnn_train_step  one forward/backward/Adam (lr) step on one image;
+ *                     loss_out host or NULL (no sync)
+ *   holo_cnn_save / holo_cnn_load  parameters, Adam moments and step
+ * Images: nx, ny powers of two in [64, 2048].  The network and its scratch
+ * live on the device current at creation.
+ * ------------------------------------------------------------------------- */
+typedef struct holo_cnn holo_cnn;
+HOLO_API int32_t holo_cnn_nparams(void);
+HOLO_API holo_status holo_cnn_create(uint64_t seed, holo_cnn** out);
+HOLO_API holo_status holo_cnn_get_params(const holo_cnn* cnn, float* host_out, int32_t n);
+HOLO_API holo_status holo_cnn_set_params(holo_cnn* cnn, const float* host_in, int32_t n);
+HOLO_API holo_status holo_cnn_infer(holo_cnn* cnn, const float* target, int64_t nx, int64_t ny, float* phasor_out,
+                                    void* hip_stream);
+HOLO_API holo_status holo_cnn_loss_grad(holo_cnn* cnn, const float* target, const float* label, int64_t nx,
+                                        int64_t ny, double* loss_out, float* grad_out, void* hip_stream);
+HOLO_API holo_status holo_cnn_train_step(holo_cnn* cnn, const float* target, const float* label, int64_t nx,
+                                         int64_t ny, float lr, double* loss_out, void* hip_stream);
+HOLO_API holo_status holo_cnn_save(const holo_cnn* cnn, const char* path);
+HOLO_API holo_status holo_cnn_load(const char* path, holo_cnn** out);
+HOLO_API void holo_cnn_free(holo_cnn* cnn);
+
+/* ---------------------------------------------------------------------------
  * holo_fft2 -- the unitary transform pair itself: Eq. (1) for sign = -1,
  * Eq. (2) for sign = +1, complex [ny][nx] device in -> device out (may alias).
  * ------------------------------------------------------------------------- */

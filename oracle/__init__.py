@@ -62,9 +62,10 @@ def _load():
         "orc_num_threads": (i32, []),
         "orc_conv3x3": (None, [P, i32, i32, i32, P, P, i32, P]),
         "orc_cnn_nparams": (i32, [i32]),
-        "orc_cnn_forward": (None, [P, i32, P, i32, i32, P, P, P]),
+        "orc_bf16": (dbl, [dbl]),
+        "orc_cnn_forward": (None, [P, i32, P, i32, i32, i32, P, P, P]),
         "orc_cnn_loss": (dbl, [P, P, P, u64]),
-        "orc_cnn_backward": (dbl, [P, i32, P, P, i32, i32, P]),
+        "orc_cnn_backward": (dbl, [P, i32, P, P, i32, i32, i32, P]),
         "orc_adam": (None, [P, P, P, P, i32, i32, dbl, dbl, dbl, dbl]),
     }
     for name, (res, args) in sig.items():
@@ -244,16 +245,21 @@ def cnn_nparams(C: int) -> int:
     return int(_load().orc_cnn_nparams(C))
 
 
-def cnn_forward(params, C, target):
-    """Returns (acts [4, C, ny, nx], out2 [2, ny, nx], phasor complex [ny, nx])."""
+def bf16(v: float) -> float:
+    return float(_load().orc_bf16(float(v)))
+
+
+def cnn_forward(params, C, target, bf16_store=False):
+    """Returns (acts [4, C, ny, nx], out2 [2, ny, nx], phasor complex [ny, nx]).
+    bf16_store: hidden activations rounded to BF16 where stored."""
     pr = np.ascontiguousarray(params, dtype=np.float64)
     t = _f32(target)
     ny, nx = t.shape
     acts = np.zeros((4, C, ny, nx))
     out2 = np.zeros((2, ny, nx))
     ph = np.zeros(2 * ny * nx)
-    _load().orc_cnn_forward(pr.ctypes.data, C, t.ctypes.data, ny, nx, acts.ctypes.data, out2.ctypes.data,
-                            ph.ctypes.data)
+    _load().orc_cnn_forward(pr.ctypes.data, C, t.ctypes.data, ny, nx, int(bool(bf16_store)), acts.ctypes.data,
+                            out2.ctypes.data, ph.ctypes.data)
     return acts, out2, ph.view(np.complex128).reshape(ny, nx)
 
 
@@ -264,14 +270,16 @@ def cnn_loss(phasor, label, target) -> float:
     return float(_load().orc_cnn_loss(p.ctypes.data, q.ctypes.data, t.ctypes.data, t.size))
 
 
-def cnn_backward(params, C, target, label):
-    """Returns (loss, grad [nparams])."""
+def cnn_backward(params, C, target, label, bf16_store=False):
+    """Returns (loss, grad [nparams]).  bf16_store: hidden activations and
+    hidden-layer gradients rounded to BF16 where stored."""
     pr = np.ascontiguousarray(params, dtype=np.float64)
     t = _f32(target)
     ny, nx = t.shape
     q = _c128(label)
     g = np.zeros(pr.size)
-    loss = _load().orc_cnn_backward(pr.ctypes.data, C, t.ctypes.data, q.ctypes.data, ny, nx, g.ctypes.data)
+    loss = _load().orc_cnn_backward(pr.ctypes.data, C, t.ctypes.data, q.ctypes.data, ny, nx,
+                                    int(bool(bf16_store)), g.ctypes.data)
     return float(loss), g
 
 

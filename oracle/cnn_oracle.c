@@ -15,6 +15,12 @@
  *   out[co][y][x] = b[co] + sum_{ci, dy, dx} w[co][ci][dy+1][dx+1] *
  *                   in[ci][(y + dy) mod ny][(x + dx) mod nx].
  *
+ * Storage model (bf16_store != 0): the hidden activations, and in the
+ * backward pass the hidden-layer gradients after the ReLU gate, are rounded
+ * to BF16 (8 significant bits, round to nearest, ties to even) where they are
+ * stored, as a device implementation that keeps them in BF16 does; all sums
+ * stay FP64.  bf16_store = 0 is the exact network.
+ *
  * Loss (global-phase invariant, target-intensity weighted): with w = T^2,
  * label phasor q and Z = sum w p conj(q), W = sum w,
  *   L = 1 - |Z| / W
@@ -25,6 +31,19 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Round to the nearest BF16 value (the upper 16 bits of an IEEE binary32),
+ * ties to even, via binary32.  Finite inputs only. */
+double orc_bf16(double v)
+{
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u = (u + 0x7FFFu + lsb) & 0xFFFF0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
 
 /* one 3x3 circular convolution layer */
 void orc_conv3x3(const double *in, int cin, int ny, int nx, const double *w, const double *b, int cout,
@@ -67,8 +86,8 @@ int orc_cnn_nparams(int C)
 /* Forward pass.  acts (may be NULL) receives the post-ReLU activations of
  * layers 1..4 ([4][C][ny][nx]); out2 the raw 2-channel output, phasor the
  * normalised output ([ny][nx] interleaved re, im). */
-void orc_cnn_forward(const double *params, int C, const float *target, int ny, int nx, double *acts,
-                     double *out2, double *phasor)
+void orc_cnn_forward(const double *params, int C, const float *target, int ny, int nx, int bf16_store,
+                     double *acts, double *out2, double *phasor)
 {
     const size_t np = (size_t)ny * nx;
     double *a = (double *)malloc(sizeof(double) * np * (size_t)C);
@@ -85,7 +104,10 @@ void orc_cnn_forward(const double *params, int C, const float *target, int ny, i
         double *dst = l == 4 ? out2 : (in == a ? bufb : a);
         orc_conv3x3(in, ci, ny, nx, w, b, co, dst);
         if (l < 4) {
-            for (size_t i = 0; i < np * (size_t)co; ++i) dst[i] = dst[i] > 0.0 ? dst[i] : 0.0;
+            for (size_t i = 0; i < np * (size_t)co; ++i) {
+                const double r = dst[i] > 0.0 ? dst[i] : 0.0;
+                dst[i] = bf16_store ? orc_bf16(r) : r;
+            }
             if (acts) memcpy(acts + (size_t)l * np * C, dst, sizeof(double) * np * C);
         }
         in = dst;
@@ -115,15 +137,15 @@ double orc_cnn_loss(const double *phasor, const double *label, const float *targ
 }
 
 /* Gradient of the loss with respect to all parameters (analytic backward
- * pass).  Returns the loss. */
+ * pass).  Returns the loss.  The label is used as given (a unit phasor). */
 double orc_cnn_backward(const double *params, int C, const float *target, const double *label, int ny, int nx,
-                        double *grad)
+                        int bf16_store, double *grad)
 {
     const size_t np = (size_t)ny * nx;
     double *acts = (double *)malloc(sizeof(double) * np * (size_t)C * 4);
     double *out2 = (double *)malloc(sizeof(double) * np * 2);
     double *ph = (double *)malloc(sizeof(double) * np * 2);
-    orc_cnn_forward(params, C, target, ny, nx, acts, out2, ph);
+    orc_cnn_forward(params, C, target, ny, nx, bf16_store, acts, out2, ph);
 
     /* dL/dp = -(w / (W |Z|)) * Z q (complex product), then through the
      * normalisation p = o/|o|: dL/do = (g - (g.p) p) / |o|. */
@@ -202,7 +224,7 @@ double orc_cnn_backward(const double *params, int C, const float *target, const 
                                      dcur[((size_t)c2 * ny + yo) * nx + xo];
                             }
                     size_t i = ((size_t)c1 * ny + y) * nx + x;
-                    dprev[i] = in[i] > 0.0 ? s : 0.0;
+                    dprev[i] = in[i] > 0.0 ? (bf16_store ? orc_bf16(s) : s) : 0.0;
                 }
         double *tmp = dcur;
         dcur = dprev;

@@ -52,6 +52,16 @@ SIGNATURES = {
     "holo_plan_load": (_I32, [C.c_char_p]),
     "holo_set_graphs": (_I32, [_I32]),
     "holo_ospr_generate_batched": (_I32, [_P, _I32, _P, C.POINTER(_U64), _P, _I32, _U32, _P]),
+    "holo_cnn_nparams": (_I32, []),
+    "holo_cnn_create": (_I32, [_U64, C.POINTER(_P)]),
+    "holo_cnn_get_params": (_I32, [_P, _P, _I32]),
+    "holo_cnn_set_params": (_I32, [_P, _P, _I32]),
+    "holo_cnn_infer": (_I32, [_P, _P, _I64, _I64, _P, _P]),
+    "holo_cnn_loss_grad": (_I32, [_P, _P, _P, _I64, _I64, _P, _P, _P]),
+    "holo_cnn_train_step": (_I32, [_P, _P, _P, _I64, _I64, C.c_float, _P, _P]),
+    "holo_cnn_save": (_I32, [_P, C.c_char_p]),
+    "holo_cnn_load": (_I32, [C.c_char_p, C.POINTER(_P)]),
+    "holo_cnn_free": (None, [_P]),
 }
 
 
@@ -357,3 +367,75 @@ def ospr_generate_batched(targets, n_sfs, lut: Lut, cursor: int, bits=None, reco
     _check(lib().holo_ospr_generate_batched(C.cast(arr, C.c_void_p), n, lut.handle, C.byref(cur), nm_p, FP32,
                                             flags, _stream(stream)))
     return bits, nm, int(cur.value)
+
+
+class Cnn:
+    """Learned GS seed network (holo_cnn_*)."""
+
+    def __init__(self, seed: int = 1, path: str | None = None):
+        h = C.c_void_p()
+        if path is not None:
+            _check(lib().holo_cnn_load(path.encode(), C.byref(h)))
+        else:
+            _check(lib().holo_cnn_create(seed, C.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def nparams() -> int:
+        return int(lib().holo_cnn_nparams())
+
+    def params(self):
+        import numpy as np
+        out = np.zeros(self.nparams(), dtype=np.float32)
+        _check(lib().holo_cnn_get_params(self._h, out.ctypes.data_as(C.c_void_p), out.size))
+        return out
+
+    def set_params(self, p):
+        import numpy as np
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        _check(lib().holo_cnn_set_params(self._h, a.ctypes.data_as(C.c_void_p), a.size))
+
+    def infer(self, target, out=None, stream=None):
+        """target cuda float32 [ny, nx] -> cuda complex64 phasor [ny, nx]."""
+        _dev(target, torch.float32, None, "target")
+        ny, nx = target.shape
+        if out is None:
+            out = torch.empty((ny, nx), dtype=torch.complex64, device=target.device)
+        _dev(out, torch.complex64, (ny, nx), "out")
+        _check(lib().holo_cnn_infer(self._h, _ptr(target), nx, ny, _ptr(out), _stream(stream)))
+        return out
+
+    def loss_grad(self, target, label, stream=None):
+        """(loss, grad [nparams] float32) for one image; label cuda complex64."""
+        import numpy as np
+        _dev(target, torch.float32, None, "target")
+        ny, nx = target.shape
+        _dev(label, torch.complex64, (ny, nx), "label")
+        loss = C.c_double()
+        g = np.zeros(self.nparams(), dtype=np.float32)
+        _check(lib().holo_cnn_loss_grad(self._h, _ptr(target), _ptr(label), nx, ny, C.byref(loss),
+                                        g.ctypes.data_as(C.c_void_p), _stream(stream)))
+        return loss.value, g
+
+    def train_step(self, target, label, lr: float, want_loss: bool = True, stream=None):
+        _dev(target, torch.float32, None, "target")
+        ny, nx = target.shape
+        _dev(label, torch.complex64, (ny, nx), "label")
+        loss = C.c_double()
+        _check(lib().holo_cnn_train_step(self._h, _ptr(target), _ptr(label), nx, ny, lr,
+                                         C.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None
+
+    def save(self, path: str):
+        _check(lib().holo_cnn_save(self._h, path.encode()))
+
+    def close(self):
+        if self._h:
+            lib().holo_cnn_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,7 +16,18 @@
 #include <vector>
 
 #include "../../include/holo.h"
+#include "cnn.hpp"
 #include "kernels.hpp"
+
+struct holo_cnn {
+    int device = 0;
+    holo::CnnLayout lay;
+    holo::CnnBuffers b{};
+    size_t img_px = 0;          // capacity of the per-image buffers (pixels)
+    int img_rows = 0;           // rows the gradient partials are sized for
+    int step = 0;               // Adam steps taken
+    float2* ph = nullptr;       // phasor scratch for training
+};
 
 struct holo_lut {
     int device;
@@ -1118,6 +1129,239 @@ holo_status holo_set_graphs(int32_t on)
 {
     g_use_graphs = on != 0;
     return HOLO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned GS seed network
+// ---------------------------------------------------------------------------
+namespace holo {
+namespace {
+bool cnn_size_ok(int64_t n) { return n >= 64 && n <= 2048 && (n & (n - 1)) == 0; }
+
+void cnn_free_images(holo_cnn* c)
+{
+    for (int i = 0; i < 4; ++i) (void)hipFree(c->b.act[i]), c->b.act[i] = nullptr;
+    for (int i = 0; i < 2; ++i) (void)hipFree(c->b.dact[i]), c->b.dact[i] = nullptr;
+    (void)hipFree(c->b.o5), (void)hipFree(c->b.d5), (void)hipFree(c->b.part), (void)hipFree(c->ph);
+    c->b.o5 = c->b.d5 = nullptr;
+    c->b.part = nullptr;
+    c->ph = nullptr;
+    c->img_px = 0;
+}
+
+holo_status cnn_images(holo_cnn* c, int64_t nx, int64_t ny)
+{
+    const size_t npx = (size_t)nx * (size_t)ny;
+    const int rpb = ny >= 256 ? (int)(ny / 256) : 1;
+    const int nblk = (int)((ny + rpb - 1) / rpb);
+    if (npx <= c->img_px && nblk <= c->img_rows) {
+        c->b.rows_per_block = rpb;
+        return HOLO_OK;
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    cnn_free_images(c);
+    bool ok = true;
+    for (int i = 0; i < 4; ++i) ok = ok && hipMalloc(&c->b.act[i], npx * 32 * 2) == hipSuccess;
+    for (int i = 0; i < 2; ++i) ok = ok && hipMalloc(&c->b.dact[i], npx * 32 * 2) == hipSuccess;
+    ok = ok && hipMalloc(&c->b.o5, npx * sizeof(float2)) == hipSuccess;
+    ok = ok && hipMalloc(&c->b.d5, npx * sizeof(float2)) == hipSuccess;
+    ok = ok && hipMalloc(&c->ph, npx * sizeof(float2)) == hipSuccess;
+    ok = ok && hipMalloc(&c->b.part, (size_t)nblk * (32 * 32 * 9 + 32) * sizeof(float)) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        cnn_free_images(c);
+        return fail(HOLO_ENOMEM, "network buffers for %lld x %lld", (long long)nx, (long long)ny);
+    }
+    c->img_px = npx;
+    c->img_rows = nblk;
+    c->b.rows_per_block = rpb;
+    return HOLO_OK;
+}
+
+holo_status cnn_check(const holo_cnn* c, int64_t nx, int64_t ny)
+{
+    if (!c) return fail(HOLO_EINVAL, "network is NULL");
+    if (!cnn_size_ok(nx) || !cnn_size_ok(ny))
+        return fail(HOLO_EUNSUPPORTED, "network images must be powers of two in [64, 2048]");
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    if (device != c->device) return fail(HOLO_EINVAL, "network lives on device %d", c->device);
+    return HOLO_OK;
+}
+}  // namespace
+}  // namespace holo
+
+int32_t holo_cnn_nparams(void) { return CnnLayout().n; }
+
+holo_status holo_cnn_create(uint64_t seed, holo_cnn** out)
+{
+    if (!out) return fail(HOLO_EINVAL, "out is NULL");
+    *out = nullptr;
+    holo_cnn* c = new holo_cnn();
+    HIP_TRY(hipGetDevice(&c->device));
+    const int n = c->lay.n;
+    for (int l = 0; l < 5; ++l) c->b.off[l] = c->lay.off[l];
+    // He-uniform initialisation from SplitMix64: w ~ U(-a, a), a = sqrt(6 / fan_in); biases 0
+    std::vector<float> p(n, 0.0f);
+    uint64_t st = seed;
+    for (int l = 0; l < 5; ++l) {
+        const int ci = l == 0 ? 1 : kCnnC, co = l == 4 ? 2 : kCnnC;
+        const double a = std::sqrt(6.0 / (9.0 * ci));
+        for (int j = 0; j < co * ci * 9; ++j) {
+            const double u = (double)(splitmix64(st) >> 11) * 0x1.0p-53;
+            p[c->lay.off[l] + j] = (float)((2.0 * u - 1.0) * a);
+        }
+    }
+    bool ok = hipMalloc(&c->b.params, n * 4) == hipSuccess && hipMalloc(&c->b.m, n * 4) == hipSuccess &&
+              hipMalloc(&c->b.v, n * 4) == hipSuccess && hipMalloc(&c->b.grad, n * 4) == hipSuccess &&
+              hipMalloc(&c->b.loss_part, 256 * 3 * 8) == hipSuccess && hipMalloc(&c->b.zsum, 4 * 8) == hipSuccess;
+    for (int i = 0; i < 3 && ok; ++i)
+        ok = hipMalloc(&c->b.wf[i], 32 * 32 * 9 * 2) == hipSuccess && hipMalloc(&c->b.wt[i], 32 * 32 * 9 * 2) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        holo_cnn_free(c);
+        return fail(HOLO_ENOMEM, "network parameters");
+    }
+    HIP_TRY(hipMemcpy(c->b.params, p.data(), n * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(c->b.m, 0, n * 4));
+    HIP_TRY(hipMemset(c->b.v, 0, n * 4));
+    HIP_TRY(cnn_launch_pack(c->b, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    *out = c;
+    return HOLO_OK;
+}
+
+holo_status holo_cnn_get_params(const holo_cnn* c, float* host_out, int32_t n)
+{
+    if (!c || !host_out) return fail(HOLO_EINVAL, "network and out are required");
+    if (n != c->lay.n) return fail(HOLO_EINVAL, "network has %d parameters, not %d", c->lay.n, n);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(host_out, c->b.params, (size_t)n * 4, hipMemcpyDeviceToHost));
+    return HOLO_OK;
+}
+
+holo_status holo_cnn_set_params(holo_cnn* c, const float* host_in, int32_t n)
+{
+    if (!c || !host_in) return fail(HOLO_EINVAL, "network and parameters are required");
+    if (n != c->lay.n) return fail(HOLO_EINVAL, "network has %d parameters, not %d", c->lay.n, n);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(c->b.params, host_in, (size_t)n * 4, hipMemcpyHostToDevice));
+    HIP_TRY(cnn_launch_pack(c->b, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    return HOLO_OK;
+}
+
+holo_status holo_cnn_infer(holo_cnn* c, const float* target, int64_t nx, int64_t ny, float* phasor_out,
+                           void* hip_stream)
+{
+    holo_status st = cnn_check(c, nx, ny);
+    if (st) return st;
+    if (!target || !phasor_out) return fail(HOLO_EINVAL, "target and phasor_out are required");
+    if ((st = cnn_images(c, nx, ny))) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    LAUNCH("cnn_forward", s, cnn_launch_forward(c->b, target, (int)ny, (int)nx, (float2*)phasor_out, s));
+    return HOLO_OK;
+}
+
+holo_status holo_cnn_loss_grad(holo_cnn* c, const float* target, const float* label, int64_t nx, int64_t ny,
+                               double* loss_out, float* grad_out, void* hip_stream)
+{
+    holo_status st = cnn_check(c, nx, ny);
+    if (st) return st;
+    if (!target || !label) return fail(HOLO_EINVAL, "target and label are required");
+    if ((st = cnn_images(c, nx, ny))) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int n = (int)(nx * ny);
+    LAUNCH("cnn_forward", s, cnn_launch_forward(c->b, target, (int)ny, (int)nx, c->ph, s));
+    LAUNCH("cnn_loss", s, cnn_launch_loss(c->b, target, (const float2*)label, c->ph, n, s));
+    LAUNCH("cnn_backward", s, cnn_launch_backward(c->b, target, (const float2*)label, (int)ny, (int)nx, s));
+    if (loss_out) {
+        HIP_TRY(hipMemcpyAsync(loss_out, c->b.zsum + 3, 8, hipMemcpyDeviceToHost, s));
+    }
+    if (grad_out) {
+        HIP_TRY(hipMemcpyAsync(grad_out, c->b.grad, (size_t)c->lay.n * 4, hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return HOLO_OK;
+}
+
+holo_status holo_cnn_train_step(holo_cnn* c, const float* target, const float* label, int64_t nx, int64_t ny,
+                                float lr, double* loss_out, void* hip_stream)
+{
+    holo_status st = cnn_check(c, nx, ny);
+    if (st) return st;
+    if (!target || !label) return fail(HOLO_EINVAL, "target and label are required");
+    if (!(lr > 0.0f)) return fail(HOLO_EINVAL, "lr must be > 0");
+    if ((st = cnn_images(c, nx, ny))) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int n = (int)(nx * ny);
+    LAUNCH("cnn_forward", s, cnn_launch_forward(c->b, target, (int)ny, (int)nx, c->ph, s));
+    LAUNCH("cnn_loss", s, cnn_launch_loss(c->b, target, (const float2*)label, c->ph, n, s));
+    LAUNCH("cnn_backward", s, cnn_launch_backward(c->b, target, (const float2*)label, (int)ny, (int)nx, s));
+    c->step += 1;
+    LAUNCH("cnn_adam", s, cnn_launch_adam(c->b, c->lay.n, lr, c->step, s));
+    if (loss_out) {
+        HIP_TRY(hipMemcpyAsync(loss_out, c->b.zsum + 3, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return HOLO_OK;
+}
+
+holo_status holo_cnn_save(const holo_cnn* c, const char* path)
+{
+    if (!c || !path) return fail(HOLO_EINVAL, "network and path are required");
+    const int n = c->lay.n;
+    std::vector<float> buf((size_t)3 * n);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(buf.data(), c->b.params, n * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(buf.data() + n, c->b.m, n * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(buf.data() + 2 * n, c->b.v, n * 4, hipMemcpyDeviceToHost));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(HOLO_EINVAL, "cannot write %s", path);
+    const char magic[8] = {'H', 'O', 'L', 'O', 'C', 'N', 'N', '1'};
+    int32_t hdr[2] = {n, c->step};
+    bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, 4, 2, f) == 2 &&
+              std::fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+    std::fclose(f);
+    return ok ? HOLO_OK : fail(HOLO_EINVAL, "short write to %s", path);
+}
+
+holo_status holo_cnn_load(const char* path, holo_cnn** out)
+{
+    if (!path || !out) return fail(HOLO_EINVAL, "path and out are required");
+    *out = nullptr;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(HOLO_EINVAL, "cannot read %s", path);
+    char magic[8];
+    int32_t hdr[2];
+    const int n = CnnLayout().n;
+    std::vector<float> buf((size_t)3 * n);
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "HOLOCNN1", 8) == 0 &&
+              std::fread(hdr, 4, 2, f) == 2 && hdr[0] == n && std::fread(buf.data(), 4, buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok) return fail(HOLO_EINVAL, "%s is not a saved network", path);
+    holo_cnn* c = nullptr;
+    holo_status st = holo_cnn_create(0, &c);
+    if (st) return st;
+    HIP_TRY(hipMemcpy(c->b.params, buf.data(), n * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->b.m, buf.data() + n, n * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->b.v, buf.data() + 2 * n, n * 4, hipMemcpyHostToDevice));
+    HIP_TRY(cnn_launch_pack(c->b, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    c->step = hdr[1];
+    *out = c;
+    return HOLO_OK;
+}
+
+void holo_cnn_free(holo_cnn* c)
+{
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    cnn_free_images(c);
+    (void)hipFree(c->b.params), (void)hipFree(c->b.m), (void)hipFree(c->b.v), (void)hipFree(c->b.grad);
+    (void)hipFree(c->b.loss_part), (void)hipFree(c->b.zsum);
+    for (int i = 0; i < 3; ++i) (void)hipFree(c->b.wf[i]), (void)hipFree(c->b.wt[i]);
+    delete c;
 }
 
 holo_status holo_prof_enable(int32_t on)

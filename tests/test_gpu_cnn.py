@@ -1,0 +1,147 @@
+"""GPU parity of the learned GS seed network against the oracle, and that
+training on the project's own GS output reduces the loss.
+
+The GPU keeps weights, hidden activations and hidden-layer gradients in BF16
+and accumulates in FP32.  The oracle is given the BF16-rounded weights and run
+with its BF16 storage model (the same values rounded where they are stored,
+FP64 sums), so what remains is FP32-versus-FP64 accumulation: ~sqrt(288) *
+2^-24 relative per sum, which flips a stored BF16 value (spacing 2^-8
+relative) with probability ~1e-3 and moves the output by ~2^-8/sqrt(288) per
+flip in its receptive field.  Bounds: output error (phasor angle scaled by
+|o| / rms|o|) median < 1e-4 and max < 5e-3; gradient relative L2 < 1e-2; loss
+within 1e-4 relative.  Against the exact (unrounded) network the four BF16
+roundings (2^-9 each, in quadrature) bound the median scaled error at 6e-3."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u << 16).astype(np.uint32).view(np.float32)
+
+
+def _rounded_params(p, orc):
+    """the network's compute copy: every weight to BF16, biases FP32."""
+    q = p.astype(np.float64).copy()
+    C = 32
+    o = 0
+    for l in range(5):
+        ci = 1 if l == 0 else C
+        co = 2 if l == 4 else C
+        nw = co * ci * 9
+        q[o:o + nw] = _bf16(p[o:o + nw])
+        o += nw + co
+    return q
+
+
+@pytest.fixture(scope="module")
+def holo():
+    import paper_2004_04049_amd as h
+    h.lib()
+    return h
+
+
+def test_forward_matches_oracle(holo, orc):
+    net = holo.Cnn(seed=5)
+    p = net.params()
+    assert p.size == orc.cnn_nparams(32)
+    t = synth.blob_target(64, 64, 3)
+    ph = net.infer(torch.from_numpy(t).cuda()).cpu().numpy()
+    q = _rounded_params(p, orc)
+    for store, med_tol, max_tol in ((True, 1e-4, 5e-3), (False, 6e-3, None)):
+        _, out2, ref = orc.cnn_forward(q, 32, t, bf16_store=store)
+        mag = np.hypot(out2[0], out2[1])
+        err = np.abs(np.angle(ph * np.conj(ref))) * mag / np.sqrt(np.mean(mag ** 2))
+        print(f"bf16_store={store}: scaled phasor angle error median {np.median(err):.2e}, "
+              f"99% {np.quantile(err, 0.99):.2e}, max {err.max():.2e}")
+        assert np.median(err) < med_tol
+        if max_tol is not None:
+            assert err.max() < max_tol
+
+
+def test_gradient_matches_oracle(holo, orc):
+    net = holo.Cnn(seed=6)
+    p = net.params()
+    t = synth.blob_target(64, 64, 4)
+    rng = np.random.default_rng(0)
+    q = np.exp(1j * rng.uniform(0, 2 * np.pi, t.shape)).astype(np.complex64)
+    loss, g = net.loss_grad(torch.from_numpy(t).cuda(), torch.from_numpy(q).cuda())
+    rl, rg = orc.cnn_backward(_rounded_params(p, orc), 32, t, q.astype(np.complex128), bf16_store=True)
+    rel = float(np.linalg.norm(g - rg) / np.linalg.norm(rg))
+    per_layer = []
+    o = 0
+    for l in range(5):
+        ci = 1 if l == 0 else 32
+        co = 2 if l == 4 else 32
+        k = co * ci * 9 + co
+        per_layer.append(float(np.linalg.norm(g[o:o + k] - rg[o:o + k]) / np.linalg.norm(rg[o:o + k])))
+        o += k
+    print(f"loss {loss:.8f} oracle {rl:.8f}; gradient rel L2 {rel:.3e}, per layer "
+          + " ".join(f"{x:.1e}" for x in per_layer))
+    assert loss == pytest.approx(rl, rel=1e-4)
+    assert rel < 1e-2 and max(per_layer) < 2e-2
+
+
+def test_adam_step_matches_oracle(holo, orc):
+    """One train_step = the oracle's Adam applied to the GPU gradient, from
+    zero moments (FP32 parameter update: 1e-6 relative + lr * 1e-4 absolute)."""
+    net = holo.Cnn(seed=8)
+    t = torch.from_numpy(synth.blob_target(64, 64, 5)).cuda()
+    rng = np.random.default_rng(1)
+    q = torch.from_numpy(np.exp(1j * rng.uniform(0, 2 * np.pi, (64, 64))).astype(np.complex64)).cuda()
+    p0 = net.params().astype(np.float64)
+    _, g = net.loss_grad(t, q)
+    lr = 1e-3
+    net.train_step(t, q, lr)
+    p1 = net.params()
+    ref = p0.copy()
+    m = np.zeros_like(ref)
+    v = np.zeros_like(ref)
+    orc.adam(ref, g.astype(np.float64), m, v, 1, lr)
+    np.testing.assert_allclose(p1, ref, rtol=1e-6, atol=lr * 1e-4)
+    assert np.abs(p1 - p0).max() > 0.5 * lr
+
+
+def test_training_reduces_loss_and_roundtrip(holo, tmp_path):
+    """Training drives the loss down on labels the network can represent
+    (phase = pi * T, a pointwise function of the target), and also lowers it on
+    GS-50 replay phases; save/load restores the network bit for bit."""
+    n = 64
+    net = holo.Cnn(seed=7)
+    targets = [torch.from_numpy(synth.blob_target(n, n, synth.SEED_CNN_TRAIN0 + i)).cuda() for i in range(8)]
+    learnable = [torch.exp(1j * np.pi * t.to(torch.complex64)) for t in targets]
+    first = [net.loss_grad(t, q)[0] for t, q in zip(targets, learnable)]
+    for epoch in range(40):
+        for t, q in zip(targets, learnable):
+            net.train_step(t, q, 2e-3, want_loss=False)
+    last = [net.loss_grad(t, q)[0] for t, q in zip(targets, learnable)]
+    print(f"pointwise labels: mean loss {np.mean(first):.4f} -> {np.mean(last):.4f}")
+    assert np.mean(last) < 0.5 * np.mean(first)
+
+    gs_net = holo.Cnn(seed=9)
+    lut = holo.Lut(4096, 1)
+    labels = [holo.gs_iterate(t, 50, lut, 0, want_final=False)["field"].clone() for t in targets]
+    first = [gs_net.loss_grad(t, q)[0] for t, q in zip(targets, labels)]
+    for epoch in range(30):
+        for t, q in zip(targets, labels):
+            gs_net.train_step(t, q, 1e-3, want_loss=False)
+    last = [gs_net.loss_grad(t, q)[0] for t, q in zip(targets, labels)]
+    print(f"GS-50 labels: mean loss {np.mean(first):.4f} -> {np.mean(last):.4f}")
+    assert np.mean(last) < np.mean(first)
+
+    path = str(tmp_path / "net.bin")
+    net.save(path)
+    net2 = holo.Cnn(path=path)
+    np.testing.assert_array_equal(net2.params(), net.params())
+    assert torch.equal(net.infer(targets[0]), net2.infer(targets[0]))
+    # the restored Adam state continues identically
+    net.train_step(targets[1], learnable[1], 2e-3)
+    net2.train_step(targets[1], learnable[1], 2e-3)
+    np.testing.assert_array_equal(net2.params(), net.params())

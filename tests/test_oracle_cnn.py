@@ -77,3 +77,44 @@ def test_adam_worked_step(orc):
     np.testing.assert_allclose(p, [0.9, -1.9], atol=1e-7)
     np.testing.assert_allclose(m, [0.2, -0.05])
     np.testing.assert_allclose(v, [0.004, 0.00025])
+
+
+def test_bf16_rounding_values(orc):
+    # BF16 keeps 8 significant bits: spacing 2^-7 on [1, 2)
+    assert orc.bf16(1.0) == 1.0
+    assert orc.bf16(1.0 + 2.0 ** -8) == 1.0                        # tie -> even (1.0)
+    assert orc.bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6        # tie -> even (1 + 2^-6)
+    assert orc.bf16(1.0 + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7
+    assert orc.bf16(-(1.0 + 2.0 ** -8 + 2.0 ** -20)) == -(1.0 + 2.0 ** -7)
+    assert orc.bf16(0.0) == 0.0
+    assert orc.bf16(3.0e38) == 226 / 128 * 2.0 ** 127               # 3e38 = 225.7/128 * 2^127
+    rng = np.random.default_rng(3)
+    for v in rng.standard_normal(200) * 10.0 ** rng.integers(-20, 20, 200):
+        r = orc.bf16(v)
+        m, e = np.frexp(r)
+        assert m * 256 == np.round(m * 256)                        # 8 significant bits
+        assert abs(r - v) <= 2.0 ** -9 * 2.0 ** e                  # half a spacing of r's binade
+
+
+def test_bf16_storage_model(orc):
+    """Rounding sits where the activations and hidden gradients are stored;
+    the outcome stays within the BF16 error of the exact network."""
+    rng = np.random.default_rng(4)
+    C, ny, nx = 4, 8, 8
+    n = orc.cnn_nparams(C)
+    params = rng.standard_normal(n) * 0.4
+    t = (0.2 + rng.random((ny, nx))).astype(np.float32)
+    acts, out2, ph = orc.cnn_forward(params, C, t)
+    acts_b, out2_b, ph_b = orc.cnn_forward(params, C, t, bf16_store=True)
+    rb = np.vectorize(orc.bf16)
+    np.testing.assert_array_equal(acts_b[0], rb(acts[0]))         # layer 1 sees the same input
+    np.testing.assert_array_equal(acts_b, rb(acts_b))             # everything stored is BF16
+    assert not np.array_equal(acts_b[3], acts[3])
+    rel = np.linalg.norm(out2_b - out2) / np.linalg.norm(out2)
+    assert 0 < rel < 4 * 2.0 ** -8
+    q = np.exp(1j * rng.uniform(0, 2 * np.pi, (ny, nx)))
+    l0, g0 = orc.cnn_backward(params, C, t, q)
+    l1, g1 = orc.cnn_backward(params, C, t, q, bf16_store=True)
+    assert l1 == pytest.approx(orc.cnn_loss(ph_b, q, t), rel=1e-13)
+    assert abs(l1 - l0) < 0.05 * l0
+    assert np.linalg.norm(g1 - g0) / np.linalg.norm(g0) < 0.05
