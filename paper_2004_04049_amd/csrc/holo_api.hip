@@ -1152,7 +1152,7 @@ void cnn_free_images(holo_cnn* c)
 holo_status cnn_images(holo_cnn* c, int64_t nx, int64_t ny)
 {
     const size_t npx = (size_t)nx * (size_t)ny;
-    const int rpb = ny >= 256 ? (int)(ny / 256) : 1;
+    const int rpb = 1;   // one image row per weight-gradient block: ny blocks
     const int nblk = (int)((ny + rpb - 1) / rpb);
     if (npx <= c->img_px && nblk <= c->img_rows) {
         c->b.rows_per_block = rpb;

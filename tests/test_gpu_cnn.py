@@ -145,3 +145,22 @@ def test_training_reduces_loss_and_roundtrip(holo, tmp_path):
     net.train_step(targets[1], learnable[1], 2e-3)
     net2.train_step(targets[1], learnable[1], 2e-3)
     np.testing.assert_array_equal(net2.params(), net.params())
+
+
+def test_seed_comparison_runs(holo):
+    """The learned-seed comparison reports iterations that are consistent with
+    the per-iteration NMSE it was computed from."""
+    from paper_2004_04049_amd import seed
+    n = 64
+    targets = [torch.from_numpy(synth.blob_target(n, n, synth.SEED_CNN_HELDOUT0 + i)).cuda() for i in range(3)]
+    lut = holo.Lut(4096, 1)
+    net = holo.Cnn(seed=2)
+    res = seed.compare(net, targets, lut, n_ref=20, max_iter=40)
+    assert res["n"] == 3 and 0 <= res["reached"] <= 3
+    for r, t in zip(res["rows"], targets):
+        run = holo.gs_iterate(t, 40, None, 0, init_phasor=net.infer(t), want_final=False)
+        if r["iters"] is not None:
+            assert run["nmse"][r["iters"] - 1] <= r["goal_nmse"]
+            assert r["iters"] == 1 or run["nmse"][r["iters"] - 2] > r["goal_nmse"]
+        else:
+            assert np.all(run["nmse"] > r["goal_nmse"])
