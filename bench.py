@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -200,28 +202,51 @@ def main():
 def bench_batched(h, synth, torch, dev):
     """64 frames, sizes uniform over {256, 512, 1024, 2048}^2, n_sf uniform in
     8..24 (seed 14), targets seeds 1000+f, LUT 10007 chained across frames, one
-    graph launch per batch."""
+    graph launch per batch; DFT stages in FP32, then BF16 and FP16 on the
+    matrix cores, each reported against the FP32 run of the same batch (bit
+    mismatch, NMSE and replay-intensity differences per frame)."""
     layout = synth.batch_layout(64, synth.SEED_BATCH)
     targets = [torch.from_numpy(synth.blob_target(n, n, synth.SEED_BATCH_TARGET0 + f)).to(dev)
                for f, (n, _) in enumerate(layout)]
     nsfs = [k for _, k in layout]
     lut = h.Lut(10007, synth.SEED_LUT)
-    nm = torch.zeros((64, 2), dtype=torch.float64, device=dev)
-    bits, _, c = h.ospr_generate_batched(targets, nsfs, lut, 0, nmse_out=nm)
-    torch.cuda.synchronize()
-    reps = 5
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        bits, _, c = h.ospr_generate_batched(targets, nsfs, lut, c, bits=bits, nmse_out=nm)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
     pxsf = sum(n * n * k for n, k in layout)
     canon = sum(n * n * (k * 32.125 + 8) for n, k in layout)
-    return {"frames": 64, "px_subframes": pxsf, "ms_per_batch": round(1e3 * dt, 3),
-            "px_subframes_per_s": round(pxsf / dt, 1), "canonical_GB": round(canon / 1e9, 3),
-            "hbm_frac": round(canon / dt / 1e9 / HBM_PEAK_GBS, 4), "dtype": "f32",
-            "sizes": {str(s_): sum(1 for n, _ in layout if n == s_) for s_ in (256, 512, 1024, 2048)},
-            "nmse_mean": float(nm[:, 0].mean().item())}
+    res = {"frames": 64, "px_subframes": pxsf, "canonical_GB": round(canon / 1e9, 3),
+           "sizes": {str(s_): sum(1 for n, _ in layout if n == s_) for s_ in (256, 512, 1024, 2048)}}
+    ref = None
+    for prec, name in ((h.FP32, "fp32"), (h.BF16, "bf16"), (h.FP16, "fp16")):
+        nm = torch.zeros((64, 2), dtype=torch.float64, device=dev)
+        recons = [torch.empty_like(t) for t in targets]
+        bits, _, c = h.ospr_generate_batched(targets, nsfs, lut, 0, recons=recons, nmse_out=nm, precision=prec)
+        torch.cuda.synchronize()
+        out_bits = [b.clone() for b in bits]
+        out_nm = nm.cpu().numpy().copy()
+        out_rec = [r.clone() for r in recons]
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            bits, _, c = h.ospr_generate_batched(targets, nsfs, lut, c, bits=bits, nmse_out=nm, precision=prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        r = {"ms_per_batch": round(1e3 * dt, 3), "px_subframes_per_s": round(pxsf / dt, 1),
+             "hbm_frac": round(canon / dt / 1e9 / HBM_PEAK_GBS, 4), "nmse_mean": float(out_nm[:, 0].mean())}
+        if ref is None:
+            ref = (out_bits, out_nm, out_rec)
+        else:
+            mism, nrel, irel = [], [], []
+            for f, (n, k) in enumerate(layout):
+                a = h.unpack_bits(out_bits[f], n * n)
+                b = h.unpack_bits(ref[0][f], n * n)
+                mism.append(float((a != b).mean()))
+                nrel.append(abs(out_nm[f, 0] - ref[1][f, 0]) / ref[1][f, 0])
+                irel.append(float(torch.linalg.vector_norm(out_rec[f] - ref[2][f]) /
+                                  torch.linalg.vector_norm(ref[2][f])))
+            r["vs_fp32"] = {"bit_mismatch_mean": float(np.mean(mism)), "bit_mismatch_max": float(np.max(mism)),
+                            "nmse_rel_mean": float(np.mean(nrel)), "nmse_rel_max": float(np.max(nrel)),
+                            "ibar_rel_l2_mean": float(np.mean(irel)), "ibar_rel_l2_max": float(np.max(irel))}
+        res[name] = r
+    return res
 
 
 def bench_gs(h, synth, torch, dev):

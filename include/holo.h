@@ -51,7 +51,18 @@ enum {
     HOLO_EDEVICE = -4       /* a HIP call failed; text in holo_last_error()  */
 };
 
-/* Arithmetic of the transform stages. */
+/* Arithmetic of the transform stages.
+ *   HOLO_FP32  radix stages in FP32 on the vector ALUs.
+ *   HOLO_BF16, HOLO_FP16  every radix-R stage of every transform as a small
+ *              DFT-matrix product on the matrix cores: data rounded once per
+ *              stage to BF16 (8 significant bits) or FP16 (11), DFT matrix
+ *              split into two operand-format terms (hi + lo), FP32
+ *              accumulation; inter-stage twiddles, pointwise steps and all
+ *              sums stay FP32/FP64.  Sides of 256 and more only.  Results are
+ *              not bit-exact: binarisation flips pixels whose Re H is within
+ *              the rounding error of 0.
+ * Entry points that take a precision return HOLO_EUNSUPPORTED for BF16/FP16
+ * below 256 and HOLO_EINVAL for other values. */
 enum { HOLO_FP32 = 0, HOLO_BF16 = 1, HOLO_FP16 = 2 };
 
 /* Flags. */
@@ -108,7 +119,7 @@ HOLO_API uint32_t holo_lut_check(uint64_t n_lut, int64_t nx, int64_t ny, int32_t
  *   nmse2      {NMSE vs T^2, NMSE vs the point-symmetrised T^2} or NULL, where
  *              NMSE(I, W) = 1 - (sum I W)^2 / (sum I^2 * sum W^2), the
  *              optimal-scale normalised MSE, accumulated in FP64
- *   precision  HOLO_FP32 (BF16/FP16 through holo_ospr_generate_batched)
+ *   precision  HOLO_FP32, HOLO_BF16 or HOLO_FP16 (stages of all transforms)
  * Errors: HOLO_EINVAL for null target/lut/cursor/holo_bits or n_sf < 1.
  * ------------------------------------------------------------------------- */
 HOLO_API holo_status holo_ospr_generate(const float* target, int64_t nx, int64_t ny, int32_t n_sf,
@@ -229,10 +240,11 @@ HOLO_API void holo_cnn_free(holo_cnn* cnn);
 
 /* ---------------------------------------------------------------------------
  * holo_fft2 -- the unitary transform pair itself: Eq. (1) for sign = -1,
- * Eq. (2) for sign = +1, complex [ny][nx] device in -> device out (may alias).
+ * Eq. (2) for sign = +1, complex [ny][nx] device in -> device out (may alias),
+ * with the stage arithmetic `precision` (HOLO_FP32, HOLO_BF16, HOLO_FP16).
  * ------------------------------------------------------------------------- */
 HOLO_API holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t ny, int32_t sign,
-                               void* hip_stream);
+                               int32_t precision, void* hip_stream);
 
 /* ---------------------------------------------------------------------------
  * Launch plans and the autotuner (implementation choices, not part of the

@@ -39,7 +39,7 @@ SIGNATURES = {
     "holo_gs_iterate": (_I32, [_P, _I64, _I64, _I32, _P, C.POINTER(_U64), _P, _P, _P, _P, _P, _P, _P, _I32,
                                _U32, _P]),
     "holo_reconstruct_nmse": (_I32, [_P, _I32, _I64, _I64, _I32, _P, _P, _P, _U32, _P]),
-    "holo_fft2": (_I32, [_P, _P, _I64, _I64, _I32, _P]),
+    "holo_fft2": (_I32, [_P, _P, _I64, _I64, _I32, _I32, _P]),
     "holo_shutdown": (None, []),
     "holo_prof_enable": (_I32, [_I32]),
     "holo_prof_read": (_I32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(_I64)]),
@@ -174,7 +174,7 @@ def _nmse_buf(n, device_out):
 
 
 def ospr_generate(target, n_sf: int, lut: Lut, cursor: int, bits=None, recon=None, want_nmse=True,
-                  nmse_out=None, stream=None):
+                  nmse_out=None, stream=None, precision: int = FP32):
     """holo_ospr_generate.  Returns (bits, nmse2 or None, new_cursor).
     target: cuda float32 [ny, nx]; bits: cuda int32 [n_sf, nx*ny/32] (allocated
     if None); recon: cuda float32 [ny, nx] or None; nmse_out: cuda float64 [2]
@@ -191,7 +191,7 @@ def ospr_generate(target, n_sf: int, lut: Lut, cursor: int, bits=None, recon=Non
         nm, nm_p, flags = _nmse_buf(2, nmse_out)
     cur = C.c_uint64(cursor)
     _check(lib().holo_ospr_generate(_ptr(target), nx, ny, n_sf, lut.handle, C.byref(cur), _ptr(bits),
-                                    _ptr(recon), nm_p, FP32, flags, _stream(stream)))
+                                    _ptr(recon), nm_p, precision, flags, _stream(stream)))
     return bits, nm, int(cur.value)
 
 
@@ -245,14 +245,14 @@ def reconstruct_nmse(holo, levels: int, nx: int, ny: int, n_sf: int, target, rec
     return nm
 
 
-def fft2(x, sign: int, out=None, stream=None):
+def fft2(x, sign: int, out=None, stream=None, precision: int = FP32):
     """holo_fft2: unitary Eq. (1) (sign -1) or Eq. (2) (sign +1) of a complex64 [ny, nx] tensor."""
     _dev(x, torch.complex64, None, "x")
     ny, nx = x.shape
     if out is None:
         out = torch.empty_like(x)
     _dev(out, torch.complex64, (ny, nx), "out")
-    _check(lib().holo_fft2(_ptr(x), _ptr(out), nx, ny, sign, _stream(stream)))
+    _check(lib().holo_fft2(_ptr(x), _ptr(out), nx, ny, sign, precision, _stream(stream)))
     return out
 
 
@@ -338,7 +338,7 @@ def set_graphs(on: bool):
 
 
 def ospr_generate_batched(targets, n_sfs, lut: Lut, cursor: int, bits=None, recons=None, nmse_out=None,
-                          stream=None):
+                          stream=None, precision: int = FP32):
     """holo_ospr_generate_batched.  targets: list of cuda float32 [ny, nx];
     n_sfs: list of sub-frame counts; bits: list of int32 [n_sf, nx*ny/32]
     (allocated if None).  Returns (bits list, nmse [n, 2] or None, cursor).
@@ -364,8 +364,8 @@ def ospr_generate_batched(targets, n_sfs, lut: Lut, cursor: int, bits=None, reco
         nm = np.zeros((n, 2))
         nm_p, flags = nm.ctypes.data_as(C.c_void_p), 0
     cur = C.c_uint64(cursor)
-    _check(lib().holo_ospr_generate_batched(C.cast(arr, C.c_void_p), n, lut.handle, C.byref(cur), nm_p, FP32,
-                                            flags, _stream(stream)))
+    _check(lib().holo_ospr_generate_batched(C.cast(arr, C.c_void_p), n, lut.handle, C.byref(cur), nm_p,
+                                            precision, flags, _stream(stream)))
     return bits, nm, int(cur.value)
 
 

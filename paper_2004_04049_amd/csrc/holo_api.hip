@@ -632,6 +632,23 @@ uint32_t holo_lut_check(uint64_t n_lut, int64_t nx, int64_t ny, int32_t n_sf)
     return w;
 }
 
+namespace holo {
+namespace {
+// DFT-stage precision: FP32 everywhere; BF16/FP16 matrix-core stages for
+// sides of 256 and more.
+holo_status check_precision(int32_t precision, int64_t nx, int64_t ny)
+{
+    if (precision == HOLO_FP32) return HOLO_OK;
+    if (precision != HOLO_BF16 && precision != HOLO_FP16)
+        return fail(HOLO_EINVAL, "precision must be HOLO_FP32, HOLO_BF16 or HOLO_FP16 (got %d)", precision);
+    if (nx < 256 || ny < 256)
+        return fail(HOLO_EUNSUPPORTED, "BF16/FP16 DFT stages need nx, ny >= 256 (got %lld x %lld)", (long long)nx,
+                    (long long)ny);
+    return HOLO_OK;
+}
+}  // namespace
+}  // namespace holo
+
 holo_status holo_ospr_generate(const float* target, int64_t nx, int64_t ny, int32_t n_sf, const holo_lut* lut,
                                uint64_t* cursor, uint32_t* holo_bits, float* recon, double* nmse2,
                                int32_t precision, uint32_t flags, void* hip_stream)
@@ -641,12 +658,13 @@ holo_status holo_ospr_generate(const float* target, int64_t nx, int64_t ny, int3
     if (!pow2_in_range(nx) || !pow2_in_range(ny))
         return fail(HOLO_EUNSUPPORTED, "nx, ny must be powers of two in [16, 2048] (got %lld x %lld)",
                     (long long)nx, (long long)ny);
-    if (precision != HOLO_FP32) return fail(HOLO_EUNSUPPORTED, "holo_ospr_generate computes in FP32 only");
+    holo_status st = check_precision(precision, nx, ny);
+    if (st) return st;
     int device = 0;
     HIP_TRY(hipGetDevice(&device));
-    holo_status st = check_lut(lut, device);
-    if (st) return st;
-    const LaunchCfg cfg = plan_get(PLAN_OSPR, nx, ny, n_sf);
+    if ((st = check_lut(lut, device))) return st;
+    LaunchCfg cfg = plan_get(PLAN_OSPR, nx, ny, n_sf);
+    cfg.prec = precision;
     if ((st = ospr_run(device, target, nx, ny, n_sf, lut, *cursor, holo_bits, recon, nmse2, flags,
                        (hipStream_t)hip_stream, cfg)))
         return st;
@@ -712,23 +730,27 @@ holo_status holo_gs_iterate(const float* target, int64_t nx, int64_t ny, int32_t
     return HOLO_OK;
 }
 
-holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t ny, int32_t sign, void* hip_stream)
+holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t ny, int32_t sign, int32_t precision,
+                      void* hip_stream)
 {
     if (!in || !out) return fail(HOLO_EINVAL, "in and out are required");
     if (sign != 1 && sign != -1) return fail(HOLO_EINVAL, "sign must be +1 or -1");
     if (!pow2_in_range(nx) || !pow2_in_range(ny))
         return fail(HOLO_EUNSUPPORTED, "nx, ny must be powers of two in [16, 2048]");
+    holo_status st = check_precision(precision, nx, ny);
+    if (st) return st;
     int device = 0;
     HIP_TRY(hipGetDevice(&device));
     hipStream_t s = (hipStream_t)hip_stream;
-    holo_status st;
     const float2 *tw_x, *tw_y;
     if ((st = get_twiddles(device, (int)nx, s, &tw_x))) return st;
     if ((st = get_twiddles(device, (int)ny, s, &tw_y))) return st;
     void* ws;
     if ((st = get_workspace(device, s, sizeof(float2) * (size_t)nx * ny, &ws))) return st;
+    LaunchCfg cfg = default_cfg();
+    cfg.prec = precision;
     LAUNCH("fft2", s, launch_fft2((const float2*)in, (float2*)ws, (float2*)out, (int)nx, (int)ny, sign, tw_x, tw_y,
-                        default_cfg(), s));
+                                  cfg, s));
     return HOLO_OK;
 }
 
@@ -744,8 +766,8 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
         if (fr.n_sf < 1) return fail(HOLO_EINVAL, "frame %d: n_sf must be >= 1", f);
         if (!pow2_in_range(fr.nx) || !pow2_in_range(fr.ny))
             return fail(HOLO_EUNSUPPORTED, "frame %d: nx, ny must be powers of two in [16, 2048]", f);
+        if (holo_status e = check_precision(precision, fr.nx, fr.ny)) return e;
     }
-    if (precision != HOLO_FP32) return fail(HOLO_EUNSUPPORTED, "precision %d is not available", precision);
     int device = 0;
     HIP_TRY(hipGetDevice(&device));
     holo_status st = check_lut(lut, device);
@@ -761,6 +783,7 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
     for (int f = 0; f < n_frames; ++f) {
         const holo_frame& fr = frames[f];
         cfg[f] = plan_get(PLAN_OSPR, fr.nx, fr.ny, fr.n_sf);
+        cfg[f].prec = precision;
         lay[f] = ospr_layout(fr.nx, fr.ny, fr.n_sf, cfg[f]);
         off[f] = total;
         total += (uint64_t)fr.n_sf * (uint64_t)fr.nx * (uint64_t)fr.ny;
@@ -839,7 +862,8 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
                                        (uintptr_t)fr.holo_bits, (uintptr_t)fr.recon, (uintptr_t)(off[f] % L),
                                        (uintptr_t)c.cols_per_block, (uintptr_t)c.rows_per_block,
                                        (uintptr_t)c.ksplit, (uintptr_t)c.recon_cols_per_block,
-                                       (uintptr_t)(intptr_t)c.pad, (uintptr_t)(intptr_t)c.chunk});
+                                       (uintptr_t)(intptr_t)c.pad, (uintptr_t)(intptr_t)c.chunk,
+                                       (uintptr_t)c.prec});
         }
         hipGraphExec_t exec = nullptr;
         {

@@ -15,6 +15,7 @@ struct LaunchCfg {
     int recon_cols_per_block = 0;  // C of the reconstruction column pass
     int pad = -1;                  // extra elements per row of internal fields (-1 = heuristic)
     int chunk = 0;                 // OSPR sub-frames per generation chunk (0 = all at once)
+    int prec = 0;                  // DFT stages: 0 FP32 registers, 1 BF16 MFMA, 2 FP16 MFMA (sizes >= 256)
 };
 
 // Row pitch (complex elements) of the library's internal [rows][nx] fields:

@@ -17,6 +17,7 @@
 // positive scale.
 #include "fft_engine.hpp"
 #include "kernels.hpp"
+#include "mfma_dft.hpp"
 
 namespace holo {
 
@@ -33,20 +34,43 @@ namespace holo {
         default: return hipErrorInvalidValue;              \
     }
 
-// Column-tile width C (columns transformed side by side by one block).
-#define HOLO_SWITCH_C(c, ...)                                    \
-    switch (c) {                                                 \
-        case 2: { constexpr int C_ = 2; __VA_ARGS__; } break;    \
-        case 4: { constexpr int C_ = 4; __VA_ARGS__; } break;    \
-        case 8: { constexpr int C_ = 8; __VA_ARGS__; } break;    \
-        case 16: { constexpr int C_ = 16; __VA_ARGS__; } break;  \
-        default: return hipErrorInvalidValue;                    \
+// Sizes with a matrix-core variant (blocks of whole waves at every plan).
+#define HOLO_SWITCH_NM(n, ...)                             \
+    switch (n) {                                           \
+        case 256: { constexpr int N_ = 256; __VA_ARGS__; } break;   \
+        case 512: { constexpr int N_ = 512; __VA_ARGS__; } break;   \
+        case 1024: { constexpr int N_ = 1024; __VA_ARGS__; } break; \
+        case 2048: { constexpr int N_ = 2048; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue;              \
     }
-#define HOLO_SWITCH_C816(c, ...)                                 \
-    switch (c) {                                                 \
-        case 8: { constexpr int C_ = 8; __VA_ARGS__; } break;    \
-        case 16: { constexpr int C_ = 16; __VA_ARGS__; } break;  \
-        default: return hipErrorInvalidValue;                    \
+// Size and DFT-stage precision (0 FP32 registers, 1 BF16 MFMA, 2 FP16 MFMA).
+#define HOLO_SWITCH_NP(n, p, ...)                                               \
+    if ((p) == 0) {                                                             \
+        HOLO_SWITCH_N(n, { constexpr int P_ = 0; __VA_ARGS__; })                \
+    } else if ((p) == 1) {                                                      \
+        HOLO_SWITCH_NM(n, { constexpr int P_ = 1; __VA_ARGS__; })               \
+    } else if ((p) == 2) {                                                      \
+        HOLO_SWITCH_NM(n, { constexpr int P_ = 2; __VA_ARGS__; })               \
+    } else {                                                                    \
+        return hipErrorInvalidValue;                                            \
+    }
+
+// Column-tile width C (columns transformed side by side by one block).
+// Matrix-core variants (P_ != 0) exist for C = 8 only (the launchers pick
+// C = 8 for them), so every other case maps to that instantiation.
+#define HOLO_SWITCH_C(c, ...)                                                \
+    switch (c) {                                                             \
+        case 2: { constexpr int C_ = P_ ? 8 : 2; __VA_ARGS__; } break;       \
+        case 4: { constexpr int C_ = P_ ? 8 : 4; __VA_ARGS__; } break;       \
+        case 8: { constexpr int C_ = 8; __VA_ARGS__; } break;                \
+        case 16: { constexpr int C_ = P_ ? 8 : 16; __VA_ARGS__; } break;     \
+        default: return hipErrorInvalidValue;                                \
+    }
+#define HOLO_SWITCH_C816(c, ...)                                             \
+    switch (c) {                                                             \
+        case 8: { constexpr int C_ = 8; __VA_ARGS__; } break;                \
+        case 16: { constexpr int C_ = P_ ? 8 : 16; __VA_ARGS__; } break;     \
+        default: return hipErrorInvalidValue;                                \
     }
 
 // Runtime LDS addressing (block shape chosen at launch).
@@ -55,10 +79,12 @@ struct RowAddrR {
     __device__ __forceinline__ int operator()(int p) const { return base + p; }
 };
 
-static int row_block_rows(int n, int nrows, int planned)
+static int row_block_rows(int n, int nrows, int planned, int prec = 0)
 {
     const int T = n / kP;
     int rows = planned > 0 ? planned : (256 / T > 0 ? 256 / T : 1);
+    if (prec && rows * T < 64) rows = 64 / T;   // matrix cores: whole waves
+    if (prec && rows * T > 256) rows = 256 / T; // ... and at most 256 threads (register budget)
     if (rows * T > 1024) rows = 1024 / T;
     if (rows < 1) rows = 1;
     while (rows > 1 && (nrows % rows)) rows >>= 1;
@@ -105,8 +131,8 @@ hipError_t launch_twiddle_gen(float2* tw, int n, hipStream_t s)
 // -------------------------------------------------------------------------
 // Plain 2D transform (used by the unitary holo_fft2 entry point and tests).
 // -------------------------------------------------------------------------
-template <int N, int SIGN>
-__global__ __launch_bounds__(1024) void k_fft_rows(const float2* __restrict__ in, float2* __restrict__ out,
+template <int N, int SIGN, int P>
+__global__ __launch_bounds__(P ? 256 : 1024) void k_fft_rows(const float2* __restrict__ in, float2* __restrict__ out,
                                                    int nrows, const float2* __restrict__ tw)
 {
     extern __shared__ float2 lds[];
@@ -118,13 +144,13 @@ __global__ __launch_bounds__(1024) void k_fft_rows(const float2* __restrict__ in
     const float2* src = in + y * N;
 #pragma unroll
     for (int m = 0; m < kP; ++m) v[m] = src[t + T * m];
-    fft_stages<N, SIGN, RowAddrR, (N / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<N>::v}, tw);
+    fft_any<N, SIGN, P, (N / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<N>::v}, RowsOf<N>{}, tw);
     float2* dst = out + y * N;
 #pragma unroll
     for (int m = 0; m < kP; ++m) dst[t + T * m] = v[m];
 }
 
-template <int N, int SIGN, int C>
+template <int N, int SIGN, int C, int P>
 __global__ __launch_bounds__(C * (N / kP)) void k_fft_cols(const float2* __restrict__ in, float2* __restrict__ out,
                                                            int nx, float scale, const float2* __restrict__ tw)
 {
@@ -137,7 +163,7 @@ __global__ __launch_bounds__(C * (N / kP)) void k_fft_cols(const float2* __restr
     float2 v[kP];
 #pragma unroll
     for (int m = 0; m < kP; ++m) v[m] = ld_off(in + x0 + m * mstride, toff);
-    fft_stages<N, SIGN>(v, t, lds, ColAddr<C>{c}, tw);
+    fft_any<N, SIGN, P>(v, t, lds, ColAddr<C>{c}, ColsOf<N, C>{}, tw);
 #pragma unroll
     for (int m = 0; m < kP; ++m) st_off(out + x0 + m * mstride, toff, make_float2(v[m].x * scale, v[m].y * scale));
 }
@@ -152,34 +178,36 @@ hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int n
                        const float2* tw_x, const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
 {
     {
-        const int rows = row_block_rows(nx, ny, cfg.rows_per_block);
-        HOLO_SWITCH_N(nx, {
+        const int rows = row_block_rows(nx, ny, cfg.rows_per_block, cfg.prec);
+        HOLO_SWITCH_NP(nx, cfg.prec, {
             constexpr int T = N_ / kP;
             size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
             if (sign < 0) {
-                allow_lds(k_fft_rows<N_, -1>, lds);
-                hipLaunchKernelGGL((k_fft_rows<N_, -1>), dim3(ny / rows), dim3(rows * T), lds, s, in, tmp, ny, tw_x);
+                allow_lds(k_fft_rows<N_, -1, P_>, lds);
+                hipLaunchKernelGGL((k_fft_rows<N_, -1, P_>), dim3(ny / rows), dim3(rows * T), lds, s, in, tmp, ny,
+                                   tw_x);
             } else {
-                allow_lds(k_fft_rows<N_, 1>, lds);
-                hipLaunchKernelGGL((k_fft_rows<N_, 1>), dim3(ny / rows), dim3(rows * T), lds, s, in, tmp, ny, tw_x);
+                allow_lds(k_fft_rows<N_, 1, P_>, lds);
+                hipLaunchKernelGGL((k_fft_rows<N_, 1, P_>), dim3(ny / rows), dim3(rows * T), lds, s, in, tmp, ny,
+                                   tw_x);
             }
         });
     }
     {
-        const int C = col_block_cols(ny, nx, 1, cfg.cols_per_block, 2);
+        const int C = cfg.prec ? 8 : col_block_cols(ny, nx, 1, cfg.cols_per_block, 2);
         const float scale = (float)(1.0 / sqrt((double)nx * (double)ny));
-        HOLO_SWITCH_N(ny, HOLO_SWITCH_C(C, {
+        HOLO_SWITCH_NP(ny, cfg.prec, HOLO_SWITCH_C(C, {
             constexpr int T = N_ / kP;
             if (C_ * T <= 1024) {
                 size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
                 if (sign < 0) {
-                    allow_lds(k_fft_cols<N_, -1, C_>, lds);
-                    hipLaunchKernelGGL((k_fft_cols<N_, -1, C_>), dim3(nx / C_), dim3(C_ * T), lds, s, tmp, out, nx,
-                                       scale, tw_y);
+                    allow_lds(k_fft_cols<N_, -1, C_, P_>, lds);
+                    hipLaunchKernelGGL((k_fft_cols<N_, -1, C_, P_>), dim3(nx / C_), dim3(C_ * T), lds, s, tmp, out,
+                                       nx, scale, tw_y);
                 } else {
-                    allow_lds(k_fft_cols<N_, 1, C_>, lds);
-                    hipLaunchKernelGGL((k_fft_cols<N_, 1, C_>), dim3(nx / C_), dim3(C_ * T), lds, s, tmp, out, nx,
-                                       scale, tw_y);
+                    allow_lds(k_fft_cols<N_, 1, C_, P_>, lds);
+                    hipLaunchKernelGGL((k_fft_cols<N_, 1, C_, P_>), dim3(nx / C_), dim3(C_ * T), lds, s, tmp, out,
+                                       nx, scale, tw_y);
                 }
             }
         }));
@@ -191,8 +219,8 @@ hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int n
 // K1: LUT phase randomisation fused with the inverse row transform.
 // Grid: (ny / rows) * n_sf blocks of rows * (nx/16) threads.
 // -------------------------------------------------------------------------
-template <int NX>
-__global__ __launch_bounds__(1024) void k_ospr_rows(const float* __restrict__ target, int ny,
+template <int NX, int P>
+__global__ __launch_bounds__(P ? 256 : 1024) void k_ospr_rows(const float* __restrict__ target, int ny,
                                                     const float2* __restrict__ lut, uint32_t n_lut, uint64_t c0,
                                                     const uint64_t* __restrict__ c0_base,
                                                     float2* __restrict__ x1, const float2* __restrict__ tw,
@@ -224,7 +252,7 @@ __global__ __launch_bounds__(1024) void k_ospr_rows(const float* __restrict__ ta
         idx += step;
         if (idx >= n_lut) idx -= n_lut;
     }
-    fft_stages<NX, 1, RowAddrR, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, tw);
+    fft_any<NX, 1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, RowsOf<NX>{}, tw);
     const size_t plane = (size_t)ny * pitch;
     const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
     const uint32_t ooff = ((uint32_t)y * (uint32_t)pitch + (uint32_t)t) * 8u;
@@ -236,12 +264,12 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
                             uint32_t n_lut, uint64_t c0, const uint64_t* c0_base, float2* x1, const float2* tw_x,
                             const LaunchCfg& cfg, hipStream_t s)
 {
-    const int rows = row_block_rows(nx, ny, cfg.rows_per_block);
-    HOLO_SWITCH_N(nx, {
+    const int rows = row_block_rows(nx, ny, cfg.rows_per_block, cfg.prec);
+    HOLO_SWITCH_NP(nx, cfg.prec, {
         constexpr int T = N_ / kP;
         size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
-        allow_lds(k_ospr_rows<N_>, lds);
-        hipLaunchKernelGGL((k_ospr_rows<N_>), dim3((ny / rows) * n_sf), dim3(rows * T), lds, s, target, ny, lut,
+        allow_lds(k_ospr_rows<N_, P_>, lds);
+        hipLaunchKernelGGL((k_ospr_rows<N_, P_>), dim3((ny / rows) * n_sf), dim3(rows * T), lds, s, target, ny, lut,
                            n_lut, c0, c0_base, x1, tw_x, row_pitch(nx, cfg));
     });
     return hipGetLastError();
@@ -254,7 +282,7 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
 // column x0 + c, rows t + T*m.  The C lanes of a row segment are adjacent in
 // the wave, so a ballot yields that row's C bits in raster order.
 // -------------------------------------------------------------------------
-template <int NY, int C>
+template <int NY, int C, int P>
 __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __restrict__ x1, int nx,
                                                             uint32_t* __restrict__ bits, float2* __restrict__ x2,
                                                             const float2* __restrict__ tw, int pitch)
@@ -277,7 +305,7 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __res
     float2 v[kP];
 #pragma unroll
     for (int m = 0; m < kP; ++m) v[m] = buf_ld2(rin, voff, m * mst);
-    fft_stages<NY, 1>(v, t, lds, ColAddr<C>{c}, tw);
+    fft_any<NY, 1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw);
 
     // nearest of {+1, -1}: bit = (Re H < 0); Re H = 0 -> +1
     const auto rbits = make_rsrc(bits + (size_t)k * (npix / 32), (uint32_t)(npix / 8));
@@ -294,7 +322,7 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __res
         }
         v[m] = make_float2(neg ? -1.0f : 1.0f, 0.0f);
     }
-    fft_stages<NY, -1>(v, t, lds, ColAddr<C>{c}, tw);
+    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw);
     // rows v = t + T*m <= NY/2: every slot m < 8, and m = 8 for t = 0 only
     const size_t hplane = (size_t)(NY / 2 + 1) * pitch;
     const auto rout = make_rsrc(x2 + (size_t)k * hplane, (uint32_t)(hplane * 8));
@@ -306,13 +334,13 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __res
 hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
                             const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
 {
-    const int C = col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8);
-    HOLO_SWITCH_N(ny, HOLO_SWITCH_C816(C, {
+    const int C = cfg.prec ? 8 : col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8);
+    HOLO_SWITCH_NP(ny, cfg.prec, HOLO_SWITCH_C816(C, {
         constexpr int T = N_ / kP;
         if (C_ * T <= 1024) {
             size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
-            allow_lds(k_ospr_cols<N_, C_>, lds);
-            hipLaunchKernelGGL((k_ospr_cols<N_, C_>), dim3((nx / C_) * n_sf), dim3(C_ * T), lds, s, x1, nx, bits,
+            allow_lds(k_ospr_cols<N_, C_, P_>, lds);
+            hipLaunchKernelGGL((k_ospr_cols<N_, C_, P_>), dim3((nx / C_) * n_sf), dim3(C_ * T), lds, s, x1, nx, bits,
                                x2, tw_y, row_pitch(nx, cfg));
         }
     }));
@@ -339,7 +367,7 @@ __device__ __forceinline__ float2 level8_phasor(int m)
     }
 }
 
-template <int NY, int C>
+template <int NY, int C, int P>
 __global__ __launch_bounds__(C * (NY / kP)) void k_recon_cols(const void* __restrict__ holo, int levels, int nx,
                                                              float2* __restrict__ x2, const float2* __restrict__ tw,
                                                              int pitch)
@@ -367,7 +395,7 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_recon_cols(const void* __rest
 #pragma unroll
         for (int m = 0; m < kP; ++m) v[m] = level8_phasor(cd[(size_t)(t + T * m) * nx + x]);
     }
-    fft_stages<NY, -1>(v, t, lds, ColAddr<C>{c}, tw);
+    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw);
     const int vmax = levels == 2 ? NY / 2 : NY - 1;
     float2* dst = x2 + (size_t)k * (vmax + 1) * pitch;
 #pragma unroll
@@ -380,13 +408,13 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_recon_cols(const void* __rest
 hipError_t launch_recon_cols(const void* holo, int levels, int nx, int ny, int n_sf, float2* x2,
                              const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
 {
-    const int C = col_block_cols(ny, nx, n_sf, cfg.recon_cols_per_block, 2);
-    HOLO_SWITCH_N(ny, HOLO_SWITCH_C(C, {
+    const int C = cfg.prec ? 8 : col_block_cols(ny, nx, n_sf, cfg.recon_cols_per_block, 2);
+    HOLO_SWITCH_NP(ny, cfg.prec, HOLO_SWITCH_C(C, {
         constexpr int T = N_ / kP;
         if (C_ * T <= 1024) {
             size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
-            allow_lds(k_recon_cols<N_, C_>, lds);
-            hipLaunchKernelGGL((k_recon_cols<N_, C_>), dim3((nx / C_) * n_sf), dim3(C_ * T), lds, s, holo, levels,
+            allow_lds(k_recon_cols<N_, C_, P_>, lds);
+            hipLaunchKernelGGL((k_recon_cols<N_, C_, P_>), dim3((nx / C_) * n_sf), dim3(C_ * T), lds, s, holo, levels,
                                nx, x2, tw_y, row_pitch(nx, cfg));
         }
     }));
@@ -401,8 +429,8 @@ hipError_t launch_recon_cols(const void* holo, int levels, int nx, int ny, int n
 // partials[v*5 + {0..4}] = {S_II, S_IT, S_ITs, S_TT, S_TsTs} over the pixels
 // this row stands for (itself and, for the half spectrum, its point mirror).
 // -------------------------------------------------------------------------
-template <int NX>
-__global__ __launch_bounds__(512) void k_recon_rows(const float2* __restrict__ x2, int ny, int n_sf, int half,
+template <int NX, int P>
+__global__ __launch_bounds__(P ? 256 : 512) void k_recon_rows(const float2* __restrict__ x2, int ny, int n_sf, int half,
                                                      const float* __restrict__ target, float* __restrict__ recon,
                                                      double* __restrict__ partials, const float2* __restrict__ tw,
                                                      float inv_scale, int pitch)
@@ -439,7 +467,7 @@ __global__ __launch_bounds__(512) void k_recon_rows(const float2* __restrict__ x
 #pragma unroll
             for (int m = 0; m < kP; ++m) nxt[m] = buf_ld2(rx, roff + ko, (uint32_t)(m * T * 8));
         }
-        fft_stages<NX, -1, RowAddrR, (NX / kP <= 64)>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, tw);
+        fft_any<NX, -1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, RowsOf<NX>{}, tw);
         if (valid) {
 #pragma unroll
             for (int m = 0; m < kP; ++m) acc[m] = fmaf(v[m].x, v[m].x, fmaf(v[m].y, v[m].y, acc[m]));
@@ -506,16 +534,20 @@ hipError_t launch_recon_rows(const float2* x2, int nx, int ny, int n_sf, bool ha
                              hipStream_t s)
 {
     const int nrows_spec = half ? ny / 2 + 1 : ny;
-    HOLO_SWITCH_N(nx, {
+    HOLO_SWITCH_NP(nx, cfg.prec, {
         constexpr int T = N_ / kP;
         int G = cfg.ksplit > 0 ? cfg.ksplit : 4;
         while (G > 1 && (G * T > 512 || G > n_sf)) G >>= 1;
+        // matrix cores: whole waves (groups past n_sf transform zeros and add
+        // nothing), at most 256 threads
+        if (P_ && G * T > 256) G = 256 / T;
+        if (P_ && G * T < 64) G = 64 / T;
         size_t fft_lds = (size_t)G * PadLen<N_>::v * sizeof(float2);
         size_t red_lds = (size_t)5 * (G * T / 64 + 1) * sizeof(double);
         size_t lds = fft_lds > red_lds ? fft_lds : red_lds;
         const float inv_scale = (float)(1.0 / ((double)n_sf * (double)nx * (double)ny));
-        allow_lds(k_recon_rows<N_>, lds);
-        hipLaunchKernelGGL((k_recon_rows<N_>), dim3(nrows_spec), dim3(G * T), lds, s, x2, ny, n_sf, half ? 1 : 0,
+        allow_lds(k_recon_rows<N_, P_>, lds);
+        hipLaunchKernelGGL((k_recon_rows<N_, P_>), dim3(nrows_spec), dim3(G * T), lds, s, x2, ny, n_sf, half ? 1 : 0,
                            target, recon, partials, tw_x, inv_scale, row_pitch(nx, cfg));
     });
     return hipGetLastError();

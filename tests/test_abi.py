@@ -68,6 +68,13 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert st == h.HOLO_EINVAL   # nmse_final2 without codes
     st = lib.holo_reconstruct_nmse(fake, 4, 64, 64, 1, fake, None, None, 0, None)
     assert st == h.HOLO_EINVAL
-    st = lib.holo_fft2(fake, fake, 64, 64, 2, None)
+    st = lib.holo_fft2(fake, fake, 64, 64, 2, 0, None)
     assert st == h.HOLO_EINVAL
+    # matrix-core stages: sides of 256 and more; unknown precisions rejected
+    st = lib.holo_fft2(fake, fake, 128, 256, -1, h.BF16, None)
+    assert st == h.HOLO_EUNSUPPORTED
+    st = lib.holo_fft2(fake, fake, 256, 256, -1, 3, None)
+    assert st == h.HOLO_EINVAL
+    st = lib.holo_ospr_generate(fake, 256, 128, 8, fake, C.byref(cur), fake, None, None, h.FP16, 0, None)
+    assert st == h.HOLO_EUNSUPPORTED
     assert cur.value == 0

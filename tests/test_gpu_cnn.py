@@ -10,7 +10,8 @@ relative) with probability ~1e-3 and moves the output by ~2^-8/sqrt(288) per
 flip in its receptive field.  Bounds: output error (phasor angle scaled by
 |o| / rms|o|) median < 1e-4 and max < 5e-3; gradient relative L2 < 1e-2; loss
 within 1e-4 relative.  Against the exact (unrounded) network the four BF16
-roundings (2^-9 each, in quadrature) bound the median scaled error at 6e-3."""
+roundings (unit roundoff 2^-8 each, in quadrature) bound the median scaled
+error at 6e-3."""
 import numpy as np
 import pytest
 import torch
