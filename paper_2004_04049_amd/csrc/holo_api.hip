@@ -79,6 +79,7 @@ struct Workspace {
 
 struct DeviceState {
     std::map<int, float2*> twiddles;                   // length -> W_N^k table
+    std::map<int, void*> dftops;                       // precision -> DFT-matrix operand table
     std::map<hipStream_t, Workspace> workspaces;       // per stream
 };
 
@@ -102,6 +103,27 @@ holo_status get_twiddles(int device, int n, hipStream_t s, const float2** out)
     HIP_TRY(hipStreamSynchronize(s));
     d.twiddles[n] = tw;
     *out = tw;
+    return HOLO_OK;
+}
+
+// DFT-matrix operand table of the matrix-core stages for `prec`, generated
+// in FP64 on the device at first use.
+holo_status get_dftop(int device, int prec, hipStream_t s, const void** out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceState& d = g_dev[device];
+    auto it = d.dftops.find(prec);
+    if (it != d.dftops.end()) {
+        *out = it->second;
+        return HOLO_OK;
+    }
+    void* t = nullptr;
+    if (hipMalloc(&t, 4 * 2 * 4 * 64 * 8 * sizeof(uint16_t)) != hipSuccess)
+        return fail(HOLO_ENOMEM, "DFT operand table");
+    HIP_TRY(launch_dft_operand_gen((uint16_t*)t, prec, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    d.dftops[prec] = t;
+    *out = t;
     return HOLO_OK;
 }
 
@@ -665,6 +687,7 @@ holo_status holo_ospr_generate(const float* target, int64_t nx, int64_t ny, int3
     if ((st = check_lut(lut, device))) return st;
     LaunchCfg cfg = plan_get(PLAN_OSPR, nx, ny, n_sf);
     cfg.prec = precision;
+    if (precision && (st = get_dftop(device, precision, (hipStream_t)hip_stream, &cfg.dftop))) return st;
     if ((st = ospr_run(device, target, nx, ny, n_sf, lut, *cursor, holo_bits, recon, nmse2, flags,
                        (hipStream_t)hip_stream, cfg)))
         return st;
@@ -749,6 +772,7 @@ holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t ny, int32
     if ((st = get_workspace(device, s, sizeof(float2) * (size_t)nx * ny, &ws))) return st;
     LaunchCfg cfg = default_cfg();
     cfg.prec = precision;
+    if (precision && (st = get_dftop(device, precision, s, &cfg.dftop))) return st;
     LAUNCH("fft2", s, launch_fft2((const float2*)in, (float2*)ws, (float2*)out, (int)nx, (int)ny, sign, tw_x, tw_y,
                                   cfg, s));
     return HOLO_OK;
@@ -780,10 +804,13 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
     std::vector<OsprLayout> lay(n_frames);
     std::vector<uint64_t> off(n_frames);
     uint64_t total = 0;
+    const void* dftop = nullptr;
+    if (precision && (st = get_dftop(device, precision, s, &dftop))) return st;
     for (int f = 0; f < n_frames; ++f) {
         const holo_frame& fr = frames[f];
         cfg[f] = plan_get(PLAN_OSPR, fr.nx, fr.ny, fr.n_sf);
         cfg[f].prec = precision;
+        cfg[f].dftop = dftop;
         lay[f] = ospr_layout(fr.nx, fr.ny, fr.n_sf, cfg[f]);
         off[f] = total;
         total += (uint64_t)fr.n_sf * (uint64_t)fr.nx * (uint64_t)fr.ny;
@@ -1422,6 +1449,7 @@ void holo_shutdown(void)
         (void)hipSetDevice(kv.first);
         (void)hipDeviceSynchronize();
         for (auto& t : kv.second.twiddles) (void)hipFree(t.second);
+        for (auto& t : kv.second.dftops) (void)hipFree(t.second);
         for (auto& w : kv.second.workspaces)
             if (w.second.base) (void)hipFree(w.second.base);
     }

@@ -16,6 +16,7 @@ struct LaunchCfg {
     int pad = -1;                  // extra elements per row of internal fields (-1 = heuristic)
     int chunk = 0;                 // OSPR sub-frames per generation chunk (0 = all at once)
     int prec = 0;                  // DFT stages: 0 FP32 registers, 1 BF16 MFMA, 2 FP16 MFMA (sizes >= 256)
+    const void* dftop = nullptr;   // DFT-matrix operand table of `prec` (launch_dft_operand_gen)
 };
 
 // Row pitch (complex elements) of the library's internal [rows][nx] fields:
@@ -33,6 +34,10 @@ int col_block_cols(int n, int ncols, int nbatch, int planned, int cmin);
 
 // FP64 twiddle generation on the device: tw[k] = fp32(exp(-2*pi*i*k/n)).
 hipError_t launch_twiddle_gen(float2* tw, int n, hipStream_t s);
+
+// DFT-matrix operand table of the matrix-core stages, 32 KiB: prec 1 (BF16)
+// or 2 (FP16), FP64 evaluation on the device.
+hipError_t launch_dft_operand_gen(uint16_t* out, int prec, hipStream_t s);
 
 // Plain unitary 2D transform (Eq. (1) for sign < 0, Eq. (2) for sign > 0):
 // rows of `in` into `tmp`, columns of `tmp` into `out` (1/sqrt(N) applied).

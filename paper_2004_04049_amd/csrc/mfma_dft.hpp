@@ -16,7 +16,8 @@
 // as two real products per K block (Re X and Im X against [[Re W, Im W],
 // [-Im W, Re W]]), 32 output columns = 16 real parts then 16 imaginary
 // parts.  W is split W = W_hi + W_lo (W_hi = rn(W), W_lo = rn(W - W_hi) in the
-// operand format), so each product is X*W_hi + X*W_lo accumulated in FP32:
+// operand format, from FP64 values generated on the device), so each product
+// is X*W_hi + X*W_lo accumulated in FP32:
 // four MFMAs per 32 vectors.  The data are rounded to the operand format once
 // per stage (after the FP32 twiddle).  The 1/R per stage keeps FP16 operands
 // in range and is undone exactly (x N, a power of two) on exit.
@@ -34,13 +35,6 @@ namespace holo {
 typedef float mf32x16 __attribute__((ext_vector_type(16)));
 typedef float mf32x8 __attribute__((ext_vector_type(8)));
 
-// cos(2*pi*k/16), FP32 roundings; sin(2*pi*k/16) = entry (k - 4) mod 16.
-__device__ __constant__ const float kCos16[16] = {
-    1.0f, 0.923879532511286756f, 0.707106781186547524f, 0.382683432365089772f,
-    0.0f, -0.382683432365089772f, -0.707106781186547524f, -0.923879532511286756f,
-    -1.0f, -0.923879532511286756f, -0.707106781186547524f, -0.382683432365089772f,
-    0.0f, 0.382683432365089772f, 0.707106781186547524f, 0.923879532511286756f};
-
 template <int PREC>
 struct MfmaOp;
 
@@ -49,7 +43,6 @@ template <>
 struct MfmaOp<1> {
     typedef __bf16 v8 __attribute__((ext_vector_type(8)));
     static __device__ __forceinline__ v8 cvt(mf32x8 x) { return __builtin_convertvector(x, v8); }
-    static __device__ __forceinline__ mf32x8 back(v8 x) { return __builtin_convertvector(x, mf32x8); }
     static __device__ __forceinline__ mf32x16 mma(v8 a, v8 b, mf32x16 c)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -61,7 +54,6 @@ template <>
 struct MfmaOp<2> {
     typedef _Float16 v8 __attribute__((ext_vector_type(8)));
     static __device__ __forceinline__ v8 cvt(mf32x8 x) { return __builtin_convertvector(x, v8); }
-    static __device__ __forceinline__ mf32x8 back(v8 x) { return __builtin_convertvector(x, mf32x8); }
     static __device__ __forceinline__ mf32x16 mma(v8 a, v8 b, mf32x16 c)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
@@ -85,47 +77,35 @@ struct ColsOf {   // C interleaved transforms: thread (c, t) = c + C*t
     __device__ __forceinline__ int base(int tid) const { return tid & (C - 1); }
 };
 
-// This lane's row of W^T for radix R (see below): columns k = 8*half + e as
-// coefficients of Re X[k] (a1) and Im X[k] (a2), each split hi + lo.
+// DFT-matrix operands, generated once per device in FP64 (launch_dft_operand_gen):
+// for radix R in {2, 4, 8, 16} (index log2(R) - 1), sign (0: -, 1: +) and part
+// (Re-coefficient hi, lo; Im-coefficient hi, lo), lane l holds 8 operand-format
+// values as one 16-byte word: uint4 index ((ri*2 + si)*4 + part)*64 + l.
+// Row o = l & 31 of W^T is output o >> 1, real part (o even) or imaginary
+// part (o odd); column k = 8*(l >> 5) + e is input point k.
 template <int PREC, int R, int SIGN>
-__device__ __forceinline__ void dft_operand(int half, int l32, typename MfmaOp<PREC>::v8& a1h,
-                                            typename MfmaOp<PREC>::v8& a1l, typename MfmaOp<PREC>::v8& a2h,
-                                            typename MfmaOp<PREC>::v8& a2l)
+__device__ __forceinline__ void load_operand(const uint4* __restrict__ op, int lane, typename MfmaOp<PREC>::v8 (&a)[4])
 {
-    using M = MfmaOp<PREC>;
-    const int ko = l32 & 15;
-    const bool im_out = l32 >= 16;
-    constexpr float inv_r = 1.0f / (float)R;   // exact
-    mf32x8 w1, w2;
+    constexpr int ri = R == 16 ? 3 : R == 8 ? 2 : R == 4 ? 1 : 0;
+    const uint4* p = op + ((ri * 2 + (SIGN > 0 ? 1 : 0)) * 4) * 64 + lane;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int k = 8 * half + e;
-        const bool same = (k / R) == (ko / R);
-        const int ang = ((k % R) * (ko % R) * (16 / R)) & 15;   // angle 2*pi*ang/16
-        const float c = kCos16[ang] * inv_r;
-        const float sn = kCos16[(ang - 4) & 15] * (SIGN > 0 ? inv_r : -inv_r);
-        w1[e] = same ? (im_out ? sn : c) : 0.0f;
-        w2[e] = same ? (im_out ? c : -sn) : 0.0f;
-    }
-    a1h = M::cvt(w1);
-    a1l = M::cvt(w1 - M::back(a1h));
-    a2h = M::cvt(w2);
-    a2l = M::cvt(w2 - M::back(a2h));
+    for (int q = 0; q < 4; ++q) a[q] = __builtin_bit_cast(typename MfmaOp<PREC>::v8, p[q * 64]);
 }
 
 // The DFT-matrix product runs transposed, D = W^T X^T: the A operand holds
-// the 32 output rows (16 real parts, then 16 imaginary parts) of W^T, the B
-// operand 32 vectors (lane l32 of each half-wave holds points 8*half..+7 of
-// vector l32), and register i of the result holds, for the lane's vector,
-// output 8*((i>>2)&1) + 4*half + (i&3) (real part for i < 8, imaginary part of
-// the same output in i + 8).  So every LDS access of a lane is a per-lane base
-// plus a compile-time offset, and outputs leave as complex pairs.  The
+// the 32 output rows of W^T (real and imaginary part of each output, in
+// turn), the B operand 32 vectors (lane l32 of each half-wave holds points
+// 8*half..+7 of vector l32), and registers 2p, 2p+1 of the result hold, for
+// the lane's vector, the real and imaginary part of output
+// 4*(p>>1) + 2*half + (p&1).  So every LDS access of a lane is a per-lane base
+// plus a compile-time offset, and outputs leave as complex pairs straight from
+// adjacent accumulator registers.  The
 // padded positions (one spare slot per 16, as in the register engine) keep
 // the strided accesses on distinct banks; T = N/16 is a multiple of 16, so
 // pad(x + 16m) = pad(x) + 17m splits every address that way.
 template <int N, int SIGN, int PREC, typename Lay, bool WAVE_LOCAL = false>
 __device__ __forceinline__ void fft_stages_mfma(float2 (&v)[kP], float2* lds, const Lay& lay,
-                                                const float2* __restrict__ tw)
+                                                const float2* __restrict__ tw, const uint4* __restrict__ dftop)
 {
     using M = MfmaOp<PREC>;
     constexpr int T = N / kP;
@@ -139,6 +119,7 @@ __device__ __forceinline__ void fft_stages_mfma(float2 (&v)[kP], float2* lds, co
     const int tid = threadIdx.x;
     const int lane = tid & 63, half = lane >> 5, l32 = lane & 31;
     const int wbase = tid - lane;
+    const auto rtw = make_rsrc(tw, (uint32_t)(N * sizeof(float2)));
 
     {
         const int b = lay.base(tid) + lds_pad(lay.t(tid)) * S;
@@ -154,14 +135,10 @@ __device__ __forceinline__ void fft_stages_mfma(float2 (&v)[kP], float2* lds, co
         tt[g] = lay.t(vt);
         bs[g] = lay.base(vt);
     }
-    typename M::v8 a16[4];   // radix-16 operand, shared by all radix-16 stages
-    dft_operand<PREC, 16, SIGN>(half, l32, a16[0], a16[1], a16[2], a16[3]);
     int Ns = 1;
 #pragma unroll
     for (int s = 0; s < NSTAGE; ++s) {
         const int R = (s < NS16) ? 16 : (1 << REM);
-        typename M::v8 a1h = a16[0], a1l = a16[1], a2h = a16[2], a2l = a16[3];
-        if (R != 16) dft_operand<PREC, (1 << (REM ? REM : 1)), SIGN>(half, l32, a1h, a1l, a2h, a2l);
         // B operands: points k = 8*half + e of the wave's 64 vectors, FP32
         // twiddle W_{Ns R}^{(j mod Ns) r} first (butterfly j = tt + b*T reads
         // element j + r*N/R)
@@ -178,7 +155,7 @@ __device__ __forceinline__ void fft_stages_mfma(float2 (&v)[kP], float2* lds, co
                 if (Ns > 1) {
                     const int r = R == 16 ? 8 * half + e : e % R;
                     const int j = tt[g] + (bh + (R == 16 ? 0 : e / R)) * T;
-                    const float2 w = tw[(j & (Ns - 1)) * (N / (Ns * R)) * r];
+                    const float2 w = buf_ld2(rtw, (uint32_t)((j & (Ns - 1)) * (N / (Ns * R)) * r) * 8u, 0);
                     x = SIGN < 0 ? cmul(x, w) : cmulc(x, w);
                 }
                 fr[e] = x.x;
@@ -188,31 +165,34 @@ __device__ __forceinline__ void fft_stages_mfma(float2 (&v)[kP], float2* lds, co
             xi[g] = M::cvt(fi);
         }
         exchange_sync<WAVE_LOCAL>();
+        typename M::v8 a[4];
+        if (R == 16) load_operand<PREC, 16, SIGN>(dftop, lane, a);
+        else load_operand<PREC, (1 << (REM ? REM : 1)), SIGN>(dftop, lane, a);
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
             mf32x16 acc = {};
-            acc = M::mma(a1h, xr[g], acc);
-            acc = M::mma(a1l, xr[g], acc);
-            acc = M::mma(a2h, xi[g], acc);
-            acc = M::mma(a2l, xi[g], acc);
-            // output ko = 8*((i>>2)&1) + 4*half + (i&3) of butterfly j = tt + (ko/R)*T
+            acc = M::mma(a[0], xr[g], acc);
+            acc = M::mma(a[1], xr[g], acc);
+            acc = M::mma(a[2], xi[g], acc);
+            acc = M::mma(a[3], xi[g], acc);
+            // output ko = 4*(p>>1) + 2*half + (p&1) of butterfly j = tt + (ko/R)*T
             // goes to Stockham position (j/Ns)*Ns*R + (j mod Ns) + (ko mod R)*Ns
             int sb;
             if (Ns == 1) {   // first stage, R = 16: 16*tt + ko, padded 17*tt + ko
-                sb = bs[g] + (17 * tt[g] + 4 * half) * S;
+                sb = bs[g] + (17 * tt[g] + 2 * half) * S;
             } else if (R == 16) {
                 const int j = tt[g];
-                sb = bs[g] + (lds_pad((j / Ns) * 16 * Ns + (j & (Ns - 1))) + 4 * half * (Ns / 16) * 17) * S;
+                sb = bs[g] + (lds_pad((j / Ns) * 16 * Ns + (j & (Ns - 1))) + 2 * half * (Ns / 16) * 17) * S;
             } else {         // last stage, j < Ns: position j + q*Ns
-                sb = bs[g] + (lds_pad(tt[g]) + ((4 * half / R) * T + (4 * half % R) * Ns) / 16 * 17) * S;
+                sb = bs[g] + (lds_pad(tt[g]) + ((2 * half / R) * T + (2 * half % R) * Ns) / 16 * 17) * S;
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int kc = 8 * ((i >> 2) & 1) + (i & 3);
+            for (int p = 0; p < 8; ++p) {
+                const int kc = 4 * (p >> 1) + (p & 1);
                 const int off = Ns == 1 ? kc
                                 : R == 16 ? kc * (Ns / 16) * 17
                                           : ((kc / R) * T + (kc % R) * Ns) / 16 * 17;
-                lds[sb + off * S] = make_float2(acc[i], acc[i + 8]);
+                lds[sb + off * S] = make_float2(acc[2 * p], acc[2 * p + 1]);
             }
         }
         exchange_sync<WAVE_LOCAL>();
@@ -236,10 +216,10 @@ __device__ __forceinline__ void fft_stages_mfma(float2 (&v)[kP], float2* lds, co
 // matrix-core engine.
 template <int N, int SIGN, int PREC, bool WAVE_LOCAL = false, typename Addr, typename Lay>
 __device__ __forceinline__ void fft_any(float2 (&v)[kP], int t, float2* lds, Addr addr, const Lay& lay,
-                                        const float2* __restrict__ tw)
+                                        const float2* __restrict__ tw, const uint4* __restrict__ dftop)
 {
     if constexpr (PREC == 0) fft_stages<N, SIGN, Addr, WAVE_LOCAL>(v, t, lds, addr, tw);
-    else fft_stages_mfma<N, SIGN, PREC, Lay, WAVE_LOCAL>(v, lds, lay, tw);
+    else fft_stages_mfma<N, SIGN, PREC, Lay, WAVE_LOCAL>(v, lds, lay, tw, dftop);
 }
 
 }  // namespace holo

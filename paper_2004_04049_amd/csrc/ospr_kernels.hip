@@ -129,11 +129,58 @@ hipError_t launch_twiddle_gen(float2* tw, int n, hipStream_t s)
 }
 
 // -------------------------------------------------------------------------
+// DFT-matrix operands of the matrix-core stages (layout in mfma_dft.hpp):
+// W_R[r][q] = exp(sign*2*pi*i*r*q/R)/R evaluated in FP64 (sincospi: exact at
+// multiples of pi/2), each coefficient split hi = rn(w), lo = rn(w - hi) in the
+// operand format.  One thread per (radix, sign, part, lane, element).
+// -------------------------------------------------------------------------
+__global__ void k_dft_operand_gen(uint16_t* __restrict__ out, int prec)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;   // < 4*2*4*64*8
+    if (idx >= 4 * 2 * 4 * 64 * 8) return;
+    const int e = idx & 7, lane = (idx >> 3) & 63, part = (idx >> 9) & 3, si = (idx >> 11) & 1, ri = idx >> 12;
+    const int R = 2 << ri;
+    const int half = lane >> 5, l32 = lane & 31;
+    const int ko = l32 >> 1;
+    const bool im_out = (l32 & 1) != 0;
+    const int k = 8 * half + e;
+    double wr = 0.0, wi = 0.0;
+    if (k / R == ko / R) {
+        double sn, cs;
+        sincospi(2.0 * (double)(((k % R) * (ko % R)) % R) / (double)R, &sn, &cs);
+        wr = cs / R;
+        wi = (si ? sn : -sn) / R;
+    }
+    // coefficient of Re X[k] (parts 0, 1) and of Im X[k] (parts 2, 3)
+    const double w = part < 2 ? (im_out ? wi : wr) : (im_out ? wr : -wi);
+    uint16_t bits;
+    if (prec == 1) {
+        const __bf16 hi = (__bf16)(float)w;
+        const __bf16 lo = (__bf16)(float)(w - (double)(float)hi);
+        bits = __builtin_bit_cast(uint16_t, (part & 1) ? lo : hi);
+    } else {
+        const _Float16 hi = (_Float16)(float)w;
+        const _Float16 lo = (_Float16)(float)(w - (double)(float)hi);
+        bits = __builtin_bit_cast(uint16_t, (part & 1) ? lo : hi);
+    }
+    out[idx] = bits;
+}
+
+hipError_t launch_dft_operand_gen(uint16_t* out, int prec, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dft_operand_gen, dim3(4 * 2 * 4 * 64 * 8 / 256), dim3(256), 0, s, out, prec);
+    return hipGetLastError();
+}
+
+#define DFTOP(cfg) (reinterpret_cast<const uint4*>((cfg).dftop))
+
+// -------------------------------------------------------------------------
 // Plain 2D transform (used by the unitary holo_fft2 entry point and tests).
 // -------------------------------------------------------------------------
 template <int N, int SIGN, int P>
 __global__ __launch_bounds__(P ? 256 : 1024) void k_fft_rows(const float2* __restrict__ in, float2* __restrict__ out,
-                                                   int nrows, const float2* __restrict__ tw)
+                                                   int nrows, const float2* __restrict__ tw,
+                                                   const uint4* __restrict__ dftop)
 {
     extern __shared__ float2 lds[];
     constexpr int T = N / kP;
@@ -144,7 +191,7 @@ __global__ __launch_bounds__(P ? 256 : 1024) void k_fft_rows(const float2* __res
     const float2* src = in + y * N;
 #pragma unroll
     for (int m = 0; m < kP; ++m) v[m] = src[t + T * m];
-    fft_any<N, SIGN, P, (N / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<N>::v}, RowsOf<N>{}, tw);
+    fft_any<N, SIGN, P, (N / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<N>::v}, RowsOf<N>{}, tw, dftop);
     float2* dst = out + y * N;
 #pragma unroll
     for (int m = 0; m < kP; ++m) dst[t + T * m] = v[m];
@@ -152,7 +199,8 @@ __global__ __launch_bounds__(P ? 256 : 1024) void k_fft_rows(const float2* __res
 
 template <int N, int SIGN, int C, int P>
 __global__ __launch_bounds__(C * (N / kP)) void k_fft_cols(const float2* __restrict__ in, float2* __restrict__ out,
-                                                           int nx, float scale, const float2* __restrict__ tw)
+                                                           int nx, float scale, const float2* __restrict__ tw,
+                                                           const uint4* __restrict__ dftop)
 {
     extern __shared__ float2 lds[];
     constexpr int T = N / kP;
@@ -163,7 +211,7 @@ __global__ __launch_bounds__(C * (N / kP)) void k_fft_cols(const float2* __restr
     float2 v[kP];
 #pragma unroll
     for (int m = 0; m < kP; ++m) v[m] = ld_off(in + x0 + m * mstride, toff);
-    fft_any<N, SIGN, P>(v, t, lds, ColAddr<C>{c}, ColsOf<N, C>{}, tw);
+    fft_any<N, SIGN, P>(v, t, lds, ColAddr<C>{c}, ColsOf<N, C>{}, tw, dftop);
 #pragma unroll
     for (int m = 0; m < kP; ++m) st_off(out + x0 + m * mstride, toff, make_float2(v[m].x * scale, v[m].y * scale));
 }
@@ -185,11 +233,11 @@ hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int n
             if (sign < 0) {
                 allow_lds(k_fft_rows<N_, -1, P_>, lds);
                 hipLaunchKernelGGL((k_fft_rows<N_, -1, P_>), dim3(ny / rows), dim3(rows * T), lds, s, in, tmp, ny,
-                                   tw_x);
+                                   tw_x, DFTOP(cfg));
             } else {
                 allow_lds(k_fft_rows<N_, 1, P_>, lds);
                 hipLaunchKernelGGL((k_fft_rows<N_, 1, P_>), dim3(ny / rows), dim3(rows * T), lds, s, in, tmp, ny,
-                                   tw_x);
+                                   tw_x, DFTOP(cfg));
             }
         });
     }
@@ -203,11 +251,11 @@ hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int n
                 if (sign < 0) {
                     allow_lds(k_fft_cols<N_, -1, C_, P_>, lds);
                     hipLaunchKernelGGL((k_fft_cols<N_, -1, C_, P_>), dim3(nx / C_), dim3(C_ * T), lds, s, tmp, out,
-                                       nx, scale, tw_y);
+                                       nx, scale, tw_y, DFTOP(cfg));
                 } else {
                     allow_lds(k_fft_cols<N_, 1, C_, P_>, lds);
                     hipLaunchKernelGGL((k_fft_cols<N_, 1, C_, P_>), dim3(nx / C_), dim3(C_ * T), lds, s, tmp, out,
-                                       nx, scale, tw_y);
+                                       nx, scale, tw_y, DFTOP(cfg));
                 }
             }
         }));
@@ -224,7 +272,7 @@ __global__ __launch_bounds__(P ? 256 : 1024) void k_ospr_rows(const float* __res
                                                     const float2* __restrict__ lut, uint32_t n_lut, uint64_t c0,
                                                     const uint64_t* __restrict__ c0_base,
                                                     float2* __restrict__ x1, const float2* __restrict__ tw,
-                                                    int pitch)
+                                                    int pitch, const uint4* __restrict__ dftop)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NX / kP;
@@ -252,7 +300,7 @@ __global__ __launch_bounds__(P ? 256 : 1024) void k_ospr_rows(const float* __res
         idx += step;
         if (idx >= n_lut) idx -= n_lut;
     }
-    fft_any<NX, 1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, RowsOf<NX>{}, tw);
+    fft_any<NX, 1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, RowsOf<NX>{}, tw, dftop);
     const size_t plane = (size_t)ny * pitch;
     const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
     const uint32_t ooff = ((uint32_t)y * (uint32_t)pitch + (uint32_t)t) * 8u;
@@ -270,7 +318,7 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
         size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
         allow_lds(k_ospr_rows<N_, P_>, lds);
         hipLaunchKernelGGL((k_ospr_rows<N_, P_>), dim3((ny / rows) * n_sf), dim3(rows * T), lds, s, target, ny, lut,
-                           n_lut, c0, c0_base, x1, tw_x, row_pitch(nx, cfg));
+                           n_lut, c0, c0_base, x1, tw_x, row_pitch(nx, cfg), DFTOP(cfg));
     });
     return hipGetLastError();
 }
@@ -285,7 +333,8 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
 template <int NY, int C, int P>
 __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __restrict__ x1, int nx,
                                                             uint32_t* __restrict__ bits, float2* __restrict__ x2,
-                                                            const float2* __restrict__ tw, int pitch)
+                                                            const float2* __restrict__ tw, int pitch,
+                                                            const uint4* __restrict__ dftop)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NY / kP;
@@ -305,7 +354,7 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __res
     float2 v[kP];
 #pragma unroll
     for (int m = 0; m < kP; ++m) v[m] = buf_ld2(rin, voff, m * mst);
-    fft_any<NY, 1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw);
+    fft_any<NY, 1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
 
     // nearest of {+1, -1}: bit = (Re H < 0); Re H = 0 -> +1
     const auto rbits = make_rsrc(bits + (size_t)k * (npix / 32), (uint32_t)(npix / 8));
@@ -322,7 +371,7 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __res
         }
         v[m] = make_float2(neg ? -1.0f : 1.0f, 0.0f);
     }
-    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw);
+    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
     // rows v = t + T*m <= NY/2: every slot m < 8, and m = 8 for t = 0 only
     const size_t hplane = (size_t)(NY / 2 + 1) * pitch;
     const auto rout = make_rsrc(x2 + (size_t)k * hplane, (uint32_t)(hplane * 8));
@@ -341,7 +390,7 @@ hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t
             size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
             allow_lds(k_ospr_cols<N_, C_, P_>, lds);
             hipLaunchKernelGGL((k_ospr_cols<N_, C_, P_>), dim3((nx / C_) * n_sf), dim3(C_ * T), lds, s, x1, nx, bits,
-                               x2, tw_y, row_pitch(nx, cfg));
+                               x2, tw_y, row_pitch(nx, cfg), DFTOP(cfg));
         }
     }));
     return hipGetLastError();
@@ -370,7 +419,7 @@ __device__ __forceinline__ float2 level8_phasor(int m)
 template <int NY, int C, int P>
 __global__ __launch_bounds__(C * (NY / kP)) void k_recon_cols(const void* __restrict__ holo, int levels, int nx,
                                                              float2* __restrict__ x2, const float2* __restrict__ tw,
-                                                             int pitch)
+                                                             int pitch, const uint4* __restrict__ dftop)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NY / kP;
@@ -395,7 +444,7 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_recon_cols(const void* __rest
 #pragma unroll
         for (int m = 0; m < kP; ++m) v[m] = level8_phasor(cd[(size_t)(t + T * m) * nx + x]);
     }
-    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw);
+    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
     const int vmax = levels == 2 ? NY / 2 : NY - 1;
     float2* dst = x2 + (size_t)k * (vmax + 1) * pitch;
 #pragma unroll
@@ -415,7 +464,7 @@ hipError_t launch_recon_cols(const void* holo, int levels, int nx, int ny, int n
             size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
             allow_lds(k_recon_cols<N_, C_, P_>, lds);
             hipLaunchKernelGGL((k_recon_cols<N_, C_, P_>), dim3((nx / C_) * n_sf), dim3(C_ * T), lds, s, holo, levels,
-                               nx, x2, tw_y, row_pitch(nx, cfg));
+                               nx, x2, tw_y, row_pitch(nx, cfg), DFTOP(cfg));
         }
     }));
     return hipGetLastError();
@@ -433,7 +482,7 @@ template <int NX, int P>
 __global__ __launch_bounds__(P ? 256 : 512) void k_recon_rows(const float2* __restrict__ x2, int ny, int n_sf, int half,
                                                      const float* __restrict__ target, float* __restrict__ recon,
                                                      double* __restrict__ partials, const float2* __restrict__ tw,
-                                                     float inv_scale, int pitch)
+                                                     float inv_scale, int pitch, const uint4* __restrict__ dftop)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NX / kP;
@@ -467,7 +516,7 @@ __global__ __launch_bounds__(P ? 256 : 512) void k_recon_rows(const float2* __re
 #pragma unroll
             for (int m = 0; m < kP; ++m) nxt[m] = buf_ld2(rx, roff + ko, (uint32_t)(m * T * 8));
         }
-        fft_any<NX, -1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, RowsOf<NX>{}, tw);
+        fft_any<NX, -1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, RowsOf<NX>{}, tw, dftop);
         if (valid) {
 #pragma unroll
             for (int m = 0; m < kP; ++m) acc[m] = fmaf(v[m].x, v[m].x, fmaf(v[m].y, v[m].y, acc[m]));
@@ -548,7 +597,7 @@ hipError_t launch_recon_rows(const float2* x2, int nx, int ny, int n_sf, bool ha
         const float inv_scale = (float)(1.0 / ((double)n_sf * (double)nx * (double)ny));
         allow_lds(k_recon_rows<N_, P_>, lds);
         hipLaunchKernelGGL((k_recon_rows<N_, P_>), dim3(nrows_spec), dim3(G * T), lds, s, x2, ny, n_sf, half ? 1 : 0,
-                           target, recon, partials, tw_x, inv_scale, row_pitch(nx, cfg));
+                           target, recon, partials, tw_x, inv_scale, row_pitch(nx, cfg), DFTOP(cfg));
     });
     return hipGetLastError();
 }
