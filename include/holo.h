@@ -248,21 +248,27 @@ HOLO_API holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t 
 
 /* ---------------------------------------------------------------------------
  * Launch plans and the autotuner (implementation choices, not part of the
- * method: every plan computes the same holograms).
- * A plan is six ints {cols, rows, ksplit, recon_cols, pad, chunk}:
+ * method: every plan computes the same holograms, except that the GS points
+ * per thread change the FP32 factorisation and so the rounding).
+ * A plan is seven ints {cols, rows, ksplit, recon_cols, pad, chunk, pts}:
  * column-tile width of the generation column pass (OSPR: 8 or 16; GS: 2, 4, 8
  * or 16), row transforms per block of the row pass, sub-frame groups per
  * block of the reconstruction row pass, column-tile width of the
  * reconstruction column pass (0 selects the built-in heuristic for these
  * four); extra elements per row of the library's internal fields (-1:
- * heuristic); and OSPR sub-frames generated per chunk (0: all; a chunk's
- * intermediate planes are reused, so they can stay in the last-level cache).  Plans are keyed by kind
- * (0 = OSPR, 1 = GS), nx, ny and n_sf (ignored for GS).
+ * heuristic); OSPR sub-frames generated per chunk (0: all; a chunk's
+ * intermediate planes are reused, so they can stay in the last-level cache);
+ * and points per thread of the GS transforms (4, 8 or 16; 0: heuristic, more
+ * threads per transform when a single field offers few transforms; the
+ * heuristic and the autotuner use 8 or 16 only, as 4 rounds more often).  Plans
+ * are keyed by kind (0 = OSPR, 1 = GS), nx, ny and n_sf (ignored for GS).
  * holo_autotune_ospr / holo_autotune_gs time candidate plans on the caller's
  * inputs (coordinate descent, `reps` timed runs each) and keep the fastest
  * whose holograms (bits / codes) equal those of the default plan exactly and
  * whose NMSE agrees to 1e-6 relative (FP32 summation order of the average);
- * `chosen` (int[6] or NULL) receives it.  scratch_bits: device
+ * GS points-per-thread candidates are kept when codes differ on at most 1e-3
+ * of the pixels and the per-iteration NMSE agrees to 1e-5 relative after four
+ * iterations.  `chosen` (int[7] or NULL) receives the plan.  scratch_bits: device
  * uint32[n_sf][nx*ny/32], overwritten.  holo_plan_save / holo_plan_load
  * write and read all plans as JSON.  holo_set_graphs(0) disables the HIP
  * graph replay of holo_gs_iterate (on by default).
@@ -272,8 +278,8 @@ HOLO_API holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t
                                         void* hip_stream);
 HOLO_API holo_status holo_autotune_gs(const float* target, int64_t nx, int64_t ny, const holo_lut* lut,
                                       int32_t reps, int32_t* chosen, void* hip_stream);
-HOLO_API holo_status holo_plan_set(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, const int32_t* cfg4);
-HOLO_API holo_status holo_plan_get(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, int32_t* cfg4);
+HOLO_API holo_status holo_plan_set(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, const int32_t* cfg7);
+HOLO_API holo_status holo_plan_get(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, int32_t* cfg7);
 HOLO_API holo_status holo_plan_save(const char* path);
 HOLO_API holo_status holo_plan_load(const char* path);
 HOLO_API holo_status holo_set_graphs(int32_t on);

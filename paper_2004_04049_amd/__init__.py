@@ -281,12 +281,12 @@ def prof_reset():
 
 
 PLAN_OSPR, PLAN_GS = 0, 1
-PLAN_INTS = 6
-DEFAULT_PLAN = [0, 0, 0, 0, -1, 0]
+PLAN_INTS = 7
+DEFAULT_PLAN = [0, 0, 0, 0, -1, 0, 0]
 
 
 def autotune_ospr(target, n_sf: int, lut: Lut, reps: int = 5, stream=None):
-    """holo_autotune_ospr: returns the chosen plan [cols, rows, ksplit, recon_cols, pad, chunk]."""
+    """holo_autotune_ospr: returns the chosen plan [cols, rows, ksplit, recon_cols, pad, chunk, pts]."""
     import numpy as np
     ny, nx = target.shape
     _dev(target, torch.float32, None, "target")
@@ -298,7 +298,7 @@ def autotune_ospr(target, n_sf: int, lut: Lut, reps: int = 5, stream=None):
 
 
 def autotune_gs(target, lut: Lut, reps: int = 5, stream=None):
-    """holo_autotune_gs: returns the chosen plan [cols, rows, ksplit, recon_cols, pad, chunk]."""
+    """holo_autotune_gs: returns the chosen plan [cols, rows, ksplit, recon_cols, pad, chunk, pts]."""
     import numpy as np
     ny, nx = target.shape
     _dev(target, torch.float32, None, "target")
@@ -309,12 +309,13 @@ def autotune_gs(target, lut: Lut, reps: int = 5, stream=None):
 
 
 def plan_set(kind: int, nx: int, ny: int, n_sf: int, cfg):
-    """cfg: [cols, rows, ksplit, recon_cols, pad, chunk]; DEFAULT_PLAN
-    selects the built-in heuristics."""
+    """cfg: [cols, rows, ksplit, recon_cols, pad, chunk, pts] (a 6-int plan
+    gets pts = 0); DEFAULT_PLAN selects the built-in heuristics."""
     import numpy as np
-    a = np.ascontiguousarray(cfg, dtype=np.int32)
+    a = np.ascontiguousarray(list(cfg) + [0] * (PLAN_INTS - len(cfg)) if len(cfg) == PLAN_INTS - 1 else cfg,
+                             dtype=np.int32)
     if a.size != PLAN_INTS:
-        raise ValueError("a plan is 6 ints: cols, rows, ksplit, recon_cols, pad, chunk")
+        raise ValueError("a plan is 7 ints: cols, rows, ksplit, recon_cols, pad, chunk, pts")
     _check(lib().holo_plan_set(kind, nx, ny, n_sf, a.ctypes.data_as(C.c_void_p)))
 
 

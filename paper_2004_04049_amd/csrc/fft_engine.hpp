@@ -130,6 +130,12 @@ __device__ __forceinline__ int lds_pad(int e) { return e + (e >> 4); }
 template <int N>
 struct PadLen { static constexpr int v = N + N / 16; };
 __host__ __device__ constexpr int pad_len(int n) { return n + n / 16; }
+// The same with one spare slot every P elements, for engines with P points per
+// thread (radix-P stages write at strides that are multiples of P).
+template <int P>
+__device__ __forceinline__ int lds_pad_p(int e) { return e + e / P; }
+template <int N, int P>
+struct PadLenP { static constexpr int v = N + N / P; };
 // Threads per column-transform block: 512 keeps up to 256 VGPRs per lane for
 // the two chained transforms; 2048-point columns need 1024 to hold 8 columns.
 __host__ __device__ constexpr int col_bound(int n) { return n >= 2048 ? 1024 : 512; }
@@ -184,13 +190,13 @@ __device__ __forceinline__ void apply_twiddles(float2 (&u)[R], const float2* __r
     }
 }
 
-// One radix-R stage on butterfly b of thread t (slots b + r*16/R).
-template <int N, int R, int SIGN>
-__device__ __forceinline__ void stage_butterfly(float2 (&v)[kP], int t, int b, int Ns,
+// One radix-R stage on butterfly b of thread t (slots b + r*P/R).
+template <int N, int R, int SIGN, int P = kP>
+__device__ __forceinline__ void stage_butterfly(float2 (&v)[P], int t, int b, int Ns,
                                                 const float2* __restrict__ tw)
 {
-    constexpr int T = N / kP;
-    constexpr int nb = kP / R;
+    constexpr int T = N / P;
+    constexpr int nb = P / R;
     const int j = t + b * T;
     float2 u[R];
 #pragma unroll
@@ -224,51 +230,54 @@ __device__ __forceinline__ void exchange_sync()
     }
 }
 
-template <int N, int SIGN, typename Addr, bool WAVE_LOCAL = false>
-__device__ __forceinline__ void fft_stages(float2 (&v)[kP], int t, float2* lds, Addr addr,
+template <int N, int SIGN, typename Addr, bool WAVE_LOCAL = false, int P = kP>
+__device__ __forceinline__ void fft_stages(float2 (&v)[P], int t, float2* lds, Addr addr,
                                            const float2* __restrict__ tw)
 {
-    constexpr int T = N / kP;
+    static_assert(P == 4 || P == 8 || P == 16, "points per thread");
+    constexpr int T = N / P;
     constexpr int L = ilog2<N>::v;
-    constexpr int NS16 = L / 4;          // radix-16 stages
-    constexpr int REM = L % 4;           // bits left for the last small stage
-    constexpr int NSTAGE = NS16 + (REM ? 1 : 0);
+    constexpr int LP = ilog2<P>::v;
+    constexpr int NSP = L / LP;          // radix-P stages
+    constexpr int REM = L % LP;          // bits left for the last small stage
+    constexpr int NSTAGE = NSP + (REM ? 1 : 0);
+    auto pad = [](int e) { return P == 16 ? lds_pad(e) : lds_pad_p<P>(e); };
     int Ns = 1;
 #pragma unroll
     for (int s = 0; s < NSTAGE; ++s) {
         const bool last = (s == NSTAGE - 1);
-        const int R = (s < NS16) ? 16 : (1 << REM);
-        const int nb = kP / R;
+        const int R = (s < NSP) ? P : (1 << REM);
+        const int nb = P / R;
 #pragma unroll
         for (int b = 0; b < nb; ++b) {
-            if (R == 16) stage_butterfly<N, 16, SIGN>(v, t, b, Ns, tw);
-            else if (R == 8) stage_butterfly<N, 8, SIGN>(v, t, b, Ns, tw);
-            else if (R == 4) stage_butterfly<N, 4, SIGN>(v, t, b, Ns, tw);
-            else stage_butterfly<N, 2, SIGN>(v, t, b, Ns, tw);
+            if (R == 16) stage_butterfly<N, 16, SIGN, P>(v, t, b, Ns, tw);
+            else if (R == 8) stage_butterfly<N, 8, SIGN, P>(v, t, b, Ns, tw);
+            else if (R == 4) stage_butterfly<N, 4, SIGN, P>(v, t, b, Ns, tw);
+            else stage_butterfly<N, 2, SIGN, P>(v, t, b, Ns, tw);
         }
         if (!last) {
             // exchange: write outputs at their Stockham positions, read back the
             // t + T*m set for the next stage.  Addresses are padded indices
-            // p = e + e/16.  Radix-16 stages run first, so Ns is 1 or a multiple
-            // of 16 here and element base + r*Ns pads to pad(base) + r*ps with a
-            // compile-time ps; likewise t + T*m pads to pad(t) + m*T*17/16 when
-            // 16 divides T.  The addr functor gets padded indices.
-            const int ps = Ns == 1 ? 1 : (Ns / 16) * 17;
+            // p = e + e/P.  Radix-P stages run first, so Ns is 1 or a multiple
+            // of P here and element base + r*Ns pads to pad(base) + r*ps with a
+            // compile-time ps; likewise t + T*m pads to pad(t) + m*T*(P+1)/P when
+            // P divides T.  The addr functor gets padded indices.
+            const int ps = Ns == 1 ? 1 : (Ns / P) * (P + 1);
 #pragma unroll
             for (int b = 0; b < nb; ++b) {
                 const int j = t + b * T;
-                const int pb = lds_pad((j / Ns) * Ns * R + (j & (Ns - 1)));
+                const int pb = pad((j / Ns) * Ns * R + (j & (Ns - 1)));
 #pragma unroll
                 for (int r = 0; r < R; ++r) lds[addr(pb + r * ps)] = v[b + r * nb];
             }
             exchange_sync<WAVE_LOCAL>();
-            if (T % 16 == 0) {
-                const int pt = lds_pad(t);
+            if (T % P == 0) {
+                const int pt = pad(t);
 #pragma unroll
-                for (int m = 0; m < kP; ++m) v[m] = lds[addr(pt + m * (T / 16) * 17)];
+                for (int m = 0; m < P; ++m) v[m] = lds[addr(pt + m * (T / P) * (P + 1))];
             } else {
 #pragma unroll
-                for (int m = 0; m < kP; ++m) v[m] = lds[addr(lds_pad(t + T * m))];
+                for (int m = 0; m < P; ++m) v[m] = lds[addr(pad(t + T * m))];
             }
             exchange_sync<WAVE_LOCAL>();
         }

@@ -92,8 +92,8 @@ __device__ __forceinline__ uint8_t quant8(float2 h)
 // Rows pass.  partials layout: [ny][3] = {S_II, S_IT, E} for ITER/FINAL,
 // [ny][2] = {sum T^2, sum T^4} for INIT.
 // -------------------------------------------------------------------------
-template <int NX, int MODE>
-__global__ __launch_bounds__(256) void k_gs_rows(const float* __restrict__ target, int ny,
+template <int NX, int MODE, int P>
+__global__ __launch_bounds__(P == 16 ? 256 : 512) void k_gs_rows(const float* __restrict__ target, int ny,
                                                   const float2* __restrict__ lut, uint32_t n_lut, uint64_t c0,
                                                   const float2* __restrict__ init, float2* __restrict__ state,
                                                   float2* __restrict__ field_out, double* __restrict__ partials,
@@ -101,23 +101,26 @@ __global__ __launch_bounds__(256) void k_gs_rows(const float* __restrict__ targe
                                                   int pitch)
 {
     extern __shared__ float2 lds[];
-    constexpr int T = NX / kP;
+    constexpr int T = NX / P;
     const int rows = blockDim.x / T;
     const int row = threadIdx.x / T, t = threadIdx.x % T;
     const int y = blockIdx.x * rows + row;
-    const float* trow = target + (size_t)y * NX;
     float2* srow = state + (size_t)y * pitch;
-    float2 v[kP];
-    float ta[kP];
+    float2 v[P];
+    float ta[P];
+    {
+        const auto rt = make_rsrc(target, (uint32_t)((size_t)ny * NX * sizeof(float)));
+        const uint32_t toff = ((uint32_t)y * NX + (uint32_t)t) * 4u;
 #pragma unroll
-    for (int m = 0; m < kP; ++m) ta[m] = trow[t + T * m];
+        for (int m = 0; m < P; ++m) ta[m] = buf_ld1(rt, toff, (uint32_t)(m * T * 4));
+    }
 
     if (MODE == GS_INIT) {
         double s2 = 0.0, s4 = 0.0;
         if (init) {
             const float2* irow = init + (size_t)y * NX;
 #pragma unroll
-            for (int m = 0; m < kP; ++m) {
+            for (int m = 0; m < P; ++m) {
                 const float2 p = irow[t + T * m];
                 const float mag = sqrtf(p.x * p.x + p.y * p.y);
                 v[m] = mag > 0.0f ? make_float2(ta[m] * (p.x / mag), ta[m] * (p.y / mag)) : make_float2(ta[m], 0.0f);
@@ -126,7 +129,7 @@ __global__ __launch_bounds__(256) void k_gs_rows(const float* __restrict__ targe
             uint32_t idx = (uint32_t)((c0 + (uint64_t)y * NX + (uint64_t)t) % n_lut);
             const uint32_t step = (uint32_t)(T % n_lut);
 #pragma unroll
-            for (int m = 0; m < kP; ++m) {
+            for (int m = 0; m < P; ++m) {
                 const float2 p = lut[idx];
                 v[m] = make_float2(ta[m] * p.x, ta[m] * p.y);
                 idx += step;
@@ -134,14 +137,14 @@ __global__ __launch_bounds__(256) void k_gs_rows(const float* __restrict__ targe
             }
         }
 #pragma unroll
-        for (int m = 0; m < kP; ++m) {
+        for (int m = 0; m < P; ++m) {
             const double q = (double)ta[m] * (double)ta[m];
             s2 += q;
             s4 += q * q;
         }
-        fft_stages<NX, 1, RowAddrG, (NX / kP <= 64)>(v, t, lds, RowAddrG{row * PadLen<NX>::v}, tw);
+        fft_stages<NX, 1, RowAddrG, (NX / P <= 64), P>(v, t, lds, RowAddrG{row * PadLenP<NX, P>::v}, tw);
 #pragma unroll
-        for (int m = 0; m < kP; ++m) srow[t + T * m] = v[m];
+        for (int m = 0; m < P; ++m) srow[t + T * m] = v[m];
         double a2[2] = {s2, s4};
         row_sum<2>(a2, reinterpret_cast<double*>(lds), T, row, t);
         if (t == 0) {
@@ -151,37 +154,43 @@ __global__ __launch_bounds__(256) void k_gs_rows(const float* __restrict__ targe
         return;
     }
 
+    // state and target through buffer descriptors: one lane offset, slot m at
+    // the uniform offset m*T elements
+    const auto rs = make_rsrc(state, (uint32_t)((size_t)ny * pitch * sizeof(float2)));
+    const uint32_t soff = ((uint32_t)y * (uint32_t)pitch + (uint32_t)t) * 8u;
 #pragma unroll
-    for (int m = 0; m < kP; ++m) v[m] = srow[t + T * m];
-    fft_stages<NX, -1, RowAddrG, (NX / kP <= 64)>(v, t, lds, RowAddrG{row * PadLen<NX>::v}, tw);
+    for (int m = 0; m < P; ++m) v[m] = buf_ld2(rs, soff, (uint32_t)(m * T * 8));
+    fft_stages<NX, -1, RowAddrG, (NX / P <= 64), P>(v, t, lds, RowAddrG{row * PadLenP<NX, P>::v}, tw);
     // R' (unscaled) = sqrt(N) * R'_unitary; intensity in unitary units
     const float inv_n = 1.0f / (float)((size_t)NX * (size_t)ny);
     const float inv_sqrt_n = (float)(1.0 / sqrt((double)NX * (double)ny));
-    const double te = consts->te_scale;
+    const float te = (float)consts->te_scale;
     double s_ii = 0.0, s_it = 0.0, e = 0.0;
 #pragma unroll
-    for (int m = 0; m < kP; ++m) {
+    for (int m = 0; m < P; ++m) {
         const float i_u = (v[m].x * v[m].x + v[m].y * v[m].y) * inv_n;
         const double ib = (double)i_u;
         const double t2 = (double)ta[m] * (double)ta[m];
         s_ii += ib * ib;
         s_it += ib * t2;
-        const double d = sqrt(ib) - (double)ta[m] * te;
-        e += d * d;
+        // amplitude error term in FP32 (relative error ~1e-7), summed in FP64
+        const float d = sqrtf(i_u) - ta[m] * te;
+        e += (double)(d * d);
     }
     if (MODE == GS_FINAL) {
         float2* frow = field_out + (size_t)y * NX;
 #pragma unroll
-        for (int m = 0; m < kP; ++m) frow[t + T * m] = make_float2(v[m].x * inv_sqrt_n, v[m].y * inv_sqrt_n);
+        for (int m = 0; m < P; ++m) frow[t + T * m] = make_float2(v[m].x * inv_sqrt_n, v[m].y * inv_sqrt_n);
     } else {
 #pragma unroll
-        for (int m = 0; m < kP; ++m) {
-            const float mag = sqrtf(v[m].x * v[m].x + v[m].y * v[m].y);
-            v[m] = mag > 0.0f ? make_float2(ta[m] * (v[m].x / mag), ta[m] * (v[m].y / mag)) : make_float2(ta[m], 0.0f);
+        for (int m = 0; m < P; ++m) {
+            const float m2 = v[m].x * v[m].x + v[m].y * v[m].y;
+            const float k = ta[m] * rsqrtf(m2);   // T / |R'|
+            v[m] = m2 > 0.0f ? make_float2(k * v[m].x, k * v[m].y) : make_float2(ta[m], 0.0f);
         }
-        fft_stages<NX, 1, RowAddrG, (NX / kP <= 64)>(v, t, lds, RowAddrG{row * PadLen<NX>::v}, tw);
+        fft_stages<NX, 1, RowAddrG, (NX / P <= 64), P>(v, t, lds, RowAddrG{row * PadLenP<NX, P>::v}, tw);
 #pragma unroll
-        for (int m = 0; m < kP; ++m) srow[t + T * m] = v[m];
+        for (int m = 0; m < P; ++m) buf_st2(rs, soff, (uint32_t)(m * T * 8), v[m]);
     }
     double a3[3] = {s_ii, s_it, e};
     row_sum<3>(a3, reinterpret_cast<double*>(lds), T, row, t);
@@ -192,95 +201,133 @@ __global__ __launch_bounds__(256) void k_gs_rows(const float* __restrict__ targe
     }
 }
 
+// Points per thread of the GS passes: the plan's value (4, 8 or 16), or else
+// 8 when 16 would give the launch fewer than 2^17 threads (two waves per SIMD
+// on 256 CUs; a single 1024^2 field has only 1024 transforms per axis), 16
+// otherwise.  4 is never chosen by itself: its five radix-4 stages per 1024
+// points round more often, and 50-iteration GS trajectories drift from FP64
+// about 2.5x further than with 8 or 16.
+static int gs_points(int n, int ntrans, int planned)
+{
+    if (planned == 4 || planned == 8 || planned == 16) return planned;
+    return (long)ntrans * (n / 16) < (1L << 17) ? 8 : 16;
+}
+
+#define HOLO_SWITCH_P(p, ...)                                    \
+    switch (p) {                                                 \
+        case 4: { constexpr int P_ = 4; __VA_ARGS__; } break;    \
+        case 8: { constexpr int P_ = 8; __VA_ARGS__; } break;    \
+        case 16: { constexpr int P_ = 16; __VA_ARGS__; } break;  \
+        default: return hipErrorInvalidValue;                    \
+    }
+
 hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const float2* lut, uint32_t n_lut,
                           uint64_t c0, const float2* init, float2* state, float2* field_out,
                           double* partials, const GsConsts* consts, const float2* tw_x,
                           const LaunchCfg& cfg, hipStream_t s)
 {
-    const int T = nx / kP;
+    const int P = gs_points(nx, ny, cfg.pts);
+    const int T = nx / P;
+    const int bound = P == 16 ? 256 : 512;   // launch bound of k_gs_rows
+    if (T > bound) return hipErrorInvalidValue;
     int rows = cfg.rows_per_block;
     if (rows <= 0) {   // widest block that still leaves >= 512 blocks
         rows = 256 / T > 0 ? 256 / T : 1;
         while (rows > 1 && ny / rows < 512) rows >>= 1;
     }
-    while (rows > 1 && rows * T > 256) rows >>= 1;   // launch bound of k_gs_rows
+    while (rows > 1 && rows * T > bound) rows >>= 1;
     while (rows > 1 && (ny % rows)) rows >>= 1;
     if (rows > ny) rows = ny;
-    HOLO_SWITCH_N(nx, {
-        size_t fft_lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
-        size_t red_lds = (size_t)3 * (rows * T / 64 + 1) * sizeof(double);
-        size_t lds = fft_lds > red_lds ? fft_lds : red_lds;
-        if (mode == GS_INIT) {
-            allow_lds_g(k_gs_rows<N_, GS_INIT>, lds);
-            hipLaunchKernelGGL((k_gs_rows<N_, GS_INIT>), dim3(ny / rows), dim3(rows * T), lds, s, target, ny, lut,
-                               n_lut, c0, init, state, field_out, partials, consts, tw_x,
-                               row_pitch(nx, cfg));
-        } else if (mode == GS_ITER) {
-            allow_lds_g(k_gs_rows<N_, GS_ITER>, lds);
-            hipLaunchKernelGGL((k_gs_rows<N_, GS_ITER>), dim3(ny / rows), dim3(rows * T), lds, s, target, ny, lut,
-                               n_lut, c0, init, state, field_out, partials, consts, tw_x,
-                               row_pitch(nx, cfg));
-        } else {
-            allow_lds_g(k_gs_rows<N_, GS_FINAL>, lds);
-            hipLaunchKernelGGL((k_gs_rows<N_, GS_FINAL>), dim3(ny / rows), dim3(rows * T), lds, s, target, ny, lut,
-                               n_lut, c0, init, state, field_out, partials, consts, tw_x,
-                               row_pitch(nx, cfg));
+    HOLO_SWITCH_P(P, HOLO_SWITCH_N(nx, {
+        if (N_ >= P_) {
+            size_t fft_lds = (size_t)rows * PadLenP<N_, P_>::v * sizeof(float2);
+            size_t red_lds = (size_t)3 * (rows * T / 64 + 1) * sizeof(double);
+            size_t lds = fft_lds > red_lds ? fft_lds : red_lds;
+            if (mode == GS_INIT) {
+                allow_lds_g(k_gs_rows<N_, GS_INIT, P_>, lds);
+                hipLaunchKernelGGL((k_gs_rows<N_, GS_INIT, P_>), dim3(ny / rows), dim3(rows * T), lds, s, target,
+                                   ny, lut, n_lut, c0, init, state, field_out, partials, consts, tw_x,
+                                   row_pitch(nx, cfg));
+            } else if (mode == GS_ITER) {
+                allow_lds_g(k_gs_rows<N_, GS_ITER, P_>, lds);
+                hipLaunchKernelGGL((k_gs_rows<N_, GS_ITER, P_>), dim3(ny / rows), dim3(rows * T), lds, s, target,
+                                   ny, lut, n_lut, c0, init, state, field_out, partials, consts, tw_x,
+                                   row_pitch(nx, cfg));
+            } else {
+                allow_lds_g(k_gs_rows<N_, GS_FINAL, P_>, lds);
+                hipLaunchKernelGGL((k_gs_rows<N_, GS_FINAL, P_>), dim3(ny / rows), dim3(rows * T), lds, s, target,
+                                   ny, lut, n_lut, c0, init, state, field_out, partials, consts, tw_x,
+                                   row_pitch(nx, cfg));
+            }
         }
-    });
+    }));
     return hipGetLastError();
 }
 
 // -------------------------------------------------------------------------
 // Columns pass (in place on `state`).
 // -------------------------------------------------------------------------
-template <int NY, int C>
-__global__ __launch_bounds__(C * (NY / kP)) void k_gs_cols(float2* __restrict__ state, int nx,
+template <int NY, int C, int P>
+__global__ __launch_bounds__(C * (NY / P)) void k_gs_cols(float2* __restrict__ state, int nx,
                                                           uint8_t* __restrict__ codes, const float2* __restrict__ tw,
                                                           int pitch)
 {
     extern __shared__ float2 lds[];
-    constexpr int T = NY / kP;
+    constexpr int T = NY / P;
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int x0 = xcd_tile(blockIdx.x, gridDim.x) * C;
-    const size_t mstride = (size_t)T * pitch;
-    const uint32_t toff = ((uint32_t)t * (uint32_t)pitch + (uint32_t)c) * (uint32_t)sizeof(float2);
-    float2* col = state + x0;
-    float2 v[kP];
+    // buffer descriptors over the whole field: lane offset (t*pitch + x0 + c),
+    // slot m at the uniform offset m*T rows
+    const auto rs = make_rsrc(state, (uint32_t)((size_t)NY * pitch * sizeof(float2)));
+    const uint32_t toff = ((uint32_t)t * (uint32_t)pitch + (uint32_t)(x0 + c)) * 8u;
+    const uint32_t mst = (uint32_t)T * (uint32_t)pitch * 8u;
+    float2 v[P];
 #pragma unroll
-    for (int m = 0; m < kP; ++m) v[m] = ld_off(col + m * mstride, toff);
-    fft_stages<NY, 1>(v, t, lds, ColAddr<C>{c}, tw);
+    for (int m = 0; m < P; ++m) v[m] = buf_ld2(rs, toff, m * mst);
+    fft_stages<NY, 1, ColAddr<C>, false, P>(v, t, lds, ColAddr<C>{c}, tw);
     if (codes) {
-        const uint32_t coff = (uint32_t)t * (uint32_t)nx + (uint32_t)c;
-        const size_t cstride = (size_t)T * nx;
+        const auto rc = make_rsrc(codes, (uint32_t)((size_t)NY * nx));
+        const uint32_t coff = (uint32_t)t * (uint32_t)nx + (uint32_t)(x0 + c);
 #pragma unroll
-        for (int m = 0; m < kP; ++m) st_off(codes + x0 + m * cstride, coff, quant8(v[m]));
+        for (int m = 0; m < P; ++m)
+            __builtin_amdgcn_raw_buffer_store_b8((unsigned char)quant8(v[m]), rc, coff, (uint32_t)(m * T * nx), 0);
     }
 #pragma unroll
-    for (int m = 0; m < kP; ++m) {
-        const float mag = sqrtf(v[m].x * v[m].x + v[m].y * v[m].y);
-        v[m] = mag > 0.0f ? make_float2(v[m].x / mag, v[m].y / mag) : make_float2(1.0f, 0.0f);
+    for (int m = 0; m < P; ++m) {
+        const float m2 = v[m].x * v[m].x + v[m].y * v[m].y;
+        const float k = rsqrtf(m2);   // 1 / |H|
+        v[m] = m2 > 0.0f ? make_float2(k * v[m].x, k * v[m].y) : make_float2(1.0f, 0.0f);
     }
-    fft_stages<NY, -1>(v, t, lds, ColAddr<C>{c}, tw);
+    fft_stages<NY, -1, ColAddr<C>, false, P>(v, t, lds, ColAddr<C>{c}, tw);
 #pragma unroll
-    for (int m = 0; m < kP; ++m) st_off(col + m * mstride, toff, v[m]);
+    for (int m = 0; m < P; ++m) buf_st2(rs, toff, m * mst, v[m]);
 }
 
 hipError_t launch_gs_cols(float2* state, int nx, int ny, uint8_t* codes, const float2* tw_y,
                           const LaunchCfg& cfg, hipStream_t s)
 {
-    const int T = ny / kP;
-    const int C = col_block_cols(ny, nx, 1, cfg.cols_per_block, 2);
-#define HOLO_GS_COLS_CASE(CC)                                                                                \
-    case CC: {                                                                                               \
-        constexpr int C_ = CC;                                                                               \
-        HOLO_SWITCH_N(ny, {                                                                                  \
-            if (C_ * (N_ / kP) <= 1024) {                                                                    \
-                size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);                                   \
-                allow_lds_g(k_gs_cols<N_, C_>, lds);                                                         \
-                hipLaunchKernelGGL((k_gs_cols<N_, C_>), dim3(nx / C_), dim3(C_ * T), lds, s, state, nx, codes, \
-                                   tw_y, row_pitch(nx, cfg));                                                \
-            }                                                                                                \
-        });                                                                                                  \
+    const int P = gs_points(ny, nx, cfg.pts);
+    const int T = ny / P;
+    // column-tile width: the plan's, or the widest that keeps >= 512 blocks;
+    // at most 1024 threads and 160 KiB of LDS per block
+    int C = cfg.cols_per_block > 0 ? cfg.cols_per_block : 16;
+    if (cfg.cols_per_block <= 0)
+        while (C > 2 && nx / C < 512) C >>= 1;
+    if (C > 16) C = 16;
+    while (C > 2 && (C * T > 1024 || (size_t)C * (ny + ny / P) * sizeof(float2) > 160 * 1024)) C >>= 1;
+    if (C > nx) C = nx;
+    if (C * T > 1024) return hipErrorInvalidValue;
+#define HOLO_GS_COLS_CASE(CC)                                                                                 \
+    case CC: {                                                                                                \
+        constexpr int C_ = CC;                                                                                \
+        HOLO_SWITCH_P(P, HOLO_SWITCH_N(ny, {                                                                  \
+            if (N_ >= P_ && C_ * (N_ / P_) <= 1024) {                                                         \
+                size_t lds = (size_t)C_ * PadLenP<N_, P_>::v * sizeof(float2);                               \
+                allow_lds_g(k_gs_cols<N_, C_, P_>, lds);                                                      \
+                hipLaunchKernelGGL((k_gs_cols<N_, C_, P_>), dim3(nx / C_), dim3(C_ * T), lds, s, state, nx,   \
+                                   codes, tw_y, row_pitch(nx, cfg));                                          \
+            }                                                                                                 \
+        }));                                                                                                  \
     } break;
     switch (C) {
         HOLO_GS_COLS_CASE(2)

@@ -470,7 +470,7 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
                       (uintptr_t)a.codes, (uintptr_t)(a.final2 != nullptr), (uintptr_t)a.recon, (uintptr_t)ws,
                       (uintptr_t)cfg.cols_per_block, (uintptr_t)cfg.rows_per_block, (uintptr_t)cfg.ksplit,
                       (uintptr_t)cfg.recon_cols_per_block, (uintptr_t)(intptr_t)cfg.pad,
-                      (uintptr_t)(intptr_t)cfg.chunk}};
+                      (uintptr_t)(intptr_t)cfg.chunk, (uintptr_t)cfg.pts}};
         hipGraphExec_t exec = nullptr;
         {
             std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -1019,6 +1019,7 @@ holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t ny, int3
         chosen[3] = best.recon_cols_per_block;
         chosen[4] = best.pad;
         chosen[5] = best.chunk;
+        chosen[6] = best.pts;
     }
     g_err.clear();
     return HOLO_OK;
@@ -1052,20 +1053,41 @@ holo_status holo_autotune_gs(const float* target, int64_t nx, int64_t ny, const 
         q.nmse = nullptr;
         auto run = [&](const LaunchCfg& c) { return gs_run(device, q, s, c); };
         st = time_runs(s, reps, [&] { return run(best); }, &best_ms);
+        // points per thread first (changes the FP32 factorisation, so its
+        // guard is a tolerance: per-iteration NMSE within 1e-5 relative and
+        // codes within 1e-3 of the pixels), then the shapes (exact guard)
+        const int pts_opts[] = {16, 8, 8, 8};
         const int cols_opts[] = {2, 4, 8, 16};
         const int rows_opts[] = {1, 2, 4, 8};
         const int pad_opts[] = {0, 16, 64, 64};
-        for (int dim = 0; dim < 3 && !st; ++dim) {
-            const int* opts = dim == 0 ? cols_opts : dim == 1 ? rows_opts : pad_opts;
+        for (int dim = 0; dim < 4 && !st; ++dim) {
+            const int* opts = dim == 0 ? pts_opts : dim == 1 ? cols_opts : dim == 2 ? rows_opts : pad_opts;
+            if (dim == 1) {   // later dimensions compare against the chosen pts
+                GsArgs v = a;
+                v.nmse = ref_nm;
+                if ((st = gs_run(device, v, s, best))) break;
+                (void)hipMemcpy(ref_codes.data(), codes, npix, hipMemcpyDeviceToHost);
+            }
             for (int i = 0; i < 4; ++i) {
                 LaunchCfg c = best;
-                (dim == 0 ? c.cols_per_block : dim == 1 ? c.rows_per_block : c.pad) = opts[i];
+                (dim == 0 ? c.pts : dim == 1 ? c.cols_per_block : dim == 2 ? c.rows_per_block : c.pad) = opts[i];
                 GsArgs v = a;
                 v.nmse = nm;
-                if (gs_run(device, v, s, c) != HOLO_OK) continue;
+                if (gs_run(device, v, s, c) != HOLO_OK) {
+                    (void)hipGetLastError();
+                    continue;
+                }
                 (void)hipMemcpy(cd.data(), codes, npix, hipMemcpyDeviceToHost);
-                bool same = cd == ref_codes;
-                for (int k = 0; k < n_iter; ++k) same = same && nm[k] == ref_nm[k];
+                bool same = true;
+                if (dim == 0) {
+                    size_t diff = 0;
+                    for (size_t p = 0; p < npix; ++p) diff += cd[p] != ref_codes[p];
+                    same = diff <= npix / 1000;
+                    for (int k = 0; k < n_iter; ++k) same = same && std::fabs(nm[k] - ref_nm[k]) <= 1e-5 * ref_nm[k];
+                } else {
+                    same = cd == ref_codes;
+                    for (int k = 0; k < n_iter; ++k) same = same && nm[k] == ref_nm[k];
+                }
                 if (!same) continue;
                 double ms = 0.0;
                 if (time_runs(s, reps, [&] { return run(c); }, &ms)) continue;
@@ -1087,35 +1109,40 @@ holo_status holo_autotune_gs(const float* target, int64_t nx, int64_t ny, const 
         chosen[3] = best.recon_cols_per_block;
         chosen[4] = best.pad;
         chosen[5] = best.chunk;
+        chosen[6] = best.pts;
     }
     g_err.clear();
     return HOLO_OK;
 }
 
-holo_status holo_plan_set(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, const int32_t* cfg4)
+holo_status holo_plan_set(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, const int32_t* cfg)
 {
-    if ((kind != 0 && kind != 1) || !cfg4) return fail(HOLO_EINVAL, "kind must be 0 (OSPR) or 1 (GS), cfg4 set");
+    if ((kind != 0 && kind != 1) || !cfg) return fail(HOLO_EINVAL, "kind must be 0 (OSPR) or 1 (GS), cfg set");
+    if (cfg[6] != 0 && cfg[6] != 4 && cfg[6] != 8 && cfg[6] != 16)
+        return fail(HOLO_EINVAL, "points per thread must be 0, 4, 8 or 16 (got %d)", cfg[6]);
     LaunchCfg c;
-    c.cols_per_block = cfg4[0];
-    c.rows_per_block = cfg4[1];
-    c.ksplit = cfg4[2];
-    c.recon_cols_per_block = cfg4[3];
-    c.pad = cfg4[4];
-    c.chunk = cfg4[5];
+    c.cols_per_block = cfg[0];
+    c.rows_per_block = cfg[1];
+    c.ksplit = cfg[2];
+    c.recon_cols_per_block = cfg[3];
+    c.pad = cfg[4];
+    c.chunk = cfg[5];
+    c.pts = cfg[6];
     plan_put(kind, nx, ny, n_sf, c);
     return HOLO_OK;
 }
 
-holo_status holo_plan_get(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, int32_t* cfg4)
+holo_status holo_plan_get(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, int32_t* cfg)
 {
-    if ((kind != 0 && kind != 1) || !cfg4) return fail(HOLO_EINVAL, "kind must be 0 (OSPR) or 1 (GS), cfg4 set");
+    if ((kind != 0 && kind != 1) || !cfg) return fail(HOLO_EINVAL, "kind must be 0 (OSPR) or 1 (GS), cfg set");
     const LaunchCfg c = plan_get(kind, nx, ny, n_sf);
-    cfg4[0] = c.cols_per_block;
-    cfg4[1] = c.rows_per_block;
-    cfg4[2] = c.ksplit;
-    cfg4[3] = c.recon_cols_per_block;
-    cfg4[4] = c.pad;
-    cfg4[5] = c.chunk;
+    cfg[0] = c.cols_per_block;
+    cfg[1] = c.rows_per_block;
+    cfg[2] = c.ksplit;
+    cfg[3] = c.recon_cols_per_block;
+    cfg[4] = c.pad;
+    cfg[5] = c.chunk;
+    cfg[6] = c.pts;
     return HOLO_OK;
 }
 
@@ -1129,10 +1156,10 @@ holo_status holo_plan_save(const char* path)
     bool first = true;
     for (auto& kv : g_plans) {
         std::fprintf(f,
-                     "%s\n  {\"kind\": %d, \"nx\": %lld, \"ny\": %lld, \"n_sf\": %d, \"cfg\": [%d, %d, %d, %d, %d, %d]}",
+                     "%s\n  {\"kind\": %d, \"nx\": %lld, \"ny\": %lld, \"n_sf\": %d, \"cfg\": [%d, %d, %d, %d, %d, %d, %d]}",
                      first ? "" : ",", kv.first.kind, (long long)kv.first.nx, (long long)kv.first.ny, kv.first.n_sf,
                      kv.second.cols_per_block, kv.second.rows_per_block, kv.second.ksplit,
-                     kv.second.recon_cols_per_block, kv.second.pad, kv.second.chunk);
+                     kv.second.recon_cols_per_block, kv.second.pad, kv.second.chunk, kv.second.pts);
         first = false;
     }
     std::fprintf(f, "\n]}\n");
@@ -1150,15 +1177,15 @@ holo_status holo_plan_load(const char* path)
     size_t n;
     while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
     std::fclose(f);
-    // entries written by holo_plan_save: {"kind": K, "nx": X, "ny": Y, "n_sf": S, "cfg": [a, b, c, d]}
+    // entries written by holo_plan_save: {"kind": K, "nx": X, "ny": Y, "n_sf": S, "cfg": [7 ints]}
     size_t pos = 0;
     int loaded = 0;
     while ((pos = txt.find("{\"kind\"", pos)) != std::string::npos) {
-        int kind, sf, c0, c1, c2, c3, c4, c5;
+        int kind, sf, c0, c1, c2, c3, c4, c5, c6;
         long long nx, ny;
         if (std::sscanf(txt.c_str() + pos,
-                        "{\"kind\": %d, \"nx\": %lld, \"ny\": %lld, \"n_sf\": %d, \"cfg\": [%d, %d, %d, %d, %d, %d]}",
-                        &kind, &nx, &ny, &sf, &c0, &c1, &c2, &c3, &c4, &c5) == 10) {
+                        "{\"kind\": %d, \"nx\": %lld, \"ny\": %lld, \"n_sf\": %d, \"cfg\": [%d, %d, %d, %d, %d, %d, %d]}",
+                        &kind, &nx, &ny, &sf, &c0, &c1, &c2, &c3, &c4, &c5, &c6) == 11) {
             LaunchCfg c;
             c.cols_per_block = c0;
             c.rows_per_block = c1;
@@ -1166,6 +1193,7 @@ holo_status holo_plan_load(const char* path)
             c.recon_cols_per_block = c3;
             c.pad = c4;
             c.chunk = c5;
+            c.pts = c6;
             plan_put(kind, nx, ny, sf, c);
             ++loaded;
         } else {

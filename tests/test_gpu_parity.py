@@ -193,6 +193,18 @@ def test_gs_other_sizes(holo, orc, nx, ny):
     _gs_case(holo, orc, nx, ny, 6, 10007, 4)
 
 
+@pytest.mark.parametrize("pts", [4, 8, 16])
+@pytest.mark.parametrize("nx,ny", [(1024, 512), (64, 2048), (256, 16)])
+def test_gs_points_per_thread(holo, orc, pts, nx, ny):
+    # every points-per-thread factorisation of the GS transforms meets the
+    # same oracle bar (plans are restored afterwards)
+    holo.plan_set(holo.PLAN_GS, nx, ny, 1, [0, 0, 0, 0, -1, 0, pts])
+    try:
+        _gs_case(holo, orc, nx, ny, 5, 10007, 6)
+    finally:
+        holo.plan_set(holo.PLAN_GS, nx, ny, 1, holo.DEFAULT_PLAN)
+
+
 def test_gs_fixed_point_and_resume(holo, orc):
     nx, ny = 64, 32
     rng = np.random.default_rng(3)
@@ -258,9 +270,9 @@ def test_gs_graph_replay_matches_eager(holo):
 
 
 @pytest.mark.parametrize("plan", [
-    [16, 2, 4, 0, 16, 5],        # chunks of 5 over 13 sub-frames (ragged last chunk)
-    [8, 1, 2, 0, 0, 4],          # no padding
-    [8, 8, 8, 4, 64, 0],
+    [16, 2, 4, 0, 16, 5, 0],     # chunks of 5 over 13 sub-frames (ragged last chunk)
+    [8, 1, 2, 0, 0, 4, 0],       # no padding
+    [8, 8, 8, 4, 64, 0, 0],
 ])
 def test_launch_plans_give_identical_holograms(holo, plan):
     nx, ny, nsf = 256, 512, 13
