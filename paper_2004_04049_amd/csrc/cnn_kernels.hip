@@ -79,66 +79,96 @@ __global__ __launch_bounds__(256) void k_conv1(const float* __restrict__ target,
 }
 
 // ---------------------------------------------------------------------------
-// 32 -> 32 layer on MFMA.  Block = 4 waves = 4 output rows y0..y0+3 of one
-// 32-pixel segment x0..x0+31; each wave computes D[32 px][32 ch] with 18
-// MFMA steps of K = 16 (tap t = step/2, channels 16*(step%2) .. +15).
+// 32 -> 32 layer on MFMA.  Block = 4 waves over a tile of kConvRows rows x 32
+// pixels; wave w computes tile rows w*kConvRows/4 .. +kConvRows/4-1, one 32-pixel x
+// 32-channel result per row, from 18 MFMA steps of K = 16 (tap t = step/2,
+// input channels 16*(step%2) .. +15).  The weights stay in registers for the
+// whole tile (lane l holds the 18 B-operand words of output channel l%32);
+// the activations come from an LDS halo tile [18 rows][34 px][32 ch].
 // MODE 0 (forward): input = activation, weights Wk[co][t][ci], epilogue
 //   relu(acc + b[co]).
 // MODE 1 (backward data): input = dY, weights Wk[ci][8-t][co] (transposed,
 //   taps reversed), epilogue acc * (act_prev > 0).
-// LDS: input halo tile [6 rows][34 px][32 ch] and weights [32][9][32], BF16.
 // ---------------------------------------------------------------------------
+constexpr int kConvRows = 8;
+constexpr int kOutPitch = 40;   // u16 per staged output pixel (80-byte rows)
 template <int MODE>
 __global__ __launch_bounds__(256) void k_conv32(const uint16_t* __restrict__ in, int ny, int nx,
                                                 const uint16_t* __restrict__ wk, const float* __restrict__ bias,
                                                 const uint16_t* __restrict__ act_prev, uint16_t* __restrict__ out)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t tile[6 * 34 * 32];
-    __shared__ __attribute__((aligned(16))) uint16_t wl[32 * 9 * 32];
+    __shared__ __attribute__((aligned(16))) uint16_t tile[(kConvRows + 2) * 34 * 32];
+    __shared__ __attribute__((aligned(16))) uint16_t opage[4][32 * kOutPitch];   // per-wave output staging
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 31, kh = lane >> 5;   // pixel row of A / channel column of B; K half
     const int nseg = nx / 32;
     const int x0 = (blockIdx.x % nseg) * 32;
-    const int y0 = (blockIdx.x / nseg) * 4;
-    // stage weights (18 KiB) and the halo tile: 6*34 pixels x 64 bytes
-    {
-        const uint4* src = reinterpret_cast<const uint4*>(wk);
-        uint4* dst = reinterpret_cast<uint4*>(wl);
-        for (int i = threadIdx.x; i < 32 * 9 * 32 / 8; i += 256) dst[i] = src[i];
-    }
-    for (int i = threadIdx.x; i < 6 * 34 * 4; i += 256) {
-        const int q = i & 3, pix = i >> 2;
+    const int y0 = (blockIdx.x / nseg) * kConvRows;
+    // weights: B[k][n = i] for step s = 8 channels of tap s/2
+    uint4 bw[18];
+#pragma unroll
+    for (int st = 0; st < 18; ++st)
+        bw[st] = *reinterpret_cast<const uint4*>(wk + (i * 9 + (st >> 1)) * 32 + 16 * (st & 1) + 8 * kh);
+    const int rows = ny - y0 < kConvRows ? ny - y0 : kConvRows;
+    for (int j = threadIdx.x; j < (rows + 2) * 34 * 4; j += 256) {
+        const int q = j & 3, pix = j >> 2;
         const int r = pix / 34, c = pix - r * 34;
         const int yy = (y0 + r - 1 + ny) & (ny - 1), xx = (x0 + c - 1 + nx) & (nx - 1);
-        reinterpret_cast<uint4*>(tile)[pix * 4 + q] =
-            reinterpret_cast<const uint4*>(in + ((size_t)yy * nx + xx) * 32)[q];
+        reinterpret_cast<uint4*>(tile)[pix * 4 + q] = reinterpret_cast<const uint4*>(in + ((size_t)yy * nx + xx) * 32)[q];
     }
     __syncthreads();
-    f32x16 acc = {};
-    const int i = lane & 31, kh = lane >> 5;   // pixel row of A / channel column of B; K half
-#pragma unroll
-    for (int step = 0; step < 18; ++step) {
-        const int t = step >> 1, c0 = 16 * (step & 1) + 8 * kh;
-        const int dy = t / 3, dx = t % 3;   // tile offsets (halo origin at -1)
-        const uint4 a = *reinterpret_cast<const uint4*>(tile + ((wave + dy) * 34 + (i + dx)) * 32 + c0);
-        const uint4 bw = *reinterpret_cast<const uint4*>(wl + (i * 9 + t) * 32 + c0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, bw),
-                                                      acc, 0, 0, 0);
-    }
-    // D[px][ch]: register r holds pixel 8*(r/4) + 4*kh + (r%4), channel i
-    const int y = y0 + wave;
     const float bb = MODE == 0 ? bias[i] : 0.0f;
+    for (int rr = 0; rr < kConvRows / 4; ++rr) {
+        const int rl = wave * (kConvRows / 4) + rr;   // tile row
+        if (rl >= rows) break;
+        f32x16 acc = {};
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int px = 8 * (r >> 2) + 4 * kh + (r & 3);
-        const size_t o = ((size_t)y * nx + x0 + px) * 32 + i;
-        float v = acc[r];
-        if (MODE == 0) {
-            v += bb;
-            v = v > 0.0f ? v : 0.0f;
-        } else {
-            v = act_prev[o] != 0 ? v : 0.0f;   // ReLU gate (activations are >= 0)
+        for (int st = 0; st < 18; ++st) {
+            const int t = st >> 1, c0 = 16 * (st & 1) + 8 * kh;
+            const int dy = t / 3, dx = t % 3;   // tile offsets (halo origin at -1)
+            const uint4 a = *reinterpret_cast<const uint4*>(tile + ((rl + dy) * 34 + (i + dx)) * 32 + c0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                          __builtin_bit_cast(bf16x8, bw[st]), acc, 0, 0, 0);
         }
-        out[o] = f2bf(v);
+        // D[px][ch]: register r holds pixel 8*(r/4) + 4*kh + (r%4), channel i.
+        // Through this wave's LDS page to [px][ch] order, then 16-byte stores
+        // (8 channels of one pixel); MODE 1 gates with the matching 16-byte
+        // word of act_prev.
+        uint16_t* pg = opage[wave];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int px = 8 * (r >> 2) + 4 * kh + (r & 3);
+            float v = acc[r];
+            if (MODE == 0) {
+                v += bb;
+                v = v > 0.0f ? v : 0.0f;
+            }
+            pg[px * kOutPitch + i] = f2bf(v);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int y = y0 + rl;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int w = lane + 64 * h;          // 128 words: pixel w/4, channels 8*(w%4)..
+            const int px = w >> 2, q = w & 3;
+            uint4 u = *reinterpret_cast<const uint4*>(pg + px * kOutPitch + 8 * q);
+            uint4* dst = reinterpret_cast<uint4*>(out + ((size_t)y * nx + x0 + px) * 32) + q;
+            if (MODE == 1) {
+                const uint4 g = reinterpret_cast<const uint4*>(act_prev + ((size_t)y * nx + x0 + px) * 32)[q];
+                auto gate = [](uint32_t val, uint32_t gw) {
+                    const uint32_t lo = (gw & 0xFFFFu) ? (val & 0xFFFFu) : 0u;
+                    const uint32_t hi = (gw >> 16) ? (val & 0xFFFF0000u) : 0u;
+                    return lo | hi;
+                };
+                u = make_uint4(gate(u.x, g.x), gate(u.y, g.y), gate(u.z, g.z), gate(u.w, g.w));
+            }
+            *dst = u;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -291,131 +321,271 @@ __global__ __launch_bounds__(256) void k_conv5_bwd_data(const float2* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradients (VALU, FP32 accumulation), per-block partials over a
-// contiguous range of rows, reduced by k_grad_reduce in a fixed order.
-// 32 -> 32: thread = (tap, 4 output channels, 4 input channels): 576 threads;
-// per pixel one 8-byte LDS read of dY and one of X, 16 FMAs.
-// partial layout per block: [co][ci][t] (oracle order) then bias [co].
+// Weight gradients, FP32 accumulation, one partial per block over a
+// contiguous range of image rows, reduced by k_grad_reduce in a fixed order.
+// Partial layout per block: [co][ci][t] (the oracle's order), then bias [co].
 // ---------------------------------------------------------------------------
-constexpr int kSeg = 256;   // pixels per row segment staged in LDS
-__global__ __launch_bounds__(576) void k_dw32(const uint16_t* __restrict__ x /* act_{l-1} */,
+
+// 32 -> 32 on MFMA: for tap t = (dy, dx), dW_t[co][ci] = sum_p dY[p][co] *
+// X[p + (dy, dx)][ci] is a 32x32 product with K = pixels.  The pixel axis has
+// to be the operand's contiguous axis, so each 32-pixel segment of a row is
+// staged in LDS transposed, dYt[co][px] and Xt[dy][ci][halo px], by threads
+// that load 8 pixels x 8 channels (eight 16-byte words), transpose the 8x8
+// block in registers and write eight 16-byte rows.  Block = 3 waves; wave w
+// owns the taps of kernel row dy = w - 1 (three 32x32 accumulators); the
+// dx-shifted B operand comes from two aligned 16-byte reads and a funnel
+// shift.  D = A B with A[m = co][k = px] and B[k = px][n = ci]; register r of
+// lane l holds co = 8*(r/4) + 4*(l/32) + r%4, ci = l%32.  The next segment's
+// words are loaded while the current one is multiplied.
+constexpr int kDwSeg = 64;                    // output pixels per staged segment
+constexpr int kDwGx = (kDwSeg + 2 + 7) / 8;   // 8-pixel groups of a halo row
+constexpr int kDwPitch = 8 * kDwGx;           // u16 per LDS channel row (16-byte aligned rows)
+constexpr int kDwNx = 3 * 4 * kDwGx;          // X staging threads
+constexpr int kDwNd = 4 * (kDwSeg / 8);       // dY staging threads
+
+// 8 pixels x 8 channels (w[p] = channels 0..7 of pixel p) -> channel e's 8
+// pixels as one 16-byte word.
+__device__ __forceinline__ uint4 transpose_ch(const uint4 (&w)[8], int e)
+{
+    uint32_t d[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint4 a = w[2 * j], b = w[2 * j + 1];
+        const uint32_t av = (e >> 1) == 0 ? a.x : (e >> 1) == 1 ? a.y : (e >> 1) == 2 ? a.z : a.w;
+        const uint32_t bv = (e >> 1) == 0 ? b.x : (e >> 1) == 1 ? b.y : (e >> 1) == 2 ? b.z : b.w;
+        d[j] = (e & 1) ? ((av >> 16) | (bv & 0xFFFF0000u)) : ((av & 0xFFFFu) | (bv << 16));
+    }
+    return make_uint4(d[0], d[1], d[2], d[3]);
+}
+
+__global__ __launch_bounds__(192) void k_dw32(const uint16_t* __restrict__ x /* act_{l-1} */,
                                               const uint16_t* __restrict__ dy, int ny, int nx,
                                               int rows_per_block, float* __restrict__ part)
 {
-    // one row segment of `seg` pixels: dY [seg][32] and X [3][seg + 2][32]
-    __shared__ __attribute__((aligned(16))) uint16_t sdy[kSeg * 32];
-    __shared__ __attribute__((aligned(16))) uint16_t sx[3 * (kSeg + 2) * 32];
-    const int seg = nx < kSeg ? nx : kSeg;
+    __shared__ __attribute__((aligned(16))) uint16_t dyt[32 * kDwPitch];
+    __shared__ __attribute__((aligned(16))) uint16_t xt[3 * 32 * kDwPitch];
     const int tid = threadIdx.x;
-    const int t = tid / 64, cog = (tid >> 3) & 7, cig = tid & 7;
-    const int dyo = t / 3, dxo = t % 3;
-    float acc[4][4] = {};
-    float accb = 0.0f;   // bias gradient: threads 0..31 own channel tid
+    const int lane = tid & 63, wave = tid >> 6;
+    const int l32 = lane & 31, half = lane >> 5;
+    f32x16 acc[3] = {};
+    float accb = 0.0f;   // bias gradient of channel tid (tid < 32)
     const int ybeg = blockIdx.x * rows_per_block;
-    for (int y = ybeg; y < ybeg + rows_per_block && y < ny; ++y)
-        for (int xs = 0; xs < nx; xs += seg) {
-            __syncthreads();
-            for (int i = tid; i < seg * 4; i += 576)
-                reinterpret_cast<uint4*>(sdy)[i] =
-                    reinterpret_cast<const uint4*>(dy + ((size_t)y * nx + xs) * 32)[i];
-            for (int i = tid; i < 3 * (seg + 2) * 4; i += 576) {
-                const int q = i & 3, pix = i >> 2;
-                const int r = pix / (seg + 2), c = pix - r * (seg + 2);
-                const int yy = (y + r - 1 + ny) & (ny - 1), xx = (xs + c - 1 + nx) & (nx - 1);
-                reinterpret_cast<uint4*>(sx)[pix * 4 + q] =
-                    reinterpret_cast<const uint4*>(x + ((size_t)yy * nx + xx) * 32)[q];
-            }
-            __syncthreads();
-            for (int px = 0; px < seg; ++px) {
-                const uint2 gd = *reinterpret_cast<const uint2*>(sdy + px * 32 + 4 * cog);
-                const uint2 gx = *reinterpret_cast<const uint2*>(sx + (dyo * (seg + 2) + px + dxo) * 32 + 4 * cig);
-                const float d[4] = {bf2f(gd.x & 0xFFFF), bf2f(gd.x >> 16), bf2f(gd.y & 0xFFFF), bf2f(gd.y >> 16)};
-                const float v[4] = {bf2f(gx.x & 0xFFFF), bf2f(gx.x >> 16), bf2f(gx.y & 0xFFFF), bf2f(gx.y >> 16)};
+    const int yend = ybeg + rows_per_block < ny ? ybeg + rows_per_block : ny;
+    const int segs_per_row = nx / kDwSeg;
+    const int nseg = (yend - ybeg) * segs_per_row;
+    // staging roles: tid < kDwNx: X row r, channels 8q.., halo pixels
+    // 8g..8g+7 (halo pixel c is x0 - 1 + c); the next kDwNd threads: dY
+    // channels 8q.., pixels 8g..
+    static_assert(kDwNx + kDwNd <= 192, "staging threads");
+    const bool sx = tid < kDwNx, sd = tid >= kDwNx && tid < kDwNx + kDwNd;
+    const int j_ = sd ? tid - kDwNx : tid;
+    const int r_ = sx ? tid / (4 * kDwGx) : 0;
+    const int q_ = sx ? (tid % (4 * kDwGx)) / kDwGx : j_ / (kDwSeg / 8);
+    const int g_ = sx ? tid % kDwGx : j_ % (kDwSeg / 8);
+    uint4 w[8];
+    auto fetch = [&](int sidx) {
+        const int y = ybeg + sidx / segs_per_row, x0 = (sidx % segs_per_row) * kDwSeg;
+        if (sx) {
+            const int yy = (y + r_ - 1 + ny) & (ny - 1);
 #pragma unroll
-                for (int a2 = 0; a2 < 4; ++a2)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[a2][c] = fmaf(d[a2], v[c], acc[a2][c]);
+            for (int p = 0; p < 8; ++p) {
+                const int xx = (x0 + 8 * g_ + p - 1 + nx) & (nx - 1);
+                w[p] = reinterpret_cast<const uint4*>(x + ((size_t)yy * nx + xx) * 32)[q_];
             }
-            if (tid < 32)
-                for (int px = 0; px < seg; ++px) accb += bf2f(sdy[px * 32 + tid]);
+        } else if (sd) {
+#pragma unroll
+            for (int p = 0; p < 8; ++p)
+                w[p] = reinterpret_cast<const uint4*>(dy + ((size_t)y * nx + x0 + 8 * g_ + p) * 32)[q_];
         }
+    };
+    if (nseg > 0) fetch(0);
+    for (int sidx = 0; sidx < nseg; ++sidx) {
+        __syncthreads();
+        if (sx) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                *reinterpret_cast<uint4*>(xt + (r_ * 32 + 8 * q_ + e) * kDwPitch + 8 * g_) = transpose_ch(w, e);
+        } else if (sd) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                *reinterpret_cast<uint4*>(dyt + (8 * q_ + e) * kDwPitch + 8 * g_) = transpose_ch(w, e);
+        }
+        __syncthreads();
+        if (sidx + 1 < nseg) fetch(sidx + 1);   // next segment in flight during the products
+#pragma unroll
+        for (int ks = 0; ks < kDwSeg / 16; ++ks) {
+            const int c0 = 16 * ks + 8 * half;
+            const uint4 a = *reinterpret_cast<const uint4*>(dyt + l32 * kDwPitch + c0);
+            const uint16_t* xr = xt + (wave * 32 + l32) * kDwPitch + c0;
+            const uint4 lo = *reinterpret_cast<const uint4*>(xr);
+            const uint4 hi = *reinterpret_cast<const uint4*>(xr + 8);
+            // output pixel c0 + e with tap dx reads halo pixel c0 + e + dx
+            const uint4 b0 = lo;
+            const uint4 b1 = make_uint4(__builtin_amdgcn_alignbit(lo.y, lo.x, 16), __builtin_amdgcn_alignbit(lo.z, lo.y, 16),
+                                        __builtin_amdgcn_alignbit(lo.w, lo.z, 16), __builtin_amdgcn_alignbit(hi.x, lo.w, 16));
+            const uint4 b2 = make_uint4(lo.y, lo.z, lo.w, hi.x);
+            const bf16x8 av = __builtin_bit_cast(bf16x8, a);
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, b0), acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, b1), acc[1], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8, b2), acc[2], 0, 0, 0);
+        }
+        if (tid < 32)
+#pragma unroll 8
+            for (int px = 0; px < kDwSeg; ++px) accb += bf2f(dyt[tid * kDwPitch + px]);
+    }
     float* o = part + (size_t)blockIdx.x * (32 * 32 * 9 + 32);
 #pragma unroll
-    for (int a2 = 0; a2 < 4; ++a2)
+    for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) o[((4 * cog + a2) * 32 + 4 * cig + c) * 9 + t] = acc[a2][c];
+        for (int r = 0; r < 16; ++r) {
+            const int co = 8 * (r >> 2) + 4 * half + (r & 3);
+            o[(co * 32 + l32) * 9 + wave * 3 + dx] = acc[dx][r];
+        }
     if (tid < 32) o[32 * 32 * 9 + tid] = accb;
 }
 
-// Layer 1 weight gradient: dW1[co][t] = sum_p dY1[p][co] T[p + d(t)]; thread
-// (co, t) = 288 threads, loops over the block's rows.
-__global__ __launch_bounds__(320) void k_dw1(const float* __restrict__ target, const uint16_t* __restrict__ dy,
+// Layers 1 and 5 (few outputs, K = all pixels) on the vector ALUs: block = 8
+// groups x 32 lanes and one image row; group g runs over pixels
+// [g*nx/8, (g+1)*nx/8) with a 3x3 window of its lane's input values in
+// registers (one new column per pixel), and the 8 groups' sums are added in
+// group order through LDS.
+// Layer 5: lane = input channel ci; per pixel 18 FMAs (2 outputs x 9 taps);
+// lanes 0, 1 of group 0.. also sum the bias of output channel lane.
+__global__ __launch_bounds__(256) void k_dw5(const uint16_t* __restrict__ x4, const float2* __restrict__ d5,
                                              int ny, int nx, int rows_per_block, float* __restrict__ part)
 {
-    const int tid = threadIdx.x;
-    const int co = tid / 10, t = tid % 10;   // t == 9: bias
-    float acc = 0.0f;
-    if (co < 32) {
-        const int ybeg = blockIdx.x * rows_per_block;
-        for (int y = ybeg; y < ybeg + rows_per_block && y < ny; ++y)
-            for (int x = 0; x < nx; ++x) {
-                const float d = bf2f(dy[((size_t)y * nx + x) * 32 + co]);
-                float v = 1.0f;
-                if (t < 9) {
-                    const int yy = (y + t / 3 - 1 + ny) & (ny - 1), xx = (x + t % 3 - 1 + nx) & (nx - 1);
-                    v = target[yy * nx + xx];
-                }
-                acc = fmaf(d, v, acc);
-            }
-        float* o = part + (size_t)blockIdx.x * (32 * 9 + 32);
-        if (t < 9) o[co * 9 + t] = acc;
-        else o[32 * 9 + co] = acc;
-    }
-}
-
-// Layer 5 weight gradient: dW5[co][ci][t] = sum_p d5[p][co] X4[p + d(t)][ci];
-// thread (ci, t) handles both output channels: 288 threads (+2 bias).
-__global__ __launch_bounds__(320) void k_dw5(const uint16_t* __restrict__ x4, const float2* __restrict__ d5,
-                                             int ny, int nx, int rows_per_block, float* __restrict__ part)
-{
-    const int tid = threadIdx.x;
-    const int ci = tid / 9, t = tid % 9;
-    float a0 = 0.0f, a1 = 0.0f;
+    constexpr int NO = 2 * 32 * 9 + 2;
+    __shared__ float red[8][NO];
+    const int ci = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int seg = nx / 8;
+    float a0[9] = {}, a1[9] = {};
+    float b0 = 0.0f, b1 = 0.0f;
     const int ybeg = blockIdx.x * rows_per_block;
-    for (int y = ybeg; y < ybeg + rows_per_block && y < ny; ++y)
-        for (int x = 0; x < nx; ++x) {
-            const float2 d = d5[(size_t)y * nx + x];
-            if (tid < 288) {
-                const int yy = (y + t / 3 - 1 + ny) & (ny - 1), xx = (x + t % 3 - 1 + nx) & (nx - 1);
-                const float v = bf2f(x4[((size_t)yy * nx + xx) * 32 + ci]);
-                a0 = fmaf(d.x, v, a0);
-                a1 = fmaf(d.y, v, a1);
-            } else if (tid == 288) {
-                a0 += d.x;
-            } else if (tid == 289) {
-                a1 += d.y;
+    for (int y = ybeg; y < ybeg + rows_per_block && y < ny; ++y) {
+        size_t rowo[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) rowo[r] = (size_t)((y + r - 1 + ny) & (ny - 1)) * nx;
+        const int xs = g * seg;
+        float wv[3][3];   // [row][col] = X[y+row-1][x+col-1][ci]
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            wv[r][0] = bf2f(x4[(rowo[r] + ((xs - 1 + nx) & (nx - 1))) * 32 + ci]);
+            wv[r][1] = bf2f(x4[(rowo[r] + xs) * 32 + ci]);
+        }
+        for (int xi = xs; xi < xs + seg; ++xi) {
+            const int xn = (xi + 1) & (nx - 1);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) wv[r][2] = bf2f(x4[(rowo[r] + xn) * 32 + ci]);
+            const float2 d = d5[(size_t)y * nx + xi];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                a0[t] = fmaf(d.x, wv[t / 3][t % 3], a0[t]);
+                a1[t] = fmaf(d.y, wv[t / 3][t % 3], a1[t]);
+            }
+            b0 += d.x;
+            b1 += d.y;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                wv[r][0] = wv[r][1];
+                wv[r][1] = wv[r][2];
             }
         }
-    float* o = part + (size_t)blockIdx.x * (2 * 32 * 9 + 2);
-    if (tid < 288) {
-        o[(0 * 32 + ci) * 9 + t] = a0;
-        o[(1 * 32 + ci) * 9 + t] = a1;
-    } else if (tid == 288) {
-        o[2 * 32 * 9] = a0;
-    } else if (tid == 289) {
-        o[2 * 32 * 9 + 1] = a1;
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        red[g][(0 * 32 + ci) * 9 + t] = a0[t];
+        red[g][(1 * 32 + ci) * 9 + t] = a1[t];
+    }
+    if (ci == 0) {
+        red[g][2 * 32 * 9] = b0;
+        red[g][2 * 32 * 9 + 1] = b1;
+    }
+    __syncthreads();
+    float* o = part + (size_t)blockIdx.x * NO;
+    for (int j = threadIdx.x; j < NO; j += 256) {
+        float s = red[0][j];
+#pragma unroll
+        for (int gg = 1; gg < 8; ++gg) s += red[gg][j];
+        o[j] = s;
     }
 }
 
-// grad[j] = sum over blocks of part[b][j], fixed order.
+// Layer 1: lane = output channel co; 3x3 window of the target (broadcast
+// loads) in registers, per pixel 9 FMAs and the bias sum.
+__global__ __launch_bounds__(256) void k_dw1(const float* __restrict__ target, const uint16_t* __restrict__ dy,
+                                             int ny, int nx, int rows_per_block, float* __restrict__ part)
+{
+    constexpr int NO = 32 * 9 + 32;
+    __shared__ float red[8][NO];
+    const int co = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int seg = nx / 8;
+    float a[9] = {};
+    float ab = 0.0f;
+    const int ybeg = blockIdx.x * rows_per_block;
+    for (int y = ybeg; y < ybeg + rows_per_block && y < ny; ++y) {
+        size_t rowo[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) rowo[r] = (size_t)((y + r - 1 + ny) & (ny - 1)) * nx;
+        const int xs = g * seg;
+        float wv[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            wv[r][0] = target[rowo[r] + ((xs - 1 + nx) & (nx - 1))];
+            wv[r][1] = target[rowo[r] + xs];
+        }
+        for (int xi = xs; xi < xs + seg; ++xi) {
+            const int xn = (xi + 1) & (nx - 1);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) wv[r][2] = target[rowo[r] + xn];
+            const float d = bf2f(dy[((size_t)y * nx + xi) * 32 + co]);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) a[t] = fmaf(d, wv[t / 3][t % 3], a[t]);
+            ab += d;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                wv[r][0] = wv[r][1];
+                wv[r][1] = wv[r][2];
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) red[g][co * 9 + t] = a[t];
+    red[g][32 * 9 + co] = ab;
+    __syncthreads();
+    float* o = part + (size_t)blockIdx.x * NO;
+    for (int j = threadIdx.x; j < NO; j += 256) {
+        float s = red[0][j];
+#pragma unroll
+        for (int gg = 1; gg < 8; ++gg) s += red[gg][j];
+        o[j] = s;
+    }
+}
+
+// grad[j] = sum over blocks b of part[b][j] in a fixed order: thread (j, s)
+// adds blocks s, s+4, s+8, ... (four loads in flight), then the four slices
+// are added in slice order.  Block = 64 outputs x 4 slices.
 __global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ part, int nblocks, int n,
                                                      float* __restrict__ grad)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+    __shared__ float red[4][64];
+    const int jl = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + jl;
     float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * n + j];
-    grad[j] = s;
+    if (j < n) {
+        int b = sl;
+        for (; b + 12 < nblocks; b += 16) {
+            const float v0 = part[(size_t)b * n + j], v1 = part[(size_t)(b + 4) * n + j];
+            const float v2 = part[(size_t)(b + 8) * n + j], v3 = part[(size_t)(b + 12) * n + j];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; b < nblocks; b += 4) s += part[(size_t)b * n + j];
+    }
+    red[sl][jl] = s;
+    __syncthreads();
+    if (sl == 0 && j < n) grad[j] = ((red[0][jl] + red[1][jl]) + red[2][jl]) + red[3][jl];
 }
 
 // Adam (Kingma & Ba 2015) on the FP32 master parameters.
@@ -457,7 +627,7 @@ hipError_t cnn_launch_forward(const CnnBuffers& b, const float* target, int ny, 
     using namespace cnn;
     const int npx = nx * ny;
     const int g256 = (npx + 255) / 256;
-    const dim3 gmf((nx / 32) * (ny / 4));
+    const dim3 gmf((nx / 32) * ((ny + kConvRows - 1) / kConvRows));
     hipLaunchKernelGGL(k_conv1, dim3(g256), dim3(256), 0, s, target, ny, nx, b.params + b.off[0],
                        b.params + b.off[0] + 32 * 9, b.act[0]);
     for (int l = 1; l <= 3; ++l)
@@ -484,13 +654,13 @@ hipError_t cnn_launch_backward(const CnnBuffers& b, const float* target, const f
     using namespace cnn;
     const int npx = nx * ny;
     const int g256 = (npx + 255) / 256;
-    const dim3 gmf((nx / 32) * (ny / 4));
+    const dim3 gmf((nx / 32) * ((ny + kConvRows - 1) / kConvRows));
     const int rpb = b.rows_per_block;
     const int nblk = (ny + rpb - 1) / rpb;
     hipLaunchKernelGGL(k_loss_grad, dim3(g256), dim3(256), 0, s, b.o5, label, target, npx, b.zsum, b.d5);
     // layer 5
-    hipLaunchKernelGGL(k_dw5, dim3(nblk), dim3(320), 0, s, b.act[3], b.d5, ny, nx, rpb, b.part);
-    hipLaunchKernelGGL(k_grad_reduce, dim3((2 * 32 * 9 + 2 + 255) / 256), dim3(256), 0, s, b.part, nblk,
+    hipLaunchKernelGGL(k_dw5, dim3(nblk), dim3(256), 0, s, b.act[3], b.d5, ny, nx, rpb, b.part);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((2 * 32 * 9 + 2 + 63) / 64), dim3(256), 0, s, b.part, nblk,
                        2 * 32 * 9 + 2, b.grad + b.off[4]);
     hipLaunchKernelGGL(k_conv5_bwd_data, dim3(g256), dim3(256), 0, s, b.d5, ny, nx, b.params + b.off[4], b.act[3],
                        b.dact[0]);
@@ -498,8 +668,8 @@ hipError_t cnn_launch_backward(const CnnBuffers& b, const float* target, const f
     uint16_t* dcur = b.dact[0];
     uint16_t* dnext = b.dact[1];
     for (int l = 3; l >= 1; --l) {
-        hipLaunchKernelGGL(k_dw32, dim3(nblk), dim3(576), 0, s, b.act[l - 1], dcur, ny, nx, rpb, b.part);
-        hipLaunchKernelGGL(k_grad_reduce, dim3((32 * 32 * 9 + 32 + 255) / 256), dim3(256), 0, s, b.part, nblk,
+        hipLaunchKernelGGL(k_dw32, dim3(nblk), dim3(192), 0, s, b.act[l - 1], dcur, ny, nx, rpb, b.part);
+        hipLaunchKernelGGL(k_grad_reduce, dim3((32 * 32 * 9 + 32 + 63) / 64), dim3(256), 0, s, b.part, nblk,
                            32 * 32 * 9 + 32, b.grad + b.off[l]);
         hipLaunchKernelGGL(k_conv32<1>, gmf, dim3(256), 0, s, dcur, ny, nx, b.wt[l - 1], nullptr, b.act[l - 1],
                            dnext);
@@ -508,8 +678,8 @@ hipError_t cnn_launch_backward(const CnnBuffers& b, const float* target, const f
         dnext = tmp;
     }
     // layer 1
-    hipLaunchKernelGGL(k_dw1, dim3(nblk), dim3(320), 0, s, target, dcur, ny, nx, rpb, b.part);
-    hipLaunchKernelGGL(k_grad_reduce, dim3((32 * 9 + 32 + 255) / 256), dim3(256), 0, s, b.part, nblk, 32 * 9 + 32,
+    hipLaunchKernelGGL(k_dw1, dim3(nblk), dim3(256), 0, s, target, dcur, ny, nx, rpb, b.part);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((32 * 9 + 32 + 63) / 64), dim3(256), 0, s, b.part, nblk, 32 * 9 + 32,
                        b.grad + b.off[0]);
     return hipGetLastError();
 }
