@@ -317,7 +317,7 @@ def bench_cnn(h, synth, torch, dev, args):
     # control: the same network before training (a smooth but unlearned seed)
     ctrl = seed.compare(h.Cnn(seed=1), he, lut, 50, 100)
     net = h.Cnn(seed=1)
-    hist = seed.train(net, tr, labels, args.cnn_epochs, 1e-3)
+    hist = seed.train(net, tr, labels, args.cnn_epochs, 1e-3, batch=4)
     cmp_ = seed.compare(net, he, lut, 50, 100)
     f = cnn_flops(n)
     return {
@@ -325,7 +325,9 @@ def bench_cnn(h, synth, torch, dev, args):
         "infer_TFLOPs": round(f / t_inf / 1e12, 2), "infer_frac_mfma": round(f / t_inf / 1e12 / MFMA_BF16_TFLOPS, 4),
         "train_step_ms": round(1e3 * t_train, 4), "train_images_per_s": round(1.0 / t_train, 2),
         "train_TFLOPs": round(3 * f / t_train / 1e12, 2),
-        "train_set": len(tr), "epochs": args.cnn_epochs, "epoch_loss": [round(x, 5) for x in hist["epoch_loss"]],
+        "train_set": len(tr), "epochs": args.cnn_epochs, "batch": 4,
+        "train_loop_images_per_s": round(hist["images_per_s"], 1),
+        "epoch_loss": [round(x, 5) for x in hist["epoch_loss"]],
         "held_out": {k: v for k, v in cmp_.items() if k != "rows"},
         "held_out_untrained": {k: v for k, v in ctrl.items() if k != "rows"},
     }

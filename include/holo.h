@@ -217,8 +217,11 @@ HOLO_API holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_
  *   holo_cnn_infer    target device float[ny][nx] -> phasor_out device
  *                     float2[ny][nx] (stream-ordered)
  *   holo_cnn_loss_grad  loss and parameter gradient (host outputs, sync)
- *   holo_cnn_train_step  one forward/backward/Adam (lr) step on one image;
- *                     loss_out host or NULL (no sync)
+ *   holo_cnn_train_step  one Adam (lr) step on a batch: targets device
+ *                     float[batch][ny][nx], labels device float2[batch][ny][nx];
+ *                     the gradient and loss are the means over the batch
+ *                     (per-image forward/backward, gradients accumulated in
+ *                     FP32); loss_out host (synchronises) or NULL
  *   holo_cnn_save / holo_cnn_load  parameters, Adam moments and step
  * Images: nx, ny powers of two in [64, 2048].  The network and its scratch
  * live on the device current at creation.
@@ -232,8 +235,8 @@ HOLO_API holo_status holo_cnn_infer(holo_cnn* cnn, const float* target, int64_t 
                                     void* hip_stream);
 HOLO_API holo_status holo_cnn_loss_grad(holo_cnn* cnn, const float* target, const float* label, int64_t nx,
                                         int64_t ny, double* loss_out, float* grad_out, void* hip_stream);
-HOLO_API holo_status holo_cnn_train_step(holo_cnn* cnn, const float* target, const float* label, int64_t nx,
-                                         int64_t ny, float lr, double* loss_out, void* hip_stream);
+HOLO_API holo_status holo_cnn_train_step(holo_cnn* cnn, const float* targets, const float* labels, int32_t batch,
+                                         int64_t nx, int64_t ny, float lr, double* loss_out, void* hip_stream);
 HOLO_API holo_status holo_cnn_save(const holo_cnn* cnn, const char* path);
 HOLO_API holo_status holo_cnn_load(const char* path, holo_cnn** out);
 HOLO_API void holo_cnn_free(holo_cnn* cnn);

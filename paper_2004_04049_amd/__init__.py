@@ -58,7 +58,7 @@ SIGNATURES = {
     "holo_cnn_set_params": (_I32, [_P, _P, _I32]),
     "holo_cnn_infer": (_I32, [_P, _P, _I64, _I64, _P, _P]),
     "holo_cnn_loss_grad": (_I32, [_P, _P, _P, _I64, _I64, _P, _P, _P]),
-    "holo_cnn_train_step": (_I32, [_P, _P, _P, _I64, _I64, C.c_float, _P, _P]),
+    "holo_cnn_train_step": (_I32, [_P, _P, _P, _I32, _I64, _I64, C.c_float, _P, _P]),
     "holo_cnn_save": (_I32, [_P, C.c_char_p]),
     "holo_cnn_load": (_I32, [C.c_char_p, C.POINTER(_P)]),
     "holo_cnn_free": (None, [_P]),
@@ -419,11 +419,17 @@ class Cnn:
         return loss.value, g
 
     def train_step(self, target, label, lr: float, want_loss: bool = True, stream=None):
+        """One Adam step on a batch.  target: cuda float32 [ny, nx] or
+        [batch, ny, nx]; label: complex64 of the same shape.  Returns the mean
+        loss (or None)."""
+        if target.dim() == 2:
+            target = target.unsqueeze(0)
+            label = label.unsqueeze(0)
         _dev(target, torch.float32, None, "target")
-        ny, nx = target.shape
-        _dev(label, torch.complex64, (ny, nx), "label")
+        b, ny, nx = target.shape
+        _dev(label, torch.complex64, (b, ny, nx), "label")
         loss = C.c_double()
-        _check(lib().holo_cnn_train_step(self._h, _ptr(target), _ptr(label), nx, ny, lr,
+        _check(lib().holo_cnn_train_step(self._h, _ptr(target), _ptr(label), b, nx, ny, lr,
                                          C.byref(loss) if want_loss else None, _stream(stream)))
         return loss.value if want_loss else None
 

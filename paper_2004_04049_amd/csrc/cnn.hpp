@@ -38,16 +38,18 @@ struct CnnBuffers {
     float2* d5;        // its gradient
     float* part;       // weight-gradient partials
     double* loss_part; // [256][3]
-    double* zsum;      // {Re Z, Im Z, W, loss}
+    double* zsum;      // {Re Z, Im Z, W, loss, batch mean loss}
     int rows_per_block;
 };
 
 hipError_t cnn_launch_forward(const CnnBuffers& b, const float* target, int ny, int nx, float2* phasor,
                               hipStream_t s);
+// loss of one image into zsum[0..3]; zsum[4] (+)= loss * inv_batch
 hipError_t cnn_launch_loss(const CnnBuffers& b, const float* target, const float2* label, const float2* phasor,
-                           int n, hipStream_t s);
+                           int n, int accumulate, double inv_batch, hipStream_t s);
+// gradient of one image: grad (+)= scale * dL/dparams
 hipError_t cnn_launch_backward(const CnnBuffers& b, const float* target, const float2* label, int ny, int nx,
-                               hipStream_t s);
+                               float scale, int accumulate, hipStream_t s);
 hipError_t cnn_launch_adam(const CnnBuffers& b, int n, float lr, int step, hipStream_t s);
 hipError_t cnn_launch_pack(const CnnBuffers& b, hipStream_t s);
 

@@ -239,7 +239,8 @@ __global__ __launch_bounds__(256) void k_loss_partial(const float2* __restrict__
 }
 
 __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ part, int nb,
-                                                    double* __restrict__ zsum /* zr, zi, W, loss */)
+                                                    double* __restrict__ zsum /* zr, zi, W, loss, batch mean */,
+                                                    int accumulate, double inv_batch)
 {
     __shared__ double red[3 * 8];
     double a[3] = {0.0, 0.0, 0.0};
@@ -252,6 +253,7 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
         zsum[1] = s[1];
         zsum[2] = s[2];
         zsum[3] = s[2] > 0.0 ? 1.0 - sqrt(s[0] * s[0] + s[1] * s[1]) / s[2] : 0.0;
+        zsum[4] = (accumulate ? zsum[4] : 0.0) + zsum[3] * inv_batch;
     }
 }
 
@@ -561,11 +563,11 @@ __global__ __launch_bounds__(256) void k_dw1(const float* __restrict__ target, c
     }
 }
 
-// grad[j] = sum over blocks b of part[b][j] in a fixed order: thread (j, s)
+// grad[j] (+)= scale * sum over blocks b of part[b][j] in a fixed order: thread (j, s)
 // adds blocks s, s+4, s+8, ... (four loads in flight), then the four slices
 // are added in slice order.  Block = 64 outputs x 4 slices.
 __global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ part, int nblocks, int n,
-                                                     float* __restrict__ grad)
+                                                     float scale, int accumulate, float* __restrict__ grad)
 {
     __shared__ float red[4][64];
     const int jl = threadIdx.x & 63, sl = threadIdx.x >> 6;
@@ -585,7 +587,10 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ p
     }
     red[sl][jl] = s;
     __syncthreads();
-    if (sl == 0 && j < n) grad[j] = ((red[0][jl] + red[1][jl]) + red[2][jl]) + red[3][jl];
+    if (sl == 0 && j < n) {
+        const float g = (((red[0][jl] + red[1][jl]) + red[2][jl]) + red[3][jl]) * scale;
+        grad[j] = accumulate ? grad[j] + g : g;
+    }
 }
 
 // Adam (Kingma & Ba 2015) on the FP32 master parameters.
@@ -639,17 +644,17 @@ hipError_t cnn_launch_forward(const CnnBuffers& b, const float* target, int ny, 
 }
 
 hipError_t cnn_launch_loss(const CnnBuffers& b, const float* target, const float2* label, const float2* phasor,
-                           int n, hipStream_t s)
+                           int n, int accumulate, double inv_batch, hipStream_t s)
 {
     using namespace cnn;
     const int nb = 256;
     hipLaunchKernelGGL(k_loss_partial, dim3(nb), dim3(256), 0, s, phasor, label, target, n, b.loss_part);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, b.loss_part, nb, b.zsum);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, b.loss_part, nb, b.zsum, accumulate, inv_batch);
     return hipGetLastError();
 }
 
 hipError_t cnn_launch_backward(const CnnBuffers& b, const float* target, const float2* label, int ny, int nx,
-                               hipStream_t s)
+                               float scale, int accumulate, hipStream_t s)
 {
     using namespace cnn;
     const int npx = nx * ny;
@@ -661,7 +666,7 @@ hipError_t cnn_launch_backward(const CnnBuffers& b, const float* target, const f
     // layer 5
     hipLaunchKernelGGL(k_dw5, dim3(nblk), dim3(256), 0, s, b.act[3], b.d5, ny, nx, rpb, b.part);
     hipLaunchKernelGGL(k_grad_reduce, dim3((2 * 32 * 9 + 2 + 63) / 64), dim3(256), 0, s, b.part, nblk,
-                       2 * 32 * 9 + 2, b.grad + b.off[4]);
+                       2 * 32 * 9 + 2, scale, accumulate, b.grad + b.off[4]);
     hipLaunchKernelGGL(k_conv5_bwd_data, dim3(g256), dim3(256), 0, s, b.d5, ny, nx, b.params + b.off[4], b.act[3],
                        b.dact[0]);
     // layers 4, 3, 2 (index l = 3, 2, 1): dW from act[l-1] and dY; dX through MFMA
@@ -670,7 +675,7 @@ hipError_t cnn_launch_backward(const CnnBuffers& b, const float* target, const f
     for (int l = 3; l >= 1; --l) {
         hipLaunchKernelGGL(k_dw32, dim3(nblk), dim3(192), 0, s, b.act[l - 1], dcur, ny, nx, rpb, b.part);
         hipLaunchKernelGGL(k_grad_reduce, dim3((32 * 32 * 9 + 32 + 63) / 64), dim3(256), 0, s, b.part, nblk,
-                           32 * 32 * 9 + 32, b.grad + b.off[l]);
+                           32 * 32 * 9 + 32, scale, accumulate, b.grad + b.off[l]);
         hipLaunchKernelGGL(k_conv32<1>, gmf, dim3(256), 0, s, dcur, ny, nx, b.wt[l - 1], nullptr, b.act[l - 1],
                            dnext);
         uint16_t* tmp = dcur;
@@ -680,7 +685,7 @@ hipError_t cnn_launch_backward(const CnnBuffers& b, const float* target, const f
     // layer 1
     hipLaunchKernelGGL(k_dw1, dim3(nblk), dim3(256), 0, s, target, dcur, ny, nx, rpb, b.part);
     hipLaunchKernelGGL(k_grad_reduce, dim3((32 * 9 + 32 + 63) / 64), dim3(256), 0, s, b.part, nblk, 32 * 9 + 32,
-                       b.grad + b.off[0]);
+                       scale, accumulate, b.grad + b.off[0]);
     return hipGetLastError();
 }
 

@@ -1293,7 +1293,7 @@ holo_status holo_cnn_create(uint64_t seed, holo_cnn** out)
     }
     bool ok = hipMalloc(&c->b.params, n * 4) == hipSuccess && hipMalloc(&c->b.m, n * 4) == hipSuccess &&
               hipMalloc(&c->b.v, n * 4) == hipSuccess && hipMalloc(&c->b.grad, n * 4) == hipSuccess &&
-              hipMalloc(&c->b.loss_part, 256 * 3 * 8) == hipSuccess && hipMalloc(&c->b.zsum, 4 * 8) == hipSuccess;
+              hipMalloc(&c->b.loss_part, 256 * 3 * 8) == hipSuccess && hipMalloc(&c->b.zsum, 5 * 8) == hipSuccess;
     for (int i = 0; i < 3 && ok; ++i)
         ok = hipMalloc(&c->b.wf[i], 32 * 32 * 9 * 2) == hipSuccess && hipMalloc(&c->b.wt[i], 32 * 32 * 9 * 2) == hipSuccess;
     if (!ok) {
@@ -1352,8 +1352,8 @@ holo_status holo_cnn_loss_grad(holo_cnn* c, const float* target, const float* la
     hipStream_t s = (hipStream_t)hip_stream;
     const int n = (int)(nx * ny);
     LAUNCH("cnn_forward", s, cnn_launch_forward(c->b, target, (int)ny, (int)nx, c->ph, s));
-    LAUNCH("cnn_loss", s, cnn_launch_loss(c->b, target, (const float2*)label, c->ph, n, s));
-    LAUNCH("cnn_backward", s, cnn_launch_backward(c->b, target, (const float2*)label, (int)ny, (int)nx, s));
+    LAUNCH("cnn_loss", s, cnn_launch_loss(c->b, target, (const float2*)label, c->ph, n, 0, 1.0, s));
+    LAUNCH("cnn_backward", s, cnn_launch_backward(c->b, target, (const float2*)label, (int)ny, (int)nx, 1.0f, 0, s));
     if (loss_out) {
         HIP_TRY(hipMemcpyAsync(loss_out, c->b.zsum + 3, 8, hipMemcpyDeviceToHost, s));
     }
@@ -1364,23 +1364,29 @@ holo_status holo_cnn_loss_grad(holo_cnn* c, const float* target, const float* la
     return HOLO_OK;
 }
 
-holo_status holo_cnn_train_step(holo_cnn* c, const float* target, const float* label, int64_t nx, int64_t ny,
-                                float lr, double* loss_out, void* hip_stream)
+holo_status holo_cnn_train_step(holo_cnn* c, const float* targets, const float* labels, int32_t batch, int64_t nx,
+                                int64_t ny, float lr, double* loss_out, void* hip_stream)
 {
     holo_status st = cnn_check(c, nx, ny);
     if (st) return st;
-    if (!target || !label) return fail(HOLO_EINVAL, "target and label are required");
+    if (!targets || !labels) return fail(HOLO_EINVAL, "targets and labels are required");
+    if (batch < 1) return fail(HOLO_EINVAL, "batch must be >= 1 (got %d)", batch);
     if (!(lr > 0.0f)) return fail(HOLO_EINVAL, "lr must be > 0");
     if ((st = cnn_images(c, nx, ny))) return st;
     hipStream_t s = (hipStream_t)hip_stream;
     const int n = (int)(nx * ny);
-    LAUNCH("cnn_forward", s, cnn_launch_forward(c->b, target, (int)ny, (int)nx, c->ph, s));
-    LAUNCH("cnn_loss", s, cnn_launch_loss(c->b, target, (const float2*)label, c->ph, n, s));
-    LAUNCH("cnn_backward", s, cnn_launch_backward(c->b, target, (const float2*)label, (int)ny, (int)nx, s));
+    const double inv_b = 1.0 / batch;
+    for (int i = 0; i < batch; ++i) {
+        const float* t = targets + (size_t)i * n;
+        const float2* q = reinterpret_cast<const float2*>(labels) + (size_t)i * n;
+        LAUNCH("cnn_forward", s, cnn_launch_forward(c->b, t, (int)ny, (int)nx, c->ph, s));
+        LAUNCH("cnn_loss", s, cnn_launch_loss(c->b, t, q, c->ph, n, i > 0, inv_b, s));
+        LAUNCH("cnn_backward", s, cnn_launch_backward(c->b, t, q, (int)ny, (int)nx, (float)inv_b, i > 0, s));
+    }
     c->step += 1;
     LAUNCH("cnn_adam", s, cnn_launch_adam(c->b, c->lay.n, lr, c->step, s));
     if (loss_out) {
-        HIP_TRY(hipMemcpyAsync(loss_out, c->b.zsum + 3, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(loss_out, c->b.zsum + 4, 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
     return HOLO_OK;

@@ -25,24 +25,29 @@ def gs_labels(targets, lut: Lut, n_label: int = 50):
     return [gs_iterate(t, n_label, lut, 0, want_nmse=False, want_final=False)["field"].clone() for t in targets]
 
 
-def train(net: Cnn, targets, labels, epochs: int, lr: float, order_seed: int = 0):
-    """Plain per-image Adam steps; the visiting order of each epoch is a
-    permutation drawn from `order_seed`.  Returns the per-epoch mean loss and
-    the measured training rate (images/s, device-synchronised)."""
+def train(net: Cnn, targets, labels, epochs: int, lr: float, batch: int = 1, order_seed: int = 0):
+    """Adam steps on mini-batches of `batch` images (mean gradient); the
+    visiting order of each epoch is a permutation drawn from `order_seed`.
+    Returns the per-epoch mean loss and the measured training rate
+    (images/s, device-synchronised)."""
     rng = np.random.default_rng(order_seed)
     losses = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    steps = 0
+    images = 0
     for _ in range(epochs):
         acc = []
-        for i in rng.permutation(len(targets)):
-            acc.append(net.train_step(targets[i], labels[i], lr, want_loss=True))
-            steps += 1
+        order = rng.permutation(len(targets))
+        for s in range(0, len(order), batch):
+            idx = order[s:s + batch]
+            tb = torch.stack([targets[i] for i in idx])
+            qb = torch.stack([labels[i] for i in idx])
+            acc.append(net.train_step(tb, qb, lr, want_loss=True))
+            images += len(idx)
         losses.append(float(np.mean(acc)))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"epoch_loss": losses, "images_per_s": steps / dt if dt > 0 else 0.0}
+    return {"epoch_loss": losses, "images_per_s": images / dt if dt > 0 else 0.0}
 
 
 def _first_reach(nmse, goal):

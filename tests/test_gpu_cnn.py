@@ -147,6 +147,27 @@ def test_adam_step_matches_oracle(holo, orc):
     assert np.abs(p1 - p0).max() > 0.5 * lr
 
 
+def test_batch_step_is_mean_of_image_gradients(holo, orc):
+    """A batch step applies Adam to the mean of the per-image gradients and
+    reports the mean loss."""
+    net = holo.Cnn(seed=12)
+    n = 64
+    ts = torch.stack([torch.from_numpy(synth.blob_target(n, n, 20 + i)) for i in range(3)]).cuda().contiguous()
+    rng = np.random.default_rng(5)
+    qs = torch.from_numpy(np.exp(1j * rng.uniform(0, 2 * np.pi, (3, n, n))).astype(np.complex64)).cuda()
+    p0 = net.params().astype(np.float64)
+    lg = [net.loss_grad(ts[i], qs[i]) for i in range(3)]
+    gmean = np.mean([g for _, g in lg], axis=0).astype(np.float64)
+    lr = 1e-3
+    loss = net.train_step(ts, qs, lr)
+    assert loss == pytest.approx(np.mean([l for l, _ in lg]), rel=1e-12)
+    ref = p0.copy()
+    m = np.zeros_like(ref)
+    v = np.zeros_like(ref)
+    orc.adam(ref, gmean, m, v, 1, lr)
+    np.testing.assert_allclose(net.params(), ref, rtol=1e-6, atol=lr * 1e-4)
+
+
 def test_training_reduces_loss_and_roundtrip(holo, tmp_path):
     """Training drives the loss down on labels the network can represent
     (phase = pi * T, a pointwise function of the target), and also lowers it on
