@@ -98,3 +98,4 @@ SEED_BATCH = 14
 SEED_BATCH_TARGET0 = 1000
 SEED_CNN_TRAIN0 = 100000
 SEED_CNN_HELDOUT0 = 200000
+SEED_LUT_STUDY0 = 300000

@@ -316,3 +316,21 @@ def test_batched_equals_sequential_calls(holo, orc):
     ref = orc.ospr(t, nsfs[f], orc.lut_phases(10007, 1), 10007, 5 + sum(k * m * m for m, k in layout[:f]))
     _check_bits(holo, orc, bits[f], ref, n * n)
     np.testing.assert_allclose(nm[f], ref["nmse2"], rtol=NMSE_RTOL)
+
+
+def test_lut_study_orders_pool_lengths(holo):
+    # the LUT-length study on a small case: a pool no longer than the
+    # sub-frame count (2 <= 24) is far worse than the paper's 10007, and the
+    # non-repeating reference is the best of the three
+    from paper_2004_04049_amd import lut_study
+    targets = [torch.from_numpy(synth.blob_target(64, 64, synth.SEED_LUT_STUDY0 + i)).cuda() for i in range(2)]
+    holo.set_graphs(False)
+    try:
+        res = lut_study.sweep(targets, 24, [2, 10007], 3)
+    finally:
+        holo.set_graphs(True)
+    sm = lut_study.summarize(res, 64, 24)
+    added = {r["n_lut"]: r["added_sym_pct"] for r in sm["rows"]}
+    print(sm["nonrepeating"], added)
+    assert added[2] > 10 * max(added[10007], 1.0)
+    assert added[10007] > -5.0
