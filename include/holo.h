@@ -86,18 +86,54 @@ HOLO_API int32_t holo_version(void);
 /* ---------------------------------------------------------------------------
  * Phase LUT (Section 4: a pool of random phases fixed ahead of time).
  *
- * holo_lut_build: n_lut phases phi_j = 2*pi*u_j, u_j = (x_j >> 11) * 2^-53 from
- * SplitMix64 seeded with `seed` (uniform on [0, 2*pi)); the device holds them
- * as FP32 unit phasors (cos phi_j, sin phi_j) so no trigonometry runs per
- * pixel.  n_lut = 0 builds the flat-phase table (phasor 1).  n_lut must be
- * < 2^31.  The table lives on the current device.  *out receives the handle.
+ * Every entry point that draws random phases takes a holo_lut handle and reads
+ * its pool at positions c + k*nx*ny + p (Section 5, Fig. 3); the handle decides
+ * how a position becomes a unit phasor.  Handles are immutable and live on the
+ * device current at creation; holo_lut_free releases any of them.
+ *
+ * holo_lut_build (HOLO_SRC_TABLE, the method as published): n_lut phases
+ * phi_j = 2*pi*u_j, u_j = (x_j >> 11) * 2^-53 from SplitMix64 seeded with
+ * `seed` (x_j = output j; uniform on [0, 2*pi)); the device holds them as FP32
+ * unit phasors (cos phi_j, sin phi_j) so no trigonometry runs per pixel.
+ * n_lut = 0 builds the flat-phase table (phasor 1).  n_lut must be < 2^29
+ * (HOLO_EUNSUPPORTED): the kernels address the table with 32-bit byte offsets.
  * holo_lut_from_phases: the same from caller phases (host, FP64, n_lut).
- * holo_lut_phases: copies min(n, n_lut) FP64 phases to host `out`.
+ *
+ * holo_lut_build_codes (HOLO_SRC_CODES8; the one-byte-per-entry reading of the
+ * LUT storage figure of Section 5.2): n_lut 8-bit codes q_j = x_j >> 56 of the
+ * same SplitMix64 outputs, phase 2*pi*q_j/256; the device holds one byte per
+ * entry and the 256 phasors exp(2*pi*i*q/256) (FP64, rounded to FP32).
+ * 1 <= n_lut < 2^31.
+ *
+ * holo_lut_prng (HOLO_SRC_PRNG; Section 3's software route, a PRNG plus
+ * trigonometric functions): no table.  Position i (unbounded, the cursor taken
+ * mod 2^64) gets x_i = SplitMix64 output i of `seed` in counter form (the x_j
+ * of holo_lut_build, so the pool is an endless table of that seed), phase
+ * 2*pi*floor(2^24 * u_i)/2^24 (u_i as above, truncated to 24 bits), phasor from
+ * the GPU's FP32 sine/cosine evaluated on the device at each use.
+ *
+ * holo_lut_mseq (HOLO_SRC_MSEQ; Section 7's M-sequence alternative, which
+ * still needs sine and cosine tables): bits s_n of the binary M-sequence of the
+ * primitive trinomial x^31 + x^3 + 1, s_{n+31} = s_{n+3} xor s_n, with s_0..s_30
+ * = bits 30..0 of (SplitMix64 output 0 of `seed`) & (2^31 - 1) (1 if that is 0);
+ * position i gets code q_i = bits s_{8i}..s_{8i+7} (s_{8i} most significant),
+ * phase 2*pi*q_i/256, phasor from the 256-entry table.  Period 2^31 - 1, so it
+ * behaves as a pool of n_lut = 2^31 - 1 entries.
+ *
+ * holo_lut_kind: HOLO_SRC_* of a handle (-1 for NULL).
+ * holo_lut_size: n_lut (PRNG: UINT64_MAX; MSEQ: 2^31 - 1).
+ * holo_lut_phases: copies min(n, n_lut) FP64 phases to host `out` (TABLE,
+ * CODES8); HOLO_EUNSUPPORTED for PRNG and MSEQ, which keep no table.
  * holo_lut_check: bitmask of HOLO_LUT_* warnings; never an error, because the
  * paper's own sweeps break these rules on purpose.
  * ------------------------------------------------------------------------- */
+enum { HOLO_SRC_TABLE = 0, HOLO_SRC_CODES8 = 1, HOLO_SRC_PRNG = 2, HOLO_SRC_MSEQ = 3 };
 HOLO_API holo_status holo_lut_build(uint64_t n_lut, uint64_t seed, holo_lut** out);
 HOLO_API holo_status holo_lut_from_phases(const double* phases, uint64_t n_lut, holo_lut** out);
+HOLO_API holo_status holo_lut_build_codes(uint64_t n_lut, uint64_t seed, holo_lut** out);
+HOLO_API holo_status holo_lut_prng(uint64_t seed, holo_lut** out);
+HOLO_API holo_status holo_lut_mseq(uint64_t seed, holo_lut** out);
+HOLO_API int32_t holo_lut_kind(const holo_lut* lut);
 HOLO_API holo_status holo_lut_phases(const holo_lut* lut, double* out, uint64_t n);
 HOLO_API uint64_t holo_lut_size(const holo_lut* lut);
 HOLO_API void holo_lut_free(holo_lut* lut);
@@ -248,6 +284,18 @@ HOLO_API void holo_cnn_free(holo_cnn* cnn);
  * ------------------------------------------------------------------------- */
 HOLO_API holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t ny, int32_t sign,
                                int32_t precision, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * holo_phase_mask -- the random phasors a generation call would draw (Section
+ * 5, Fig. 3): out[(k*ny + y)*nx + x] = phasor of pool position
+ * cursor + k*nx*ny + y*nx + x, for k < n_sf, as interleaved (re, im) FP32 pairs
+ * in caller-owned device memory of n_sf*ny*nx*8 bytes.  Runs the same device
+ * code as the OSPR row pass.  The cursor is not advanced.  nx, ny: powers of two
+ * in [16, 2048] (HOLO_EUNSUPPORTED); n_sf >= 1, out and lut non-NULL
+ * (HOLO_EINVAL).
+ * ------------------------------------------------------------------------- */
+HOLO_API holo_status holo_phase_mask(const holo_lut* lut, uint64_t cursor, int64_t nx, int64_t ny, int32_t n_sf,
+                                     float* out, void* hip_stream);
 
 /* ---------------------------------------------------------------------------
  * Launch plans and the autotuner (implementation choices, not part of the

@@ -4,8 +4,8 @@ TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
 leg of the benchmark may use this package; the product library never does.
 It shares no code with the HIP path and imports nothing from it.
 
-This module is a thin numpy/ctypes wrapper around ``holo_oracle.c`` (and
-``cnn_oracle.c``), which hold all the arithmetic.  Conventions follow
+This module is a thin numpy/ctypes wrapper around ``holo_oracle.c``,
+``cnn_oracle.c`` and ``phase_oracle.c``, which hold all the arithmetic.  Conventions follow
 Eq. (1)-(2) of the paper: unitary DFT pair, forward kernel e^{-}, row-major
 [ny][nx] images with raster index p = y*nx + x.
 """
@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["holo_oracle.c", "cnn_oracle.c"]
+_SOURCES = ["holo_oracle.c", "cnn_oracle.c", "phase_oracle.c"]
 _lib = None
 
 
@@ -60,6 +60,13 @@ def _load():
         "orc_ospr": (None, [P, i64, i64, i32, P, u64, u64, P, P, P, P]),
         "orc_gs": (None, [P, i64, i64, i32, P, P, P, P, P, P]),
         "orc_num_threads": (i32, []),
+        "orc_splitmix64_at": (u64, [u64, u64]),
+        "orc_prng_phases": (None, [u64, u64, u64, P]),
+        "orc_codes8_phases": (None, [u64, u64, P]),
+        "orc_mseq_bits": (None, [C.c_uint32, u64, P]),
+        "orc_mseq_codes": (i32, [C.c_uint32, u64, u64, P]),
+        "orc_mseq_window": (C.c_uint32, [u64]),
+        "orc_mseq_phases": (i32, [u64, u64, u64, P]),
         "orc_conv3x3": (None, [P, i32, i32, i32, P, P, i32, P]),
         "orc_cnn_nparams": (i32, [i32]),
         "orc_bf16": (dbl, [dbl]),
@@ -106,6 +113,49 @@ def lut_phases(n_lut: int, seed: int) -> np.ndarray:
     out = np.zeros(max(n_lut, 1), dtype=np.float64)
     _load().orc_lut_phases(n_lut, seed, out.ctypes.data)
     return out[:n_lut]
+
+
+# ----------------------------------------------------------------------------
+# Other phase sources (Section 3: PRNG + trigonometry; Section 7: M-sequence +
+# sine/cosine tables; an 8-bit-code table).  Each gives the phases of pool
+# positions start .. start+n-1.
+# ----------------------------------------------------------------------------
+def splitmix64_at(seed: int, i: int) -> int:
+    return int(_load().orc_splitmix64_at(seed, i))
+
+
+def prng_phases(seed: int, start: int, n: int) -> np.ndarray:
+    out = np.zeros(max(n, 1))
+    _load().orc_prng_phases(seed, start, n, out.ctypes.data)
+    return out[:n]
+
+
+def codes8_phases(n: int, seed: int) -> np.ndarray:
+    out = np.zeros(max(n, 1))
+    _load().orc_codes8_phases(n, seed, out.ctypes.data)
+    return out[:n]
+
+
+def mseq_bits(window: int, nbits: int) -> np.ndarray:
+    out = np.zeros(max(nbits, 1), dtype=np.uint8)
+    _load().orc_mseq_bits(window, nbits, out.ctypes.data)
+    return out[:nbits]
+
+
+def mseq_codes(window: int, start: int, n: int) -> np.ndarray:
+    out = np.zeros(max(n, 1), dtype=np.uint8)
+    assert _load().orc_mseq_codes(window, start, n, out.ctypes.data) == 0
+    return out[:n]
+
+
+def mseq_window(seed: int) -> int:
+    return int(_load().orc_mseq_window(seed))
+
+
+def mseq_phases(seed: int, start: int, n: int) -> np.ndarray:
+    out = np.zeros(max(n, 1))
+    assert _load().orc_mseq_phases(seed, start, n, out.ctypes.data) == 0
+    return out[:n]
 
 
 def lut_index(cursor: int, k: int, npix: int, p: int, n_lut: int) -> int:

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libholo.so")
 
 HOLO_OK, HOLO_EINVAL, HOLO_EUNSUPPORTED, HOLO_ENOMEM, HOLO_EDEVICE = 0, -1, -2, -3, -4
 FP32, BF16, FP16 = 0, 1, 2
+SRC_TABLE, SRC_CODES8, SRC_PRNG, SRC_MSEQ = 0, 1, 2, 3
 F_NMSE_DEVICE = 1
 LUT_FLAT, LUT_NOT_PRIME, LUT_LE_NSF, LUT_LE_MAXDIM, LUT_DIVIDES_FRAME, LUT_LT_FULL = 1, 2, 4, 8, 16, 32
 
@@ -31,6 +32,10 @@ SIGNATURES = {
     "holo_version": (_I32, []),
     "holo_lut_build": (_I32, [_U64, _U64, C.POINTER(_P)]),
     "holo_lut_from_phases": (_I32, [_P, _U64, C.POINTER(_P)]),
+    "holo_lut_build_codes": (_I32, [_U64, _U64, C.POINTER(_P)]),
+    "holo_lut_prng": (_I32, [_U64, C.POINTER(_P)]),
+    "holo_lut_mseq": (_I32, [_U64, C.POINTER(_P)]),
+    "holo_lut_kind": (_I32, [_P]),
     "holo_lut_phases": (_I32, [_P, _P, _U64]),
     "holo_lut_size": (_U64, [_P]),
     "holo_lut_free": (None, [_P]),
@@ -40,6 +45,7 @@ SIGNATURES = {
                                _U32, _P]),
     "holo_reconstruct_nmse": (_I32, [_P, _I32, _I64, _I64, _I32, _P, _P, _P, _U32, _P]),
     "holo_fft2": (_I32, [_P, _P, _I64, _I64, _I32, _I32, _P]),
+    "holo_phase_mask": (_I32, [_P, _U64, _I64, _I64, _I32, _P, _P]),
     "holo_shutdown": (None, []),
     "holo_prof_enable": (_I32, [_I32]),
     "holo_prof_read": (_I32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(_I64)]),
@@ -119,11 +125,20 @@ def _stream(stream):
 
 
 class Lut:
-    """Phase LUT handle (holo_lut_build / holo_lut_from_phases)."""
+    """Phase-pool handle.  Lut(n, seed) / Lut(n, phases=...): FP32 phasor table
+    (holo_lut_build / holo_lut_from_phases); Lut.codes(n, seed): 8-bit codes;
+    Lut.prng(seed): counter-based SplitMix64 + sine/cosine; Lut.mseq(seed):
+    M-sequence codes."""
 
-    def __init__(self, n_lut: int, seed: int = 1, phases=None):
+    def __init__(self, n_lut: int, seed: int = 1, phases=None, _kind=SRC_TABLE):
         h = C.c_void_p()
-        if phases is not None:
+        if _kind == SRC_CODES8:
+            _check(lib().holo_lut_build_codes(n_lut, seed, C.byref(h)))
+        elif _kind == SRC_PRNG:
+            _check(lib().holo_lut_prng(seed, C.byref(h)))
+        elif _kind == SRC_MSEQ:
+            _check(lib().holo_lut_mseq(seed, C.byref(h)))
+        elif phases is not None:
             import numpy as np
             ph = np.ascontiguousarray(phases, dtype=np.float64)
             _check(lib().holo_lut_from_phases(ph.ctypes.data_as(C.c_void_p), len(ph), C.byref(h)))
@@ -131,16 +146,38 @@ class Lut:
             _check(lib().holo_lut_build(n_lut, seed, C.byref(h)))
         self._h = h
 
+    @classmethod
+    def codes(cls, n_lut: int, seed: int = 1):
+        return cls(n_lut, seed, _kind=SRC_CODES8)
+
+    @classmethod
+    def prng(cls, seed: int = 1):
+        return cls(0, seed, _kind=SRC_PRNG)
+
+    @classmethod
+    def mseq(cls, seed: int = 1):
+        return cls(0, seed, _kind=SRC_MSEQ)
+
     @property
     def handle(self):
         return self._h
 
-    def __len__(self):
+    @property
+    def kind(self) -> int:
+        return int(lib().holo_lut_kind(self._h))
+
+    @property
+    def size(self) -> int:
+        """Pool length (PRNG: 2**64 - 1, unbounded; MSEQ: 2**31 - 1)."""
         return int(lib().holo_lut_size(self._h))
 
+    def __len__(self):
+        return self.size
+
     def phases(self):
+        """FP64 phases of a table source (TABLE, CODES8); raises for PRNG and MSEQ."""
         import numpy as np
-        n = len(self)
+        n = self.size if self.kind in (SRC_TABLE, SRC_CODES8) else 0
         out = np.zeros(max(n, 1), dtype=np.float64)
         _check(lib().holo_lut_phases(self._h, out.ctypes.data_as(C.c_void_p), n))
         return out[:n]
@@ -253,6 +290,14 @@ def fft2(x, sign: int, out=None, stream=None, precision: int = FP32):
         out = torch.empty_like(x)
     _dev(out, torch.complex64, (ny, nx), "out")
     _check(lib().holo_fft2(_ptr(x), _ptr(out), nx, ny, sign, precision, _stream(stream)))
+    return out
+
+
+def phase_mask(lut: Lut, cursor: int, nx: int, ny: int, n_sf: int = 1, stream=None):
+    """holo_phase_mask: complex64 [n_sf, ny, nx] phasors of pool positions
+    cursor + k*nx*ny + y*nx + x, as the generation kernels draw them."""
+    out = torch.empty((n_sf, ny, nx), dtype=torch.complex64, device="cuda")
+    _check(lib().holo_phase_mask(lut.handle, cursor, nx, ny, n_sf, _ptr(out), _stream(stream)))
     return out
 
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -31,10 +32,15 @@ struct holo_cnn {
 
 struct holo_lut {
     int device;
-    uint64_t n_lut;              // as requested (0 = flat)
-    uint32_t n_dev;              // entries on the device (>= 1)
-    std::vector<double> phases;  // FP64 phases, host copy
-    float2* dev;                 // FP32 unit phasors on `device`
+    int kind;                    // holo::SRC_*
+    uint64_t id;                 // unique per handle (graph keys), never reused
+    uint64_t n_lut;              // as requested (0 = flat); PRNG: UINT64_MAX (unbounded); MSEQ: 2^31 - 1
+    uint32_t n_dev;              // pool length of the cyclic kinds (>= 1)
+    uint64_t seed;
+    std::vector<double> phases;  // FP64 phases, host copy (TABLE, CODES8)
+    float2* dev = nullptr;       // TABLE: n_dev FP32 unit phasors; CODES8, MSEQ: the 256 code phasors
+    uint8_t* codes = nullptr;    // CODES8: n_dev codes
+    uint32_t* mseq = nullptr;    // MSEQ: x^(2^j) for j < 31, S_0, then [12][4][256] jump tables (strides 2^0..2^11)
 };
 
 namespace holo {
@@ -70,6 +76,51 @@ uint64_t splitmix64(uint64_t& s)
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// Phase sources (phase_src.hpp): host side.
+// ---------------------------------------------------------------------------
+std::atomic<uint64_t> g_lut_ids{1};
+
+// GF(2)[x] / (x^31 + x^3 + 1)
+uint32_t gf_mul_host(uint32_t a, uint32_t b)
+{
+    uint64_t acc = 0;
+    for (int i = 0; i < 31; ++i)
+        if ((b >> i) & 1u) acc ^= (uint64_t)a << i;
+    for (int r = 0; r < 2; ++r) {
+        const uint64_t hi = acc >> 31;
+        acc = (acc & kMseqM) ^ (hi << 3) ^ hi;
+    }
+    return (uint32_t)acc;
+}
+uint32_t gf_xpow_host(uint64_t e)   // x^e
+{
+    e %= kMseqM;
+    uint32_t r = 1, b = 2;
+    for (; e; e >>= 1) {
+        if (e & 1) r = gf_mul_host(r, b);
+        b = gf_mul_host(b, b);
+    }
+    return r;
+}
+
+// Pool position `v` as the kernels take it: mod the pool length for the
+// cyclic kinds, unchanged (mod 2^64) for the counter-based PRNG.
+uint64_t lut_wrap(const holo_lut* l, uint64_t v) { return l->kind == SRC_PRNG ? v : v % l->n_dev; }
+
+PhaseSrc make_src(const holo_lut* l, const uint32_t* rows)
+{
+    PhaseSrc p{};
+    p.kind = l->kind;
+    p.tab = l->dev;
+    p.codes = l->codes;
+    p.jump = l->mseq ? l->mseq + 32 : nullptr;
+    p.rows = rows;
+    p.seed = l->seed;
+    p.n = l->n_dev;
+    return p;
 }
 
 struct Workspace {
@@ -290,7 +341,7 @@ void plan_put(int kind, int64_t nx, int64_t ny, int n_sf, const LaunchCfg& c)
 // ---------------------------------------------------------------------------
 // Workspace of one OSPR frame: intermediate planes and reduction scratch.
 struct OsprLayout {
-    size_t o_x1, o_x2, o_part, o_nm, bytes;
+    size_t o_x1, o_x2, o_part, o_nm, o_rs, bytes;
     int chunk;
 };
 
@@ -311,13 +362,14 @@ OsprLayout ospr_layout(int64_t nx, int64_t ny, int n_sf, const LaunchCfg& cfg)
     l.o_x2 = cv.take(sizeof(float2) * nspec * n_sf);
     l.o_part = cv.take(sizeof(double) * 5 * (size_t)(ny / 2 + 1));
     l.o_nm = cv.take(sizeof(double) * 2);
+    l.o_rs = cv.take(sizeof(uint32_t) * (size_t)n_sf * (size_t)ny);   // M-sequence row states
     l.bytes = cv.off;
     return l;
 }
 
 // Device work of one OSPR frame on stream s, scratch at `b` (layout `l`),
 // {NMSE, NMSE_sym} to device `nm_out`.  The frame starts in the pool at
-// (c0 + *c0_base) mod L (c0 < L; c0_base may be NULL).
+// c0 + *c0_base (both reduced by lut_wrap; c0_base may be NULL).
 holo_status ospr_enqueue(const float* target, int64_t nx, int64_t ny, int n_sf, const holo_lut* lut, uint64_t c0,
                          const uint64_t* c0_base, uint32_t* holo_bits, float* recon, double* nm_out,
                          const float2* tw_x, const float2* tw_y, char* b, const OsprLayout& l, hipStream_t s,
@@ -328,13 +380,15 @@ holo_status ospr_enqueue(const float* target, int64_t nx, int64_t ny, int n_sf, 
     float2* x1 = (float2*)(b + l.o_x1);
     float2* x2 = (float2*)(b + l.o_x2);
     double* part = (double*)(b + l.o_part);
-    const uint32_t L = lut->n_dev;
+    uint32_t* rs = (uint32_t*)(b + l.o_rs);
     const size_t words = (size_t)nx * (size_t)ny / 32;
+    if (lut->kind == SRC_MSEQ)
+        LAUNCH("mseq_rows", s, launch_mseq_rows(lut->mseq, c0, c0_base, (int)nx, (int)ny, n_sf, rs, s));
     for (int k0 = 0; k0 < n_sf; k0 += l.chunk) {
         const int ns = n_sf - k0 < l.chunk ? n_sf - k0 : l.chunk;
-        const uint64_t ck = (uint64_t)(((unsigned __int128)c0 + (unsigned __int128)k0 * (uint64_t)(nx * ny)) % L);
-        LAUNCH("ospr_rows", s, launch_ospr_rows(target, (int)nx, (int)ny, ns, lut->dev, L, ck, c0_base, x1, tw_x,
-                                                cfg, s));
+        const uint64_t ck = lut_wrap(lut, c0 + (uint64_t)k0 * (uint64_t)(nx * ny));
+        const PhaseSrc src = make_src(lut, rs + (size_t)k0 * (size_t)ny);
+        LAUNCH("ospr_rows", s, launch_ospr_rows(target, (int)nx, (int)ny, ns, src, ck, c0_base, x1, tw_x, cfg, s));
         LAUNCH("ospr_cols", s, launch_ospr_cols(x1, (int)nx, (int)ny, ns, holo_bits + (size_t)k0 * words,
                                                 x2 + (size_t)k0 * nspec, tw_y, cfg, s));
     }
@@ -356,7 +410,7 @@ holo_status ospr_run(int device, const float* target, int64_t nx, int64_t ny, in
     if ((st = get_workspace(device, s, l.bytes, &ws))) return st;
     char* b = (char*)ws;
     double* nm = (double*)(b + l.o_nm);
-    if ((st = ospr_enqueue(target, nx, ny, n_sf, lut, cursor % lut->n_dev, nullptr, holo_bits, recon, nm, tw_x,
+    if ((st = ospr_enqueue(target, nx, ny, n_sf, lut, lut_wrap(lut, cursor), nullptr, holo_bits, recon, nm, tw_x,
                            tw_y, b, l, s, cfg)))
         return st;
     return copy_out(nmse2, nm, 2, flags, s);
@@ -393,7 +447,7 @@ bool g_use_graphs = true;
 
 holo_status gs_enqueue(const GsArgs& a, hipStream_t s, const LaunchCfg& cfg, const float2* tw_x, const float2* tw_y,
                        char* b, size_t o_state, size_t o_field, size_t o_pinit, size_t o_piter, size_t o_consts,
-                       size_t o_nm, size_t o_er, size_t o_x2, size_t o_p5, size_t o_f2)
+                       size_t o_nm, size_t o_er, size_t o_x2, size_t o_p5, size_t o_f2, size_t o_rs)
 {
     const int inx = (int)a.nx, iny = (int)a.ny;
     float2* state = (float2*)(b + o_state);
@@ -404,16 +458,22 @@ holo_status gs_enqueue(const GsArgs& a, hipStream_t s, const LaunchCfg& cfg, con
     double* nm = (double*)(b + o_nm);
     double* er = (double*)(b + o_er);
     const bool use_lut = a.init == nullptr;
-    const uint32_t L = use_lut ? a.lut->n_dev : 1u;
-    const uint64_t c0 = use_lut ? a.cursor % L : 0;
-    const float2* lutp = use_lut ? a.lut->dev : nullptr;
-    LAUNCH("gs_rows", s, launch_gs_rows(GS_INIT, a.target, inx, iny, lutp, L, c0, (const float2*)a.init, state,
+    const uint64_t c0 = use_lut ? lut_wrap(a.lut, a.cursor) : 0;
+    PhaseSrc src{};
+    src.n = 1;
+    if (use_lut) {
+        uint32_t* rs = (uint32_t*)(b + o_rs);
+        src = make_src(a.lut, rs);
+        if (a.lut->kind == SRC_MSEQ)
+            LAUNCH("mseq_rows", s, launch_mseq_rows(a.lut->mseq, c0, nullptr, inx, iny, 1, rs, s));
+    }
+    LAUNCH("gs_rows", s, launch_gs_rows(GS_INIT, a.target, inx, iny, src, c0, (const float2*)a.init, state,
                                         nullptr, pinit, consts, tw_x, cfg, s));
     LAUNCH("gs_consts", s, launch_gs_consts(pinit, iny, inx, consts, s));
     for (int it = 0; it < a.n_iter; ++it) {
         const bool last = it == a.n_iter - 1;
         LAUNCH("gs_cols", s, launch_gs_cols(state, inx, iny, last ? a.codes : nullptr, tw_y, cfg, s));
-        LAUNCH("gs_rows", s, launch_gs_rows(last ? GS_FINAL : GS_ITER, a.target, inx, iny, lutp, L, c0, nullptr,
+        LAUNCH("gs_rows", s, launch_gs_rows(last ? GS_FINAL : GS_ITER, a.target, inx, iny, src, c0, nullptr,
                                             state, fout, piter + (size_t)it * 3 * iny, consts, tw_x, cfg, s));
     }
     LAUNCH("gs_finalize", s, launch_gs_finalize(piter, a.n_iter, iny, consts, nm, er, s));
@@ -448,6 +508,7 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
     const size_t o_x2 = cv.take(a.codes ? sizeof(float2) * pitched : 0);
     const size_t o_p5 = cv.take(sizeof(double) * 5 * ny);
     const size_t o_f2 = cv.take(sizeof(double) * 2);
+    const size_t o_rs = cv.take(sizeof(uint32_t) * ny);   // M-sequence row states
     void* ws;
     if ((st = get_workspace(device, s, cv.off, &ws))) return st;
     char* b = (char*)ws;
@@ -460,13 +521,12 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
     // the legacy default stream cannot be captured: launch directly there
     if (!g_use_graphs || prof_on || s == nullptr) {
         if ((st = gs_enqueue(a, s, cfg, tw_x, tw_y, b, o_state, o_field, o_pinit, o_piter, o_consts, o_nm, o_er,
-                             o_x2, o_p5, o_f2)))
+                             o_x2, o_p5, o_f2, o_rs)))
             return st;
     } else {
-        const uint32_t L = a.init ? 1u : a.lut->n_dev;
         GraphKey key{{(uintptr_t)device, (uintptr_t)s, (uintptr_t)a.target, (uintptr_t)a.nx, (uintptr_t)a.ny,
-                      (uintptr_t)a.n_iter, (uintptr_t)(a.init ? nullptr : a.lut->dev), (uintptr_t)L,
-                      (uintptr_t)(a.init ? 0 : a.cursor % L), (uintptr_t)a.init, (uintptr_t)a.field,
+                      (uintptr_t)a.n_iter, (uintptr_t)(a.init ? 0 : a.lut->id),
+                      (uintptr_t)(a.init ? 0 : lut_wrap(a.lut, a.cursor)), (uintptr_t)a.init, (uintptr_t)a.field,
                       (uintptr_t)a.codes, (uintptr_t)(a.final2 != nullptr), (uintptr_t)a.recon, (uintptr_t)ws,
                       (uintptr_t)cfg.cols_per_block, (uintptr_t)cfg.rows_per_block, (uintptr_t)cfg.ksplit,
                       (uintptr_t)cfg.recon_cols_per_block, (uintptr_t)(intptr_t)cfg.pad,
@@ -481,7 +541,7 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
             hipGraph_t graph = nullptr;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             holo_status est = gs_enqueue(a, s, cfg, tw_x, tw_y, b, o_state, o_field, o_pinit, o_piter, o_consts,
-                                         o_nm, o_er, o_x2, o_p5, o_f2);
+                                         o_nm, o_er, o_x2, o_p5, o_f2, o_rs);
             hipError_t ce = hipStreamEndCapture(s, &graph);
             if (est) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -567,6 +627,52 @@ holo_status time_runs(hipStream_t s, int reps, F f, double* ms_out)
 
 using namespace holo;
 
+// A new handle on the current device (NULL after a failed device query).
+static holo_lut* new_lut(int kind, uint64_t n_lut, uint32_t n_dev, uint64_t seed)
+{
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(HOLO_EDEVICE, "no current device");
+        return nullptr;
+    }
+    holo_lut* l = new holo_lut();
+    l->device = device;
+    l->kind = kind;
+    l->id = g_lut_ids.fetch_add(1);
+    l->n_lut = n_lut;
+    l->n_dev = n_dev;
+    l->seed = seed;
+    return l;
+}
+
+// Copies `bytes` to a new device allocation *dst; on failure frees the whole handle.
+static holo_status upload_lut(void** dst, const void* src, size_t bytes, holo_lut* l)
+{
+    if (hipMalloc(dst, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *dst = nullptr;
+        holo_lut_free(l);
+        return fail(HOLO_ENOMEM, "phase source of %zu bytes", bytes);
+    }
+    hipError_t e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        holo_lut_free(l);
+        return fail(HOLO_EDEVICE, "phase source upload: %s", hipGetErrorString(e));
+    }
+    return HOLO_OK;
+}
+
+// The 256 code phasors exp(2*pi*i*q/256), FP64 then rounded.
+static holo_status upload_code_phasors(holo_lut* l)
+{
+    std::vector<float2> ph(256);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int q = 0; q < 256; ++q)
+        ph[q] = make_float2((float)std::cos(two_pi * (q / 256.0)), (float)std::sin(two_pi * (q / 256.0)));
+    return upload_lut((void**)&l->dev, ph.data(), sizeof(float2) * 256, l);
+}
+
 extern "C" {
 
 const char* holo_last_error(void) { return g_err.c_str(); }
@@ -577,28 +683,15 @@ holo_status holo_lut_from_phases(const double* phases, uint64_t n_lut, holo_lut*
     if (!out) return fail(HOLO_EINVAL, "out is NULL");
     *out = nullptr;
     if (n_lut && !phases) return fail(HOLO_EINVAL, "phases is NULL");
-    if (n_lut >= (1ull << 31)) return fail(HOLO_EUNSUPPORTED, "n_lut %llu >= 2^31", (unsigned long long)n_lut);
-    int device = 0;
-    HIP_TRY(hipGetDevice(&device));
-    holo_lut* l = new holo_lut();
-    l->device = device;
-    l->n_lut = n_lut;
-    l->n_dev = n_lut ? (uint32_t)n_lut : 1u;
+    // the kernels address the table with 32-bit byte offsets
+    if (n_lut >= (1ull << 29)) return fail(HOLO_EUNSUPPORTED, "n_lut %llu >= 2^29", (unsigned long long)n_lut);
+    holo_lut* l = new_lut(SRC_TABLE, n_lut, n_lut ? (uint32_t)n_lut : 1u, 0);
+    if (!l) return HOLO_EDEVICE;
     l->phases.assign(phases, phases + n_lut);
     std::vector<float2> ph(l->n_dev);
     if (n_lut == 0) ph[0] = make_float2(1.0f, 0.0f);
     for (uint64_t j = 0; j < n_lut; ++j) ph[j] = make_float2((float)std::cos(phases[j]), (float)std::sin(phases[j]));
-    if (hipMalloc(&l->dev, sizeof(float2) * l->n_dev) != hipSuccess) {
-        (void)hipGetLastError();
-        delete l;
-        return fail(HOLO_ENOMEM, "LUT of %u entries", l->n_dev);
-    }
-    hipError_t e = hipMemcpy(l->dev, ph.data(), sizeof(float2) * l->n_dev, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        (void)hipFree(l->dev);
-        delete l;
-        return fail(HOLO_EDEVICE, "LUT upload: %s", hipGetErrorString(e));
-    }
+    if (holo_status st = upload_lut((void**)&l->dev, ph.data(), sizeof(float2) * l->n_dev, l)) return st;
     *out = l;
     return HOLO_OK;
 }
@@ -606,7 +699,7 @@ holo_status holo_lut_from_phases(const double* phases, uint64_t n_lut, holo_lut*
 holo_status holo_lut_build(uint64_t n_lut, uint64_t seed, holo_lut** out)
 {
     if (!out) return fail(HOLO_EINVAL, "out is NULL");
-    if (n_lut >= (1ull << 31)) return fail(HOLO_EUNSUPPORTED, "n_lut %llu >= 2^31", (unsigned long long)n_lut);
+    if (n_lut >= (1ull << 29)) return fail(HOLO_EUNSUPPORTED, "n_lut %llu >= 2^29", (unsigned long long)n_lut);
     std::vector<double> phi(n_lut);
     const double two_pi = 6.283185307179586476925286766559;
     uint64_t s = seed;
@@ -617,9 +710,69 @@ holo_status holo_lut_build(uint64_t n_lut, uint64_t seed, holo_lut** out)
     return holo_lut_from_phases(phi.data(), n_lut, out);
 }
 
+holo_status holo_lut_build_codes(uint64_t n_lut, uint64_t seed, holo_lut** out)
+{
+    if (!out) return fail(HOLO_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_lut == 0) return fail(HOLO_EINVAL, "n_lut must be >= 1");
+    if (n_lut >= (1ull << 31)) return fail(HOLO_EUNSUPPORTED, "n_lut %llu >= 2^31", (unsigned long long)n_lut);
+    holo_lut* l = new_lut(SRC_CODES8, n_lut, (uint32_t)n_lut, seed);
+    if (!l) return HOLO_EDEVICE;
+    std::vector<uint8_t> q(n_lut);
+    l->phases.resize(n_lut);
+    const double two_pi = 6.283185307179586476925286766559;
+    uint64_t s = seed;
+    for (uint64_t j = 0; j < n_lut; ++j) {
+        q[j] = (uint8_t)(splitmix64(s) >> 56);
+        l->phases[j] = two_pi * ((double)q[j] / 256.0);
+    }
+    if (holo_status st = upload_lut((void**)&l->codes, q.data(), n_lut, l)) return st;
+    if (holo_status st = upload_code_phasors(l)) return st;
+    *out = l;
+    return HOLO_OK;
+}
+
+holo_status holo_lut_prng(uint64_t seed, holo_lut** out)
+{
+    if (!out) return fail(HOLO_EINVAL, "out is NULL");
+    *out = new_lut(SRC_PRNG, UINT64_MAX, 1u, seed);
+    return *out ? HOLO_OK : HOLO_EDEVICE;
+}
+
+holo_status holo_lut_mseq(uint64_t seed, holo_lut** out)
+{
+    if (!out) return fail(HOLO_EINVAL, "out is NULL");
+    *out = nullptr;
+    holo_lut* l = new_lut(SRC_MSEQ, kMseqM, kMseqM, seed);
+    if (!l) return HOLO_EDEVICE;
+    // first 31 bits s_0..s_30 = bits 30..0 of w; the Galois state with
+    // coefficient-of-x^30 read-out that produces them is w ^ (w >> 28)
+    uint64_t st = seed;
+    uint32_t w = (uint32_t)(splitmix64(st) & kMseqM);
+    if (w == 0) w = 1;
+    std::vector<uint32_t> aux(32 + 12 * 1024);
+    aux[0] = 2;   // x
+    for (int j = 1; j < 31; ++j) aux[j] = gf_mul_host(aux[j - 1], aux[j - 1]);
+    aux[31] = w ^ (w >> 28);
+    for (int j = 0; j < 12; ++j) {   // stride 2^j: multiply by x^(8 * 2^j)
+        const uint32_t c = gf_xpow_host(8ull << j);
+        for (int b = 0; b < 4; ++b)
+            for (uint32_t v = 0; v < 256; ++v)
+                aux[32 + j * 1024 + b * 256 + v] = gf_mul_host(c, gf_mul_host(v, gf_xpow_host(8ull * b)));
+    }
+    if (holo_status e = upload_lut((void**)&l->mseq, aux.data(), aux.size() * sizeof(uint32_t), l)) return e;
+    if (holo_status e = upload_code_phasors(l)) return e;
+    *out = l;
+    return HOLO_OK;
+}
+
+int32_t holo_lut_kind(const holo_lut* lut) { return lut ? lut->kind : -1; }
+
 holo_status holo_lut_phases(const holo_lut* lut, double* out, uint64_t n)
 {
     if (!lut || (!out && n)) return fail(HOLO_EINVAL, "lut/out is NULL");
+    if (lut->kind == SRC_PRNG || lut->kind == SRC_MSEQ)
+        return fail(HOLO_EUNSUPPORTED, "this phase source keeps no table (holo_phase_mask gives its phasors)");
     uint64_t m = n < lut->n_lut ? n : lut->n_lut;
     if (m) std::memcpy(out, lut->phases.data(), m * sizeof(double));
     return HOLO_OK;
@@ -633,7 +786,9 @@ void holo_lut_free(holo_lut* lut)
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(lut->device);
-    (void)hipFree(lut->dev);
+    if (lut->dev) (void)hipFree(lut->dev);
+    if (lut->codes) (void)hipFree(lut->codes);
+    if (lut->mseq) (void)hipFree(lut->mseq);
     (void)hipSetDevice(cur);
     delete lut;
 }
@@ -778,6 +933,30 @@ holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t ny, int32
     return HOLO_OK;
 }
 
+holo_status holo_phase_mask(const holo_lut* lut, uint64_t cursor, int64_t nx, int64_t ny, int32_t n_sf, float* out,
+                            void* hip_stream)
+{
+    if (!out) return fail(HOLO_EINVAL, "out is required");
+    if (n_sf < 1) return fail(HOLO_EINVAL, "n_sf must be >= 1");
+    if (!pow2_in_range(nx) || !pow2_in_range(ny))
+        return fail(HOLO_EUNSUPPORTED, "nx, ny must be powers of two in [16, 2048]");
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    holo_status st = check_lut(lut, device);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const uint64_t c0 = lut_wrap(lut, cursor);
+    uint32_t* rs = nullptr;
+    if (lut->kind == SRC_MSEQ) {
+        void* ws;
+        if ((st = get_workspace(device, s, sizeof(uint32_t) * (size_t)n_sf * (size_t)ny, &ws))) return st;
+        rs = (uint32_t*)ws;
+        LAUNCH("mseq_rows", s, launch_mseq_rows(lut->mseq, c0, nullptr, (int)nx, (int)ny, n_sf, rs, s));
+    }
+    LAUNCH("phase_mask", s, launch_phase_mask(make_src(lut, rs), c0, (int)nx, (int)ny, n_sf, (float2*)out, s));
+    return HOLO_OK;
+}
+
 holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frames, const holo_lut* lut,
                                        uint64_t* cursor, double* nmse_out, int32_t precision, uint32_t flags,
                                        void* hip_stream)
@@ -797,7 +976,6 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
     holo_status st = check_lut(lut, device);
     if (st) return st;
     hipStream_t s = (hipStream_t)hip_stream;
-    const uint32_t L = lut->n_dev;
 
     // per-frame plans, layouts, pool offsets (exclusive prefix sum of n_sf*N)
     std::vector<LaunchCfg> cfg(n_frames);
@@ -855,14 +1033,14 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
     double* nm = (double*)(b + o_nm);
 
     // the only per-call value inside the graph: the pool start, in device memory
-    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, dbase, *cursor % L);
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, dbase, lut_wrap(lut, *cursor));
     HIP_TRY(hipGetLastError());
 
     auto enqueue_all = [&](bool branches, BatchSync* bs) -> holo_status {
         for (int f = 0; f < n_frames; ++f) {
             const holo_frame& fr = frames[f];
             hipStream_t fs = branches ? bs->br[branch[f]] : s;
-            holo_status e = ospr_enqueue(fr.target, fr.nx, fr.ny, fr.n_sf, lut, off[f] % L, dbase, fr.holo_bits,
+            holo_status e = ospr_enqueue(fr.target, fr.nx, fr.ny, fr.n_sf, lut, lut_wrap(lut, off[f]), dbase, fr.holo_bits,
                                          fr.recon, nm + 2 * f, tw[(int)fr.nx], tw[(int)fr.ny],
                                          b + o_branch[branch[f]], lay[f], fs, cfg[f]);
             if (e) return e;
@@ -880,13 +1058,13 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
         BatchSync* bs = nullptr;
         if ((st = get_batch_sync(device, &bs))) return st;
         GraphKey key;
-        key.k = {(uintptr_t)0xBA7C, (uintptr_t)device, (uintptr_t)s, (uintptr_t)ws, (uintptr_t)lut->dev,
-                 (uintptr_t)L, (uintptr_t)n_frames};
+        key.k = {(uintptr_t)0xBA7C, (uintptr_t)device, (uintptr_t)s, (uintptr_t)ws, (uintptr_t)lut->id,
+                 (uintptr_t)n_frames};
         for (int f = 0; f < n_frames; ++f) {
             const holo_frame& fr = frames[f];
             const LaunchCfg& c = cfg[f];
             key.k.insert(key.k.end(), {(uintptr_t)fr.nx, (uintptr_t)fr.ny, (uintptr_t)fr.n_sf, (uintptr_t)fr.target,
-                                       (uintptr_t)fr.holo_bits, (uintptr_t)fr.recon, (uintptr_t)(off[f] % L),
+                                       (uintptr_t)fr.holo_bits, (uintptr_t)fr.recon, (uintptr_t)lut_wrap(lut, off[f]),
                                        (uintptr_t)c.cols_per_block, (uintptr_t)c.rows_per_block,
                                        (uintptr_t)c.ksplit, (uintptr_t)c.recon_cols_per_block,
                                        (uintptr_t)(intptr_t)c.pad, (uintptr_t)(intptr_t)c.chunk,

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "phase_src.hpp"
+
 namespace holo {
 
 // Launch shapes of one plan (0 = built-in heuristic).  Chosen per
@@ -45,12 +47,23 @@ hipError_t launch_dft_operand_gen(uint16_t* out, int prec, hipStream_t s);
 hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int ny, int sign,
                        const float2* tw_x, const float2* tw_y, const LaunchCfg& cfg, hipStream_t s);
 
-// OSPR K1: R = T * LUT phasor, inverse row transform, all n_sf sub-frames.
-// The pool position of the launch's first pixel is (c0 + *c0_base) mod n_lut
-// (c0_base may be NULL; both terms < n_lut).
-hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const float2* lut,
-                            uint32_t n_lut, uint64_t c0, const uint64_t* c0_base, float2* x1, const float2* tw_x,
-                            const LaunchCfg& cfg, hipStream_t s);
+// OSPR K1: R = T * pool phasor, inverse row transform, all n_sf sub-frames.
+// The pool position of the launch's first pixel is c0 + *c0_base, reduced mod
+// the pool length for the cyclic sources (c0_base may be NULL; both terms
+// already reduced).  For SRC_MSEQ, src.rows holds the launch's n_sf*ny row
+// states (launch_mseq_rows with the same c0, c0_base).
+hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const PhaseSrc& src, uint64_t c0,
+                            const uint64_t* c0_base, float2* x1, const float2* tw_x, const LaunchCfg& cfg,
+                            hipStream_t s);
+
+// M-sequence source: Galois state of the first pixel of every (sub-frame,
+// row) of a launch, rows[k*ny + y]; aux = x^(2^j) for j < 31, then S_0.
+hipError_t launch_mseq_rows(const uint32_t* aux, uint64_t c0, const uint64_t* c0_base, int nx, int ny, int n_sf,
+                            uint32_t* rows, hipStream_t s);
+// Phasors of pixels (k, y, x) of n_sf sub-frames from pool position c0, as the
+// generation kernels draw them: out[(k*ny + y)*nx + x].
+hipError_t launch_phase_mask(const PhaseSrc& src, uint64_t c0, int nx, int ny, int n_sf, float2* out,
+                             hipStream_t s);
 // OSPR K2: inverse column transform, binarise + pack, forward column transform
 // of the +-1 column, half spectrum (rows 0..ny/2) out.
 hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
@@ -72,8 +85,8 @@ enum GsRowMode { GS_INIT = 0, GS_ITER = 1, GS_FINAL = 2 };
 struct GsConsts {
     double sum_t2, sum_t4, te_scale;
 };
-hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const float2* lut, uint32_t n_lut,
-                          uint64_t c0, const float2* init, float2* state, float2* field_out,
+hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const PhaseSrc& src, uint64_t c0,
+                          const float2* init, float2* state, float2* field_out,
                           double* partials, const GsConsts* consts, const float2* tw_x,
                           const LaunchCfg& cfg, hipStream_t s);
 hipError_t launch_gs_cols(float2* state, int nx, int ny, uint8_t* codes, const float2* tw_y,

@@ -269,7 +269,7 @@ hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int n
 // -------------------------------------------------------------------------
 template <int NX, int P>
 __global__ __launch_bounds__(P ? 256 : 1024) void k_ospr_rows(const float* __restrict__ target, int ny,
-                                                    const float2* __restrict__ lut, uint32_t n_lut, uint64_t c0,
+                                                    PhaseSrc src, uint64_t c0,
                                                     const uint64_t* __restrict__ c0_base,
                                                     float2* __restrict__ x1, const float2* __restrict__ tw,
                                                     int pitch, const uint4* __restrict__ dftop)
@@ -282,24 +282,20 @@ __global__ __launch_bounds__(P ? 256 : 1024) void k_ospr_rows(const float* __res
     const int k = blockIdx.x / blocks_per_sf;
     const int y = (blockIdx.x % blocks_per_sf) * rows + row;
     const uint64_t npix = (uint64_t)NX * (uint64_t)ny;
-    // Cyclic LUT address of pixel (t, y) in sub-frame k; then +T per slot.
-    // start of this launch in the pool: c0, plus a base read from device memory
-    // when given (lets a replayed graph follow a cursor that moves per call)
-    const uint64_t cb = c0_base ? *c0_base : 0;
-    uint32_t idx = (uint32_t)((cb + c0 + (uint64_t)k * npix + (uint64_t)y * NX + (uint64_t)t) % n_lut);
-    const uint32_t step = (uint32_t)(T % n_lut);
+    // pool position of pixel (t, y) of sub-frame k, then +T per slot; the
+    // launch's start is c0 plus a base read from device memory when given
+    // (lets a replayed graph follow a cursor that moves per call)
+    const uint64_t pos0 = pool_pos(src, c0, c0_base, (uint64_t)k * npix + (uint64_t)y * NX + (uint64_t)t);
+    const uint32_t rs = src.kind == SRC_MSEQ ? src.rows[(size_t)k * ny + y] : 0u;
     const auto rt = make_rsrc(target, (uint32_t)(npix * 4));
-    const auto rl = make_rsrc(lut, n_lut * 8u);
     const uint32_t toff = ((uint32_t)y * NX + (uint32_t)t) * 4u;
-    float2 v[kP];
+    float a[kP];
 #pragma unroll
-    for (int m = 0; m < kP; ++m) {
-        const float a = buf_ld1(rt, toff, (uint32_t)(m * T * 4));
-        const float2 ph = buf_ld2(rl, idx * 8u, 0);
-        v[m] = make_float2(a * ph.x, a * ph.y);
-        idx += step;
-        if (idx >= n_lut) idx -= n_lut;
-    }
+    for (int m = 0; m < kP; ++m) a[m] = buf_ld1(rt, toff, (uint32_t)(m * T * 4));
+    float2 v[kP];
+    phase_slots<kP>(src, pos0, (uint32_t)T, t, rs, v);
+#pragma unroll
+    for (int m = 0; m < kP; ++m) v[m] = make_float2(a[m] * v[m].x, a[m] * v[m].y);
     fft_any<NX, 1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, RowsOf<NX>{}, tw, dftop);
     const size_t plane = (size_t)ny * pitch;
     const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
@@ -308,17 +304,17 @@ __global__ __launch_bounds__(P ? 256 : 1024) void k_ospr_rows(const float* __res
     for (int m = 0; m < kP; ++m) buf_st2(ro, ooff, (uint32_t)(m * T * 8), v[m]);
 }
 
-hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const float2* lut,
-                            uint32_t n_lut, uint64_t c0, const uint64_t* c0_base, float2* x1, const float2* tw_x,
-                            const LaunchCfg& cfg, hipStream_t s)
+hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const PhaseSrc& src, uint64_t c0,
+                            const uint64_t* c0_base, float2* x1, const float2* tw_x, const LaunchCfg& cfg,
+                            hipStream_t s)
 {
     const int rows = row_block_rows(nx, ny, cfg.rows_per_block, cfg.prec);
     HOLO_SWITCH_NP(nx, cfg.prec, {
         constexpr int T = N_ / kP;
         size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
         allow_lds(k_ospr_rows<N_, P_>, lds);
-        hipLaunchKernelGGL((k_ospr_rows<N_, P_>), dim3((ny / rows) * n_sf), dim3(rows * T), lds, s, target, ny, lut,
-                           n_lut, c0, c0_base, x1, tw_x, row_pitch(nx, cfg), DFTOP(cfg));
+        hipLaunchKernelGGL((k_ospr_rows<N_, P_>), dim3((ny / rows) * n_sf), dim3(rows * T), lds, s, target, ny, src,
+                           c0, c0_base, x1, tw_x, row_pitch(nx, cfg), DFTOP(cfg));
     });
     return hipGetLastError();
 }

@@ -78,3 +78,14 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     st = lib.holo_ospr_generate(fake, 256, 128, 8, fake, C.byref(cur), fake, None, None, h.FP16, 0, None)
     assert st == h.HOLO_EUNSUPPORTED
     assert cur.value == 0
+    # phase sources: table offsets are 32-bit byte offsets; a code table needs entries
+    out = P()
+    assert lib.holo_lut_build(1 << 29, 1, C.byref(out)) == h.HOLO_EUNSUPPORTED
+    assert lib.holo_lut_build_codes(0, 1, C.byref(out)) == h.HOLO_EINVAL
+    assert lib.holo_lut_build_codes(1 << 31, 1, C.byref(out)) == h.HOLO_EUNSUPPORTED
+    assert lib.holo_lut_prng(1, None) == h.HOLO_EINVAL
+    assert lib.holo_lut_mseq(1, None) == h.HOLO_EINVAL
+    assert lib.holo_lut_kind(None) == -1
+    assert lib.holo_phase_mask(fake, 0, 64, 64, 1, None, None) == h.HOLO_EINVAL
+    assert lib.holo_phase_mask(fake, 0, 64, 64, 0, fake, None) == h.HOLO_EINVAL
+    assert lib.holo_phase_mask(fake, 0, 100, 64, 1, fake, None) == h.HOLO_EUNSUPPORTED
