@@ -189,6 +189,7 @@ def main():
         out["batched"] = bench_batched(h, synth, torch, dev)
         out["gs"] = bench_gs(h, synth, torch, dev)
         out["lut_sweep"] = bench_lut_sweep(h, synth, torch, dev, target, nx, ny, n_sf)
+        out["phase_sources"] = bench_phase_sources(h, synth, torch, dev, target, nx, ny, n_sf)
         out["cnn_seed"] = bench_cnn(h, synth, torch, dev, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(synth, nx, ny, n_lut)
@@ -350,6 +351,59 @@ def bench_lut_sweep(h, synth, torch, dev, target, nx, ny, n_sf):
         dt = (time.perf_counter() - t0) / steps
         res.append({"n_lut": L, "subframes_per_s": round(n_sf / dt, 1), "nmse": float(nm[0]),
                     "nmse_sym": float(nm[1]), "warnings": h.lut_check(L, nx, ny, n_sf)})
+        lut.close()
+    return res
+
+
+def bench_phase_sources(h, synth, torch, dev, target, nx, ny, n_sf, steps=50):
+    """The LUT against the other ways of drawing the phases, on the headline
+    workload: the software route (counter-based SplitMix64 + FP32 sine/cosine
+    per pixel), the M-sequence route (x^31 + x^3 + 1, 8 bits per pixel, phasor
+    table), and 8-bit code tables.  Per source: sub-frames/s of whole frames,
+    the row pass per launch (the only kernel that differs), the NMSE pair of
+    the frame at cursor 0 and the bytes the source keeps on the device."""
+    full = nx * ny * n_sf
+    cases = [("table", 65536), ("table", 10007), ("table", full), ("codes8", 65536), ("codes8", 1048573),
+             ("codes8", full), ("prng", None), ("mseq", None)]
+    bits = torch.empty((n_sf, nx * ny // 32), dtype=torch.int32, device=dev)
+    nm_dev = torch.empty(2, dtype=torch.float64, device=dev)
+    ref_mask = h.phase_mask(h.Lut(1 << 20, synth.SEED_LUT), 0, nx, ny, 1)
+    res = []
+    for kind, L in cases:
+        if kind == "table":
+            lut, nbytes = h.Lut(L, synth.SEED_LUT), 8 * L
+        elif kind == "codes8":
+            lut, nbytes = h.Lut.codes(L, synth.SEED_LUT), L + 2048
+        elif kind == "prng":
+            lut, nbytes = h.Lut.prng(synth.SEED_LUT), 0
+        else:
+            lut, nbytes = h.Lut.mseq(synth.SEED_LUT), 2048 + 128 + 12 * 4096
+        _, nm, c = h.ospr_generate(target, n_sf, lut, 0, bits=bits)
+        for _ in range(3):
+            _, _, c = h.ospr_generate(target, n_sf, lut, c, bits=bits, want_nmse=False, nmse_out=nm_dev)
+        torch.cuda.synchronize()
+        dt = float("inf")
+        for _ in range(3):   # best of three timed loops
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, _, c = h.ospr_generate(target, n_sf, lut, c, bits=bits, want_nmse=False, nmse_out=nm_dev)
+            torch.cuda.synchronize()
+            dt = min(dt, (time.perf_counter() - t0) / steps)
+        h.prof_reset()
+        h.prof_enable(True)
+        for _ in range(10):
+            _, _, c = h.ospr_generate(target, n_sf, lut, c, bits=bits, want_nmse=False, nmse_out=nm_dev)
+        torch.cuda.synchronize()
+        h.prof_enable(False)
+        ms, cnt = h.prof_read("ospr_rows")
+        row = {"source": kind, "n_lut": L, "device_bytes": nbytes, "subframes_per_s": round(n_sf / dt, 1),
+               "ospr_rows_us": round(1e3 * ms / max(cnt, 1), 2), "nmse": float(nm[0]), "nmse_sym": float(nm[1])}
+        if kind == "prng":
+            # same SplitMix64 outputs as a table of the same seed: the FP32
+            # sine/cosine plus 24-bit truncation against FP64-rounded phasors
+            d = (h.phase_mask(lut, 0, nx, ny, 1) - ref_mask).abs().max().item()
+            row["phasor_vs_table_max"] = d
+        res.append(row)
         lut.close()
     return res
 

@@ -293,7 +293,12 @@ __global__ __launch_bounds__(P ? 256 : 1024) void k_ospr_rows(const float* __res
 #pragma unroll
     for (int m = 0; m < kP; ++m) a[m] = buf_ld1(rt, toff, (uint32_t)(m * T * 4));
     float2 v[kP];
-    phase_slots<kP>(src, pos0, (uint32_t)T, t, rs, v);
+    uint32_t* lt = nullptr;
+    if (phase_uses_lds(src)) {   // code tables after the transform's LDS rows
+        lt = (uint32_t*)(lds + rows * PadLen<NX>::v);
+        phase_stage(src, (uint32_t)T, lt);
+    }
+    phase_slots<kP>(src, pos0, (uint32_t)T, t, rs, v, lt);
 #pragma unroll
     for (int m = 0; m < kP; ++m) v[m] = make_float2(a[m] * v[m].x, a[m] * v[m].y);
     fft_any<NX, 1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, RowsOf<NX>{}, tw, dftop);
@@ -311,7 +316,8 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
     const int rows = row_block_rows(nx, ny, cfg.rows_per_block, cfg.prec);
     HOLO_SWITCH_NP(nx, cfg.prec, {
         constexpr int T = N_ / kP;
-        size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2);
+        size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2) +
+                     (src.kind == SRC_MSEQ || src.kind == SRC_CODES8 ? kPhaseLdsWords * sizeof(uint32_t) : 0);
         allow_lds(k_ospr_rows<N_, P_>, lds);
         hipLaunchKernelGGL((k_ospr_rows<N_, P_>), dim3((ny / rows) * n_sf), dim3(rows * T), lds, s, target, ny, src,
                            c0, c0_base, x1, tw_x, row_pitch(nx, cfg), DFTOP(cfg));

@@ -83,13 +83,36 @@ __device__ __forceinline__ uint64_t splitmix_mix(uint64_t z)
     return z ^ (z >> 31);
 }
 
+// Words of LDS that phase_stage fills: the jump table of one stride (MSEQ),
+// then the 256 code phasors (MSEQ, CODES8).
+constexpr int kPhaseLdsWords = 1024 + 512;
+
+__device__ __forceinline__ bool phase_uses_lds(const PhaseSrc& src)
+{
+    return src.kind == SRC_MSEQ || src.kind == SRC_CODES8;
+}
+
+// Copies the code tables of `src` into LDS `lt` (kPhaseLdsWords words); every
+// thread of the block calls it, for kinds where phase_uses_lds holds.
+__device__ __forceinline__ void phase_stage(const PhaseSrc& src, uint32_t T, uint32_t* lt)
+{
+    if (src.kind == SRC_MSEQ) {
+        const uint32_t* j = src.jump + 1024u * (uint32_t)(31 - __builtin_clz(T));
+        for (int i = threadIdx.x; i < 1024; i += blockDim.x) lt[i] = j[i];
+    }
+    const uint32_t* ph = (const uint32_t*)src.tab;
+    for (int i = threadIdx.x; i < 512; i += blockDim.x) lt[1024 + i] = ph[i];
+    __syncthreads();
+}
+
 // Phasors of the pool positions pos0 + T*m, m = 0..P-1, for a thread whose
 // slot-0 pixel is pixel t of its row.  pos0: the cyclic kinds take it reduced
 // mod n; PRNG takes the absolute position.  `rs`: MSEQ only, the Galois state
-// of the row's first pixel.
+// of the row's first pixel; `lt`: code tables staged by phase_stage, or NULL
+// to read them from global memory.
 template <int P>
 __device__ __forceinline__ void phase_slots(const PhaseSrc& src, uint64_t pos0, uint32_t T, int t, uint32_t rs,
-                                            float2 (&ph)[P])
+                                            float2 (&ph)[P], const uint32_t* lt = nullptr)
 {
     if (src.kind == SRC_PRNG) {
         uint64_t z = src.seed + (pos0 + 1) * kGolden;
@@ -111,15 +134,25 @@ __device__ __forceinline__ void phase_slots(const PhaseSrc& src, uint64_t pos0, 
             s = gf_xshift(s, d);
             k -= d;
         }
+        if (lt) {
+            const float2* lph = (const float2*)(lt + 1024);
 #pragma unroll
-        for (int m = 0; m < P; ++m) {
-            ph[m] = buf_ld2(rt, (s >> 23) * 8u, 0);
-            if (m + 1 < P) {
-                const uint32_t b0 = s & 255u, b1 = (s >> 8) & 255u, b2 = (s >> 16) & 255u, b3 = s >> 24;
-                s = __builtin_bit_cast(uint32_t, buf_ld1(rj, b0 * 4u, 0)) ^
-                    __builtin_bit_cast(uint32_t, buf_ld1(rj, b1 * 4u, 1024u)) ^
-                    __builtin_bit_cast(uint32_t, buf_ld1(rj, b2 * 4u, 2048u)) ^
-                    __builtin_bit_cast(uint32_t, buf_ld1(rj, b3 * 4u, 3072u));
+            for (int m = 0; m < P; ++m) {
+                ph[m] = lph[s >> 23];
+                if (m + 1 < P)
+                    s = lt[s & 255u] ^ lt[256 + ((s >> 8) & 255u)] ^ lt[512 + ((s >> 16) & 255u)] ^ lt[768 + (s >> 24)];
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+                ph[m] = buf_ld2(rt, (s >> 23) * 8u, 0);
+                if (m + 1 < P) {
+                    const uint32_t b0 = s & 255u, b1 = (s >> 8) & 255u, b2 = (s >> 16) & 255u, b3 = s >> 24;
+                    s = __builtin_bit_cast(uint32_t, buf_ld1(rj, b0 * 4u, 0)) ^
+                        __builtin_bit_cast(uint32_t, buf_ld1(rj, b1 * 4u, 1024u)) ^
+                        __builtin_bit_cast(uint32_t, buf_ld1(rj, b2 * 4u, 2048u)) ^
+                        __builtin_bit_cast(uint32_t, buf_ld1(rj, b3 * 4u, 3072u));
+                }
             }
         }
     } else {
@@ -129,13 +162,16 @@ __device__ __forceinline__ void phase_slots(const PhaseSrc& src, uint64_t pos0, 
         if (src.kind == SRC_CODES8) {
             const auto rc = make_rsrc(src.codes, n);
             const auto rt = make_rsrc(src.tab, 256u * 8u);
+            uint32_t q[P];
 #pragma unroll
             for (int m = 0; m < P; ++m) {
-                const uint32_t q = __builtin_amdgcn_raw_buffer_load_b8(rc, idx, 0, 0);
-                ph[m] = buf_ld2(rt, q * 8u, 0);
+                q[m] = __builtin_amdgcn_raw_buffer_load_b8(rc, idx, 0, 0);
                 idx += step;
                 if (idx >= n) idx -= n;
             }
+            const float2* lph = lt ? (const float2*)(lt + 1024) : nullptr;
+#pragma unroll
+            for (int m = 0; m < P; ++m) ph[m] = lph ? lph[q[m]] : buf_ld2(rt, q[m] * 8u, 0);
         } else {
             const auto rl = make_rsrc(src.tab, n * 8u);
 #pragma unroll

@@ -12,9 +12,10 @@ Tolerances:
     |error| <= 2^-24 per component; the M-sequence and 8-bit codes are exact
     integers and compared bit for bit;
   * PRNG phasors come from the GPU's FP32 sine/cosine of a 24-bit fraction of
-    a turn; PRNG_PHASOR_TOL bounds their error (measured max below 1e-6);
+    a turn (an exact FP32 argument); PRNG_PHASOR_TOL bounds their error at
+    about four times the largest error measured over these cases (1.3e-7);
   * OSPR bits: bit-exact except pixels with |Re H_oracle| below the tie
-    threshold (1e-5; for PRNG also at least 4x the phasor bound); NMSE 1e-4
+    threshold (1e-5, which is above 4x the PRNG phasor bound); NMSE 1e-4
     relative.
 """
 import numpy as np
@@ -26,7 +27,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 M31 = (1 << 31) - 1
-PRNG_PHASOR_TOL = 2e-6
+PRNG_PHASOR_TOL = 5e-7
 TIE = 1e-5
 
 
