@@ -65,8 +65,10 @@ enum {
  * below 256 and HOLO_EINVAL for other values. */
 enum { HOLO_FP32 = 0, HOLO_BF16 = 1, HOLO_FP16 = 2 };
 
-/* Flags. */
-enum { HOLO_F_NMSE_DEVICE = 1 };
+/* Flags.  HOLO_F_OSPR_PAIRS and HOLO_F_OSPR_LEVELS8 select an OSPR variant
+ * (holo_ospr_generate, holo_ospr_generate_batched); neither is the paper's
+ * method, which is the default binary frame. */
+enum { HOLO_F_NMSE_DEVICE = 1, HOLO_F_OSPR_PAIRS = 2, HOLO_F_OSPR_LEVELS8 = 4 };
 
 /* holo_lut_check() warning bits (Section 5.1 hard limits, Section 8 rules). */
 enum {
@@ -148,18 +150,29 @@ HOLO_API uint32_t holo_lut_check(uint64_t n_lut, int64_t nx, int64_t ny, int32_t
  * bit = (Re H_k < 0), tie Re H = 0 -> +1 (bit 0); replay I_k = |F{H'_k}|^2
  * (Eq. (1), unitary); time average I = (1/n_sf) sum_k I_k (Section 3).
  *   target     device float[ny][nx], amplitudes (any non-negative scale)
- *   cursor     host in/out; advanced by n_sf*nx*ny on success
- *   holo_bits  device uint32[n_sf][nx*ny/32]: bit p%32 of word p/32 is pixel
- *              p (LSB first); 1 means phase pi
+ *   cursor     host in/out; advanced by n_sf*nx*ny on success (pair mode:
+ *              n_sf/2*nx*ny)
+ *   holo_out   device uint32[n_sf][nx*ny/32] packed bits: bit p%32 of word
+ *              p/32 is pixel p (LSB first); 1 means phase pi.  With
+ *              HOLO_F_OSPR_LEVELS8: uint8 codes [n_sf][ny][nx] instead.
  *   recon      device float[ny][nx] time-averaged intensity, or NULL
  *   nmse2      {NMSE vs T^2, NMSE vs the point-symmetrised T^2} or NULL, where
  *              NMSE(I, W) = 1 - (sum I W)^2 / (sum I^2 * sum W^2), the
  *              optimal-scale normalised MSE, accumulated in FP64
  *   precision  HOLO_FP32, HOLO_BF16 or HOLO_FP16 (stages of all transforms)
- * Errors: HOLO_EINVAL for null target/lut/cursor/holo_bits or n_sf < 1.
+ *   flags      HOLO_F_NMSE_DEVICE, and at most one variant (not the paper's):
+ *     HOLO_F_OSPR_PAIRS: each randomised field H_j, j < n_sf/2 (pool index
+ *       k = j above), gives two binary sub-frames, 2j from Re H_j and 2j+1
+ *       from Im H_j (bit = part < 0); n_sf must be even.  Half the inverse
+ *       transforms and pool draws of the binary frame.
+ *     HOLO_F_OSPR_LEVELS8: sub-frame k is quantised to the nearest of the
+ *       eight phases exp(i*2*pi*m/8), m = round(8 arg H_k/(2 pi)) mod 8,
+ *       H = 0 -> 0, and replayed as such.
+ * Errors: HOLO_EINVAL for null target/lut/cursor/holo_out, n_sf < 1, both
+ * variant flags, or an odd n_sf in pair mode.
  * ------------------------------------------------------------------------- */
 HOLO_API holo_status holo_ospr_generate(const float* target, int64_t nx, int64_t ny, int32_t n_sf,
-                                        const holo_lut* lut, uint64_t* cursor, uint32_t* holo_bits,
+                                        const holo_lut* lut, uint64_t* cursor, void* holo_out,
                                         float* recon, double* nmse2, int32_t precision, uint32_t flags,
                                         void* hip_stream);
 
@@ -210,7 +223,9 @@ HOLO_API holo_status holo_reconstruct_nmse(const void* holo, int32_t levels, int
  * each exactly as holo_ospr_generate would compute it with the pool cursor
  * continuing from frame to frame in array order (Section 5: frames continue
  * where the previous left off): frame f starts at *cursor + sum over g < f of
- * n_sf_g * nx_g * ny_g, and *cursor advances by the total.
+ * n_sf_g * nx_g * ny_g, and *cursor advances by the total.  The variant flags
+ * of holo_ospr_generate apply to every frame (pair mode: n_sf_g/2 fields each;
+ * holo_bits then holds codes for HOLO_F_OSPR_LEVELS8).
  *   frames    host array of n_frames (1..4096) descriptors; every pointer in
  *             them is a device pointer owned by the caller
  *   nmse_out  [n_frames][2] {NMSE, NMSE_sym} per frame, host (complete on
@@ -228,7 +243,8 @@ typedef struct {
     int64_t nx, ny;
     int32_t n_sf;
     const float* target;  /* device float[ny][nx]                        */
-    uint32_t* holo_bits;  /* device uint32[n_sf][nx*ny/32], as above     */
+    void* holo_bits;      /* device: bits uint32[n_sf][nx*ny/32] or codes */
+                          /* uint8[n_sf][ny][nx], as holo_ospr_generate    */
     float* recon;         /* device float[ny][nx] time average, or NULL  */
 } holo_frame;
 

@@ -59,6 +59,7 @@ def _load():
         "orc_reconstruct": (None, [P, i32, i64, i64, i32, P]),
         "orc_ospr": (None, [P, i64, i64, i32, P, u64, u64, P, P, P, P]),
         "orc_gs": (None, [P, i64, i64, i32, P, P, P, P, P, P]),
+        "orc_ospr_mode": (None, [P, i64, i64, i32, P, u64, u64, i32, P, P, P, P]),
         "orc_num_threads": (i32, []),
         "orc_splitmix64_at": (u64, [u64, u64]),
         "orc_prng_phases": (None, [u64, u64, u64, P]),
@@ -250,6 +251,28 @@ def ospr(target, n_sf: int, phi: np.ndarray, n_lut: int, cursor: int = 0,
     _load().orc_ospr(t.ctypes.data, nx, ny, n_sf, phi.ctypes.data, n_lut, cursor,
                      bits.ctypes.data, _p(reh), _p(ibar), nm.ctypes.data)
     return {"bits": bits, "reH": reh, "ibar": ibar, "nmse2": nm}
+
+
+def ospr_mode(target, n_sf: int, phi: np.ndarray, n_lut: int, cursor: int, mode: int, want_hval: bool = True):
+    """OSPR variants: mode 1 = two binary sub-frames (Re, Im) per field,
+    mode 2 = eight phase levels.  Returns dict(holo: bits [n_sf, words]
+    uint32 or codes [n_sf, ny, nx] uint8, hval: decided values (mode 1:
+    [n_sf, ny, nx] float; mode 2: H complex [n_sf, ny, nx]), ibar, nmse2)."""
+    t = _f32(target)
+    ny, nx = t.shape
+    n = nx * ny
+    if mode == 1:
+        holo = np.zeros((n_sf, (n + 31) // 32), dtype=np.uint32)
+        hval = np.zeros((n_sf, ny, nx)) if want_hval else None
+    else:
+        holo = np.zeros((n_sf, ny, nx), dtype=np.uint8)
+        hval = np.zeros((n_sf, ny, nx), dtype=np.complex128) if want_hval else None
+    ibar = np.zeros((ny, nx))
+    nm = np.zeros(2)
+    phi = np.ascontiguousarray(phi, dtype=np.float64) if n_lut else np.zeros(1)
+    _load().orc_ospr_mode(t.ctypes.data, nx, ny, n_sf, phi.ctypes.data, n_lut, cursor, mode, holo.ctypes.data,
+                          _p(hval), ibar.ctypes.data, nm.ctypes.data)
+    return {"holo": holo, "hval": hval, "ibar": ibar, "nmse2": nm}
 
 
 def gs(target, n_iter: int, init_phasor):

@@ -316,6 +316,64 @@ void orc_ospr(const float *T, int64_t nx, int64_t ny, int n_sf, const double *ph
 }
 
 /* ------------------------------------------------------------------------ */
+/* OSPR variants (not from the paper; they change how sub-frames are drawn    */
+/* from the randomised fields, the pool is read as in orc_ospr):              */
+/*   mode 1, pairs: field j = 0..n_sf/2-1 reads the pool at k = j; its        */
+/*     H_j = F^{-1}{T exp(i phi)} gives two binary sub-frames, 2j from Re H_j */
+/*     and 2j+1 from Im H_j (nearest of {+1, -1} to each part); holo is       */
+/*     packed bits as in orc_ospr, hval[k][p] the decided value (Re or Im).    */
+/*   mode 2, eight levels: sub-frame k reads the pool at k and is quantised   */
+/*     to the nearest of exp(i*2*pi*m/8) (orc_quant8); holo is uint8 codes    */
+/*     [n_sf][N], hval[k][2p..2p+1] = H_k.                                    */
+/* Then the time-averaged replay of the quantised sub-frames and the NMSE     */
+/* pair, as for the binary frame.  n_sf must be even in mode 1.              */
+/* ------------------------------------------------------------------------ */
+void orc_ospr_mode(const float *T, int64_t nx, int64_t ny, int n_sf, const double *phi, uint64_t n_lut,
+                   uint64_t cursor, int mode, void *holo, double *hval, double *ibar, double *nmse2)
+{
+    uint64_t n = (uint64_t)(nx * ny), words = (n + 31) / 32;
+    double *h = (double *)malloc(sizeof(double) * 2 * n);
+    double *ph = (double *)malloc(sizeof(double) * 2 * n);
+    int n_fields = mode == 1 ? n_sf / 2 : n_sf;
+    if (mode == 1) memset(holo, 0, sizeof(uint32_t) * words * (uint64_t)n_sf);
+    for (int j = 0; j < n_fields; ++j) {
+        orc_lut_phasor_field(phi, n_lut, cursor, (uint64_t)j, nx, ny, ph);
+        for (uint64_t p = 0; p < n; ++p) {
+            h[2 * p] = (double)T[p] * ph[2 * p];
+            h[2 * p + 1] = (double)T[p] * ph[2 * p + 1];
+        }
+        orc_fft2(h, nx, ny, +1);
+        if (mode == 1) {
+            uint32_t *wr = (uint32_t *)holo + (uint64_t)(2 * j) * words;
+            uint32_t *wi = (uint32_t *)holo + (uint64_t)(2 * j + 1) * words;
+            for (uint64_t p = 0; p < n; ++p) {
+                if (hval) {
+                    hval[(uint64_t)(2 * j) * n + p] = h[2 * p];
+                    hval[(uint64_t)(2 * j + 1) * n + p] = h[2 * p + 1];
+                }
+                if (orc_binarise(h[2 * p])) wr[p >> 5] |= 1u << (p & 31);
+                if (orc_binarise(h[2 * p + 1])) wi[p >> 5] |= 1u << (p & 31);
+            }
+        } else {
+            uint8_t *c = (uint8_t *)holo + (uint64_t)j * n;
+            for (uint64_t p = 0; p < n; ++p) {
+                if (hval) {
+                    hval[2 * ((uint64_t)j * n + p)] = h[2 * p];
+                    hval[2 * ((uint64_t)j * n + p) + 1] = h[2 * p + 1];
+                }
+                c[p] = (uint8_t)orc_quant8(h[2 * p], h[2 * p + 1]);
+            }
+        }
+    }
+    free(h);
+    free(ph);
+    double *ib = ibar ? ibar : (double *)malloc(sizeof(double) * n);
+    orc_reconstruct(holo, mode == 1 ? 2 : 8, nx, ny, n_sf, ib);
+    if (nmse2) orc_nmse_pair(ib, T, nx, ny, nmse2);
+    if (!ibar) free(ib);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Gerchberg-Saxton (Section 2; Gerchberg & Saxton 1972) with a phase-only   */
 /* hologram constraint and an amplitude-only replay constraint.              */
 /*   R_0 = T * init/|init|            (init = 0 -> 1)                         */

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libholo.so")
 HOLO_OK, HOLO_EINVAL, HOLO_EUNSUPPORTED, HOLO_ENOMEM, HOLO_EDEVICE = 0, -1, -2, -3, -4
 FP32, BF16, FP16 = 0, 1, 2
 SRC_TABLE, SRC_CODES8, SRC_PRNG, SRC_MSEQ = 0, 1, 2, 3
-F_NMSE_DEVICE = 1
+F_NMSE_DEVICE, F_OSPR_PAIRS, F_OSPR_LEVELS8 = 1, 2, 4
 LUT_FLAT, LUT_NOT_PRIME, LUT_LE_NSF, LUT_LE_MAXDIM, LUT_DIVIDES_FRAME, LUT_LT_FULL = 1, 2, 4, 8, 16, 32
 
 _lib = None
@@ -210,22 +210,39 @@ def _nmse_buf(n, device_out):
     return a, a.ctypes.data_as(C.c_void_p), 0
 
 
+OSPR_MODES = {"binary": 0, "pairs": F_OSPR_PAIRS, "levels8": F_OSPR_LEVELS8}
+
+
+def _holo_buf(mode, n_sf, nx, ny, buf, device):
+    """Output of one frame: packed bits int32 [n_sf, nx*ny/32], or uint8 codes
+    [n_sf, ny, nx] for the eight-level variant."""
+    if mode == "levels8":
+        shape, dt = (n_sf, ny, nx), torch.uint8
+    else:
+        shape, dt = (n_sf, nx * ny // 32), torch.int32
+    if buf is None:
+        buf = torch.empty(shape, dtype=dt, device=device)
+    _dev(buf, dt, shape, "bits")
+    return buf
+
+
 def ospr_generate(target, n_sf: int, lut: Lut, cursor: int, bits=None, recon=None, want_nmse=True,
-                  nmse_out=None, stream=None, precision: int = FP32):
+                  nmse_out=None, stream=None, precision: int = FP32, mode: str = "binary"):
     """holo_ospr_generate.  Returns (bits, nmse2 or None, new_cursor).
-    target: cuda float32 [ny, nx]; bits: cuda int32 [n_sf, nx*ny/32] (allocated
-    if None); recon: cuda float32 [ny, nx] or None; nmse_out: cuda float64 [2]
-    to keep the NMSE on the device (no synchronisation)."""
+    target: cuda float32 [ny, nx]; bits: cuda int32 [n_sf, nx*ny/32] (uint8
+    [n_sf, ny, nx] codes for mode "levels8"; allocated if None); recon: cuda
+    float32 [ny, nx] or None; nmse_out: cuda float64 [2] to keep the NMSE on
+    the device (no synchronisation).  mode: "binary" (the paper's frame),
+    "pairs" (sub-frames 2j, 2j+1 from Re and Im of one field) or "levels8"."""
     ny, nx = target.shape
     _dev(target, torch.float32, None, "target")
-    if bits is None:
-        bits = torch.empty((n_sf, nx * ny // 32), dtype=torch.int32, device=target.device)
-    _dev(bits, torch.int32, (n_sf, nx * ny // 32), "bits")
+    bits = _holo_buf(mode, n_sf, nx, ny, bits, target.device)
     if recon is not None:
         _dev(recon, torch.float32, (ny, nx), "recon")
     nm, nm_p, flags = (None, None, 0)
     if want_nmse or nmse_out is not None:
         nm, nm_p, flags = _nmse_buf(2, nmse_out)
+    flags |= OSPR_MODES[mode]
     cur = C.c_uint64(cursor)
     _check(lib().holo_ospr_generate(_ptr(target), nx, ny, n_sf, lut.handle, C.byref(cur), _ptr(bits),
                                     _ptr(recon), nm_p, precision, flags, _stream(stream)))
@@ -384,21 +401,21 @@ def set_graphs(on: bool):
 
 
 def ospr_generate_batched(targets, n_sfs, lut: Lut, cursor: int, bits=None, recons=None, nmse_out=None,
-                          stream=None, precision: int = FP32):
+                          stream=None, precision: int = FP32, mode: str = "binary"):
     """holo_ospr_generate_batched.  targets: list of cuda float32 [ny, nx];
     n_sfs: list of sub-frame counts; bits: list of int32 [n_sf, nx*ny/32]
-    (allocated if None).  Returns (bits list, nmse [n, 2] or None, cursor).
-    nmse_out: cuda float64 [n, 2] keeps the NMSE on the device."""
+    (uint8 [n_sf, ny, nx] for mode "levels8"; allocated if None).  Returns
+    (bits list, nmse [n, 2] or None, cursor).  nmse_out: cuda float64 [n, 2]
+    keeps the NMSE on the device.  mode as for ospr_generate."""
     import numpy as np
     n = len(targets)
     if bits is None:
-        bits = [torch.empty((k, t.shape[0] * t.shape[1] // 32), dtype=torch.int32, device=t.device)
-                for t, k in zip(targets, n_sfs)]
+        bits = [None] * n
+    bits = [_holo_buf(mode, k, t.shape[1], t.shape[0], b, t.device) for t, k, b in zip(targets, n_sfs, bits)]
     arr = (HoloFrame * n)()
     for i, (t, k, b) in enumerate(zip(targets, n_sfs, bits)):
         _dev(t, torch.float32, None, "target")
         ny, nx = t.shape
-        _dev(b, torch.int32, (k, nx * ny // 32), "bits")
         r = recons[i] if recons is not None else None
         if r is not None:
             _dev(r, torch.float32, (ny, nx), "recon")
@@ -409,6 +426,7 @@ def ospr_generate_batched(targets, n_sfs, lut: Lut, cursor: int, bits=None, reco
     else:
         nm = np.zeros((n, 2))
         nm_p, flags = nm.ctypes.data_as(C.c_void_p), 0
+    flags |= OSPR_MODES[mode]
     cur = C.c_uint64(cursor)
     _check(lib().holo_ospr_generate_batched(C.cast(arr, C.c_void_p), n, lut.handle, C.byref(cur), nm_p,
                                             precision, flags, _stream(stream)))

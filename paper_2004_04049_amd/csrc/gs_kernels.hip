@@ -14,6 +14,7 @@
 // writes the unitary replay field R'_n instead of replacing amplitudes.
 #include "fft_engine.hpp"
 #include "kernels.hpp"
+#include "quant.hpp"
 
 namespace holo {
 
@@ -68,25 +69,6 @@ __device__ __forceinline__ void row_sum(double (&a)[NV], double* red, int T, int
 }
 }  // namespace
 
-// Nearest of the 8 phase levels exp(i*2*pi*m/8) to h, m = round(8*arg(h)/(2*pi))
-// mod 8, decided by comparing |Im| and |Re| against tan(pi/8) without atan2.
-__device__ __forceinline__ uint8_t quant8(float2 h)
-{
-    if (h.x == 0.0f && h.y == 0.0f) return 0;
-    const float t8 = 0.414213562373095049f;   // tan(pi/8)
-    const float ax = fabsf(h.x), ay = fabsf(h.y);
-    int d;                                     // 0: along Re axis, 1: diagonal, 2: along Im axis
-    if (ay < ax * t8) d = 0;
-    else if (ax < ay * t8) d = 2;
-    else d = 1;
-    const bool re_neg = h.x < 0.0f, im_neg = h.y < 0.0f;
-    int m;
-    if (!re_neg && !im_neg) m = d;             // [0, pi/2]
-    else if (re_neg && !im_neg) m = 4 - d;     // (pi/2, pi]
-    else if (re_neg && im_neg) m = 4 + d;      // (pi, 3pi/2)
-    else m = (8 - d) & 7;                      // (3pi/2, 2pi)
-    return (uint8_t)m;
-}
 
 // -------------------------------------------------------------------------
 // Rows pass.  partials layout: [ny][3] = {S_II, S_IT, E} for ITER/FINAL,

@@ -345,24 +345,29 @@ struct OsprLayout {
     int chunk;
 };
 
-OsprLayout ospr_layout(int64_t nx, int64_t ny, int n_sf, const LaunchCfg& cfg)
+// n_fields randomised fields per frame: n_sf, or n_sf/2 in pair mode
+int ospr_fields(int n_sf, int mode) { return mode == OSPR_PAIRS ? n_sf / 2 : n_sf; }
+
+OsprLayout ospr_layout(int64_t nx, int64_t ny, int n_sf, const LaunchCfg& cfg, int mode = OSPR_BINARY)
 {
     OsprLayout l;
     const size_t pitch = (size_t)row_pitch((int)nx, cfg);
     const size_t plane = (size_t)ny * pitch;
-    const size_t nspec = (size_t)(ny / 2 + 1) * pitch;
+    // half spectra of binary sub-frames (Hermitian), full spectra of 8-level ones
+    const size_t nspec = (size_t)(mode == OSPR_LEVELS8 ? ny : ny / 2 + 1) * pitch;
+    const int n_fields = ospr_fields(n_sf, mode);
     // Sub-frames are generated in chunks that reuse one set of intermediate
     // planes, so a chunk's planes can stay in the last-level cache between the
     // row pass that writes them and the column pass that reads them.  (Running
     // chunks concurrently on two streams was measured slower: the doubled
     // working set no longer fits that cache.)
-    l.chunk = (cfg.chunk > 0 && cfg.chunk < n_sf) ? cfg.chunk : n_sf;
+    l.chunk = (cfg.chunk > 0 && cfg.chunk < n_fields) ? cfg.chunk : n_fields;
     Carver cv;
     l.o_x1 = cv.take(sizeof(float2) * plane * l.chunk);
     l.o_x2 = cv.take(sizeof(float2) * nspec * n_sf);
-    l.o_part = cv.take(sizeof(double) * 5 * (size_t)(ny / 2 + 1));
+    l.o_part = cv.take(sizeof(double) * 5 * (size_t)ny);
     l.o_nm = cv.take(sizeof(double) * 2);
-    l.o_rs = cv.take(sizeof(uint32_t) * (size_t)n_sf * (size_t)ny);   // M-sequence row states
+    l.o_rs = cv.take(sizeof(uint32_t) * (size_t)n_fields * (size_t)ny);   // M-sequence row states
     l.bytes = cv.off;
     return l;
 }
@@ -371,47 +376,59 @@ OsprLayout ospr_layout(int64_t nx, int64_t ny, int n_sf, const LaunchCfg& cfg)
 // {NMSE, NMSE_sym} to device `nm_out`.  The frame starts in the pool at
 // c0 + *c0_base (both reduced by lut_wrap; c0_base may be NULL).
 holo_status ospr_enqueue(const float* target, int64_t nx, int64_t ny, int n_sf, const holo_lut* lut, uint64_t c0,
-                         const uint64_t* c0_base, uint32_t* holo_bits, float* recon, double* nm_out,
+                         const uint64_t* c0_base, void* holo_out, float* recon, double* nm_out,
                          const float2* tw_x, const float2* tw_y, char* b, const OsprLayout& l, hipStream_t s,
-                         const LaunchCfg& cfg)
+                         const LaunchCfg& cfg, int mode = OSPR_BINARY)
 {
     const size_t pitch = (size_t)row_pitch((int)nx, cfg);
-    const size_t nspec = (size_t)(ny / 2 + 1) * pitch;
+    const bool half = mode != OSPR_LEVELS8;
+    const size_t nspec = (size_t)(half ? ny / 2 + 1 : ny) * pitch;
+    const int n_fields = ospr_fields(n_sf, mode);
+    uint32_t* holo_bits = (uint32_t*)holo_out;
     float2* x1 = (float2*)(b + l.o_x1);
     float2* x2 = (float2*)(b + l.o_x2);
     double* part = (double*)(b + l.o_part);
     uint32_t* rs = (uint32_t*)(b + l.o_rs);
     const size_t words = (size_t)nx * (size_t)ny / 32;
     if (lut->kind == SRC_MSEQ)
-        LAUNCH("mseq_rows", s, launch_mseq_rows(lut->mseq, c0, c0_base, (int)nx, (int)ny, n_sf, rs, s));
-    for (int k0 = 0; k0 < n_sf; k0 += l.chunk) {
-        const int ns = n_sf - k0 < l.chunk ? n_sf - k0 : l.chunk;
+        LAUNCH("mseq_rows", s, launch_mseq_rows(lut->mseq, c0, c0_base, (int)nx, (int)ny, n_fields, rs, s));
+    for (int k0 = 0; k0 < n_fields; k0 += l.chunk) {
+        const int ns = n_fields - k0 < l.chunk ? n_fields - k0 : l.chunk;
         const uint64_t ck = lut_wrap(lut, c0 + (uint64_t)k0 * (uint64_t)(nx * ny));
         const PhaseSrc src = make_src(lut, rs + (size_t)k0 * (size_t)ny);
         LAUNCH("ospr_rows", s, launch_ospr_rows(target, (int)nx, (int)ny, ns, src, ck, c0_base, x1, tw_x, cfg, s));
-        LAUNCH("ospr_cols", s, launch_ospr_cols(x1, (int)nx, (int)ny, ns, holo_bits + (size_t)k0 * words,
-                                                x2 + (size_t)k0 * nspec, tw_y, cfg, s));
+        if (mode == OSPR_BINARY)
+            LAUNCH("ospr_cols", s, launch_ospr_cols(x1, (int)nx, (int)ny, ns, holo_bits + (size_t)k0 * words,
+                                                    x2 + (size_t)k0 * nspec, tw_y, cfg, s));
+        else if (mode == OSPR_PAIRS)
+            LAUNCH("ospr_cols", s, launch_ospr_cols_mode(mode, x1, (int)nx, (int)ny, ns,
+                                                         holo_bits + (size_t)(2 * k0) * words,
+                                                         x2 + (size_t)(2 * k0) * nspec, tw_y, cfg, s));
+        else
+            LAUNCH("ospr_cols", s, launch_ospr_cols_mode(mode, x1, (int)nx, (int)ny, ns,
+                                                         (uint8_t*)holo_out + (size_t)k0 * (size_t)(nx * ny),
+                                                         x2 + (size_t)k0 * nspec, tw_y, cfg, s));
     }
-    LAUNCH("recon_rows", s, launch_recon_rows(x2, (int)nx, (int)ny, n_sf, true, target, recon, part, tw_x, cfg, s));
-    LAUNCH("nmse_finalize", s, launch_nmse_finalize(part, (int)(ny / 2 + 1), nm_out, s));
+    LAUNCH("recon_rows", s, launch_recon_rows(x2, (int)nx, (int)ny, n_sf, half, target, recon, part, tw_x, cfg, s));
+    LAUNCH("nmse_finalize", s, launch_nmse_finalize(part, (int)(half ? ny / 2 + 1 : ny), nm_out, s));
     return HOLO_OK;
 }
 
 holo_status ospr_run(int device, const float* target, int64_t nx, int64_t ny, int n_sf, const holo_lut* lut,
-                     uint64_t cursor, uint32_t* holo_bits, float* recon, double* nmse2, uint32_t flags,
-                     hipStream_t s, const LaunchCfg& cfg)
+                     uint64_t cursor, void* holo_out, float* recon, double* nmse2, uint32_t flags,
+                     hipStream_t s, const LaunchCfg& cfg, int mode = OSPR_BINARY)
 {
     holo_status st;
     const float2 *tw_x, *tw_y;
     if ((st = get_twiddles(device, (int)nx, s, &tw_x))) return st;
     if ((st = get_twiddles(device, (int)ny, s, &tw_y))) return st;
-    const OsprLayout l = ospr_layout(nx, ny, n_sf, cfg);
+    const OsprLayout l = ospr_layout(nx, ny, n_sf, cfg, mode);
     void* ws;
     if ((st = get_workspace(device, s, l.bytes, &ws))) return st;
     char* b = (char*)ws;
     double* nm = (double*)(b + l.o_nm);
-    if ((st = ospr_enqueue(target, nx, ny, n_sf, lut, lut_wrap(lut, cursor), nullptr, holo_bits, recon, nm, tw_x,
-                           tw_y, b, l, s, cfg)))
+    if ((st = ospr_enqueue(target, nx, ny, n_sf, lut, lut_wrap(lut, cursor), nullptr, holo_out, recon, nm, tw_x,
+                           tw_y, b, l, s, cfg, mode)))
         return st;
     return copy_out(nmse2, nm, 2, flags, s);
 }
@@ -826,12 +843,24 @@ holo_status check_precision(int32_t precision, int64_t nx, int64_t ny)
 }  // namespace
 }  // namespace holo
 
+// OSPR variant selected by the flags (HOLO_EINVAL for both, or an odd n_sf in pair mode).
+holo_status ospr_mode_of(uint32_t flags, int n_sf, int* mode)
+{
+    const bool pairs = flags & HOLO_F_OSPR_PAIRS, l8 = flags & HOLO_F_OSPR_LEVELS8;
+    if (pairs && l8) return fail(HOLO_EINVAL, "HOLO_F_OSPR_PAIRS and HOLO_F_OSPR_LEVELS8 exclude each other");
+    if (pairs && (n_sf & 1)) return fail(HOLO_EINVAL, "pair mode needs an even n_sf (got %d)", n_sf);
+    *mode = pairs ? OSPR_PAIRS : l8 ? OSPR_LEVELS8 : OSPR_BINARY;
+    return HOLO_OK;
+}
+
 holo_status holo_ospr_generate(const float* target, int64_t nx, int64_t ny, int32_t n_sf, const holo_lut* lut,
-                               uint64_t* cursor, uint32_t* holo_bits, float* recon, double* nmse2,
+                               uint64_t* cursor, void* holo_out, float* recon, double* nmse2,
                                int32_t precision, uint32_t flags, void* hip_stream)
 {
-    if (!target || !cursor || !holo_bits) return fail(HOLO_EINVAL, "target, cursor and holo_bits are required");
+    if (!target || !cursor || !holo_out) return fail(HOLO_EINVAL, "target, cursor and holo_out are required");
     if (n_sf < 1) return fail(HOLO_EINVAL, "n_sf must be >= 1 (got %d)", n_sf);
+    int mode = OSPR_BINARY;
+    if (holo_status e = ospr_mode_of(flags, n_sf, &mode)) return e;
     if (!pow2_in_range(nx) || !pow2_in_range(ny))
         return fail(HOLO_EUNSUPPORTED, "nx, ny must be powers of two in [16, 2048] (got %lld x %lld)",
                     (long long)nx, (long long)ny);
@@ -843,10 +872,10 @@ holo_status holo_ospr_generate(const float* target, int64_t nx, int64_t ny, int3
     LaunchCfg cfg = plan_get(PLAN_OSPR, nx, ny, n_sf);
     cfg.prec = precision;
     if (precision && (st = get_dftop(device, precision, (hipStream_t)hip_stream, &cfg.dftop))) return st;
-    if ((st = ospr_run(device, target, nx, ny, n_sf, lut, *cursor, holo_bits, recon, nmse2, flags,
-                       (hipStream_t)hip_stream, cfg)))
+    if ((st = ospr_run(device, target, nx, ny, n_sf, lut, *cursor, holo_out, recon, nmse2, flags,
+                       (hipStream_t)hip_stream, cfg, mode)))
         return st;
-    *cursor += (uint64_t)n_sf * (uint64_t)nx * (uint64_t)ny;
+    *cursor += (uint64_t)ospr_fields(n_sf, mode) * (uint64_t)nx * (uint64_t)ny;
     return HOLO_OK;
 }
 
@@ -963,10 +992,12 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
 {
     if (!frames || !cursor) return fail(HOLO_EINVAL, "frames and cursor are required");
     if (n_frames < 1 || n_frames > 4096) return fail(HOLO_EINVAL, "n_frames must be in [1, 4096] (got %d)", n_frames);
+    int mode = OSPR_BINARY;
     for (int f = 0; f < n_frames; ++f) {
         const holo_frame& fr = frames[f];
         if (!fr.target || !fr.holo_bits) return fail(HOLO_EINVAL, "frame %d: target and holo_bits are required", f);
         if (fr.n_sf < 1) return fail(HOLO_EINVAL, "frame %d: n_sf must be >= 1", f);
+        if (holo_status e = ospr_mode_of(flags, fr.n_sf, &mode)) return e;
         if (!pow2_in_range(fr.nx) || !pow2_in_range(fr.ny))
             return fail(HOLO_EUNSUPPORTED, "frame %d: nx, ny must be powers of two in [16, 2048]", f);
         if (holo_status e = check_precision(precision, fr.nx, fr.ny)) return e;
@@ -989,9 +1020,9 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
         cfg[f] = plan_get(PLAN_OSPR, fr.nx, fr.ny, fr.n_sf);
         cfg[f].prec = precision;
         cfg[f].dftop = dftop;
-        lay[f] = ospr_layout(fr.nx, fr.ny, fr.n_sf, cfg[f]);
+        lay[f] = ospr_layout(fr.nx, fr.ny, fr.n_sf, cfg[f], mode);
         off[f] = total;
-        total += (uint64_t)fr.n_sf * (uint64_t)fr.nx * (uint64_t)fr.ny;
+        total += (uint64_t)ospr_fields(fr.n_sf, mode) * (uint64_t)fr.nx * (uint64_t)fr.ny;
     }
     // frames to branches: longest first onto the least-loaded branch
     const int nb = n_frames < kBranches ? n_frames : kBranches;
@@ -1040,9 +1071,9 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
         for (int f = 0; f < n_frames; ++f) {
             const holo_frame& fr = frames[f];
             hipStream_t fs = branches ? bs->br[branch[f]] : s;
-            holo_status e = ospr_enqueue(fr.target, fr.nx, fr.ny, fr.n_sf, lut, lut_wrap(lut, off[f]), dbase, fr.holo_bits,
-                                         fr.recon, nm + 2 * f, tw[(int)fr.nx], tw[(int)fr.ny],
-                                         b + o_branch[branch[f]], lay[f], fs, cfg[f]);
+            holo_status e = ospr_enqueue(fr.target, fr.nx, fr.ny, fr.n_sf, lut, lut_wrap(lut, off[f]), dbase,
+                                         fr.holo_bits, fr.recon, nm + 2 * f, tw[(int)fr.nx], tw[(int)fr.ny],
+                                         b + o_branch[branch[f]], lay[f], fs, cfg[f], mode);
             if (e) return e;
         }
         return HOLO_OK;
@@ -1059,7 +1090,7 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
         if ((st = get_batch_sync(device, &bs))) return st;
         GraphKey key;
         key.k = {(uintptr_t)0xBA7C, (uintptr_t)device, (uintptr_t)s, (uintptr_t)ws, (uintptr_t)lut->id,
-                 (uintptr_t)n_frames};
+                 (uintptr_t)n_frames, (uintptr_t)mode};
         for (int f = 0; f < n_frames; ++f) {
             const holo_frame& fr = frames[f];
             const LaunchCfg& c = cfg[f];

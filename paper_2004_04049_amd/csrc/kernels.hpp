@@ -68,6 +68,12 @@ hipError_t launch_phase_mask(const PhaseSrc& src, uint64_t c0, int nx, int ny, i
 // of the +-1 column, half spectrum (rows 0..ny/2) out.
 hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
                             const float2* tw_y, const LaunchCfg& cfg, hipStream_t s);
+// K2 variants: mode OSPR_PAIRS writes sub-frames 2j (Re H) and 2j+1 (Im H) of
+// each of the n_fields fields (bits, half spectra); mode OSPR_LEVELS8 writes
+// 8-level codes (uint8 [n_fields][ny*nx]) and full column spectra.
+enum OsprMode { OSPR_BINARY = 0, OSPR_PAIRS = 1, OSPR_LEVELS8 = 2 };
+hipError_t launch_ospr_cols_mode(int mode, const float2* x1, int nx, int ny, int n_fields, void* holo, float2* x2,
+                                 const float2* tw_y, const LaunchCfg& cfg, hipStream_t s);
 // Reconstruction column transform straight from a quantised hologram:
 // levels 2 (packed bits -> half spectrum) or 8 (codes -> full spectrum).
 hipError_t launch_recon_cols(const void* holo, int levels, int nx, int ny, int n_sf, float2* x2,

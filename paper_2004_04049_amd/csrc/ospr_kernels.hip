@@ -18,6 +18,7 @@
 #include "fft_engine.hpp"
 #include "kernels.hpp"
 #include "mfma_dft.hpp"
+#include "quant.hpp"
 
 namespace holo {
 
@@ -399,24 +400,162 @@ hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t
 }
 
 // -------------------------------------------------------------------------
+// K2 variants (not from the paper).
+//
+// Pairs: field j of the chunk gives sub-frames 2j (from Re H) and 2j+1 (from
+// Im H).  Both +-1 columns go through one forward transform as
+// Z = F{B_re + i B_im}; B_re, B_im are real, so per column their spectra are
+// F_re(v) = (Z(v) + conj Z(-v)) / 2 and F_im(v) = (Z(v) - conj Z(-v)) / (2i),
+// and each is written as the usual half spectrum: the reconstruction passes
+// see 2*n_fields ordinary binary sub-frames.  Row -v of column c sits in
+// thread T - t, slot 15 - m (thread 0: slot (16 - m) mod 16); the exchange
+// goes through LDS.
+//
+// Eight levels: sub-frame k is quantised to the nearest of exp(i*2*pi*m/8)
+// (codes, one byte per pixel), and the full column spectrum of its phasors is
+// written (the hologram is complex, its spectrum not Hermitian).
+// -------------------------------------------------------------------------
+template <int NY, int C, int P>
+__global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols_pair(const float2* __restrict__ x1, int nx,
+                                                                 uint32_t* __restrict__ bits,
+                                                                 float2* __restrict__ x2,
+                                                                 const float2* __restrict__ tw, int pitch,
+                                                                 const uint4* __restrict__ dftop)
+{
+    extern __shared__ float2 lds[];
+    constexpr int T = NY / kP;
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int lane = threadIdx.x & 63;
+    const int ncb = nx / C;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int j = tile / ncb;
+    const int x0 = (tile - j * ncb) * C;
+    const size_t npix = (size_t)nx * NY;
+    const size_t plane = (size_t)NY * pitch;
+    const uint32_t voff = ((uint32_t)t * (uint32_t)pitch + (uint32_t)(x0 + c)) * 8u;
+    const uint32_t mst = (uint32_t)T * (uint32_t)pitch * 8u;
+    const auto rin = make_rsrc(x1 + (size_t)j * plane, (uint32_t)(plane * 8));
+    float2 v[kP];
+#pragma unroll
+    for (int m = 0; m < kP; ++m) v[m] = buf_ld2(rin, voff, m * mst);
+    fft_any<NY, 1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
+
+    // nearest of {+1, -1} for Re H (sub-frame 2j) and Im H (sub-frame 2j+1)
+    const auto rb_re = make_rsrc(bits + (size_t)(2 * j) * (npix / 32), (uint32_t)(npix / 8));
+    const auto rb_im = make_rsrc(bits + (size_t)(2 * j + 1) * (npix / 32), (uint32_t)(npix / 8));
+    const uint32_t boff = ((uint32_t)t * (uint32_t)nx + (uint32_t)x0) / 8u;
+    const uint32_t bst = (uint32_t)T * (uint32_t)nx / 8u;
+#pragma unroll
+    for (int m = 0; m < kP; ++m) {
+        const bool nre = v[m].x < 0.0f, nim = v[m].y < 0.0f;
+        const uint64_t mre = __ballot(nre), mim = __ballot(nim);
+        if (c == 0) {
+            const uint32_t cre = (uint32_t)(mre >> (lane & ~(C - 1))), cim = (uint32_t)(mim >> (lane & ~(C - 1)));
+            if (C == 16) {
+                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)cre, rb_re, boff, m * bst, 0);
+                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)cim, rb_im, boff, m * bst, 0);
+            } else {
+                __builtin_amdgcn_raw_buffer_store_b8((unsigned char)cre, rb_re, boff, m * bst, 0);
+                __builtin_amdgcn_raw_buffer_store_b8((unsigned char)cim, rb_im, boff, m * bst, 0);
+            }
+        }
+        v[m] = make_float2(nre ? -1.0f : 1.0f, nim ? -1.0f : 1.0f);
+    }
+    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
+
+    // mirror rows through LDS (plain [row][C] layout; the engine is done with it)
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kP; ++m) lds[(t + T * m) * C + c] = v[m];
+    __syncthreads();
+    float2 fre[kP / 2 + 1], fim[kP / 2 + 1];
+#pragma unroll
+    for (int m = 0; m <= kP / 2; ++m) {
+        const int row = t + T * m;
+        const float2 z = v[m];
+        const float2 zm = lds[((NY - row) & (NY - 1)) * C + c];
+        fre[m] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));   // (Z + conj Zm) / 2
+        fim[m] = make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x));   // (Z - conj Zm) / (2i)
+    }
+    // rows v = t + T*m <= NY/2: every slot m < 8, and m = 8 for t = 0 only
+    const size_t hplane = (size_t)(NY / 2 + 1) * pitch;
+    const auto rre = make_rsrc(x2 + (size_t)(2 * j) * hplane, (uint32_t)(hplane * 8));
+    const auto rim = make_rsrc(x2 + (size_t)(2 * j + 1) * hplane, (uint32_t)(hplane * 8));
+#pragma unroll
+    for (int m = 0; m < kP / 2; ++m) {
+        buf_st2(rre, voff, m * mst, fre[m]);
+        buf_st2(rim, voff, m * mst, fim[m]);
+    }
+    if (t == 0) {
+        buf_st2(rre, voff, (kP / 2) * mst, fre[kP / 2]);
+        buf_st2(rim, voff, (kP / 2) * mst, fim[kP / 2]);
+    }
+}
+
+template <int NY, int C, int P>
+__global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols_l8(const float2* __restrict__ x1, int nx,
+                                                               uint8_t* __restrict__ codes,
+                                                               float2* __restrict__ x2,
+                                                               const float2* __restrict__ tw, int pitch,
+                                                               const uint4* __restrict__ dftop)
+{
+    extern __shared__ float2 lds[];
+    constexpr int T = NY / kP;
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int ncb = nx / C;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = tile / ncb;
+    const int x0 = (tile - k * ncb) * C;
+    const size_t npix = (size_t)nx * NY;
+    const size_t plane = (size_t)NY * pitch;
+    const uint32_t voff = ((uint32_t)t * (uint32_t)pitch + (uint32_t)(x0 + c)) * 8u;
+    const uint32_t mst = (uint32_t)T * (uint32_t)pitch * 8u;
+    const auto rin = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
+    float2 v[kP];
+#pragma unroll
+    for (int m = 0; m < kP; ++m) v[m] = buf_ld2(rin, voff, m * mst);
+    fft_any<NY, 1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
+    const auto rc = make_rsrc(codes + (size_t)k * npix, (uint32_t)npix);
+    const uint32_t coff = (uint32_t)t * (uint32_t)nx + (uint32_t)(x0 + c);
+#pragma unroll
+    for (int m = 0; m < kP; ++m) {
+        const uint8_t q = quant8(v[m]);
+        __builtin_amdgcn_raw_buffer_store_b8((unsigned char)q, rc, coff, (uint32_t)(m * T * nx), 0);
+        v[m] = level8_phasor(q);
+    }
+    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
+    const auto rout = make_rsrc(x2 + (size_t)k * plane, (uint32_t)(plane * 8));
+#pragma unroll
+    for (int m = 0; m < kP; ++m) buf_st2(rout, voff, m * mst, v[m]);
+}
+
+hipError_t launch_ospr_cols_mode(int mode, const float2* x1, int nx, int ny, int n_fields, void* holo, float2* x2,
+                                 const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
+{
+    const int C = cfg.prec ? 8 : col_block_cols(ny, nx, n_fields, cfg.cols_per_block, 8);
+    HOLO_SWITCH_NP(ny, cfg.prec, HOLO_SWITCH_C816(C, {
+        constexpr int T = N_ / kP;
+        if (C_ * T <= 1024) {
+            size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
+            if (mode == OSPR_PAIRS) {
+                allow_lds(k_ospr_cols_pair<N_, C_, P_>, lds);
+                hipLaunchKernelGGL((k_ospr_cols_pair<N_, C_, P_>), dim3((nx / C_) * n_fields), dim3(C_ * T), lds, s,
+                                   x1, nx, (uint32_t*)holo, x2, tw_y, row_pitch(nx, cfg), DFTOP(cfg));
+            } else {
+                allow_lds(k_ospr_cols_l8<N_, C_, P_>, lds);
+                hipLaunchKernelGGL((k_ospr_cols_l8<N_, C_, P_>), dim3((nx / C_) * n_fields), dim3(C_ * T), lds, s,
+                                   x1, nx, (uint8_t*)holo, x2, tw_y, row_pitch(nx, cfg), DFTOP(cfg));
+            }
+        }
+    }));
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------
 // Reconstruction column transform from a quantised hologram.
 //   levels 2: packed bits -> B = +-1 -> rows 0..ny/2 of its column spectrum
 //   levels 8: codes m -> exp(i*2*pi*m/8) -> full column spectrum
 // -------------------------------------------------------------------------
-__device__ __forceinline__ float2 level8_phasor(int m)
-{
-    const float h = 0.707106781186547524f;
-    switch (m & 7) {
-        case 0: return make_float2(1.0f, 0.0f);
-        case 1: return make_float2(h, h);
-        case 2: return make_float2(0.0f, 1.0f);
-        case 3: return make_float2(-h, h);
-        case 4: return make_float2(-1.0f, 0.0f);
-        case 5: return make_float2(-h, -h);
-        case 6: return make_float2(0.0f, -1.0f);
-        default: return make_float2(h, -h);
-    }
-}
 
 template <int NY, int C, int P>
 __global__ __launch_bounds__(C * (NY / kP)) void k_recon_cols(const void* __restrict__ holo, int levels, int nx,
