@@ -186,11 +186,15 @@ def main():
     }
 
     if not args.no_extras:
-        out["batched"] = bench_batched(h, synth, torch, dev)
-        out["gs"] = bench_gs(h, synth, torch, dev)
-        out["lut_sweep"] = bench_lut_sweep(h, synth, torch, dev, target, nx, ny, n_sf)
-        out["phase_sources"] = bench_phase_sources(h, synth, torch, dev, target, nx, ny, n_sf)
-        out["cnn_seed"] = bench_cnn(h, synth, torch, dev, args)
+        def leg(name, f):
+            print(f"bench: {name}", file=sys.stderr, flush=True)   # progress (stdout keeps the one JSON line)
+            out[name] = f()
+        leg("batched", lambda: bench_batched(h, synth, torch, dev))
+        leg("gs", lambda: bench_gs(h, synth, torch, dev))
+        leg("lut_sweep", lambda: bench_lut_sweep(h, synth, torch, dev, target, nx, ny, n_sf))
+        leg("phase_sources", lambda: bench_phase_sources(h, synth, torch, dev, target, nx, ny, n_sf))
+        leg("ospr_variants", lambda: bench_ospr_variants(h, synth, torch, dev, target, nx, ny, n_sf, lut))
+        leg("cnn_seed", lambda: bench_cnn(h, synth, torch, dev, args))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(synth, nx, ny, n_lut)
     if args.calib:
@@ -405,6 +409,49 @@ def bench_phase_sources(h, synth, torch, dev, target, nx, ny, n_sf, steps=50):
             row["phasor_vs_table_max"] = d
         res.append(row)
         lut.close()
+    return res
+
+
+def bench_ospr_variants(h, synth, torch, dev, target, nx, ny, n_sf, lut, steps=50):
+    """The binary frame against the two variants on the headline workload:
+    pairs (sub-frames 2j, 2j+1 from Re and Im of one field: half the row
+    passes and inverse column transforms) and eight phase levels.  Per mode:
+    sub-frames/s (best of three loops), per-kernel averages, the NMSE pair of
+    the frame at cursor 0, and the NMSE pair on a non-repeating pool."""
+    res = []
+    nm_dev = torch.empty(2, dtype=torch.float64, device=dev)
+    nonrep = h.Lut.prng(synth.SEED_LUT)
+    for mode in ("binary", "pairs", "levels8"):
+        bits = None
+        bits, nm, c = h.ospr_generate(target, n_sf, lut, 0, mode=mode)
+        for _ in range(3):
+            _, _, c = h.ospr_generate(target, n_sf, lut, c, bits=bits, want_nmse=False, nmse_out=nm_dev, mode=mode)
+        torch.cuda.synchronize()
+        dt = float("inf")
+        for _ in range(3):
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, _, c = h.ospr_generate(target, n_sf, lut, c, bits=bits, want_nmse=False, nmse_out=nm_dev,
+                                          mode=mode)
+            torch.cuda.synchronize()
+            dt = min(dt, (time.perf_counter() - t0) / steps)
+        h.prof_reset()
+        h.prof_enable(True)
+        for _ in range(10):
+            _, _, c = h.ospr_generate(target, n_sf, lut, c, bits=bits, want_nmse=False, nmse_out=nm_dev, mode=mode)
+        torch.cuda.synchronize()
+        h.prof_enable(False)
+        kern = {}
+        for k in ("ospr_rows", "ospr_cols", "recon_rows", "nmse_finalize"):
+            ms, cnt = h.prof_read(k)
+            if cnt:
+                kern[k] = {"avg_us": round(1e3 * ms / cnt, 2), "per_frame": cnt // 10}
+        # quality on a non-repeating pool (the headline table divides the
+        # frame, so all its fields repeat and the modes would differ in that)
+        _, nm_nr, _ = h.ospr_generate(target, n_sf, nonrep, 0, mode=mode)
+        res.append({"mode": mode, "subframes_per_s": round(n_sf / dt, 1), "ms_per_frame": round(1e3 * dt, 4),
+                    "kernels": kern, "nmse": float(nm[0]), "nmse_sym": float(nm[1]),
+                    "nmse_nonrepeating": [float(nm_nr[0]), float(nm_nr[1])]})
     return res
 
 
