@@ -426,11 +426,13 @@ holo_status ospr_run(int device, const float* target, int64_t nx, int64_t ny, in
     void* ws;
     if ((st = get_workspace(device, s, l.bytes, &ws))) return st;
     char* b = (char*)ws;
-    double* nm = (double*)(b + l.o_nm);
+    // a device destination takes the result straight from the kernel
+    const bool direct = nmse2 && (flags & HOLO_F_NMSE_DEVICE);
+    double* nm = direct ? nmse2 : (double*)(b + l.o_nm);
     if ((st = ospr_enqueue(target, nx, ny, n_sf, lut, lut_wrap(lut, cursor), nullptr, holo_out, recon, nm, tw_x,
                            tw_y, b, l, s, cfg, mode)))
         return st;
-    return copy_out(nmse2, nm, 2, flags, s);
+    return direct ? HOLO_OK : copy_out(nmse2, nm, 2, flags, s);
 }
 
 // ---------------------------------------------------------------------------
