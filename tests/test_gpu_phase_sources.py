@@ -176,3 +176,39 @@ def test_gs_seeded_per_source_matches_oracle(holo, orc, kind):
     phi = _oracle_phases(orc, kind, cursor, nx * ny).reshape(ny, nx)
     ref = orc.gs(target, n_iter, np.exp(1j * phi))
     np.testing.assert_allclose(nm, ref["nmse"], rtol=1e-4)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("prec", [1, 2])
+def test_sources_on_matrix_core_row_pass(holo, kind, prec):
+    # the phase fetch is the same code in the BF16/FP16 row pass (its code
+    # tables sit after the matrix-core LDS rows): same pool positions, so the
+    # frame differs from the FP32 one only by the stage rounding (< 2u*sqrt(S))
+    nx, ny, nsf, cursor = 256, 256, 4, 7777
+    u = {1: 2.0 ** -8, 2: 2.0 ** -11}[prec]
+    t = torch.from_numpy(synth.blob_target(nx, ny, 4500)).cuda()
+    lut = _make(holo, kind)
+    b32, nm32, c32 = holo.ospr_generate(t, nsf, lut, cursor)
+    bl, nml, cl = holo.ospr_generate(t, nsf, lut, cursor, precision=prec)
+    assert c32 == cl
+    frac = float((holo.unpack_bits(b32, nx * ny) != holo.unpack_bits(bl, nx * ny)).mean())
+    assert 0 < frac < 2 * u * np.sqrt(4)
+    np.testing.assert_allclose(nml, nm32, rtol=2e-2)
+
+
+@pytest.mark.parametrize("kind", ["prng", "mseq"])
+@pytest.mark.parametrize("pts", [4, 8, 16])
+def test_gs_seed_per_points_per_thread(holo, orc, kind, pts):
+    # GS rows with 4/8/16 points per thread: thread strides 256/128/64 at
+    # 1024 wide, i.e. the M-sequence's larger jump tables
+    nx, ny, n_iter, cursor = 1024, 64, 3, 99
+    target = synth.blob_target(nx, ny, 4600)
+    lut = _make(holo, kind)
+    holo.plan_set(holo.PLAN_GS, nx, ny, 1, [0, 0, 0, 0, -1, 0, pts])
+    try:
+        r = holo.gs_iterate(torch.from_numpy(target).cuda(), n_iter, lut, cursor)
+    finally:
+        holo.plan_set(holo.PLAN_GS, nx, ny, 1, [0, 0, 0, 0, -1, 0, 0])
+    phi = _oracle_phases(orc, kind, cursor, nx * ny).reshape(ny, nx)
+    ref = orc.gs(target, n_iter, np.exp(1j * phi))
+    np.testing.assert_allclose(r["nmse"], ref["nmse"], rtol=1e-4)
