@@ -455,22 +455,57 @@ def bench_ospr_variants(h, synth, torch, dev, target, nx, ny, n_sf, lut, steps=5
     return res
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(synth, nx, ny, n_lut):
     """The FP64 oracle, as it stands, on a bounded sample of the workload: the
-    same target, LUT and frame size, 4 frames of 24 sub-frames."""
+    same target, LUT and frame size, 4 frames of 24 sub-frames on all host
+    threads, and one frame on one thread; beside it, as context only, the
+    transforms alone (torch.fft on the CPU, complex64, all threads)."""
     import oracle
+    import torch
     t = synth.blob_target(nx, ny, synth.SEED_OSPR_1024)
     phi = oracle.lut_phases(n_lut, synth.SEED_LUT)
-    frames, n_sf = 4, 24
-    cursor = 0
+    n_sf = 24
+
+    def run(frames):
+        cursor = 0
+        t0 = time.perf_counter()
+        for _ in range(frames):
+            oracle.ospr(t, n_sf, phi, n_lut, cursor, want_reh=False, want_ibar=False)
+            cursor += n_sf * nx * ny
+        return time.perf_counter() - t0
+
+    threads = oracle.num_threads()
+    frames = 4
+    dt = run(frames)
+    oracle.set_threads(1)
+    dt1 = run(1)
+    oracle.set_threads(threads)
+    # two 2D transforms per sub-frame (generation and replay)
+    x = torch.from_numpy(t).to(torch.complex64)
+    torch.fft.fft2(torch.fft.ifft2(x))   # plan creation outside the timing
     t0 = time.perf_counter()
-    for _ in range(frames):
-        oracle.ospr(t, n_sf, phi, n_lut, cursor, want_reh=False, want_ibar=False)
-        cursor += n_sf * nx * ny
-    dt = time.perf_counter() - t0
-    return {"value": round(frames * n_sf / dt, 3), "unit": "sub-frames/s", "cores": oracle.num_threads(),
+    for _ in range(n_sf):
+        torch.fft.fft2(torch.fft.ifft2(x))
+    dt_fft = time.perf_counter() - t0
+    return {"value": round(frames * n_sf / dt, 3), "unit": "sub-frames/s", "cores": threads,
             "kind": "oracle", "sample": f"{frames} frames x {n_sf} sub-frames at {nx}x{ny}, LUT {n_lut}, "
-                                        f"{dt:.1f} s"}
+                                        f"{dt:.1f} s",
+            "single_thread": {"value": round(n_sf / dt1, 3), "unit": "sub-frames/s",
+                              "sample": f"1 frame x {n_sf} sub-frames, {dt1:.1f} s"},
+            "torch_fft_context": {"value": round(n_sf / dt_fft, 3), "unit": "sub-frames/s (transforms only)",
+                                  "threads": torch.get_num_threads()},
+            "host": {"cpu_model": cpu_model(), "nproc": os.cpu_count()}}
 
 
 if __name__ == "__main__":

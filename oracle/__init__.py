@@ -61,6 +61,7 @@ def _load():
         "orc_gs": (None, [P, i64, i64, i32, P, P, P, P, P, P]),
         "orc_ospr_mode": (None, [P, i64, i64, i32, P, u64, u64, i32, P, P, P, P]),
         "orc_num_threads": (i32, []),
+        "orc_set_threads": (None, [i32]),
         "orc_splitmix64_at": (u64, [u64, u64]),
         "orc_prng_phases": (None, [u64, u64, u64, P]),
         "orc_codes8_phases": (None, [u64, u64, P]),
@@ -86,6 +87,11 @@ def _load():
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's loops (scheduling only; results do not change)."""
+    _load().orc_set_threads(n)
 
 
 def _p(a):

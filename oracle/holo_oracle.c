@@ -442,10 +442,13 @@ void orc_gs(const float *T, int64_t nx, int64_t ny, int n_iter, const double *in
     free(r); free(h); free(t2); free(iv);
 }
 
-/* Threads the OpenMP loops above use (reported with CPU timings). */
+/* Threads the OpenMP loops above use (reported with CPU timings); setting
+ * them changes scheduling only, never a result. */
 #ifdef _OPENMP
 #include <omp.h>
 int orc_num_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 #else
 int orc_num_threads(void) { return 1; }
+void orc_set_threads(int n) { (void)n; }
 #endif
