@@ -30,6 +30,7 @@ struct CnnBuffers {
     float *params, *m, *v, *grad;
     uint16_t* wf[3];   // forward weights of layers 2..4, [co][t][ci]
     uint16_t* wt[3];   // backward-data weights, [ci][8-t][co]
+    uint32_t* w5;      // layer-5 weights as BF16 pairs, [t][ci/2][co]
     int off[5];
     // per-image activations (sized for the largest image seen)
     uint16_t* act[4];  // post-ReLU layers 1..4, [ny][nx][32] BF16

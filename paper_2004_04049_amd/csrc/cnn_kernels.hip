@@ -46,11 +46,11 @@ __global__ __launch_bounds__(256) void k_conv1(const float* __restrict__ target,
                                                const float* __restrict__ b, uint16_t* __restrict__ out)
 {
     __shared__ float ws[32 * 9 + 32];
+    __shared__ __attribute__((aligned(16))) uint16_t stage[256 * 40];
     for (int i = threadIdx.x; i < 32 * 9; i += blockDim.x) ws[i] = bfround(w[i]);
     if (threadIdx.x < 32) ws[32 * 9 + threadIdx.x] = b[threadIdx.x];
     __syncthreads();
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nx * ny) return;
+    const int p = min(blockIdx.x * blockDim.x + threadIdx.x, nx * ny - 1);   // tail lanes recompute the last pixel
     const int y = p / nx, x = p - y * nx;
     float v[9];
 #pragma unroll
@@ -66,7 +66,10 @@ __global__ __launch_bounds__(256) void k_conv1(const float* __restrict__ target,
         for (int t = 0; t < 9; ++t) a = fmaf(ws[co * 9 + t], v[t], a);
         o[co] = f2bf(a > 0.0f ? a : 0.0f);
     }
-    uint4* dst = reinterpret_cast<uint4*>(out + (size_t)p * 32);
+    // the block's 256 pixels are one contiguous 16 KiB run of the output: stage
+    // each pixel's 64 bytes in LDS (80-byte pitch against bank conflicts), then
+    // store 16-byte words at consecutive addresses
+    uint4* sp = reinterpret_cast<uint4*>(stage + threadIdx.x * 40);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         uint4 u;
@@ -74,7 +77,16 @@ __global__ __launch_bounds__(256) void k_conv1(const float* __restrict__ target,
         u.y = o[8 * q + 2] | ((uint32_t)o[8 * q + 3] << 16);
         u.z = o[8 * q + 4] | ((uint32_t)o[8 * q + 5] << 16);
         u.w = o[8 * q + 6] | ((uint32_t)o[8 * q + 7] << 16);
-        dst[q] = u;
+        sp[q] = u;
+    }
+    __syncthreads();
+    const int p0 = blockIdx.x * blockDim.x;
+    const int npx = nx * ny - p0 < (int)blockDim.x ? nx * ny - p0 : (int)blockDim.x;   // pixels in this block
+    uint4* dst = reinterpret_cast<uint4*>(out + (size_t)p0 * 32);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int w = q * (int)blockDim.x + threadIdx.x;   // 16-byte word of the run
+        if (w < npx * 4) dst[w] = *reinterpret_cast<const uint4*>(stage + (w >> 2) * 40 + (w & 3) * 8);
     }
 }
 
@@ -175,37 +187,83 @@ __global__ __launch_bounds__(256) void k_conv32(const uint16_t* __restrict__ in,
 // ---------------------------------------------------------------------------
 // Layer 5 (32 -> 2), VALU, and the phasor normalisation p = o/|o|.
 // ---------------------------------------------------------------------------
+// 32 -> 2 output layer.  Block = up to 512 pixels: a tile of R = min(512/W,
+// ny) rows x W pixels (W = min(nx, 64)), two vertically adjacent pixels per
+// thread, whose
+// halo [R+2][W+2][32 ch] is staged in LDS with coalesced 16-byte loads; a
+// thread reads the 4 x 3 neighbourhood its two pixels share from LDS.
+// Activations and weights are both BF16, so each pair of input channels is one
+// v_dot2 (two exact products accumulated in FP32); the weights, packed as BF16
+// pairs by k_pack5 in [tap][ci/2][co] order, are read with block-uniform
+// addresses (scalar loads).
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+constexpr int kC5Px = 512;                          // pixels per block
 __global__ __launch_bounds__(256) void k_conv5(const uint16_t* __restrict__ in, int ny, int nx,
-                                               const float* __restrict__ w /* [2][32][9] */,
+                                               const uint32_t* __restrict__ w5 /* [9][16][2] BF16 pairs */,
                                                const float* __restrict__ b, float2* __restrict__ o5,
                                                float2* __restrict__ phasor)
 {
-    __shared__ float ws[2 * 32 * 9];
-    for (int j = threadIdx.x; j < 2 * 32 * 9; j += blockDim.x) ws[j] = bfround(w[j]);
+    __shared__ __attribute__((aligned(16))) uint16_t tile[660 * 32];   // (R+2)(W+2) <= 660 pixels
+    const int W = nx < 64 ? nx : 64, R = kC5Px / W < ny ? kC5Px / W : ny;   // launcher: same W, R
+    const int nseg = nx / W;
+    const int x0 = (blockIdx.x % nseg) * W, y0 = (blockIdx.x / nseg) * R;
+    const int hw = W + 2, nchunk = (R + 2) * hw * 4;
+    for (int j = threadIdx.x; j < nchunk; j += blockDim.x) {
+        const int pix = j >> 2, part = j & 3;
+        const int ty = pix / hw, tx = pix - ty * hw;
+        const int gy = (y0 + ty - 1 + ny) & (ny - 1), gx = (x0 + tx - 1 + nx) & (nx - 1);
+        reinterpret_cast<uint4*>(tile)[j] =
+            reinterpret_cast<const uint4*>(in + ((size_t)gy * nx + gx) * 32)[part];
+    }
     __syncthreads();
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nx * ny) return;
-    const int y = p / nx, x = p - y * nx;
-    float a0 = b[0], a1 = b[1];
-    for (int t = 0; t < 9; ++t) {
-        const int yy = (y + t / 3 - 1 + ny) & (ny - 1), xx = (x + t % 3 - 1 + nx) & (nx - 1);
-        const uint4* src = reinterpret_cast<const uint4*>(in + ((size_t)yy * nx + xx) * 32);
+    const int r2 = threadIdx.x / W, c = threadIdx.x - r2 * W;   // pixels at tile rows 2*r2, 2*r2 + 1
+    if (2 * r2 >= R) return;                                    // a tile smaller than 512 pixels
+    float a0 = b[0], a1 = b[1], b0 = b[0], b1 = b[1];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint4 u = src[q];
-            const uint32_t wds[4] = {u.x, u.y, u.z, u.w};
+    for (int hr = 0; hr < 4; ++hr) {        // halo row 2*r2 + hr: tap row hr of pixel A, hr - 1 of pixel B
 #pragma unroll
-            for (int h = 0; h < 8; ++h) {
-                const float v = bf2f((uint16_t)(wds[h >> 1] >> (16 * (h & 1))));
-                const int ci = 8 * q + h;
-                a0 = fmaf(ws[(0 * 32 + ci) * 9 + t], v, a0);
-                a1 = fmaf(ws[(1 * 32 + ci) * 9 + t], v, a1);
+        for (int dx = 0; dx < 3; ++dx) {
+            const uint4* src = reinterpret_cast<const uint4*>(tile + ((2 * r2 + hr) * hw + c + dx) * 32);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint4 u = src[q];
+                const uint32_t wds[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {   // channels 8q + 2k, 8q + 2k + 1
+                    const bf16x2_t v = __builtin_bit_cast(bf16x2_t, wds[k]);
+                    if (hr < 3) {
+                        const int pr = (hr * 3 + dx) * 16 + 4 * q + k;
+                        a0 = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, w5[pr * 2]), v, a0, false);
+                        a1 = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, w5[pr * 2 + 1]), v, a1,
+                                                             false);
+                    }
+                    if (hr > 0) {
+                        const int pr = ((hr - 1) * 3 + dx) * 16 + 4 * q + k;
+                        b0 = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, w5[pr * 2]), v, b0, false);
+                        b1 = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, w5[pr * 2 + 1]), v, b1,
+                                                             false);
+                    }
+                }
             }
         }
     }
-    o5[p] = make_float2(a0, a1);
-    const float m = sqrtf(a0 * a0 + a1 * a1);
-    phasor[p] = m > 0.0f ? make_float2(a0 / m, a1 / m) : make_float2(1.0f, 0.0f);
+    const size_t pa = (size_t)(y0 + 2 * r2) * nx + x0 + c, pb = pa + nx;
+    o5[pa] = make_float2(a0, a1);
+    o5[pb] = make_float2(b0, b1);
+    const float ma = sqrtf(a0 * a0 + a1 * a1), mb = sqrtf(b0 * b0 + b1 * b1);
+    phasor[pa] = ma > 0.0f ? make_float2(a0 / ma, a1 / ma) : make_float2(1.0f, 0.0f);
+    phasor[pb] = mb > 0.0f ? make_float2(b0 / mb, b1 / mb) : make_float2(1.0f, 0.0f);
+}
+
+// Layer-5 weights [co][ci][t] (FP32 master) -> BF16 pairs [t][ci/2][co]
+// (channel 2k in the low half, 2k+1 in the high half).
+__global__ __launch_bounds__(256) void k_pack5(const float* __restrict__ w, uint32_t* __restrict__ w5)
+{
+    for (int j = threadIdx.x; j < 9 * 16 * 2; j += blockDim.x) {
+        const int co = j & 1, k = (j >> 1) % 16, t = j / 32;
+        const uint32_t lo = f2bf(w[(co * 32 + 2 * k) * 9 + t]), hi = f2bf(w[(co * 32 + 2 * k + 1) * 9 + t]);
+        w5[j] = lo | (hi << 16);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -638,7 +696,8 @@ hipError_t cnn_launch_forward(const CnnBuffers& b, const float* target, int ny, 
     for (int l = 1; l <= 3; ++l)
         hipLaunchKernelGGL(k_conv32<0>, gmf, dim3(256), 0, s, b.act[l - 1], ny, nx, b.wf[l - 1],
                            b.params + b.off[l] + 32 * 32 * 9, nullptr, b.act[l]);
-    hipLaunchKernelGGL(k_conv5, dim3(g256), dim3(256), 0, s, b.act[3], ny, nx, b.params + b.off[4],
+    const int w5c = nx < 64 ? nx : 64, r5 = kC5Px / w5c < ny ? kC5Px / w5c : ny;   // k_conv5's tile
+    hipLaunchKernelGGL(k_conv5, dim3((nx / w5c) * (ny / r5)), dim3(256), 0, s, b.act[3], ny, nx, b.w5,
                        b.params + b.off[4] + 2 * 32 * 9, b.o5, phasor);
     return hipGetLastError();
 }
@@ -705,6 +764,7 @@ hipError_t cnn_launch_pack(const CnnBuffers& b, hipStream_t s)
     for (int l = 1; l <= 3; ++l)
         hipLaunchKernelGGL(k_pack32, dim3((32 * 32 * 9 + 255) / 256), dim3(256), 0, s, b.params + b.off[l],
                            b.wf[l - 1], b.wt[l - 1]);
+    hipLaunchKernelGGL(k_pack5, dim3(1), dim3(256), 0, s, b.params + b.off[4], b.w5);
     return hipGetLastError();
 }
 

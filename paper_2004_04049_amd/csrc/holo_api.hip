@@ -1504,7 +1504,8 @@ holo_status holo_cnn_create(uint64_t seed, holo_cnn** out)
     }
     bool ok = hipMalloc(&c->b.params, n * 4) == hipSuccess && hipMalloc(&c->b.m, n * 4) == hipSuccess &&
               hipMalloc(&c->b.v, n * 4) == hipSuccess && hipMalloc(&c->b.grad, n * 4) == hipSuccess &&
-              hipMalloc(&c->b.loss_part, 256 * 3 * 8) == hipSuccess && hipMalloc(&c->b.zsum, 5 * 8) == hipSuccess;
+              hipMalloc(&c->b.loss_part, 256 * 3 * 8) == hipSuccess && hipMalloc(&c->b.zsum, 5 * 8) == hipSuccess &&
+              hipMalloc(&c->b.w5, 9 * 16 * 2 * 4) == hipSuccess;
     for (int i = 0; i < 3 && ok; ++i)
         ok = hipMalloc(&c->b.wf[i], 32 * 32 * 9 * 2) == hipSuccess && hipMalloc(&c->b.wt[i], 32 * 32 * 9 * 2) == hipSuccess;
     if (!ok) {
@@ -1655,7 +1656,7 @@ void holo_cnn_free(holo_cnn* c)
     (void)hipDeviceSynchronize();
     cnn_free_images(c);
     (void)hipFree(c->b.params), (void)hipFree(c->b.m), (void)hipFree(c->b.v), (void)hipFree(c->b.grad);
-    (void)hipFree(c->b.loss_part), (void)hipFree(c->b.zsum);
+    (void)hipFree(c->b.loss_part), (void)hipFree(c->b.zsum), (void)hipFree(c->b.w5);
     for (int i = 0; i < 3; ++i) (void)hipFree(c->b.wf[i]), (void)hipFree(c->b.wt[i]);
     delete c;
 }
