@@ -624,29 +624,37 @@ __global__ __launch_bounds__(256) void k_dw1(const float* __restrict__ target, c
 // grad[j] (+)= scale * sum over blocks b of part[b][j] in a fixed order: thread (j, s)
 // adds blocks s, s+4, s+8, ... (four loads in flight), then the four slices
 // are added in slice order.  Block = 64 outputs x 4 slices.
+// grad[j] (+)= scale * sum over blocks of part[b][j]: a block takes 16
+// parameters and splits the partial rows over 16 slices (slice s sums rows
+// s, s+16, ..., then the slices are added in order) -- a fixed order, so the
+// gradient is the same run to run.
+constexpr int kRedOut = 16, kRedSlices = 16;
 __global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ part, int nblocks, int n,
                                                      float scale, int accumulate, float* __restrict__ grad)
 {
-    __shared__ float red[4][64];
-    const int jl = threadIdx.x & 63, sl = threadIdx.x >> 6;
-    const int j = blockIdx.x * 64 + jl;
+    __shared__ float red[kRedSlices][kRedOut];
+    const int jl = threadIdx.x % kRedOut, sl = threadIdx.x / kRedOut;
+    const int j = blockIdx.x * kRedOut + jl;
     float s = 0.0f;
     if (j < n) {
         int b = sl;
-        for (; b + 12 < nblocks; b += 16) {
-            const float v0 = part[(size_t)b * n + j], v1 = part[(size_t)(b + 4) * n + j];
-            const float v2 = part[(size_t)(b + 8) * n + j], v3 = part[(size_t)(b + 12) * n + j];
+        for (; b + 3 * kRedSlices < nblocks; b += 4 * kRedSlices) {
+            const float v0 = part[(size_t)b * n + j], v1 = part[(size_t)(b + kRedSlices) * n + j];
+            const float v2 = part[(size_t)(b + 2 * kRedSlices) * n + j];
+            const float v3 = part[(size_t)(b + 3 * kRedSlices) * n + j];
             s += v0;
             s += v1;
             s += v2;
             s += v3;
         }
-        for (; b < nblocks; b += 4) s += part[(size_t)b * n + j];
+        for (; b < nblocks; b += kRedSlices) s += part[(size_t)b * n + j];
     }
     red[sl][jl] = s;
     __syncthreads();
     if (sl == 0 && j < n) {
-        const float g = (((red[0][jl] + red[1][jl]) + red[2][jl]) + red[3][jl]) * scale;
+        float g = red[0][jl];
+        for (int q = 1; q < kRedSlices; ++q) g += red[q][jl];
+        g *= scale;
         grad[j] = accumulate ? grad[j] + g : g;
     }
 }
@@ -724,8 +732,8 @@ hipError_t cnn_launch_backward(const CnnBuffers& b, const float* target, const f
     hipLaunchKernelGGL(k_loss_grad, dim3(g256), dim3(256), 0, s, b.o5, label, target, npx, b.zsum, b.d5);
     // layer 5
     hipLaunchKernelGGL(k_dw5, dim3(nblk), dim3(256), 0, s, b.act[3], b.d5, ny, nx, rpb, b.part);
-    hipLaunchKernelGGL(k_grad_reduce, dim3((2 * 32 * 9 + 2 + 63) / 64), dim3(256), 0, s, b.part, nblk,
-                       2 * 32 * 9 + 2, scale, accumulate, b.grad + b.off[4]);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((2 * 32 * 9 + 2 + kRedOut - 1) / kRedOut), dim3(256), 0, s, b.part,
+                       nblk, 2 * 32 * 9 + 2, scale, accumulate, b.grad + b.off[4]);
     hipLaunchKernelGGL(k_conv5_bwd_data, dim3(g256), dim3(256), 0, s, b.d5, ny, nx, b.params + b.off[4], b.act[3],
                        b.dact[0]);
     // layers 4, 3, 2 (index l = 3, 2, 1): dW from act[l-1] and dY; dX through MFMA
@@ -733,8 +741,8 @@ hipError_t cnn_launch_backward(const CnnBuffers& b, const float* target, const f
     uint16_t* dnext = b.dact[1];
     for (int l = 3; l >= 1; --l) {
         hipLaunchKernelGGL(k_dw32, dim3(nblk), dim3(192), 0, s, b.act[l - 1], dcur, ny, nx, rpb, b.part);
-        hipLaunchKernelGGL(k_grad_reduce, dim3((32 * 32 * 9 + 32 + 63) / 64), dim3(256), 0, s, b.part, nblk,
-                           32 * 32 * 9 + 32, scale, accumulate, b.grad + b.off[l]);
+        hipLaunchKernelGGL(k_grad_reduce, dim3((32 * 32 * 9 + 32 + kRedOut - 1) / kRedOut), dim3(256), 0, s,
+                           b.part, nblk, 32 * 32 * 9 + 32, scale, accumulate, b.grad + b.off[l]);
         hipLaunchKernelGGL(k_conv32<1>, gmf, dim3(256), 0, s, dcur, ny, nx, b.wt[l - 1], nullptr, b.act[l - 1],
                            dnext);
         uint16_t* tmp = dcur;
@@ -743,8 +751,8 @@ hipError_t cnn_launch_backward(const CnnBuffers& b, const float* target, const f
     }
     // layer 1
     hipLaunchKernelGGL(k_dw1, dim3(nblk), dim3(256), 0, s, target, dcur, ny, nx, rpb, b.part);
-    hipLaunchKernelGGL(k_grad_reduce, dim3((32 * 9 + 32 + 63) / 64), dim3(256), 0, s, b.part, nblk, 32 * 9 + 32,
-                       scale, accumulate, b.grad + b.off[0]);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((32 * 9 + 32 + kRedOut - 1) / kRedOut), dim3(256), 0, s, b.part, nblk,
+                       32 * 9 + 32, scale, accumulate, b.grad + b.off[0]);
     return hipGetLastError();
 }
 
