@@ -77,6 +77,7 @@ __device__ __forceinline__ void row_sum(double (&a)[NV], double* red, int T, int
 template <int NX, int MODE, int P>
 __global__ __launch_bounds__(P == 16 ? 256 : 512) void k_gs_rows(const float* __restrict__ target, int ny,
                                                   PhaseSrc src, uint64_t c0,
+                                                  const uint64_t* __restrict__ c0_base,
                                                   const float2* __restrict__ init, float2* __restrict__ state,
                                                   float2* __restrict__ field_out, double* __restrict__ partials,
                                                   const GsConsts* __restrict__ consts, const float2* __restrict__ tw,
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(P == 16 ? 256 : 512) void k_gs_rows(const float* __
                 v[m] = mag > 0.0f ? make_float2(ta[m] * (p.x / mag), ta[m] * (p.y / mag)) : make_float2(ta[m], 0.0f);
             }
         } else {
-            const uint64_t pos0 = pool_pos(src, c0, nullptr, (uint64_t)y * NX + (uint64_t)t);
+            const uint64_t pos0 = pool_pos(src, c0, c0_base, (uint64_t)y * NX + (uint64_t)t);
             const uint32_t rs = src.kind == SRC_MSEQ ? src.rows[y] : 0u;
             phase_slots<P>(src, pos0, (uint32_t)T, t, rs, v);
 #pragma unroll
@@ -200,7 +201,7 @@ static int gs_points(int n, int ntrans, int planned)
     }
 
 hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const PhaseSrc& src, uint64_t c0,
-                          const float2* init, float2* state, float2* field_out,
+                          const uint64_t* c0_base, const float2* init, float2* state, float2* field_out,
                           double* partials, const GsConsts* consts, const float2* tw_x,
                           const LaunchCfg& cfg, hipStream_t s)
 {
@@ -224,17 +225,17 @@ hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const P
             if (mode == GS_INIT) {
                 allow_lds_g(k_gs_rows<N_, GS_INIT, P_>, lds);
                 hipLaunchKernelGGL((k_gs_rows<N_, GS_INIT, P_>), dim3(ny / rows), dim3(rows * T), lds, s, target,
-                                   ny, src, c0, init, state, field_out, partials, consts, tw_x,
+                                   ny, src, c0, c0_base, init, state, field_out, partials, consts, tw_x,
                                    row_pitch(nx, cfg));
             } else if (mode == GS_ITER) {
                 allow_lds_g(k_gs_rows<N_, GS_ITER, P_>, lds);
                 hipLaunchKernelGGL((k_gs_rows<N_, GS_ITER, P_>), dim3(ny / rows), dim3(rows * T), lds, s, target,
-                                   ny, src, c0, init, state, field_out, partials, consts, tw_x,
+                                   ny, src, c0, c0_base, init, state, field_out, partials, consts, tw_x,
                                    row_pitch(nx, cfg));
             } else {
                 allow_lds_g(k_gs_rows<N_, GS_FINAL, P_>, lds);
                 hipLaunchKernelGGL((k_gs_rows<N_, GS_FINAL, P_>), dim3(ny / rows), dim3(rows * T), lds, s, target,
-                                   ny, src, c0, init, state, field_out, partials, consts, tw_x,
+                                   ny, src, c0, c0_base, init, state, field_out, partials, consts, tw_x,
                                    row_pitch(nx, cfg));
             }
         }

@@ -455,6 +455,10 @@ struct GsArgs {
     uint32_t flags;
 };
 
+// Stream-ordered store of one 64-bit value (kernel argument, so no host
+// buffer has to outlive the call).
+__global__ void k_set_u64(uint64_t* p, uint64_t v) { *p = v; }
+
 struct GraphKey {
     std::vector<uintptr_t> k;
     bool operator<(const GraphKey& o) const { return k < o.k; }
@@ -466,7 +470,8 @@ bool g_use_graphs = true;
 
 holo_status gs_enqueue(const GsArgs& a, hipStream_t s, const LaunchCfg& cfg, const float2* tw_x, const float2* tw_y,
                        char* b, size_t o_state, size_t o_field, size_t o_pinit, size_t o_piter, size_t o_consts,
-                       size_t o_nm, size_t o_er, size_t o_x2, size_t o_p5, size_t o_f2, size_t o_rs)
+                       size_t o_nm, size_t o_er, size_t o_x2, size_t o_p5, size_t o_f2, size_t o_rs,
+                       size_t o_cur)
 {
     const int inx = (int)a.nx, iny = (int)a.ny;
     float2* state = (float2*)(b + o_state);
@@ -476,24 +481,27 @@ holo_status gs_enqueue(const GsArgs& a, hipStream_t s, const LaunchCfg& cfg, con
     GsConsts* consts = (GsConsts*)(b + o_consts);
     double* nm = (double*)(b + o_nm);
     double* er = (double*)(b + o_er);
+    // the pool start comes from a device word written before the launches
+    // (gs_run), so a captured graph serves every cursor
     const bool use_lut = a.init == nullptr;
-    const uint64_t c0 = use_lut ? lut_wrap(a.lut, a.cursor) : 0;
+    const uint64_t* dcur = (const uint64_t*)(b + o_cur);
     PhaseSrc src{};
     src.n = 1;
     if (use_lut) {
         uint32_t* rs = (uint32_t*)(b + o_rs);
         src = make_src(a.lut, rs);
         if (a.lut->kind == SRC_MSEQ)
-            LAUNCH("mseq_rows", s, launch_mseq_rows(a.lut->mseq, c0, nullptr, inx, iny, 1, rs, s));
+            LAUNCH("mseq_rows", s, launch_mseq_rows(a.lut->mseq, 0, dcur, inx, iny, 1, rs, s));
     }
-    LAUNCH("gs_rows", s, launch_gs_rows(GS_INIT, a.target, inx, iny, src, c0, (const float2*)a.init, state,
-                                        nullptr, pinit, consts, tw_x, cfg, s));
+    LAUNCH("gs_rows", s, launch_gs_rows(GS_INIT, a.target, inx, iny, src, 0, use_lut ? dcur : nullptr,
+                                        (const float2*)a.init, state, nullptr, pinit, consts, tw_x, cfg, s));
     LAUNCH("gs_consts", s, launch_gs_consts(pinit, iny, inx, consts, s));
     for (int it = 0; it < a.n_iter; ++it) {
         const bool last = it == a.n_iter - 1;
         LAUNCH("gs_cols", s, launch_gs_cols(state, inx, iny, last ? a.codes : nullptr, tw_y, cfg, s));
-        LAUNCH("gs_rows", s, launch_gs_rows(last ? GS_FINAL : GS_ITER, a.target, inx, iny, src, c0, nullptr,
-                                            state, fout, piter + (size_t)it * 3 * iny, consts, tw_x, cfg, s));
+        LAUNCH("gs_rows", s, launch_gs_rows(last ? GS_FINAL : GS_ITER, a.target, inx, iny, src, 0, nullptr,
+                                            nullptr, state, fout, piter + (size_t)it * 3 * iny, consts, tw_x, cfg,
+                                            s));
     }
     LAUNCH("gs_finalize", s, launch_gs_finalize(piter, a.n_iter, iny, consts, nm, er, s));
     if (a.codes && (a.final2 || a.recon)) {
@@ -528,9 +536,14 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
     const size_t o_p5 = cv.take(sizeof(double) * 5 * ny);
     const size_t o_f2 = cv.take(sizeof(double) * 2);
     const size_t o_rs = cv.take(sizeof(uint32_t) * ny);   // M-sequence row states
+    const size_t o_cur = cv.take(sizeof(uint64_t));        // pool start of this call
     void* ws;
     if ((st = get_workspace(device, s, cv.off, &ws))) return st;
     char* b = (char*)ws;
+    if (!a.init) {
+        hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, (uint64_t*)(b + o_cur), lut_wrap(a.lut, a.cursor));
+        HIP_TRY(hipGetLastError());
+    }
 
     bool prof_on;
     {
@@ -540,12 +553,12 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
     // the legacy default stream cannot be captured: launch directly there
     if (!g_use_graphs || prof_on || s == nullptr) {
         if ((st = gs_enqueue(a, s, cfg, tw_x, tw_y, b, o_state, o_field, o_pinit, o_piter, o_consts, o_nm, o_er,
-                             o_x2, o_p5, o_f2, o_rs)))
+                             o_x2, o_p5, o_f2, o_rs, o_cur)))
             return st;
     } else {
         GraphKey key{{(uintptr_t)device, (uintptr_t)s, (uintptr_t)a.target, (uintptr_t)a.nx, (uintptr_t)a.ny,
-                      (uintptr_t)a.n_iter, (uintptr_t)(a.init ? 0 : a.lut->id),
-                      (uintptr_t)(a.init ? 0 : lut_wrap(a.lut, a.cursor)), (uintptr_t)a.init, (uintptr_t)a.field,
+                      (uintptr_t)a.n_iter, (uintptr_t)(a.init ? 0 : a.lut->id), (uintptr_t)a.init,
+                      (uintptr_t)a.field,
                       (uintptr_t)a.codes, (uintptr_t)(a.final2 != nullptr), (uintptr_t)a.recon, (uintptr_t)ws,
                       (uintptr_t)cfg.cols_per_block, (uintptr_t)cfg.rows_per_block, (uintptr_t)cfg.ksplit,
                       (uintptr_t)cfg.recon_cols_per_block, (uintptr_t)(intptr_t)cfg.pad,
@@ -560,7 +573,7 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
             hipGraph_t graph = nullptr;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             holo_status est = gs_enqueue(a, s, cfg, tw_x, tw_y, b, o_state, o_field, o_pinit, o_piter, o_consts,
-                                         o_nm, o_er, o_x2, o_p5, o_f2, o_rs);
+                                         o_nm, o_er, o_x2, o_p5, o_f2, o_rs, o_cur);
             hipError_t ce = hipStreamEndCapture(s, &graph);
             if (est) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -593,9 +606,6 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
     return HOLO_OK;
 }
 
-// Stream-ordered store of one 64-bit value (kernel argument, so no host
-// buffer has to outlive the call).
-__global__ void k_set_u64(uint64_t* p, uint64_t v) { *p = v; }
 
 // Branch streams (default priority) for the batched graph's fork/join.
 constexpr int kBranches = 4;

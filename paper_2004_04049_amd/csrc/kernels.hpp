@@ -91,8 +91,9 @@ enum GsRowMode { GS_INIT = 0, GS_ITER = 1, GS_FINAL = 2 };
 struct GsConsts {
     double sum_t2, sum_t4, te_scale;
 };
+// GS_INIT reads the pool at c0 + *c0_base (c0_base may be NULL).
 hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const PhaseSrc& src, uint64_t c0,
-                          const float2* init, float2* state, float2* field_out,
+                          const uint64_t* c0_base, const float2* init, float2* state, float2* field_out,
                           double* partials, const GsConsts* consts, const float2* tw_x,
                           const LaunchCfg& cfg, hipStream_t s);
 hipError_t launch_gs_cols(float2* state, int nx, int ny, uint8_t* codes, const float2* tw_y,

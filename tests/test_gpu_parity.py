@@ -269,6 +269,32 @@ def test_gs_graph_replay_matches_eager(holo):
             torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("kind", ["table", "prng", "mseq"])
+def test_gs_graph_serves_every_cursor(holo, kind):
+    # one captured GS graph per frame shape: the pool start is a device word
+    # written before each replay, so successive frames (cursor += N, which a
+    # 10007-entry pool sees at a new offset every time) replay the same graph
+    # and still equal direct launches at their own cursors
+    nx, ny = 256, 128
+    t = torch.from_numpy(synth.blob_target(nx, ny, 18)).cuda()
+    lut = {"table": lambda: holo.Lut(10007, 2), "prng": lambda: holo.Lut.prng(2),
+           "mseq": lambda: holo.Lut.mseq(2)}[kind]()
+    s = torch.cuda.Stream()
+    cursors = [0, nx * ny, 5 * nx * ny + 17, (1 << 33) + 3]
+    with torch.cuda.stream(s):
+        holo.set_graphs(False)
+        refs = [holo.gs_iterate(t, 6, lut, c) for c in cursors]
+        refs = [(r["nmse"].copy(), r["codes"].clone(), r["cursor"]) for r in refs]
+        holo.set_graphs(True)
+        field = torch.empty((ny, nx), dtype=torch.complex64, device="cuda")
+        codes = torch.empty((ny, nx), dtype=torch.uint8, device="cuda")
+        for c, (nm, cd, cur) in zip(cursors, refs):
+            r = holo.gs_iterate(t, 6, lut, c, field=field, codes=codes)
+            np.testing.assert_array_equal(r["nmse"], nm)
+            assert torch.equal(codes, cd) and r["cursor"] == cur
+        torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("plan", [
     [16, 2, 4, 0, 16, 5, 0],     # chunks of 5 over 13 sub-frames (ragged last chunk)
     [8, 1, 2, 0, 0, 4, 0],       # no padding
