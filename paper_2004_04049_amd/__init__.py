@@ -172,6 +172,8 @@ class Lut:
         return int(lib().holo_lut_size(self._h))
 
     def __len__(self):
+        if self.kind == SRC_PRNG:
+            raise TypeError("a counter-based PRNG pool is unbounded (Lut.size gives 2**64 - 1)")
         return self.size
 
     def phases(self):
