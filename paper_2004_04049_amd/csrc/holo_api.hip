@@ -37,7 +37,8 @@ struct holo_lut {
     uint64_t n_lut;              // as requested (0 = flat); PRNG: UINT64_MAX (unbounded); MSEQ: 2^31 - 1
     uint32_t n_dev;              // pool length of the cyclic kinds (>= 1)
     uint64_t seed;
-    std::vector<double> phases;  // FP64 phases, host copy (TABLE, CODES8)
+    std::vector<double> phases;  // FP64 phases, host copy (TABLE)
+    std::vector<uint8_t> host_codes;   // CODES8: the codes, host copy
     float2* dev = nullptr;       // TABLE: n_dev FP32 unit phasors; CODES8, MSEQ: the 256 code phasors
     uint8_t* codes = nullptr;    // CODES8: n_dev codes
     uint32_t* mseq = nullptr;    // MSEQ: x^(2^j) for j < 31, S_0, then [12][4][256] jump tables (strides 2^0..2^11)
@@ -747,15 +748,11 @@ holo_status holo_lut_build_codes(uint64_t n_lut, uint64_t seed, holo_lut** out)
     if (n_lut >= (1ull << 31)) return fail(HOLO_EUNSUPPORTED, "n_lut %llu >= 2^31", (unsigned long long)n_lut);
     holo_lut* l = new_lut(SRC_CODES8, n_lut, (uint32_t)n_lut, seed);
     if (!l) return HOLO_EDEVICE;
-    std::vector<uint8_t> q(n_lut);
-    l->phases.resize(n_lut);
-    const double two_pi = 6.283185307179586476925286766559;
+    // the host keeps the codes (1 byte each); holo_lut_phases derives phases from them
+    l->host_codes.resize(n_lut);
     uint64_t s = seed;
-    for (uint64_t j = 0; j < n_lut; ++j) {
-        q[j] = (uint8_t)(splitmix64(s) >> 56);
-        l->phases[j] = two_pi * ((double)q[j] / 256.0);
-    }
-    if (holo_status st = upload_lut((void**)&l->codes, q.data(), n_lut, l)) return st;
+    for (uint64_t j = 0; j < n_lut; ++j) l->host_codes[j] = (uint8_t)(splitmix64(s) >> 56);
+    if (holo_status st = upload_lut((void**)&l->codes, l->host_codes.data(), n_lut, l)) return st;
     if (holo_status st = upload_code_phasors(l)) return st;
     *out = l;
     return HOLO_OK;
@@ -783,11 +780,14 @@ holo_status holo_lut_mseq(uint64_t seed, holo_lut** out)
     aux[0] = 2;   // x
     for (int j = 1; j < 31; ++j) aux[j] = gf_mul_host(aux[j - 1], aux[j - 1]);
     aux[31] = w ^ (w >> 28);
+    uint32_t xb[4];   // x^(8b): the weight of byte b of a state
+    for (int b = 0; b < 4; ++b) xb[b] = gf_xpow_host(8ull * b);
     for (int j = 0; j < 12; ++j) {   // stride 2^j: multiply by x^(8 * 2^j)
         const uint32_t c = gf_xpow_host(8ull << j);
-        for (int b = 0; b < 4; ++b)
-            for (uint32_t v = 0; v < 256; ++v)
-                aux[32 + j * 1024 + b * 256 + v] = gf_mul_host(c, gf_mul_host(v, gf_xpow_host(8ull * b)));
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t cb = gf_mul_host(c, xb[b]);
+            for (uint32_t v = 0; v < 256; ++v) aux[32 + j * 1024 + b * 256 + v] = gf_mul_host(cb, v);
+        }
     }
     if (holo_status e = upload_lut((void**)&l->mseq, aux.data(), aux.size() * sizeof(uint32_t), l)) return e;
     if (holo_status e = upload_code_phasors(l)) return e;
@@ -803,7 +803,12 @@ holo_status holo_lut_phases(const holo_lut* lut, double* out, uint64_t n)
     if (lut->kind == SRC_PRNG || lut->kind == SRC_MSEQ)
         return fail(HOLO_EUNSUPPORTED, "this phase source keeps no table (holo_phase_mask gives its phasors)");
     uint64_t m = n < lut->n_lut ? n : lut->n_lut;
-    if (m) std::memcpy(out, lut->phases.data(), m * sizeof(double));
+    if (lut->kind == SRC_CODES8) {
+        const double two_pi = 6.283185307179586476925286766559;
+        for (uint64_t j = 0; j < m; ++j) out[j] = two_pi * ((double)lut->host_codes[j] / 256.0);
+    } else if (m) {
+        std::memcpy(out, lut->phases.data(), m * sizeof(double));
+    }
     return HOLO_OK;
 }
 

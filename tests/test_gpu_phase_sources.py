@@ -212,3 +212,12 @@ def test_gs_seed_per_points_per_thread(holo, orc, kind, pts):
     phi = _oracle_phases(orc, kind, cursor, nx * ny).reshape(ny, nx)
     ref = orc.gs(target, n_iter, np.exp(1j * phi))
     np.testing.assert_allclose(r["nmse"], ref["nmse"], rtol=1e-4)
+
+
+def test_code_table_phases_bit_exact(holo, orc):
+    # the host keeps the codes and derives FP64 phases 2*pi*q/256 on request
+    lut = holo.Lut.codes(4099, 17)
+    assert lut.kind == holo.SRC_CODES8 and lut.size == 4099
+    assert np.array_equal(lut.phases(), orc.codes8_phases(4099, 17))
+    with pytest.raises(holo.HoloError):
+        holo.Lut.mseq(17).phases()
