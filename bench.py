@@ -97,8 +97,8 @@ def measured_traffic(kernel, workload):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(frames and sub-frames would shard by cursor range; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(frames and sub-frames would shard by pool-cursor range)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

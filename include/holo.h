@@ -46,7 +46,7 @@ typedef int32_t holo_status;
 enum {
     HOLO_OK = 0,
     HOLO_EINVAL = -1,       /* null required pointer or out-of-range count   */
-    HOLO_EUNSUPPORTED = -2, /* size or precision this build does not handle  */
+    HOLO_EUNSUPPORTED = -2, /* size or precision the library does not handle */
     HOLO_ENOMEM = -3,       /* workspace or table allocation failed          */
     HOLO_EDEVICE = -4       /* a HIP call failed; text in holo_last_error()  */
 };
