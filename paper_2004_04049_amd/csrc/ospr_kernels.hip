@@ -383,13 +383,119 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __res
     if (t == 0) buf_st2(rout, voff, (kP / 2) * mst, v[kP / 2]);
 }
 
+// FP32 K2 on column pairs.  Binarisation needs only Re h of each column, and
+// Re IFFT{X} = IFFT{X_h} with X_h(v) = (X(v) + conj X(-v))/2, the Hermitian
+// part of the column spectrum, whose transform is real.  Columns a, b of a
+// pair therefore share one inverse transform: IFFT{2 (X_h,a + i X_h,b)} =
+// 2 (Re h_a + i Re h_b), and only signs are read from it.  Likewise their +-1
+// columns share one forward transform Z = F{B_a + i B_b}, separated as
+// F_a(v) = (Z(v) + conj Z(-v))/2, F_b(v) = (Z(v) - conj Z(-v))/(2i) (as in
+// the pair variant below).  Half the transforms of k_ospr_cols for the same
+// bytes; signs and spectra differ from it by rounding only.
+// Grid: (nx / C) * n_sf blocks of (C/2) * (ny/16) threads; thread (q, t) owns
+// columns x0 + 2q and x0 + 2q + 1 (one 16-byte load per row; the two results
+// leave as two 8-byte stores), rows t + T*m.
+// The mirror row -v of row v is exchanged through LDS in a plain [row][C/2]
+// layout: 2 (X_h,a + i X_h,b)(v) = Y(v) + Q(-v) with Y = X_a + i X_b and
+// Q = conj X_a + i conj X_b.
+// Bits 0..7 of x moved to the even positions 0, 2, .., 14.
+__device__ __forceinline__ uint32_t spread_bits8(uint32_t x)
+{
+    x = (x | (x << 4)) & 0x0F0Fu;
+    x = (x | (x << 2)) & 0x3333u;
+    return (x | (x << 1)) & 0x5555u;
+}
+
+template <int NY, int C>
+__global__ __launch_bounds__((C / 2) * (NY / kP)) void k_ospr_cols2(const float2* __restrict__ x1, int nx,
+                                                                   uint32_t* __restrict__ bits,
+                                                                   float2* __restrict__ x2,
+                                                                   const float2* __restrict__ tw, int pitch)
+{
+    extern __shared__ float2 lds[];
+    constexpr int CP = C / 2;
+    constexpr int T = NY / kP;
+    const int q = threadIdx.x % CP, t = threadIdx.x / CP;
+    const int lane = threadIdx.x & 63;
+    const int ncb = nx / C;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int k = tile / ncb;
+    const int x0 = (tile - k * ncb) * C;
+    const size_t npix = (size_t)nx * NY;
+    const size_t plane = (size_t)NY * pitch;
+    const uint32_t voff = ((uint32_t)t * (uint32_t)pitch + (uint32_t)(x0 + 2 * q)) * 8u;
+    const uint32_t mst = (uint32_t)T * (uint32_t)pitch * 8u;
+    const auto rin = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
+    float2 v[kP];
+#pragma unroll
+    for (int m = 0; m < kP; ++m) {
+        const float4 ab = buf_ld4(rin, voff, m * mst);              // X_a = (x, y), X_b = (z, w)
+        v[m] = make_float2(ab.x - ab.w, ab.y + ab.z);               // Y
+        lds[(t + T * m) * CP + q] = make_float2(ab.x + ab.w, ab.z - ab.y);   // Q
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kP; ++m) v[m] = cadd(v[m], lds[((NY - (t + T * m)) & (NY - 1)) * CP + q]);
+    __syncthreads();
+    fft_stages<NY, 1>(v, t, lds, ColAddr<CP>{q}, tw);
+
+    // nearest of {+1, -1}: bit = (Re h < 0); Re h = 0 -> +1.  The CP lanes of
+    // a row give the even columns' bits (ballot of .x) and the odd columns'
+    // (ballot of .y); interleaved, they are the row's C bits in raster order.
+    const auto rbits = make_rsrc(bits + (size_t)k * (npix / 32), (uint32_t)(npix / 8));
+    const uint32_t boff = ((uint32_t)t * (uint32_t)nx + (uint32_t)x0) / 8u;
+    const uint32_t bst = (uint32_t)T * (uint32_t)nx / 8u;
+    const int g0 = lane & ~(CP - 1);
+#pragma unroll
+    for (int m = 0; m < kP; ++m) {
+        const bool na = v[m].x < 0.0f, nb = v[m].y < 0.0f;
+        const uint64_t ma = __ballot(na), mb = __ballot(nb);
+        if (q == 0) {
+            const uint32_t w = spread_bits8((uint32_t)(ma >> g0) & ((1u << CP) - 1u)) |
+                               (spread_bits8((uint32_t)(mb >> g0) & ((1u << CP) - 1u)) << 1);
+            if (C == 16) __builtin_amdgcn_raw_buffer_store_b16((unsigned short)w, rbits, boff, m * bst, 0);
+            else __builtin_amdgcn_raw_buffer_store_b8((unsigned char)w, rbits, boff, m * bst, 0);
+        }
+        v[m] = make_float2(na ? -1.0f : 1.0f, nb ? -1.0f : 1.0f);
+    }
+    fft_stages<NY, -1>(v, t, lds, ColAddr<CP>{q}, tw);
+
+    // separation: rows v <= NY/2 (slots m < 8, and m = 8 for t = 0) need Z at
+    // -v, which lies in slots 8..15, or slot 0 for v = 0
+    __syncthreads();
+#pragma unroll
+    for (int m = kP / 2; m < kP; ++m) lds[(t + T * m) * CP + q] = v[m];
+    if (t == 0) lds[q] = v[0];
+    __syncthreads();
+    // column b through a descriptor based one element later, so the two 8-byte
+    // stores of a row are not merged into one 16-byte store
+    const size_t hplane = (size_t)(NY / 2 + 1) * pitch;
+    const auto rout_a = make_rsrc(x2 + (size_t)k * hplane, (uint32_t)(hplane * 8));
+    const auto rout_b = make_rsrc(x2 + (size_t)k * hplane + 1, (uint32_t)(hplane * 8 - 8));
+#pragma unroll
+    for (int m = 0; m <= kP / 2; ++m) {
+        if (m == kP / 2 && t != 0) break;
+        const float2 z = v[m];
+        const float2 zm = lds[((NY - (t + T * m)) & (NY - 1)) * CP + q];
+        buf_st2(rout_a, voff, m * mst, make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y)));   // (Z + conj Zm) / 2
+        buf_st2(rout_b, voff, m * mst, make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x)));   // (Z - conj Zm) / (2i)
+    }
+}
+
 hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
                             const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
 {
     const int C = cfg.prec ? 8 : col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8);
     HOLO_SWITCH_NP(ny, cfg.prec, HOLO_SWITCH_C816(C, {
         constexpr int T = N_ / kP;
-        if (C_ * T <= 1024) {
+        if constexpr (P_ == 0) {
+            if ((C_ / 2) * T <= 1024) {
+                size_t lds = (size_t)(C_ / 2) * PadLen<N_>::v * sizeof(float2);
+                allow_lds(k_ospr_cols2<N_, C_>, lds);
+                hipLaunchKernelGGL((k_ospr_cols2<N_, C_>), dim3((nx / C_) * n_sf), dim3((C_ / 2) * T), lds, s, x1,
+                                   nx, bits, x2, tw_y, row_pitch(nx, cfg));
+            }
+        } else if (C_ * T <= 1024) {
             size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
             allow_lds(k_ospr_cols<N_, C_, P_>, lds);
             hipLaunchKernelGGL((k_ospr_cols<N_, C_, P_>), dim3((nx / C_) * n_sf), dim3(C_ * T), lds, s, x1, nx, bits,

@@ -91,6 +91,9 @@ def test_ospr_uniform_64_lut256(holo, orc):
     (64, 64, 2, 0, 0),                      # flat phase
     (16, 16, 1, 17, 2 ** 63 + 5),           # smallest size, huge cursor
     (512, 512, 9, 65537, 3),
+    # multi-wave column blocks on grids of several blocks per CU
+    (1024, 512, 6, 65537, 17),
+    (128, 1024, 6, 10007, 5),
 ])
 def test_ospr_small_cases(holo, orc, nx, ny, nsf, n_lut, cursor):
     t = synth.blob_target(nx, ny, 5)
