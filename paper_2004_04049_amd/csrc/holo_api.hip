@@ -397,7 +397,11 @@ holo_status ospr_enqueue(const float* target, int64_t nx, int64_t ny, int n_sf, 
         const int ns = n_fields - k0 < l.chunk ? n_fields - k0 : l.chunk;
         const uint64_t ck = lut_wrap(lut, c0 + (uint64_t)k0 * (uint64_t)(nx * ny));
         const PhaseSrc src = make_src(lut, rs + (size_t)k0 * (size_t)ny);
-        LAUNCH("ospr_rows", s, launch_ospr_rows(target, (int)nx, (int)ny, ns, src, ck, c0_base, x1, tw_x, cfg, s));
+        // binary frames on the FP32 path transform only the Hermitian part of R
+        if (mode == OSPR_BINARY && cfg.prec == 0)
+            LAUNCH("ospr_rows", s, launch_ospr_rows_h(target, (int)nx, (int)ny, ns, src, ck, c0_base, x1, tw_x, cfg, s));
+        else
+            LAUNCH("ospr_rows", s, launch_ospr_rows(target, (int)nx, (int)ny, ns, src, ck, c0_base, x1, tw_x, cfg, s));
         if (mode == OSPR_BINARY)
             LAUNCH("ospr_cols", s, launch_ospr_cols(x1, (int)nx, (int)ny, ns, holo_bits + (size_t)k0 * words,
                                                     x2 + (size_t)k0 * nspec, tw_y, cfg, s));

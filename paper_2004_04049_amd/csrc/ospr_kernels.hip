@@ -327,6 +327,95 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
 }
 
 // -------------------------------------------------------------------------
+// K1 for binary frames (FP32).  Only Re H is binarised, and
+// Re IFFT2{R} = IFFT2{R_h} with R_h(x, y) = (R(x, y) + conj R(-x, -y))/2, the
+// Hermitian part of R (indices mod nx, ny; the 1/2 is dropped, since only
+// signs are read).  Row transforms of a Hermitian field obey
+// X(x, -y) = conj X(x, y), so rows y = 0..ny/2 are transformed and stored (a
+// half plane of ny/2 + 1 rows, pitch as x1) and the column pass rebuilds the
+// others.  Each thread draws its pixels (x, y) and their mirrors (-x, -y):
+// for x = t + T*m the mirror column is t' + T*m' with t' = (T - t) mod T and
+// m' = 15 - m (t > 0) or (16 - m) mod 16 (t = 0), i.e. slot m' of a thread t'.
+// Grid: ceil((ny/2 + 1) / rows) * n_sf blocks; the surplus rows of a
+// sub-frame's last block repeat row ny/2 and are not stored.
+// -------------------------------------------------------------------------
+template <int NX>
+__global__ __launch_bounds__(1024) void k_ospr_rows_h(const float* __restrict__ target, int ny, PhaseSrc src,
+                                                      uint64_t c0, const uint64_t* __restrict__ c0_base,
+                                                      float2* __restrict__ x1, const float2* __restrict__ tw,
+                                                      int pitch)
+{
+    extern __shared__ float2 lds[];
+    constexpr int T = NX / kP;
+    const int rows = blockDim.x / T;
+    const int row = threadIdx.x / T, t = threadIdx.x % T;
+    const int nh = ny / 2 + 1;
+    const int blocks_per_sf = (nh + rows - 1) / rows;
+    const int k = blockIdx.x / blocks_per_sf;
+    const int yr = (blockIdx.x % blocks_per_sf) * rows + row;
+    const int y = yr < nh ? yr : nh - 1;
+    const int ym = (ny - y) & (ny - 1);
+    const int tm = (T - t) & (T - 1);
+    const uint64_t npix = (uint64_t)NX * (uint64_t)ny;
+    const uint64_t pos0 = pool_pos(src, c0, c0_base, (uint64_t)k * npix + (uint64_t)y * NX + (uint64_t)t);
+    const uint64_t pos1 = pool_pos(src, c0, c0_base, (uint64_t)k * npix + (uint64_t)ym * NX + (uint64_t)tm);
+    const bool mseq = src.kind == SRC_MSEQ;
+    const uint32_t rs0 = mseq ? src.rows[(size_t)k * ny + y] : 0u;
+    const uint32_t rs1 = mseq ? src.rows[(size_t)k * ny + ym] : 0u;
+    const auto rt = make_rsrc(target, (uint32_t)(npix * 4));
+    const uint32_t toff0 = ((uint32_t)y * NX + (uint32_t)t) * 4u;
+    const uint32_t toff1 = ((uint32_t)ym * NX + (uint32_t)tm) * 4u;
+    float a[kP], b[kP];
+#pragma unroll
+    for (int m = 0; m < kP; ++m) {
+        a[m] = buf_ld1(rt, toff0, (uint32_t)(m * T * 4));
+        b[m] = buf_ld1(rt, toff1, (uint32_t)(m * T * 4));
+    }
+    uint32_t* lt = nullptr;
+    if (phase_uses_lds(src)) {
+        lt = (uint32_t*)(lds + rows * PadLen<NX>::v);
+        phase_stage(src, (uint32_t)T, lt);
+    }
+    float2 v[kP], w[kP];
+    phase_slots<kP>(src, pos0, (uint32_t)T, t, rs0, v, lt);
+    phase_slots<kP>(src, pos1, (uint32_t)T, tm, rs1, w, lt);
+    const bool t0 = t == 0;
+#pragma unroll
+    for (int m = 0; m < kP; ++m) {
+        const int mi = 15 - m, mz = (16 - m) & 15;
+        const float bm = t0 ? b[mz] : b[mi];
+        const float2 wm = t0 ? w[mz] : w[mi];
+        // R(x, y) + conj R(-x, -y)
+        v[m] = make_float2(fmaf(a[m], v[m].x, bm * wm.x), fmaf(a[m], v[m].y, -bm * wm.y));
+    }
+    fft_stages<NX, 1, RowAddrR, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, tw);
+    if (yr < nh) {
+        const size_t plane = (size_t)nh * pitch;
+        const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
+        const uint32_t ooff = ((uint32_t)y * (uint32_t)pitch + (uint32_t)t) * 8u;
+#pragma unroll
+        for (int m = 0; m < kP; ++m) buf_st2(ro, ooff, (uint32_t)(m * T * 8), v[m]);
+    }
+}
+
+hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, const PhaseSrc& src, uint64_t c0,
+                              const uint64_t* c0_base, float2* x1, const float2* tw_x, const LaunchCfg& cfg,
+                              hipStream_t s)
+{
+    const int rows = row_block_rows(nx, ny, cfg.rows_per_block, 0);
+    const int blocks_per_sf = (ny / 2 + 1 + rows - 1) / rows;
+    HOLO_SWITCH_N(nx, {
+        constexpr int T = N_ / kP;
+        size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2) +
+                     (src.kind == SRC_MSEQ || src.kind == SRC_CODES8 ? kPhaseLdsWords * sizeof(uint32_t) : 0);
+        allow_lds(k_ospr_rows_h<N_>, lds);
+        hipLaunchKernelGGL((k_ospr_rows_h<N_>), dim3(blocks_per_sf * n_sf), dim3(rows * T), lds, s, target, ny, src,
+                           c0, c0_base, x1, tw_x, row_pitch(nx, cfg));
+    });
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------
 // K2: inverse column transform, binarise + pack, forward column transform of
 // the +-1 column; writes the half spectrum rows 0..ny/2.
 // Grid: (nx / C) * n_sf blocks of C * (ny/16) threads.  Thread (c, t) owns
@@ -383,21 +472,20 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __res
     if (t == 0) buf_st2(rout, voff, (kP / 2) * mst, v[kP / 2]);
 }
 
-// FP32 K2 on column pairs.  Binarisation needs only Re h of each column, and
-// Re IFFT{X} = IFFT{X_h} with X_h(v) = (X(v) + conj X(-v))/2, the Hermitian
-// part of the column spectrum, whose transform is real.  Columns a, b of a
-// pair therefore share one inverse transform: IFFT{2 (X_h,a + i X_h,b)} =
-// 2 (Re h_a + i Re h_b), and only signs are read from it.  Likewise their +-1
-// columns share one forward transform Z = F{B_a + i B_b}, separated as
-// F_a(v) = (Z(v) + conj Z(-v))/2, F_b(v) = (Z(v) - conj Z(-v))/(2i) (as in
-// the pair variant below).  Half the transforms of k_ospr_cols for the same
-// bytes; signs and spectra differ from it by rounding only.
+// FP32 K2 on column pairs, from the half plane of k_ospr_rows_h.  Its columns
+// are Hermitian (X(-y) = conj X(y)), so their inverse transforms are real:
+// columns a, b of a pair share one inverse transform,
+// IFFT{X_a + i X_b} = h_a + i h_b with h_a, h_b real, and only signs are read
+// from it.  Likewise their +-1 columns share one forward transform
+// Z = F{B_a + i B_b}, separated as F_a(v) = (Z(v) + conj Z(-v))/2,
+// F_b(v) = (Z(v) - conj Z(-v))/(2i) (as in the pair variant below).  Half the
+// transforms of k_ospr_cols; signs and spectra differ from it by rounding only.
 // Grid: (nx / C) * n_sf blocks of (C/2) * (ny/16) threads; thread (q, t) owns
 // columns x0 + 2q and x0 + 2q + 1 (one 16-byte load per row; the two results
-// leave as two 8-byte stores), rows t + T*m.
-// The mirror row -v of row v is exchanged through LDS in a plain [row][C/2]
-// layout: 2 (X_h,a + i X_h,b)(v) = Y(v) + Q(-v) with Y = X_a + i X_b and
-// Q = conj X_a + i conj X_b.
+// leave as two 8-byte stores), rows t + T*m.  Slots m < 8 load row
+// y = t + T*m; slot m >= 8 loads the mirror row ny - y = (T - t) + T*(15 - m)
+// (also for t = 0, where slot 8 is row ny/2) and conjugates; rows 0 and ny/2
+// are real up to rounding, and their real parts are taken.
 // Bits 0..7 of x moved to the even positions 0, 2, .., 14.
 __device__ __forceinline__ uint32_t spread_bits8(uint32_t x)
 {
@@ -422,21 +510,23 @@ __global__ __launch_bounds__((C / 2) * (NY / kP)) void k_ospr_cols2(const float2
     const int k = tile / ncb;
     const int x0 = (tile - k * ncb) * C;
     const size_t npix = (size_t)nx * NY;
-    const size_t plane = (size_t)NY * pitch;
+    const size_t plane = (size_t)(NY / 2 + 1) * pitch;
     const uint32_t voff = ((uint32_t)t * (uint32_t)pitch + (uint32_t)(x0 + 2 * q)) * 8u;
+    const uint32_t moff = ((uint32_t)(T - t) * (uint32_t)pitch + (uint32_t)(x0 + 2 * q)) * 8u;
     const uint32_t mst = (uint32_t)T * (uint32_t)pitch * 8u;
     const auto rin = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
     float2 v[kP];
 #pragma unroll
-    for (int m = 0; m < kP; ++m) {
-        const float4 ab = buf_ld4(rin, voff, m * mst);              // X_a = (x, y), X_b = (z, w)
-        v[m] = make_float2(ab.x - ab.w, ab.y + ab.z);               // Y
-        lds[(t + T * m) * CP + q] = make_float2(ab.x + ab.w, ab.z - ab.y);   // Q
+    for (int m = 0; m < kP / 2; ++m) {
+        const float4 ab = buf_ld4(rin, voff, m * mst);               // X_a = (x, y), X_b = (z, w) at row y
+        v[m] = make_float2(ab.x - ab.w, ab.y + ab.z);                // X_a + i X_b
+        const float4 cd = buf_ld4(rin, moff, (kP / 2 - 1 - m) * mst); // slot m + 8: row ny - y = (T - t) + T*(7 - m)
+        v[m + kP / 2] = make_float2(cd.x + cd.w, cd.z - cd.y);       // conj X_a + i conj X_b
+        if (m == 0 && t == 0) {                                      // rows 0 and ny/2
+            v[0] = make_float2(ab.x, ab.z);
+            v[kP / 2] = make_float2(cd.x, cd.z);
+        }
     }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < kP; ++m) v[m] = cadd(v[m], lds[((NY - (t + T * m)) & (NY - 1)) * CP + q]);
-    __syncthreads();
     fft_stages<NY, 1>(v, t, lds, ColAddr<CP>{q}, tw);
 
     // nearest of {+1, -1}: bit = (Re h < 0); Re h = 0 -> +1.  The CP lanes of
