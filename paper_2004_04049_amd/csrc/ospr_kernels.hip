@@ -336,12 +336,17 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
 // others.  Each thread draws its pixels (x, y) and their mirrors (-x, -y):
 // for x = t + T*m the mirror column is t' + T*m' with t' = (T - t) mod T and
 // m' = 15 - m (t > 0) or (16 - m) mod 16 (t = 0), i.e. slot m' of a thread t'.
-// Grid: ceil((ny/2 + 1) / rows) * n_sf blocks; the surplus rows of a
-// sub-frame's last block repeat row ny/2 and are not stored.
+// A block serves kOsprRowsSf consecutive sub-frames of its rows, so each
+// thread loads its target values once for all of them (the target does not
+// stay in L2 between sub-frames of a whole-frame launch).
+// Grid: ceil((ny/2 + 1) / rows) * ceil(n_sf / kOsprRowsSf) blocks; the surplus
+// rows of the last row block repeat row ny/2 and are not stored.
 // -------------------------------------------------------------------------
+constexpr int kOsprRowsSf = 4;
+
 template <int NX>
-__global__ __launch_bounds__(1024) void k_ospr_rows_h(const float* __restrict__ target, int ny, PhaseSrc src,
-                                                      uint64_t c0, const uint64_t* __restrict__ c0_base,
+__global__ __launch_bounds__(512) void k_ospr_rows_h(const float* __restrict__ target, int ny, int n_sf,
+                                                      PhaseSrc src, uint64_t c0, const uint64_t* __restrict__ c0_base,
                                                       float2* __restrict__ x1, const float2* __restrict__ tw,
                                                       int pitch)
 {
@@ -350,18 +355,13 @@ __global__ __launch_bounds__(1024) void k_ospr_rows_h(const float* __restrict__ 
     const int rows = blockDim.x / T;
     const int row = threadIdx.x / T, t = threadIdx.x % T;
     const int nh = ny / 2 + 1;
-    const int blocks_per_sf = (nh + rows - 1) / rows;
-    const int k = blockIdx.x / blocks_per_sf;
-    const int yr = (blockIdx.x % blocks_per_sf) * rows + row;
+    const int row_blocks = (nh + rows - 1) / rows;
+    const int kb = blockIdx.x / row_blocks;
+    const int yr = (blockIdx.x % row_blocks) * rows + row;
     const int y = yr < nh ? yr : nh - 1;
     const int ym = (ny - y) & (ny - 1);
     const int tm = (T - t) & (T - 1);
     const uint64_t npix = (uint64_t)NX * (uint64_t)ny;
-    const uint64_t pos0 = pool_pos(src, c0, c0_base, (uint64_t)k * npix + (uint64_t)y * NX + (uint64_t)t);
-    const uint64_t pos1 = pool_pos(src, c0, c0_base, (uint64_t)k * npix + (uint64_t)ym * NX + (uint64_t)tm);
-    const bool mseq = src.kind == SRC_MSEQ;
-    const uint32_t rs0 = mseq ? src.rows[(size_t)k * ny + y] : 0u;
-    const uint32_t rs1 = mseq ? src.rows[(size_t)k * ny + ym] : 0u;
     const auto rt = make_rsrc(target, (uint32_t)(npix * 4));
     const uint32_t toff0 = ((uint32_t)y * NX + (uint32_t)t) * 4u;
     const uint32_t toff1 = ((uint32_t)ym * NX + (uint32_t)tm) * 4u;
@@ -376,25 +376,33 @@ __global__ __launch_bounds__(1024) void k_ospr_rows_h(const float* __restrict__ 
         lt = (uint32_t*)(lds + rows * PadLen<NX>::v);
         phase_stage(src, (uint32_t)T, lt);
     }
-    float2 v[kP], w[kP];
-    phase_slots<kP>(src, pos0, (uint32_t)T, t, rs0, v, lt);
-    phase_slots<kP>(src, pos1, (uint32_t)T, tm, rs1, w, lt);
+    const bool mseq = src.kind == SRC_MSEQ;
     const bool t0 = t == 0;
+    const size_t plane = (size_t)nh * pitch;
+    const uint32_t ooff = ((uint32_t)y * (uint32_t)pitch + (uint32_t)t) * 8u;
+    const int k_end = min(n_sf, (kb + 1) * kOsprRowsSf);
+    for (int k = kb * kOsprRowsSf; k < k_end; ++k) {   // uniform over the block
+        const uint64_t pos0 = pool_pos(src, c0, c0_base, (uint64_t)k * npix + (uint64_t)y * NX + (uint64_t)t);
+        const uint64_t pos1 = pool_pos(src, c0, c0_base, (uint64_t)k * npix + (uint64_t)ym * NX + (uint64_t)tm);
+        const uint32_t rs0 = mseq ? src.rows[(size_t)k * ny + y] : 0u;
+        const uint32_t rs1 = mseq ? src.rows[(size_t)k * ny + ym] : 0u;
+        float2 v[kP], w[kP];
+        phase_slots<kP>(src, pos0, (uint32_t)T, t, rs0, v, lt);
+        phase_slots<kP>(src, pos1, (uint32_t)T, tm, rs1, w, lt);
 #pragma unroll
-    for (int m = 0; m < kP; ++m) {
-        const int mi = 15 - m, mz = (16 - m) & 15;
-        const float bm = t0 ? b[mz] : b[mi];
-        const float2 wm = t0 ? w[mz] : w[mi];
-        // R(x, y) + conj R(-x, -y)
-        v[m] = make_float2(fmaf(a[m], v[m].x, bm * wm.x), fmaf(a[m], v[m].y, -bm * wm.y));
-    }
-    fft_stages<NX, 1, RowAddrR, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, tw);
-    if (yr < nh) {
-        const size_t plane = (size_t)nh * pitch;
-        const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
-        const uint32_t ooff = ((uint32_t)y * (uint32_t)pitch + (uint32_t)t) * 8u;
+        for (int m = 0; m < kP; ++m) {
+            const int mi = 15 - m, mz = (16 - m) & 15;
+            const float bm = t0 ? b[mz] : b[mi];
+            const float2 wm = t0 ? w[mz] : w[mi];
+            // R(x, y) + conj R(-x, -y)
+            v[m] = make_float2(fmaf(a[m], v[m].x, bm * wm.x), fmaf(a[m], v[m].y, -bm * wm.y));
+        }
+        fft_stages<NX, 1, RowAddrR, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, tw);
+        if (yr < nh) {
+            const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
 #pragma unroll
-        for (int m = 0; m < kP; ++m) buf_st2(ro, ooff, (uint32_t)(m * T * 8), v[m]);
+            for (int m = 0; m < kP; ++m) buf_st2(ro, ooff, (uint32_t)(m * T * 8), v[m]);
+        }
     }
 }
 
@@ -402,15 +410,17 @@ hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, con
                               const uint64_t* c0_base, float2* x1, const float2* tw_x, const LaunchCfg& cfg,
                               hipStream_t s)
 {
-    const int rows = row_block_rows(nx, ny, cfg.rows_per_block, 0);
-    const int blocks_per_sf = (ny / 2 + 1 + rows - 1) / rows;
+    int rows = row_block_rows(nx, ny, cfg.rows_per_block, 0);
+    while (rows > 1 && rows * (nx / kP) > 512) rows >>= 1;   // the kernel's launch bound
+    const int row_blocks = (ny / 2 + 1 + rows - 1) / rows;
+    const int sf_blocks = (n_sf + kOsprRowsSf - 1) / kOsprRowsSf;
     HOLO_SWITCH_N(nx, {
         constexpr int T = N_ / kP;
         size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2) +
                      (src.kind == SRC_MSEQ || src.kind == SRC_CODES8 ? kPhaseLdsWords * sizeof(uint32_t) : 0);
         allow_lds(k_ospr_rows_h<N_>, lds);
-        hipLaunchKernelGGL((k_ospr_rows_h<N_>), dim3(blocks_per_sf * n_sf), dim3(rows * T), lds, s, target, ny, src,
-                           c0, c0_base, x1, tw_x, row_pitch(nx, cfg));
+        hipLaunchKernelGGL((k_ospr_rows_h<N_>), dim3(row_blocks * sf_blocks), dim3(rows * T), lds, s, target, ny,
+                           n_sf, src, c0, c0_base, x1, tw_x, row_pitch(nx, cfg));
     });
     return hipGetLastError();
 }
