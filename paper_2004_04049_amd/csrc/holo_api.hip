@@ -397,8 +397,8 @@ holo_status ospr_enqueue(const float* target, int64_t nx, int64_t ny, int n_sf, 
         const int ns = n_fields - k0 < l.chunk ? n_fields - k0 : l.chunk;
         const uint64_t ck = lut_wrap(lut, c0 + (uint64_t)k0 * (uint64_t)(nx * ny));
         const PhaseSrc src = make_src(lut, rs + (size_t)k0 * (size_t)ny);
-        // binary frames on the FP32 path transform only the Hermitian part of R
-        if (mode == OSPR_BINARY && cfg.prec == 0)
+        // binary frames transform only the Hermitian part of R
+        if (mode == OSPR_BINARY)
             LAUNCH("ospr_rows", s, launch_ospr_rows_h(target, (int)nx, (int)ny, ns, src, ck, c0_base, x1, tw_x, cfg, s));
         else
             LAUNCH("ospr_rows", s, launch_ospr_rows(target, (int)nx, (int)ny, ns, src, ck, c0_base, x1, tw_x, cfg, s));
@@ -641,7 +641,11 @@ holo_status time_runs(hipStream_t s, int reps, F f, double* ms_out)
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     holo_status st = f();   // warm-up (and first-use allocations)
-    if (!st) {
+    if (!st) st = f();
+    // the fastest of three batches: a single short batch is easily skewed by
+    // clock ramps after the host-side checks between candidates
+    float best = 0.0f;
+    for (int b = 0; b < 3 && !st; ++b) {
         HIP_TRY(hipStreamSynchronize(s));
         HIP_TRY(hipEventRecord(e0, s));
         for (int r = 0; r < reps && !st; ++r) st = f();
@@ -649,8 +653,9 @@ holo_status time_runs(hipStream_t s, int reps, F f, double* ms_out)
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        *ms_out = ms / reps;
+        if (b == 0 || ms < best) best = ms;
     }
+    if (!st) *ms_out = best / reps;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return st;
@@ -1194,9 +1199,8 @@ holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t ny, int3
     };
     if ((st = time_runs(s, reps, [&] { return run(best); }, &best_ms))) return st;
     // coordinate descent over each kernel's shape; a candidate counts only if
-    // it reproduces the reference holograms bit for bit and its NMSE
-    // a candidate counts only if it reproduces the reference holograms bit for
-    // bit; its NMSE may differ by the FP32 summation order of the average
+    // it reproduces the reference holograms bit for bit; its NMSE may differ
+    // by the FP32 summation order of the average
     auto try_plan = [&](const LaunchCfg& c) {
         double ms = 0.0;
         if (run(c) != HOLO_OK) return;

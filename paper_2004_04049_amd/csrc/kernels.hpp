@@ -56,7 +56,7 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
                             const uint64_t* c0_base, float2* x1, const float2* tw_x, const LaunchCfg& cfg,
                             hipStream_t s);
 
-// OSPR K1 for binary frames on the FP32 path: the Hermitian part of R (whose
+// OSPR K1 for binary frames: the Hermitian part of R (whose
 // inverse transform is Re H), inverse row transform of rows 0..ny/2 only,
 // written as half planes of ny/2 + 1 rows (stride (ny/2 + 1) * pitch).
 hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, const PhaseSrc& src, uint64_t c0,
@@ -72,9 +72,8 @@ hipError_t launch_mseq_rows(const uint32_t* aux, uint64_t c0, const uint64_t* c0
 hipError_t launch_phase_mask(const PhaseSrc& src, uint64_t c0, int nx, int ny, int n_sf, float2* out,
                              hipStream_t s);
 // OSPR K2: inverse column transform, binarise + pack, forward column transform
-// of the +-1 column, half spectrum (rows 0..ny/2) out.  x1 comes from
-// launch_ospr_rows_h (half planes) when cfg.prec == 0, else from
-// launch_ospr_rows (full planes).
+// of the +-1 column, half spectrum (rows 0..ny/2) out; x1 holds the half
+// planes of launch_ospr_rows_h.
 hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
                             const float2* tw_y, const LaunchCfg& cfg, hipStream_t s);
 // K2 variants: mode OSPR_PAIRS writes sub-frames 2j (Re H) and 2j+1 (Im H) of

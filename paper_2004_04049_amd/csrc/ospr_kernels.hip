@@ -327,7 +327,7 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
 }
 
 // -------------------------------------------------------------------------
-// K1 for binary frames (FP32).  Only Re H is binarised, and
+// K1 for binary frames.  Only Re H is binarised, and
 // Re IFFT2{R} = IFFT2{R_h} with R_h(x, y) = (R(x, y) + conj R(-x, -y))/2, the
 // Hermitian part of R (indices mod nx, ny; the 1/2 is dropped, since only
 // signs are read).  Row transforms of a Hermitian field obey
@@ -344,11 +344,12 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
 // -------------------------------------------------------------------------
 constexpr int kOsprRowsSf = 4;
 
-template <int NX>
-__global__ __launch_bounds__(512) void k_ospr_rows_h(const float* __restrict__ target, int ny, int n_sf,
-                                                      PhaseSrc src, uint64_t c0, const uint64_t* __restrict__ c0_base,
-                                                      float2* __restrict__ x1, const float2* __restrict__ tw,
-                                                      int pitch)
+template <int NX, int P>
+__global__ __launch_bounds__(P ? 256 : 512) void k_ospr_rows_h(const float* __restrict__ target, int ny, int n_sf,
+                                                                PhaseSrc src, uint64_t c0,
+                                                                const uint64_t* __restrict__ c0_base,
+                                                                float2* __restrict__ x1, const float2* __restrict__ tw,
+                                                                int pitch, const uint4* __restrict__ dftop)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NX / kP;
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(512) void k_ospr_rows_h(const float* __restrict__ t
             // R(x, y) + conj R(-x, -y)
             v[m] = make_float2(fmaf(a[m], v[m].x, bm * wm.x), fmaf(a[m], v[m].y, -bm * wm.y));
         }
-        fft_stages<NX, 1, RowAddrR, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, tw);
+        fft_any<NX, 1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, RowsOf<NX>{}, tw, dftop);
         if (yr < nh) {
             const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
 #pragma unroll
@@ -410,17 +411,17 @@ hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, con
                               const uint64_t* c0_base, float2* x1, const float2* tw_x, const LaunchCfg& cfg,
                               hipStream_t s)
 {
-    int rows = row_block_rows(nx, ny, cfg.rows_per_block, 0);
-    while (rows > 1 && rows * (nx / kP) > 512) rows >>= 1;   // the kernel's launch bound
+    int rows = row_block_rows(nx, ny, cfg.rows_per_block, cfg.prec);
+    while (rows > 1 && rows * (nx / kP) > 512) rows >>= 1;   // the FP32 kernel's launch bound
     const int row_blocks = (ny / 2 + 1 + rows - 1) / rows;
     const int sf_blocks = (n_sf + kOsprRowsSf - 1) / kOsprRowsSf;
-    HOLO_SWITCH_N(nx, {
+    HOLO_SWITCH_NP(nx, cfg.prec, {
         constexpr int T = N_ / kP;
         size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2) +
                      (src.kind == SRC_MSEQ || src.kind == SRC_CODES8 ? kPhaseLdsWords * sizeof(uint32_t) : 0);
-        allow_lds(k_ospr_rows_h<N_>, lds);
-        hipLaunchKernelGGL((k_ospr_rows_h<N_>), dim3(row_blocks * sf_blocks), dim3(rows * T), lds, s, target, ny,
-                           n_sf, src, c0, c0_base, x1, tw_x, row_pitch(nx, cfg));
+        allow_lds(k_ospr_rows_h<N_, P_>, lds);
+        hipLaunchKernelGGL((k_ospr_rows_h<N_, P_>), dim3(row_blocks * sf_blocks), dim3(rows * T), lds, s, target, ny,
+                           n_sf, src, c0, c0_base, x1, tw_x, row_pitch(nx, cfg), DFTOP(cfg));
     });
     return hipGetLastError();
 }
@@ -428,74 +429,7 @@ hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, con
 // -------------------------------------------------------------------------
 // K2: inverse column transform, binarise + pack, forward column transform of
 // the +-1 column; writes the half spectrum rows 0..ny/2.
-// Grid: (nx / C) * n_sf blocks of C * (ny/16) threads.  Thread (c, t) owns
-// column x0 + c, rows t + T*m.  The C lanes of a row segment are adjacent in
-// the wave, so a ballot yields that row's C bits in raster order.
 // -------------------------------------------------------------------------
-template <int NY, int C, int P>
-__global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols(const float2* __restrict__ x1, int nx,
-                                                            uint32_t* __restrict__ bits, float2* __restrict__ x2,
-                                                            const float2* __restrict__ tw, int pitch,
-                                                            const uint4* __restrict__ dftop)
-{
-    extern __shared__ float2 lds[];
-    constexpr int T = NY / kP;
-    const int c = threadIdx.x % C, t = threadIdx.x / C;
-    const int lane = threadIdx.x & 63;
-    const int ncb = nx / C;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int k = tile / ncb;
-    const int x0 = (tile - k * ncb) * C;
-    const size_t npix = (size_t)nx * NY;
-    // one descriptor per sub-frame plane; lane offset (t*pitch + x0 + c)*8
-    // bytes, slot m adds the uniform m*T*pitch*8
-    const size_t plane = (size_t)NY * pitch;
-    const uint32_t voff = ((uint32_t)t * (uint32_t)pitch + (uint32_t)(x0 + c)) * 8u;
-    const uint32_t mst = (uint32_t)T * (uint32_t)pitch * 8u;
-    const auto rin = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
-    float2 v[kP];
-#pragma unroll
-    for (int m = 0; m < kP; ++m) v[m] = buf_ld2(rin, voff, m * mst);
-    fft_any<NY, 1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
-
-    // nearest of {+1, -1}: bit = (Re H < 0); Re H = 0 -> +1
-    const auto rbits = make_rsrc(bits + (size_t)k * (npix / 32), (uint32_t)(npix / 8));
-    const uint32_t boff = ((uint32_t)t * (uint32_t)nx + (uint32_t)x0) / 8u;
-    const uint32_t bst = (uint32_t)T * (uint32_t)nx / 8u;
-#pragma unroll
-    for (int m = 0; m < kP; ++m) {
-        const bool neg = v[m].x < 0.0f;
-        const uint64_t mask = __ballot(neg);
-        if (c == 0) {
-            const uint32_t chunk = (uint32_t)(mask >> (lane & ~(C - 1)));
-            if (C == 16) __builtin_amdgcn_raw_buffer_store_b16((unsigned short)chunk, rbits, boff, m * bst, 0);
-            else __builtin_amdgcn_raw_buffer_store_b8((unsigned char)chunk, rbits, boff, m * bst, 0);
-        }
-        v[m] = make_float2(neg ? -1.0f : 1.0f, 0.0f);
-    }
-    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
-    // rows v = t + T*m <= NY/2: every slot m < 8, and m = 8 for t = 0 only
-    const size_t hplane = (size_t)(NY / 2 + 1) * pitch;
-    const auto rout = make_rsrc(x2 + (size_t)k * hplane, (uint32_t)(hplane * 8));
-#pragma unroll
-    for (int m = 0; m < kP / 2; ++m) buf_st2(rout, voff, m * mst, v[m]);
-    if (t == 0) buf_st2(rout, voff, (kP / 2) * mst, v[kP / 2]);
-}
-
-// FP32 K2 on column pairs, from the half plane of k_ospr_rows_h.  Its columns
-// are Hermitian (X(-y) = conj X(y)), so their inverse transforms are real:
-// columns a, b of a pair share one inverse transform,
-// IFFT{X_a + i X_b} = h_a + i h_b with h_a, h_b real, and only signs are read
-// from it.  Likewise their +-1 columns share one forward transform
-// Z = F{B_a + i B_b}, separated as F_a(v) = (Z(v) + conj Z(-v))/2,
-// F_b(v) = (Z(v) - conj Z(-v))/(2i) (as in the pair variant below).  Half the
-// transforms of k_ospr_cols; signs and spectra differ from it by rounding only.
-// Grid: (nx / C) * n_sf blocks of (C/2) * (ny/16) threads; thread (q, t) owns
-// columns x0 + 2q and x0 + 2q + 1 (one 16-byte load per row; the two results
-// leave as two 8-byte stores), rows t + T*m.  Slots m < 8 load row
-// y = t + T*m; slot m >= 8 loads the mirror row ny - y = (T - t) + T*(15 - m)
-// (also for t = 0, where slot 8 is row ny/2) and conjugates; rows 0 and ny/2
-// are real up to rounding, and their real parts are taken.
 // Bits 0..7 of x moved to the even positions 0, 2, .., 14.
 __device__ __forceinline__ uint32_t spread_bits8(uint32_t x)
 {
@@ -504,11 +438,12 @@ __device__ __forceinline__ uint32_t spread_bits8(uint32_t x)
     return (x | (x << 1)) & 0x5555u;
 }
 
-template <int NY, int C>
+template <int NY, int C, int P>
 __global__ __launch_bounds__((C / 2) * (NY / kP)) void k_ospr_cols2(const float2* __restrict__ x1, int nx,
                                                                    uint32_t* __restrict__ bits,
                                                                    float2* __restrict__ x2,
-                                                                   const float2* __restrict__ tw, int pitch)
+                                                                   const float2* __restrict__ tw, int pitch,
+                                                                   const uint4* __restrict__ dftop)
 {
     extern __shared__ float2 lds[];
     constexpr int CP = C / 2;
@@ -537,7 +472,7 @@ __global__ __launch_bounds__((C / 2) * (NY / kP)) void k_ospr_cols2(const float2
             v[kP / 2] = make_float2(cd.x, cd.z);
         }
     }
-    fft_stages<NY, 1>(v, t, lds, ColAddr<CP>{q}, tw);
+    fft_any<NY, 1, P>(v, t, lds, ColAddr<CP>{q}, ColsOf<NY, CP>{}, tw, dftop);
 
     // nearest of {+1, -1}: bit = (Re h < 0); Re h = 0 -> +1.  The CP lanes of
     // a row give the even columns' bits (ballot of .x) and the odd columns'
@@ -558,7 +493,7 @@ __global__ __launch_bounds__((C / 2) * (NY / kP)) void k_ospr_cols2(const float2
         }
         v[m] = make_float2(na ? -1.0f : 1.0f, nb ? -1.0f : 1.0f);
     }
-    fft_stages<NY, -1>(v, t, lds, ColAddr<CP>{q}, tw);
+    fft_any<NY, -1, P>(v, t, lds, ColAddr<CP>{q}, ColsOf<NY, CP>{}, tw, dftop);
 
     // separation: rows v <= NY/2 (slots m < 8, and m = 8 for t = 0) need Z at
     // -v, which lies in slots 8..15, or slot 0 for v = 0
@@ -585,23 +520,29 @@ __global__ __launch_bounds__((C / 2) * (NY / kP)) void k_ospr_cols2(const float2
 hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
                             const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
 {
-    const int C = cfg.prec ? 8 : col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8);
-    HOLO_SWITCH_NP(ny, cfg.prec, HOLO_SWITCH_C816(C, {
+    // matrix cores: 16-column tiles, i.e. 8 transforms per block, as the
+    // engine's column layout wants
+    const int C = cfg.prec ? 16 : col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8);
+    HOLO_SWITCH_NP(ny, cfg.prec, {
         constexpr int T = N_ / kP;
-        if constexpr (P_ == 0) {
-            if ((C_ / 2) * T <= 1024) {
-                size_t lds = (size_t)(C_ / 2) * PadLen<N_>::v * sizeof(float2);
-                allow_lds(k_ospr_cols2<N_, C_>, lds);
-                hipLaunchKernelGGL((k_ospr_cols2<N_, C_>), dim3((nx / C_) * n_sf), dim3((C_ / 2) * T), lds, s, x1,
-                                   nx, bits, x2, tw_y, row_pitch(nx, cfg));
+        if constexpr (P_ != 0) {
+            if (8 * T <= 1024) {
+                size_t lds = (size_t)8 * PadLen<N_>::v * sizeof(float2);
+                allow_lds(k_ospr_cols2<N_, 16, P_>, lds);
+                hipLaunchKernelGGL((k_ospr_cols2<N_, 16, P_>), dim3((nx / 16) * n_sf), dim3(8 * T), lds, s, x1, nx,
+                                   bits, x2, tw_y, row_pitch(nx, cfg), DFTOP(cfg));
             }
-        } else if (C_ * T <= 1024) {
-            size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
-            allow_lds(k_ospr_cols<N_, C_, P_>, lds);
-            hipLaunchKernelGGL((k_ospr_cols<N_, C_, P_>), dim3((nx / C_) * n_sf), dim3(C_ * T), lds, s, x1, nx, bits,
-                               x2, tw_y, row_pitch(nx, cfg), DFTOP(cfg));
+        } else {
+            HOLO_SWITCH_C816(C, {
+                if ((C_ / 2) * T <= 1024) {
+                    size_t lds = (size_t)(C_ / 2) * PadLen<N_>::v * sizeof(float2);
+                    allow_lds(k_ospr_cols2<N_, C_, 0>, lds);
+                    hipLaunchKernelGGL((k_ospr_cols2<N_, C_, 0>), dim3((nx / C_) * n_sf), dim3((C_ / 2) * T), lds, s,
+                                       x1, nx, bits, x2, tw_y, row_pitch(nx, cfg), nullptr);
+                }
+            });
         }
-    }));
+    });
     return hipGetLastError();
 }
 
