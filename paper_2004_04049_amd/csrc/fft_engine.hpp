@@ -377,15 +377,20 @@ __device__ __forceinline__ float buf_ld1(__amdgpu_buffer_rsrc_t r, uint32_t voff
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
-// 16-byte loads only.  Buffer stores stay at 8 bytes per lane: on gfx950 a
-// 16-byte buffer store with a scalar-register offset was seen to read its data
-// registers after the next vector instruction had overwritten them (lanes
-// 12..15 of a 16-lane group, now and then), and the compiler guards that
-// hazard only for the form without a scalar offset.
+// 16-byte stores take their whole offset in the lane register and a zero
+// scalar offset.  A buffer store of more than 8 bytes per lane may read its
+// data registers after the next vector instruction has overwritten them; the
+// compiler inserts the wait for the form without a scalar-register offset, and
+// on gfx950 the form with one (which it leaves unguarded) was seen to lose
+// data words (lanes 12..15 of a 16-lane group, now and then).
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ float4 buf_ld4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
 {
     return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_st4z(__amdgpu_buffer_rsrc_t r, uint32_t voff, float4 x)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, x), r, voff, 0u, 0);
 }
 
 }  // namespace holo

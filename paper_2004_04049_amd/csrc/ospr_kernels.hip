@@ -429,6 +429,22 @@ hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, con
 // -------------------------------------------------------------------------
 // K2: inverse column transform, binarise + pack, forward column transform of
 // the +-1 column; writes the half spectrum rows 0..ny/2.
+//
+// Columns are taken in pairs, from the half plane of k_ospr_rows_h.  Its
+// columns are Hermitian (X(-y) = conj X(y)), so their inverse transforms are
+// real: columns a, b of a pair share one inverse transform,
+// IFFT{X_a + i X_b} = h_a + i h_b with h_a, h_b real, and only signs are read
+// from it.  Likewise their +-1 columns share one forward transform
+// Z = F{B_a + i B_b}, separated as F_a(v) = (Z(v) + conj Z(-v))/2,
+// F_b(v) = (Z(v) - conj Z(-v))/(2i) (as in the pair variant below).  Signs and
+// spectra differ from per-column transforms by rounding only.
+// Grid: (nx / C) * n_sf blocks of (C/2) * (ny/16) threads; thread (q, t) owns
+// columns x0 + 2q and x0 + 2q + 1 (one 16-byte load and one 16-byte store per
+// row), rows t + T*m.  Slots m < 8 load row y = t + T*m; slot m >= 8 loads the
+// mirror row ny - y = (T - t) + T*(15 - m) (also for t = 0, where slot 8 is row
+// ny/2) and conjugates; rows 0 and ny/2 are real up to rounding, and their real
+// parts are taken.  The C/2 lanes of a row segment are adjacent in the wave,
+// so two ballots give the row's C bits.
 // -------------------------------------------------------------------------
 // Bits 0..7 of x moved to the even positions 0, 2, .., 14.
 __device__ __forceinline__ uint32_t spread_bits8(uint32_t x)
@@ -502,18 +518,16 @@ __global__ __launch_bounds__((C / 2) * (NY / kP)) void k_ospr_cols2(const float2
     for (int m = kP / 2; m < kP; ++m) lds[(t + T * m) * CP + q] = v[m];
     if (t == 0) lds[q] = v[0];
     __syncthreads();
-    // column b through a descriptor based one element later, so the two 8-byte
-    // stores of a row are not merged into one 16-byte store
+    // one 16-byte store per row: F_a = (Z + conj Zm) / 2, F_b = (Z - conj Zm) / (2i)
     const size_t hplane = (size_t)(NY / 2 + 1) * pitch;
-    const auto rout_a = make_rsrc(x2 + (size_t)k * hplane, (uint32_t)(hplane * 8));
-    const auto rout_b = make_rsrc(x2 + (size_t)k * hplane + 1, (uint32_t)(hplane * 8 - 8));
+    const auto rout = make_rsrc(x2 + (size_t)k * hplane, (uint32_t)(hplane * 8));
 #pragma unroll
     for (int m = 0; m <= kP / 2; ++m) {
         if (m == kP / 2 && t != 0) break;
         const float2 z = v[m];
         const float2 zm = lds[((NY - (t + T * m)) & (NY - 1)) * CP + q];
-        buf_st2(rout_a, voff, m * mst, make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y)));   // (Z + conj Zm) / 2
-        buf_st2(rout_b, voff, m * mst, make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x)));   // (Z - conj Zm) / (2i)
+        buf_st4z(rout, voff + (uint32_t)m * mst,
+                 make_float4(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y), 0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x)));
     }
 }
 

@@ -1,13 +1,15 @@
-"""Build-level guard (CPU only): the gfx950 code of every kernel source has no
-buffer store wider than 64 bits per lane.
+"""Build-level guard (CPU only): in the gfx950 code of every kernel source, a
+buffer store wider than 64 bits per lane has a zero scalar offset, and the
+next instruction does not overwrite its data registers.
 
-A 16-byte buffer store with a scalar-register offset was seen, on gfx950, to
-read its data registers after the next vector instruction had overwritten
-them (some lanes, some blocks), and the compiler guards that hazard only for
-the form without a scalar offset.  The kernels therefore store at most 8 bytes
-per lane through buffer descriptors; this test compiles each source to AMD
-assembly with the library's own flags and checks that the compiler did not
-merge adjacent stores back into wider ones.
+A buffer store of more than 8 bytes per lane may read its data registers after
+the next vector instruction has overwritten them.  The compiler inserts the
+wait for the form without a scalar-register offset; with one, it leaves the
+store unguarded, and on gfx950 such 16-byte stores were seen to lose data words
+(some lanes, some blocks).  The kernels therefore pass the whole offset of a
+16-byte store in the lane register.  This test compiles each source to AMD
+assembly with the library's own flags and checks both properties, so that a
+change of code or compiler that brings back the unguarded form fails here.
 """
 import concurrent.futures as cf
 import os
@@ -22,7 +24,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, os.path.join(ROOT, "paper_2004_04049_amd"))
 import build as holo_build  # noqa: E402  (the package's build script; imports nothing of the library)
 
-WIDE = re.compile(r"^\s*buffer_store_dwordx[34]\b", re.M)
+WIDE = re.compile(r"^\s*buffer_store_dwordx[34]\s+(\S+),\s*(\S+),\s*(s\[\d+:\d+\]),\s*(\S+)")
+
+
+def _vregs(spec):
+    m = re.match(r"v\[(\d+):(\d+)\]$", spec)
+    if m:
+        return set(range(int(m.group(1)), int(m.group(2)) + 1))
+    m = re.match(r"v(\d+)$", spec)
+    return {int(m.group(1))} if m else set()
 
 
 def _asm(src, out_dir):
@@ -31,14 +41,43 @@ def _asm(src, out_dir):
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     with open(out) as f:
-        return os.path.basename(src), f.read()
+        return os.path.basename(src), f.read().splitlines()
+
+
+def _problems(lines):
+    bad = []
+    for i, line in enumerate(lines):
+        m = WIDE.match(line)
+        if not m:
+            continue
+        if m.group(4) != "0":
+            bad.append(("scalar offset", line.strip()))
+            continue
+        j = i + 1
+        while j < len(lines) and (not lines[j].strip() or lines[j].lstrip().startswith((";", "."))):
+            j += 1
+        nxt = lines[j].strip() if j < len(lines) else ""
+        if nxt.startswith("v_"):
+            dst = nxt.split(None, 1)[1].split(",")[0].strip()
+            if _vregs(dst) & _vregs(m.group(1)):
+                bad.append(("data overwritten", line.strip() + " / " + nxt))
+    return bad
 
 
 @pytest.mark.skipif(not os.path.exists(holo_build.HIPCC) and shutil.which("hipcc") is None,
                     reason="hipcc not available")
-def test_no_wide_buffer_stores(tmp_path):
+def test_wide_buffer_stores_are_guarded(tmp_path):
     srcs = holo_build.sources()
     with cf.ThreadPoolExecutor(max_workers=min(len(srcs), 8)) as ex:
         results = list(ex.map(lambda s: _asm(s, str(tmp_path)), srcs))
-    bad = {name: len(WIDE.findall(text)) for name, text in results if WIDE.search(text)}
-    assert not bad, f"buffer stores wider than 64 bits: {bad}"
+    bad = {name: probs[:3] for name, lines in results if (probs := _problems(lines))}
+    assert not bad, f"unguarded wide buffer stores: {bad}"
+
+
+def test_checker_flags_the_unguarded_forms():
+    # the checker itself, on hand-written lines
+    assert _problems(["buffer_store_dwordx4 v[2:5], v1, s[0:3], s77 offen", "v_mov_b32 v9, 0"])
+    assert _problems(["buffer_store_dwordx4 v[2:5], v1, s[0:3], 0 offen", "v_mul_f32_e32 v2, 0.5, v0"])
+    assert not _problems(["buffer_store_dwordx4 v[2:5], v1, s[0:3], 0 offen", "s_nop 1",
+                          "v_mul_f32_e32 v2, 0.5, v0"])
+    assert not _problems(["buffer_store_dwordx2 v[2:3], v1, s[0:3], s77 offen", "v_mov_b32 v2, 0"])
