@@ -126,7 +126,7 @@ def main():
         plan = [int(v) for v in args.plan.split(",")]
         h.plan_set(h.PLAN_OSPR, nx, ny, n_sf, plan)
     else:
-        plan = h.autotune_ospr(target, n_sf, lut, reps=5)
+        plan = h.autotune_ospr(target, n_sf, lut, reps=20)
     cursor = 0
     for _ in range(args.warmup):
         _, _, cursor = h.ospr_generate(target, n_sf, lut, cursor, bits=bits, want_nmse=False, nmse_out=nmse_dev)

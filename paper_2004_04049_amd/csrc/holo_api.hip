@@ -1197,6 +1197,10 @@ holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t ny, int3
     auto run = [&](const LaunchCfg& c) {
         return ospr_run(device, target, nx, ny, n_sf, lut, 0, scratch_bits, nullptr, nullptr, 0, s, c);
     };
+    // bring the clocks up before anything is timed: candidates are timed in a
+    // fixed order, and a ramp during the search favours the later ones
+    for (int i = 0; i < 200; ++i)
+        if ((st = run(best))) return st;
     if ((st = time_runs(s, reps, [&] { return run(best); }, &best_ms))) return st;
     // coordinate descent over each kernel's shape; a candidate counts only if
     // it reproduces the reference holograms bit for bit; its NMSE may differ
@@ -1286,7 +1290,8 @@ holo_status holo_autotune_gs(const float* target, int64_t nx, int64_t ny, const 
         GsArgs q = a;
         q.nmse = nullptr;
         auto run = [&](const LaunchCfg& c) { return gs_run(device, q, s, c); };
-        st = time_runs(s, reps, [&] { return run(best); }, &best_ms);
+        for (int i = 0; i < 20 && !st; ++i) st = run(best);   // clocks up before timing
+        if (!st) st = time_runs(s, reps, [&] { return run(best); }, &best_ms);
         // points per thread first (changes the FP32 factorisation, so its
         // guard is a tolerance: per-iteration NMSE within 1e-5 relative and
         // codes within 1e-3 of the pixels), then the shapes (exact guard)

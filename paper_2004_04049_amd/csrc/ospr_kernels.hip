@@ -336,17 +336,16 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
 // others.  Each thread draws its pixels (x, y) and their mirrors (-x, -y):
 // for x = t + T*m the mirror column is t' + T*m' with t' = (T - t) mod T and
 // m' = 15 - m (t > 0) or (16 - m) mod 16 (t = 0), i.e. slot m' of a thread t'.
-// A block serves kOsprRowsSf consecutive sub-frames of its rows, so each
-// thread loads its target values once for all of them (the target does not
-// stay in L2 between sub-frames of a whole-frame launch).
-// Grid: ceil((ny/2 + 1) / rows) * ceil(n_sf / kOsprRowsSf) blocks; the surplus
-// rows of the last row block repeat row ny/2 and are not stored.
+// A block serves `spb` consecutive sub-frames of its rows, so each thread
+// loads its target values once for all of them (the target does not stay in
+// L2 between sub-frames of a whole-frame launch).
+// Grid: ceil((ny/2 + 1) / rows) * ceil(n_sf / spb) blocks; the surplus rows of
+// the last row block repeat row ny/2 and are not stored.
 // -------------------------------------------------------------------------
-constexpr int kOsprRowsSf = 4;
 
 template <int NX, int P>
 __global__ __launch_bounds__(P ? 256 : 512) void k_ospr_rows_h(const float* __restrict__ target, int ny, int n_sf,
-                                                                PhaseSrc src, uint64_t c0,
+                                                                int spb, PhaseSrc src, uint64_t c0,
                                                                 const uint64_t* __restrict__ c0_base,
                                                                 float2* __restrict__ x1, const float2* __restrict__ tw,
                                                                 int pitch, const uint4* __restrict__ dftop)
@@ -381,8 +380,8 @@ __global__ __launch_bounds__(P ? 256 : 512) void k_ospr_rows_h(const float* __re
     const bool t0 = t == 0;
     const size_t plane = (size_t)nh * pitch;
     const uint32_t ooff = ((uint32_t)y * (uint32_t)pitch + (uint32_t)t) * 8u;
-    const int k_end = min(n_sf, (kb + 1) * kOsprRowsSf);
-    for (int k = kb * kOsprRowsSf; k < k_end; ++k) {   // uniform over the block
+    const int k_end = min(n_sf, (kb + 1) * spb);
+    for (int k = kb * spb; k < k_end; ++k) {   // uniform over the block
         const uint64_t pos0 = pool_pos(src, c0, c0_base, (uint64_t)k * npix + (uint64_t)y * NX + (uint64_t)t);
         const uint64_t pos1 = pool_pos(src, c0, c0_base, (uint64_t)k * npix + (uint64_t)ym * NX + (uint64_t)tm);
         const uint32_t rs0 = mseq ? src.rows[(size_t)k * ny + y] : 0u;
@@ -414,14 +413,18 @@ hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, con
     int rows = row_block_rows(nx, ny, cfg.rows_per_block, cfg.prec);
     while (rows > 1 && rows * (nx / kP) > 512) rows >>= 1;   // the FP32 kernel's launch bound
     const int row_blocks = (ny / 2 + 1 + rows - 1) / rows;
-    const int sf_blocks = (n_sf + kOsprRowsSf - 1) / kOsprRowsSf;
+    // sub-frames per block: 8 while the launch keeps >= 1024 blocks (measured
+    // at 1024^2, 24 sub-frames: 8 -> 37.5 us, 4 -> 38.9 us, 2 -> 39.0 us)
+    int spb = 8;
+    while (spb > 1 && (long)row_blocks * ((n_sf + spb - 1) / spb) < 1024) spb >>= 1;
+    const int sf_blocks = (n_sf + spb - 1) / spb;
     HOLO_SWITCH_NP(nx, cfg.prec, {
         constexpr int T = N_ / kP;
         size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2) +
                      (src.kind == SRC_MSEQ || src.kind == SRC_CODES8 ? kPhaseLdsWords * sizeof(uint32_t) : 0);
         allow_lds(k_ospr_rows_h<N_, P_>, lds);
         hipLaunchKernelGGL((k_ospr_rows_h<N_, P_>), dim3(row_blocks * sf_blocks), dim3(rows * T), lds, s, target, ny,
-                           n_sf, src, c0, c0_base, x1, tw_x, row_pitch(nx, cfg), DFTOP(cfg));
+                           n_sf, spb, src, c0, c0_base, x1, tw_x, row_pitch(nx, cfg), DFTOP(cfg));
     });
     return hipGetLastError();
 }
@@ -535,8 +538,10 @@ hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t
                             const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
 {
     // matrix cores: 16-column tiles, i.e. 8 transforms per block, as the
-    // engine's column layout wants
-    const int C = cfg.prec ? 16 : col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8);
+    // engine's column layout wants.  FP32: 8-column tiles (4 transforms per
+    // block) unless planned; measured at 1024^2, 24 sub-frames: 50.3 us
+    // against 55.2 us for 16-column tiles
+    const int C = cfg.prec ? 16 : cfg.cols_per_block > 0 ? col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8) : 8;
     HOLO_SWITCH_NP(ny, cfg.prec, {
         constexpr int T = N_ / kP;
         if constexpr (P_ != 0) {
