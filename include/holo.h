@@ -330,7 +330,10 @@ HOLO_API holo_status holo_phase_mask(const holo_lut* lut, uint64_t cursor, int64
  * heuristic and the autotuner use 8 or 16 only, as 4 rounds more often).  Plans
  * are keyed by kind (0 = OSPR, 1 = GS), nx, ny and n_sf (ignored for GS).
  * holo_autotune_ospr / holo_autotune_gs time candidate plans on the caller's
- * inputs (coordinate descent, `reps` timed runs each) and keep the fastest
+ * inputs (coordinate descent, after a warm-up of the default plan; a
+ * candidate's time is the fastest of three batches of `reps` runs; about
+ * 40 candidates for OSPR, so 20-run batches of a 0.12 ms frame take well under
+ * a second) and keep the fastest
  * whose holograms (bits / codes) equal those of the default plan exactly and
  * whose NMSE agrees to 1e-6 relative (FP32 summation order of the average);
  * GS points-per-thread candidates are kept when codes differ on at most 1e-3
