@@ -107,6 +107,13 @@ def test_ospr_1024_full_size(holo, orc, n_lut):
     assert ties < 24 * 1024 * 1024 * 1e-3
 
 
+def test_ospr_1024_partial_subframe_group(holo, orc):
+    # the row pass serves up to 8 sub-frames per block at this size; 12
+    # sub-frames leave a last group of 4
+    t = synth.blob_target(1024, 1024, 23)
+    _ospr_case(holo, orc, 1024, 1024, 12, 10007, 7, t)
+
+
 def test_ospr_2048_tall_and_wide(holo, orc):
     t = synth.blob_target(2048, 128, 21)
     _ospr_case(holo, orc, 2048, 128, 3, 10007, 11, t)
