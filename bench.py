@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--cnn-held", type=int, default=8, help="learned-seed held-out targets (1024^2)")
     ap.add_argument("--cnn-epochs", type=int, default=2)
     ap.add_argument("--plan", default=None,
-                    help="OSPR launch plan 'cols,rows,ksplit,recon_cols,pad' to use instead of autotuning")
+                    help="OSPR launch plan 'cols,rows,ksplit,recon_cols,pad,chunk[,pts]' to use instead of autotuning")
     ap.add_argument("--calib", action="store_true",
                     help="finish with a plain 256 MiB copy kernel (reference for memory counters)")
     return ap.parse_args()
@@ -77,9 +77,10 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, sf_per_launch):
     """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they
-    were taken on the current kernel sources; else None."""
+    were taken on the current kernel sources with the same number of
+    sub-frames per launch (chunking); else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -87,7 +88,7 @@ def measured_traffic(kernel, workload):
         with open(p) as f:
             rec = json.load(f)
         e = rec.get(workload, {}).get(kernel)
-        if not e or e.get("source_hash") != source_hash():
+        if not e or e.get("source_hash") != source_hash() or e.get("sf_per_launch") != sf_per_launch:
             return None
         return e["bytes_per_launch"]
     except Exception:
@@ -164,7 +165,8 @@ def main():
         if k in kern:
             kern[k]["algorithmic_GBps"] = kbytes[k] / (kern[k]["avg_us"] * 1e-6) / 1e9
     workload = f"ospr_{nx}x{ny}_sf{n_sf}_lut{n_lut}"
-    traffic = measured_traffic(dom, workload)
+    chunk = plan[5] if plan and len(plan) > 5 else 0
+    traffic = measured_traffic(dom, workload, chunk if 0 < chunk < n_sf else n_sf)
     step_bytes = sum(ospr_kernel_bytes(nx, ny, n_sf, n_lut).values())
     roofline = {
         "bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
