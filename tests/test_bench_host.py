@@ -1,0 +1,54 @@
+"""Host logic of bench.py (CPU only): the canonical byte model per launch and
+the gating of measured traffic on kernel sources and sub-frames per launch."""
+import json
+
+import bench
+
+
+def test_byte_model_per_subframe():
+    # per sub-frame: K1 writes 8 B/px, K2 reads 8 and writes 1/8 + 8, K3 reads 8;
+    # the target (4 B/px) is read once per frame by K1 and once by K3
+    nx = ny = 1024
+    n = nx * ny
+    n_sf = 24
+    kb = bench.ospr_kernel_bytes(nx, ny, n_sf, 65536)
+    total = sum(kb.values())
+    assert total == n * (32.125 * n_sf + 8)
+    assert kb["ospr_cols"] == n_sf * n * 16.125
+    # chunked plans: K1 and K2 per launch of `chunk` sub-frames; K3 whole frame
+    kc = bench.ospr_kernel_bytes(nx, ny, n_sf, 65536, chunk=8)
+    assert kc["ospr_cols"] == 8 * n * 16.125
+    assert kc["ospr_rows"] * 3 == kb["ospr_rows"]
+    assert kc["recon_rows"] == kb["recon_rows"]
+    # a table longer than 2^16 entries is charged to K1 (8 B per unique entry read)
+    big = bench.ospr_kernel_bytes(nx, ny, n_sf, 1 << 20)
+    assert big["ospr_rows"] - kb["ospr_rows"] == 8 * (1 << 20)
+    huge = bench.ospr_kernel_bytes(nx, ny, n_sf, 1 << 30)
+    assert huge["ospr_rows"] - kb["ospr_rows"] == 8 * n * n_sf
+
+
+def test_measured_traffic_gating(tmp_path, monkeypatch):
+    root = tmp_path
+    (root / "profiles").mkdir()
+    h = bench.source_hash()
+    rec = {"w": {"ospr_cols": {"bytes_per_launch": 123, "source_hash": h, "sf_per_launch": 24}}}
+    (root / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    monkeypatch.setattr(bench, "source_hash", lambda: h)
+    assert bench.measured_traffic("ospr_cols", "w", 24) == 123
+    assert bench.measured_traffic("ospr_cols", "w", 12) is None        # other chunking
+    assert bench.measured_traffic("ospr_rows", "w", 24) is None        # not profiled
+    assert bench.measured_traffic("ospr_cols", "other", 24) is None
+    monkeypatch.setattr(bench, "source_hash", lambda: "0" * 16)        # sources changed
+    assert bench.measured_traffic("ospr_cols", "w", 24) is None
+
+
+def test_committed_traffic_matches_sources():
+    # the committed profile summary was taken on the committed kernel sources
+    with open(bench.os.path.join(bench.ROOT, "profiles", "traffic.json")) as f:
+        rec = json.load(f)
+    entries = rec["ospr_1024x1024_sf24_lut65536"]
+    assert set(entries) >= {"ospr_rows", "ospr_cols", "recon_rows"}
+    for e in entries.values():
+        assert e["source_hash"] == bench.source_hash()
+        assert abs(e["bytes_per_launch"] - e["fetch_bytes"] - e["write_bytes"]) <= 1   # rounded separately
