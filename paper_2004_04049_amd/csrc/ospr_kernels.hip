@@ -265,63 +265,81 @@ hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int n
 }
 
 // -------------------------------------------------------------------------
-// K1: LUT phase randomisation fused with the inverse row transform.
-// Grid: (ny / rows) * n_sf blocks of rows * (nx/16) threads.
+// K1: LUT phase randomisation fused with the inverse row transform (full
+// planes, for the pair and eight-level variants).  A block serves `spb`
+// consecutive sub-frames of its rows and loads its target values once.
+// Grid: (ny / rows) * ceil(n_sf / spb) blocks of rows * (nx/16) threads.
 // -------------------------------------------------------------------------
 template <int NX, int P>
-__global__ __launch_bounds__(P ? 256 : 1024) void k_ospr_rows(const float* __restrict__ target, int ny,
-                                                    PhaseSrc src, uint64_t c0,
-                                                    const uint64_t* __restrict__ c0_base,
-                                                    float2* __restrict__ x1, const float2* __restrict__ tw,
-                                                    int pitch, const uint4* __restrict__ dftop)
+__global__ __launch_bounds__(P ? 256 : 512) void k_ospr_rows(const float* __restrict__ target, int ny, int n_sf,
+                                                              int spb, PhaseSrc src, uint64_t c0,
+                                                              const uint64_t* __restrict__ c0_base,
+                                                              float2* __restrict__ x1, const float2* __restrict__ tw,
+                                                              int pitch, const uint4* __restrict__ dftop)
 {
     extern __shared__ float2 lds[];
     constexpr int T = NX / kP;
     const int rows = blockDim.x / T;
     const int row = threadIdx.x / T, t = threadIdx.x % T;
-    const int blocks_per_sf = ny / rows;
-    const int k = blockIdx.x / blocks_per_sf;
-    const int y = (blockIdx.x % blocks_per_sf) * rows + row;
+    const int row_blocks = ny / rows;
+    const int kb = blockIdx.x / row_blocks;
+    const int y = (blockIdx.x % row_blocks) * rows + row;
     const uint64_t npix = (uint64_t)NX * (uint64_t)ny;
-    // pool position of pixel (t, y) of sub-frame k, then +T per slot; the
-    // launch's start is c0 plus a base read from device memory when given
-    // (lets a replayed graph follow a cursor that moves per call)
-    const uint64_t pos0 = pool_pos(src, c0, c0_base, (uint64_t)k * npix + (uint64_t)y * NX + (uint64_t)t);
-    const uint32_t rs = src.kind == SRC_MSEQ ? src.rows[(size_t)k * ny + y] : 0u;
     const auto rt = make_rsrc(target, (uint32_t)(npix * 4));
     const uint32_t toff = ((uint32_t)y * NX + (uint32_t)t) * 4u;
     float a[kP];
 #pragma unroll
     for (int m = 0; m < kP; ++m) a[m] = buf_ld1(rt, toff, (uint32_t)(m * T * 4));
-    float2 v[kP];
     uint32_t* lt = nullptr;
     if (phase_uses_lds(src)) {   // code tables after the transform's LDS rows
         lt = (uint32_t*)(lds + rows * PadLen<NX>::v);
         phase_stage(src, (uint32_t)T, lt);
     }
-    phase_slots<kP>(src, pos0, (uint32_t)T, t, rs, v, lt);
-#pragma unroll
-    for (int m = 0; m < kP; ++m) v[m] = make_float2(a[m] * v[m].x, a[m] * v[m].y);
-    fft_any<NX, 1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, RowsOf<NX>{}, tw, dftop);
     const size_t plane = (size_t)ny * pitch;
-    const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
     const uint32_t ooff = ((uint32_t)y * (uint32_t)pitch + (uint32_t)t) * 8u;
+    const int k_end = min(n_sf, (kb + 1) * spb);
+    for (int k = kb * spb; k < k_end; ++k) {   // uniform over the block
+        // pool position of pixel (t, y) of sub-frame k, then +T per slot; the
+        // launch's start is c0 plus a base read from device memory when given
+        // (lets a replayed graph follow a cursor that moves per call)
+        const uint64_t pos0 = pool_pos(src, c0, c0_base, (uint64_t)k * npix + (uint64_t)y * NX + (uint64_t)t);
+        const uint32_t rs = src.kind == SRC_MSEQ ? src.rows[(size_t)k * ny + y] : 0u;
+        float2 v[kP];
+        phase_slots<kP>(src, pos0, (uint32_t)T, t, rs, v, lt);
 #pragma unroll
-    for (int m = 0; m < kP; ++m) buf_st2(ro, ooff, (uint32_t)(m * T * 8), v[m]);
+        for (int m = 0; m < kP; ++m) v[m] = make_float2(a[m] * v[m].x, a[m] * v[m].y);
+        fft_any<NX, 1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, RowsOf<NX>{}, tw, dftop);
+        const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
+#pragma unroll
+        for (int m = 0; m < kP; ++m) buf_st2(ro, ooff, (uint32_t)(m * T * 8), v[m]);
+    }
+}
+
+// Sub-frames per row-pass block: 8 while the launch keeps >= 1024 blocks
+// (measured at 1024^2, 24 sub-frames, Hermitian K1: 8 -> 37.5 us,
+// 4 -> 38.9 us, 2 -> 39.0 us), fewer for smaller launches.
+static int rows_sf_per_block(int row_blocks, int n_sf)
+{
+    int spb = 8;
+    while (spb > 1 && (long)row_blocks * ((n_sf + spb - 1) / spb) < 1024) spb >>= 1;
+    return spb;
 }
 
 hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const PhaseSrc& src, uint64_t c0,
                             const uint64_t* c0_base, float2* x1, const float2* tw_x, const LaunchCfg& cfg,
                             hipStream_t s)
 {
-    const int rows = row_block_rows(nx, ny, cfg.rows_per_block, cfg.prec);
+    int rows = row_block_rows(nx, ny, cfg.rows_per_block, cfg.prec);
+    while (rows > 1 && rows * (nx / kP) > 512) rows >>= 1;   // the FP32 kernel's launch bound
+    const int row_blocks = ny / rows;
+    const int spb = rows_sf_per_block(row_blocks, n_sf);
     HOLO_SWITCH_NP(nx, cfg.prec, {
         constexpr int T = N_ / kP;
         size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2) +
                      (src.kind == SRC_MSEQ || src.kind == SRC_CODES8 ? kPhaseLdsWords * sizeof(uint32_t) : 0);
         allow_lds(k_ospr_rows<N_, P_>, lds);
-        hipLaunchKernelGGL((k_ospr_rows<N_, P_>), dim3((ny / rows) * n_sf), dim3(rows * T), lds, s, target, ny, src,
-                           c0, c0_base, x1, tw_x, row_pitch(nx, cfg), DFTOP(cfg));
+        hipLaunchKernelGGL((k_ospr_rows<N_, P_>), dim3(row_blocks * ((n_sf + spb - 1) / spb)), dim3(rows * T), lds, s,
+                           target, ny, n_sf, spb, src, c0, c0_base, x1, tw_x, row_pitch(nx, cfg), DFTOP(cfg));
     });
     return hipGetLastError();
 }
@@ -413,10 +431,7 @@ hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, con
     int rows = row_block_rows(nx, ny, cfg.rows_per_block, cfg.prec);
     while (rows > 1 && rows * (nx / kP) > 512) rows >>= 1;   // the FP32 kernel's launch bound
     const int row_blocks = (ny / 2 + 1 + rows - 1) / rows;
-    // sub-frames per block: 8 while the launch keeps >= 1024 blocks (measured
-    // at 1024^2, 24 sub-frames: 8 -> 37.5 us, 4 -> 38.9 us, 2 -> 39.0 us)
-    int spb = 8;
-    while (spb > 1 && (long)row_blocks * ((n_sf + spb - 1) / spb) < 1024) spb >>= 1;
+    const int spb = rows_sf_per_block(row_blocks, n_sf);
     const int sf_blocks = (n_sf + spb - 1) / spb;
     HOLO_SWITCH_NP(nx, cfg.prec, {
         constexpr int T = N_ / kP;
