@@ -51,6 +51,29 @@ def test_nmse_properties(orc):
 
 
 # ---------------------------------------------------------------- reconstruction
+def test_reconstruct_eight_level_map_is_a_plane_wave(orc):
+    # Codes m = x mod 8 mean H'(x, y) = exp(+i*2*pi*x/8).  Under Eq. (1)
+    # (forward kernel exp(-i*2*pi*u*x/nx)) that plane wave puts all of the
+    # replay intensity N at (u, v) = (+nx/8, 0).  A conjugated code map
+    # (exp(-i*2*pi*m/8)) would put it at u = -nx/8, a wrong step size at
+    # another order: only the map exp(+i*2*pi*m/8) passes.
+    for nx, ny in ((16, 8), (64, 16), (32, 32)):
+        n = nx * ny
+        x = np.tile(np.arange(nx), (ny, 1))
+        codes = (x % 8).astype(np.uint8).reshape(1, n)
+        iv = orc.reconstruct(codes, 8, nx, ny, 1)
+        expect = np.zeros((ny, nx))
+        expect[0, nx // 8] = n
+        np.testing.assert_allclose(iv, expect, atol=1e-9 * n)
+        # codes m = 2y mod 8: exp(+i*pi*y/2), all intensity at v = +ny/4
+        y = np.tile(np.arange(ny)[:, None], (1, nx))
+        codes = ((2 * y) % 8).astype(np.uint8).reshape(1, n)
+        iv = orc.reconstruct(codes, 8, nx, ny, 1)
+        expect = np.zeros((ny, nx))
+        expect[ny // 4, 0] = n
+        np.testing.assert_allclose(iv, expect, atol=1e-9 * n)
+
+
 def test_reconstruct_flat_hologram_is_a_delta(orc):
     nx, ny = 16, 8
     n = nx * ny
@@ -180,6 +203,31 @@ def test_gs_fixed_point(orc):
     r = orc.gs(t, 2, init)
     assert r["nmse"][0] < 1e-12
     assert r["err"][0] < 1e-10
+
+
+@pytest.mark.parametrize("scale", [3.0, 0.37])
+def test_gs_amplitude_error_scale_at_scaled_fixed_point(orc, scale):
+    # The amplitude error compares |R'| with Te = T*sqrt(N/sum T^2), the
+    # target rescaled to the replay energy of a unit-modulus hologram
+    # (Parseval: sum |R'|^2 = N).  With T = c*|F{H*}| for a phase-only H*
+    # (sum T^2 = c^2 N) the first iteration returns H* again and |R'| =
+    # |F{H*}| = T/c = Te, so E and NMSE vanish for every c.  A missing or
+    # inverted square root, or a scale taken from the wrong sum, leaves
+    # E = (1 - c^{+-1})^2 N or similar, far from zero.
+    nx, ny = 16, 8
+    n = nx * ny
+    rng = np.random.default_rng(4)
+    hs = np.exp(1j * rng.uniform(0, 2 * np.pi, (ny, nx)))
+    F = np.fft.fft2(hs, norm="ortho")
+    t = (scale * np.abs(F)).astype(np.float32)
+    init = F / np.abs(F)
+    r = orc.gs(t, 2, init)
+    # T was rounded to FP32, so |R'| = T/c only to FP32 relative precision
+    assert r["nmse"][0] < 1e-12
+    assert r["err"][0] < 1e-10 * n
+    # the same field scaled: E is measured in replay units, so it must not
+    # grow with the target's scale
+    assert r["err"][1] < 1e-10 * n
 
 
 def test_gs_error_reduction_and_parseval(orc):
