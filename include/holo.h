@@ -30,6 +30,14 @@
  *     scratch workspace per (device, stream).
  *   - Every call returns a holo_status; no exception or abort crosses the ABI.
  *     holo_last_error() gives this thread's text for the last failure.
+ *   - Environment switches, read at each use (so they may change between
+ *     calls), to exercise the failure paths:
+ *       HOLO_WORKSPACE_CAP=<bytes>  a call whose scratch workspace would
+ *                                   exceed the cap returns HOLO_ENOMEM;
+ *       HOLO_DEBUG_FAIL=device      every kernel or graph launch returns
+ *                                   HOLO_EDEVICE before it is enqueued;
+ *       HOLO_DEBUG_POISON=1         each call's workspace is filled with
+ *                                   0xFF bytes (NaN) before its kernels run.
  */
 #ifndef HOLO_H_
 #define HOLO_H_
@@ -107,7 +115,7 @@ HOLO_API int32_t holo_version(void);
  * entry and the 256 phasors exp(2*pi*i*q/256) (FP64, rounded to FP32).
  * 1 <= n_lut < 2^31.
  *
- * holo_lut_prng (HOLO_SRC_PRNG; Section 3's software route, a PRNG plus
+ * holo_lut_prng (HOLO_SRC_PRNG; Section 4's software route, a PRNG plus
  * trigonometric functions): no table.  Position i (unbounded, the cursor taken
  * mod 2^64) gets x_i = SplitMix64 output i of `seed` in counter form (the x_j
  * of holo_lut_build, so the pool is an endless table of that seed), phase

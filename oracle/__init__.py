@@ -123,7 +123,7 @@ def lut_phases(n_lut: int, seed: int) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
-# Other phase sources (Section 3: PRNG + trigonometry; Section 7: M-sequence +
+# Other phase sources (Section 4: PRNG + trigonometry; Section 7: M-sequence +
 # sine/cosine tables; an 8-bit-code table).  Each gives the phases of pool
 # positions start .. start+n-1.
 # ----------------------------------------------------------------------------

@@ -1,6 +1,6 @@
 /*
  * phase_oracle.c -- plain FP64 CPU oracle for the phase sources compared
- * against the LUT: the software route of Section 3 (a PRNG plus trigonometric
+ * against the LUT: the software route of Section 4 (a PRNG plus trigonometric
  * functions), the M-sequence route of Section 7 (a shift-register sequence
  * feeding sine/cosine tables), and an 8-bit-code table.
  *

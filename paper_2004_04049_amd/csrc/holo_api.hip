@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <atomic>
@@ -67,6 +69,35 @@ holo_status fail(holo_status code, const char* fmt, ...)
     } while (0)
 
 bool pow2_in_range(int64_t n) { return n >= 16 && n <= 2048 && (n & (n - 1)) == 0; }
+
+// Failure and debug hooks, read from the environment at each use so that a
+// caller (or a test) can switch them between calls:
+//   HOLO_WORKSPACE_CAP=<bytes>  a workspace request above it fails with
+//                               HOLO_ENOMEM (as a failed allocation would);
+//   HOLO_DEBUG_FAIL=device      every kernel or graph launch fails with
+//                               HOLO_EDEVICE before anything is enqueued;
+//   HOLO_DEBUG_POISON=1         each workspace handed to a call is first
+//                               filled with 0xFF bytes (a NaN in FP32 and
+//                               FP64), so a kernel that reads scratch it did
+//                               not write shows up in the results.
+size_t env_workspace_cap()
+{
+    const char* v = getenv("HOLO_WORKSPACE_CAP");
+    if (!v || !*v) return SIZE_MAX;
+    char* end = nullptr;
+    const unsigned long long c = strtoull(v, &end, 10);
+    return (end && *end == 0) ? (size_t)c : SIZE_MAX;
+}
+bool env_is(const char* name, const char* value)
+{
+    const char* v = getenv(name);
+    return v && strcmp(v, value) == 0;
+}
+bool debug_fail_device() { return env_is("HOLO_DEBUG_FAIL", "device"); }
+#define DEBUG_FAIL_CHECK(what) \
+    do { \
+        if (debug_fail_device()) return fail(HOLO_EDEVICE, "%s: launch failed (forced by HOLO_DEBUG_FAIL=device)", what); \
+    } while (0)
 
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): golden-gamma increment and
 // the variant-13 finaliser.
@@ -183,6 +214,9 @@ holo_status get_dftop(int device, int prec, hipStream_t s, const void** out)
 // after the stream has drained (the only user of the old buffer).
 holo_status get_workspace(int device, hipStream_t s, size_t bytes, void** out)
 {
+    const size_t ws_cap = env_workspace_cap();
+    if (bytes > ws_cap)
+        return fail(HOLO_ENOMEM, "workspace of %zu bytes exceeds HOLO_WORKSPACE_CAP=%zu", bytes, ws_cap);
     std::lock_guard<std::mutex> lk(g_mu);
     Workspace& w = g_dev[device].workspaces[s];
     if (w.cap < bytes) {
@@ -200,6 +234,7 @@ holo_status get_workspace(int device, hipStream_t s, size_t bytes, void** out)
         }
         w.cap = cap;
     }
+    if (env_is("HOLO_DEBUG_POISON", "1")) HIP_TRY(hipMemsetAsync(w.base, 0xFF, bytes, s));
     *out = w.base;
     return HOLO_OK;
 }
@@ -278,6 +313,7 @@ void prof_drain()
 
 #define LAUNCH(name, s, expr)           \
     do {                                \
+        DEBUG_FAIL_CHECK(name);         \
         ProfScope ps_(name, s);         \
         HIP_TRY(expr);                  \
     } while (0)
@@ -601,6 +637,7 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
                 g_graph_order.erase(g_graph_order.begin());
             }
         }
+        DEBUG_FAIL_CHECK("graph");
         HIP_TRY(hipGraphLaunch(exec, s));
     }
     if (a.codes && a.final2) {
@@ -1167,6 +1204,7 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
                 g_graph_order.erase(g_graph_order.begin());
             }
         }
+        DEBUG_FAIL_CHECK("graph");
         HIP_TRY(hipGraphLaunch(exec, s));
     }
     if ((st = copy_out(nmse_out, nm, 2 * (size_t)n_frames, flags, s))) return st;

@@ -819,19 +819,23 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(P
 #pragma unroll
     for (int m = 0; m < kP; ++m) acc[m] = 0.0f;
     const int rounds = (n_sf + G - 1) / G;
-    // descriptor over all sub-frames' spectra; loads of sub-frames k >= n_sf
+    // one descriptor per round, based at the round's first spectrum (64-bit
+    // pointer arithmetic) and covering the round's min(G, n_sf - r*G) spectra,
+    // so the 32-bit record count and lane offsets stay below 2^32 for any
+    // n_sf (at most G planes: < 2^30 bytes); loads of sub-frames k >= n_sf
     // fall outside it and read as zero.  No register prefetch of the next
     // sub-frame: capped at 128 VGPRs (4 waves per SIMD) the plain loop is
     // faster (35.8 against 37.2 us at 1024^2, 24 sub-frames, 4 groups)
-    const auto rx = make_rsrc(x2, (uint32_t)(sf_stride * (size_t)n_sf * 8));
-    const uint32_t roff = ((uint32_t)v_row * (uint32_t)pitch + (uint32_t)t) * 8u;
     const uint32_t kst = (uint32_t)(sf_stride * 8);
+    const uint32_t roff = ((uint32_t)v_row * (uint32_t)pitch + (uint32_t)t) * 8u + (uint32_t)g * kst;
     for (int r = 0; r < rounds; ++r) {
         const int k = r * G + g;
         const bool valid = k < n_sf;
+        const int in_round = n_sf - r * G < G ? n_sf - r * G : G;
+        const auto rx = make_rsrc(x2 + (size_t)r * G * sf_stride, (uint32_t)in_round * kst);
         float2 v[kP];
 #pragma unroll
-        for (int m = 0; m < kP; ++m) v[m] = buf_ld2(rx, roff + (uint32_t)k * kst, (uint32_t)(m * T * 8));
+        for (int m = 0; m < kP; ++m) v[m] = buf_ld2(rx, roff, (uint32_t)(m * T * 8));
         fft_any<NX, -1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, RowsOf<NX>{}, tw, dftop);
         if (valid) {
 #pragma unroll

@@ -1,8 +1,8 @@
 // phase_src.hpp -- where the random phase of pool entry i comes from.
 //
-// The method (Section 4, Fig. 3) reads a fixed pool of random phases
-// cyclically: sub-frame k of a frame that starts at pool position c gives
-// pixel p the entry at position c + k*N + p (mod the pool length).  Section 3
+// The method (the pool of Section 4, read as in Section 5, Fig. 3) reads a
+// fixed pool of random phases cyclically: sub-frame k of a frame that starts at pool position c gives
+// pixel p the entry at position c + k*N + p (mod the pool length).  Section 4
 // names the alternative a software implementation uses -- a PRNG and the
 // trigonometric functions -- and Section 7 a hardware one, an M-sequence that
 // still needs sine and cosine tables.  The library keeps the pool-position

@@ -1,8 +1,8 @@
 """Learned Gerchberg-Saxton seed: labels from the library's own GS, a training
 loop over the network's C-ABI calls, and the comparison against the LUT seed.
 
-The paper seeds GS (Sec. 3, Fig. 3) with a replay-plane phase drawn from its
-look-up table; here a network may supply that phasor instead (`init_phasor` of
+The paper seeds GS (Sections 2-3) with a replay-plane phase drawn from its
+look-up table (Sections 4-5, Fig. 3); here a network may supply that phasor instead (`init_phasor` of
 `holo_gs_iterate`).  The label of a target is the replay-plane phasor R'/|R'|
 after `n_label` LUT-seeded GS iterations; the comparison counts, on held-out
 targets, the GS iterations (and the time, inference included) a network seed

@@ -54,3 +54,29 @@ def test_committed_traffic_record_is_complete():
     for e in entries.values():
         assert len(e["source_hash"]) == 16 and e["sf_per_launch"] == 24
         assert abs(e["bytes_per_launch"] - e["fetch_bytes"] - e["write_bytes"]) <= 1   # rounded separately
+
+
+def test_design_bytes_half_planes():
+    # binary frames: half planes of (ny/2 + 1) rows, 8 B per complex value
+    nx = ny = 1024
+    n = nx * ny
+    n_sf = 24
+    half = (ny // 2 + 1) * nx * 8
+    db = bench.ospr_design_bytes(nx, ny, n_sf, 65536)
+    assert db["ospr_rows"] == n_sf * half + 4 * n
+    assert db["ospr_cols"] == n_sf * (2 * half + n / 8)
+    assert db["recon_rows"] == n_sf * half + 4 * n
+    # about half the canonical bytes, never more
+    kb = bench.ospr_kernel_bytes(nx, ny, n_sf, 65536)
+    for k in db:
+        assert 0.45 * kb[k] < db[k] < 0.55 * kb[k] + 8 * n
+    # chunking and large tables behave as in the canonical model
+    dc = bench.ospr_design_bytes(nx, ny, n_sf, 65536, chunk=8)
+    assert dc["ospr_cols"] * 3 == db["ospr_cols"]
+    big = bench.ospr_design_bytes(nx, ny, n_sf, 1 << 20)
+    assert big["ospr_rows"] - db["ospr_rows"] == 8 * (1 << 20)
+    # the committed K2 traffic agrees with the design bytes within the margin
+    with open(bench.os.path.join(bench.ROOT, "profiles", "traffic.json")) as f:
+        rec = json.load(f)
+    e = rec["ospr_1024x1024_sf24_lut65536"]["ospr_cols"]
+    assert abs(e["bytes_per_launch"] / db["ospr_cols"] - 1) <= bench.TRAFFIC_MARGIN

@@ -114,6 +114,31 @@ def test_ospr_1024_partial_subframe_group(holo, orc):
     _ospr_case(holo, orc, 1024, 1024, 12, 10007, 7, t)
 
 
+def test_ospr_subframes_past_32bit_offsets(holo, orc):
+    # 1100 sub-frames at 1024^2: the half spectra the replay pass reads span
+    # ~4.7 GB, past 32-bit byte offsets.  A 256-entry LUT divides the frame, so
+    # every sub-frame is the same hologram and the time average equals the
+    # replay of one sub-frame: the NMSE pair must equal the one-sub-frame
+    # frame's (GPU and oracle) and every sub-frame's bits the first one's.
+    nx = ny = 1024
+    t = synth.blob_target(nx, ny, 24)
+    tt = torch.from_numpy(t).cuda()
+    lut = holo.Lut(256, 1)
+    print("ospr 1024x1024 nsf=1 lut=256", flush=True)
+    b1, nm1, _ = holo.ospr_generate(tt, 1, lut, 0)
+    ref = orc.ospr(t, 1, orc.lut_phases(256, 1), 256, 0)
+    _check_bits(holo, orc, b1, ref, nx * ny)
+    np.testing.assert_allclose(nm1, ref["nmse2"], rtol=NMSE_RTOL)
+    print("ospr 1024x1024 nsf=1100 lut=256", flush=True)
+    bits, nm, cur = holo.ospr_generate(tt, 1100, lut, 0)
+    torch.cuda.synchronize()
+    assert cur == 1100 * nx * ny
+    assert bool((bits == b1[0]).all())
+    np.testing.assert_allclose(nm, nm1, rtol=1e-5)
+    del bits
+    torch.cuda.empty_cache()
+
+
 def test_ospr_2048_tall_and_wide(holo, orc):
     t = synth.blob_target(2048, 128, 21)
     _ospr_case(holo, orc, 2048, 128, 3, 10007, 11, t)
