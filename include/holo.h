@@ -214,6 +214,37 @@ HOLO_API holo_status holo_gs_iterate(const float* target, int64_t nx, int64_t ny
                                      void* hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * holo_gs_iterate_noalloc -- holo_gs_iterate for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, computation and results as
+ * holo_gs_iterate (the same kernels and launch plan), except:
+ *   - The call's scratch (the iterated field, per-iteration partial sums,
+ *     the replay spectrum, the NMSE values) is a fixed device buffer of
+ *     HOLO_GS_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held
+ *     until the process ends; no call allocates or frees anything and no
+ *     graph is captured.  A problem whose scratch would exceed the buffer
+ *     returns HOLO_EUNSUPPORTED before anything is enqueued (1024^2 with codes
+ *     and a caller field fits about 570 iterations; 2048^2 does not fit).
+ *   - nmse_per_iter, err_per_iter and nmse_final2 are device pointers and
+ *     flags must include HOLO_F_NMSE_DEVICE when any of them is given
+ *     (HOLO_EINVAL otherwise); the call never synchronises its stream, except
+ *     that the first call on a device generates the fixed twiddle tables and
+ *     waits for them (HOLO_EUNSUPPORTED if that first call is made under
+ *     stream capture).
+ *   - Every call on one GPU shares that GPU's buffer, which keeps the last
+ *     call's contents (everything a call reads it first writes): calls that
+ *     overlap on one GPU, on different streams or unordered host threads,
+ *     race and must be ordered by the caller.
+ *   - Kernel timing (holo_prof_enable) is not recorded for this call.
+ * ------------------------------------------------------------------------- */
+#define HOLO_GS_NOALLOC_SCRATCH_BYTES (32u << 20)
+HOLO_API holo_status holo_gs_iterate_noalloc(const float* target, int64_t nx, int64_t ny, int32_t n_iter,
+                                             const holo_lut* lut, uint64_t* cursor, const float* init_phasor,
+                                             float* field, uint8_t* codes, double* nmse_per_iter,
+                                             double* err_per_iter, double* nmse_final2, float* recon,
+                                             int32_t precision, uint32_t flags, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
  * holo_reconstruct_nmse -- replay of quantised holograms, R' = F{H'}
  * (Section 2), intensity time-averaged over n_sf holograms (Section 3).
  *   holo    device: levels == 2 -> packed bits as holo_ospr_generate writes

@@ -43,6 +43,8 @@ SIGNATURES = {
     "holo_ospr_generate": (_I32, [_P, _I64, _I64, _I32, _P, C.POINTER(_U64), _P, _P, _P, _I32, _U32, _P]),
     "holo_gs_iterate": (_I32, [_P, _I64, _I64, _I32, _P, C.POINTER(_U64), _P, _P, _P, _P, _P, _P, _P, _I32,
                                _U32, _P]),
+    "holo_gs_iterate_noalloc": (_I32, [_P, _I64, _I64, _I32, _P, C.POINTER(_U64), _P, _P, _P, _P, _P, _P, _P,
+                                       _I32, _U32, _P]),
     "holo_reconstruct_nmse": (_I32, [_P, _I32, _I64, _I64, _I32, _P, _P, _P, _U32, _P]),
     "holo_fft2": (_I32, [_P, _P, _I64, _I64, _I32, _I32, _P]),
     "holo_phase_mask": (_I32, [_P, _U64, _I64, _I64, _I32, _P, _P]),
@@ -280,6 +282,29 @@ def gs_iterate(target, n_iter: int, lut: Lut | None, cursor: int, init_phasor=No
         fin.ctypes.data_as(C.c_void_p) if fin is not None else None,
         _ptr(recon), FP32, 0, _stream(stream)))
     return {"nmse": nm, "err": er, "nmse_final2": fin, "field": field, "codes": codes, "cursor": int(cur.value)}
+
+
+def gs_iterate_noalloc(target, n_iter: int, lut: Lut | None, cursor: int, init_phasor=None, field=None,
+                       codes=None, nmse=None, err=None, final2=None, recon=None, stream=None):
+    """holo_gs_iterate_noalloc: gs_iterate on the library's fixed scratch (no
+    device allocation inside the call).  Every output is a caller tensor:
+    field/init_phasor complex64 [ny, nx], codes uint8 [ny, nx], recon float32
+    [ny, nx]; nmse/err float64 [n_iter] and final2 float64 [2] on the device.
+    Returns the new cursor."""
+    ny, nx = target.shape
+    _dev(target, torch.float32, None, "target")
+    for t, dt, shape, name in ((init_phasor, torch.complex64, (ny, nx), "init_phasor"),
+                               (field, torch.complex64, (ny, nx), "field"), (codes, torch.uint8, (ny, nx), "codes"),
+                               (recon, torch.float32, (ny, nx), "recon"), (nmse, torch.float64, (n_iter,), "nmse"),
+                               (err, torch.float64, (n_iter,), "err"), (final2, torch.float64, (2,), "final2")):
+        if t is not None:
+            _dev(t, dt, shape, name)
+    cur = C.c_uint64(cursor)
+    _check(lib().holo_gs_iterate_noalloc(
+        _ptr(target), nx, ny, n_iter, lut.handle if lut is not None else None, C.byref(cur), _ptr(init_phasor),
+        _ptr(field), _ptr(codes), _ptr(nmse), _ptr(err), _ptr(final2), _ptr(recon), FP32, F_NMSE_DEVICE,
+        _stream(stream)))
+    return int(cur.value)
 
 
 def reconstruct_nmse(holo, levels: int, nx: int, ny: int, n_sf: int, target, recon=None, stream=None):

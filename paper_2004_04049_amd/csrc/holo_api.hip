@@ -275,12 +275,16 @@ hipEvent_t prof_event()
     return e;
 }
 
+// Set while an entry point that must not create events runs on this thread.
+thread_local bool t_prof_suppress = false;
+
 struct ProfScope {
     const char* name;
     hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
     ProfScope(const char* n, hipStream_t st) : name(n), s(st)
     {
+        if (t_prof_suppress) return;
         std::lock_guard<std::mutex> lk(g_prof_mu);
         if (!g_prof_on) return;
         a = prof_event();
@@ -509,11 +513,40 @@ std::map<GraphKey, hipGraphExec_t> g_graphs;
 std::vector<GraphKey> g_graph_order;
 bool g_use_graphs = true;
 
-holo_status gs_enqueue(const GsArgs& a, hipStream_t s, const LaunchCfg& cfg, const float2* tw_x, const float2* tw_y,
-                       char* b, size_t o_state, size_t o_field, size_t o_pinit, size_t o_piter, size_t o_consts,
-                       size_t o_nm, size_t o_er, size_t o_x2, size_t o_p5, size_t o_f2, size_t o_rs,
-                       size_t o_cur)
+// Scratch of one GS call, carved from one buffer.
+struct GsLayout {
+    size_t o_state, o_field, o_pinit, o_piter, o_consts, o_nm, o_er, o_x2, o_p5, o_f2, o_rs, o_cur, bytes;
+};
+
+GsLayout gs_layout(const GsArgs& a, const LaunchCfg& cfg)
 {
+    const size_t npix = (size_t)a.nx * (size_t)a.ny;
+    const size_t pitched = (size_t)a.ny * (size_t)row_pitch((int)a.nx, cfg);
+    const int ny = (int)a.ny;
+    GsLayout L;
+    Carver cv;
+    L.o_state = cv.take(sizeof(float2) * pitched);
+    L.o_field = cv.take(a.field ? 0 : sizeof(float2) * npix);
+    L.o_pinit = cv.take(sizeof(double) * 2 * ny);
+    L.o_piter = cv.take(sizeof(double) * 3 * ny * (size_t)a.n_iter);
+    L.o_consts = cv.take(sizeof(GsConsts));
+    L.o_nm = cv.take(sizeof(double) * a.n_iter);
+    L.o_er = cv.take(sizeof(double) * a.n_iter);
+    L.o_x2 = cv.take(a.codes ? sizeof(float2) * pitched : 0);
+    L.o_p5 = cv.take(sizeof(double) * 5 * ny);
+    L.o_f2 = cv.take(sizeof(double) * 2);
+    L.o_rs = cv.take(sizeof(uint32_t) * ny);   // M-sequence row states
+    L.o_cur = cv.take(sizeof(uint64_t));       // pool start of this call
+    L.bytes = cv.off;
+    return L;
+}
+
+holo_status gs_enqueue(const GsArgs& a, hipStream_t s, const LaunchCfg& cfg, const float2* tw_x, const float2* tw_y,
+                       char* b, const GsLayout& L)
+{
+    const size_t o_state = L.o_state, o_field = L.o_field, o_pinit = L.o_pinit, o_piter = L.o_piter,
+                 o_consts = L.o_consts, o_nm = L.o_nm, o_er = L.o_er, o_x2 = L.o_x2, o_p5 = L.o_p5,
+                 o_f2 = L.o_f2, o_rs = L.o_rs, o_cur = L.o_cur;
     const int inx = (int)a.nx, iny = (int)a.ny;
     float2* state = (float2*)(b + o_state);
     float2* fout = a.field ? (float2*)a.field : (float2*)(b + o_field);
@@ -562,27 +595,13 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
     const float2 *tw_x, *tw_y;
     if ((st = get_twiddles(device, (int)a.nx, s, &tw_x))) return st;
     if ((st = get_twiddles(device, (int)a.ny, s, &tw_y))) return st;
-    const size_t npix = (size_t)a.nx * (size_t)a.ny;
-    const size_t pitched = (size_t)a.ny * (size_t)row_pitch((int)a.nx, cfg);
-    const int n_iter = a.n_iter, ny = (int)a.ny;
-    Carver cv;
-    const size_t o_state = cv.take(sizeof(float2) * pitched);
-    const size_t o_field = cv.take(a.field ? 0 : sizeof(float2) * npix);
-    const size_t o_pinit = cv.take(sizeof(double) * 2 * ny);
-    const size_t o_piter = cv.take(sizeof(double) * 3 * ny * (size_t)n_iter);
-    const size_t o_consts = cv.take(sizeof(GsConsts));
-    const size_t o_nm = cv.take(sizeof(double) * n_iter);
-    const size_t o_er = cv.take(sizeof(double) * n_iter);
-    const size_t o_x2 = cv.take(a.codes ? sizeof(float2) * pitched : 0);
-    const size_t o_p5 = cv.take(sizeof(double) * 5 * ny);
-    const size_t o_f2 = cv.take(sizeof(double) * 2);
-    const size_t o_rs = cv.take(sizeof(uint32_t) * ny);   // M-sequence row states
-    const size_t o_cur = cv.take(sizeof(uint64_t));        // pool start of this call
+    const int n_iter = a.n_iter;
+    const GsLayout L = gs_layout(a, cfg);
     void* ws;
-    if ((st = get_workspace(device, s, cv.off, &ws))) return st;
+    if ((st = get_workspace(device, s, L.bytes, &ws))) return st;
     char* b = (char*)ws;
     if (!a.init) {
-        hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, (uint64_t*)(b + o_cur), lut_wrap(a.lut, a.cursor));
+        hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, (uint64_t*)(b + L.o_cur), lut_wrap(a.lut, a.cursor));
         HIP_TRY(hipGetLastError());
     }
 
@@ -593,9 +612,7 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
     }
     // the legacy default stream cannot be captured: launch directly there
     if (!g_use_graphs || prof_on || s == nullptr) {
-        if ((st = gs_enqueue(a, s, cfg, tw_x, tw_y, b, o_state, o_field, o_pinit, o_piter, o_consts, o_nm, o_er,
-                             o_x2, o_p5, o_f2, o_rs, o_cur)))
-            return st;
+        if ((st = gs_enqueue(a, s, cfg, tw_x, tw_y, b, L))) return st;
     } else {
         GraphKey key{{(uintptr_t)device, (uintptr_t)s, (uintptr_t)a.target, (uintptr_t)a.nx, (uintptr_t)a.ny,
                       (uintptr_t)a.n_iter, (uintptr_t)(a.init ? 0 : a.lut->id), (uintptr_t)a.init,
@@ -613,8 +630,7 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
         if (!exec) {
             hipGraph_t graph = nullptr;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            holo_status est = gs_enqueue(a, s, cfg, tw_x, tw_y, b, o_state, o_field, o_pinit, o_piter, o_consts,
-                                         o_nm, o_er, o_x2, o_p5, o_f2, o_rs, o_cur);
+            holo_status est = gs_enqueue(a, s, cfg, tw_x, tw_y, b, L);
             hipError_t ce = hipStreamEndCapture(s, &graph);
             if (est) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -641,13 +657,61 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
         HIP_TRY(hipGraphLaunch(exec, s));
     }
     if (a.codes && a.final2) {
-        if ((st = copy_out(a.final2, (double*)(b + o_f2), 2, a.flags, s))) return st;
+        if ((st = copy_out(a.final2, (double*)(b + L.o_f2), 2, a.flags, s))) return st;
     }
-    if ((st = copy_out(a.nmse, (double*)(b + o_nm), n_iter, a.flags, s))) return st;
-    if ((st = copy_out(a.err, (double*)(b + o_er), n_iter, a.flags, s))) return st;
+    if ((st = copy_out(a.nmse, (double*)(b + L.o_nm), n_iter, a.flags, s))) return st;
+    if ((st = copy_out(a.err, (double*)(b + L.o_er), n_iter, a.flags, s))) return st;
     return HOLO_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Allocation-free GS (holo_gs_iterate_noalloc): the call's scratch lives in a
+// fixed device array of kNoAllocScratch bytes and its twiddle tables in a
+// fixed device table, both static members of the library's code object (each
+// GPU the library runs on holds its own copy until the process ends).  Host
+// code never passes the arrays' names to a kernel: their device addresses are
+// taken once per device with hipGetSymbolAddress and kept in g_noalloc.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratch = HOLO_GS_NOALLOC_SCRATCH_BYTES;
+constexpr int kNoAllocTwiddles = 4080;   // W_N^k for N = 16, 32, ..., 2048: table of N at offset N - 16
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+static __device__ __align__(256) float2 noalloc_twiddles[kNoAllocTwiddles];
+
+struct NoAllocDevice {
+    char* scratch;    // device address of `scratch` on this device
+    float2* tw;       // device address of `noalloc_twiddles`, tables generated
+};
+std::mutex g_noalloc_mu;
+std::map<int, NoAllocDevice> g_noalloc;
+
+// Device addresses of the fixed arrays on the current device; the first call
+// on a device also generates the twiddle tables (FP64 on the device, as for
+// the workspace path) and waits for them, so it must not run under capture.
+holo_status noalloc_device(int device, hipStream_t s, NoAllocDevice* out)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto it = g_noalloc.find(device);
+    if (it != g_noalloc.end()) {
+        *out = it->second;
+        return HOLO_OK;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(HOLO_EUNSUPPORTED, "holo_gs_iterate_noalloc: the first call on a device sets up its tables "
+                                       "and must not run under stream capture");
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    void* tw = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&tw, HIP_SYMBOL(noalloc_twiddles)));
+    for (int n = 16; n <= 2048; n <<= 1) HIP_TRY(launch_twiddle_gen((float2*)tw + (n - 16), n, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    NoAllocDevice d{(char*)ptr, (float2*)tw};
+    g_noalloc[device] = d;
+    *out = d;
+    return HOLO_OK;
+}
 
 // Branch streams (default priority) for the batched graph's fork/join.
 constexpr int kBranches = 4;
@@ -996,6 +1060,55 @@ holo_status holo_gs_iterate(const float* target, int64_t nx, int64_t ny, int32_t
              field, codes, nmse_per_iter, err_per_iter, nmse_final2, recon, flags};
     const LaunchCfg cfg = plan_get(PLAN_GS, nx, ny, 1);
     if ((st = gs_run(device, a, (hipStream_t)hip_stream, cfg))) return st;
+    if (!init_phasor) *cursor += (uint64_t)nx * (uint64_t)ny;
+    return HOLO_OK;
+}
+
+holo_status holo_gs_iterate_noalloc(const float* target, int64_t nx, int64_t ny, int32_t n_iter,
+                                    const holo_lut* lut, uint64_t* cursor, const float* init_phasor, float* field,
+                                    uint8_t* codes, double* nmse_per_iter, double* err_per_iter,
+                                    double* nmse_final2, float* recon, int32_t precision, uint32_t flags,
+                                    void* hip_stream)
+{
+    if (!target || !cursor) return fail(HOLO_EINVAL, "target and cursor are required");
+    if (n_iter < 1) return fail(HOLO_EINVAL, "n_iter must be >= 1 (got %d)", n_iter);
+    if ((nmse_final2 || recon) && !codes) return fail(HOLO_EINVAL, "nmse_final2/recon need codes");
+    if ((nmse_per_iter || err_per_iter || nmse_final2) && !(flags & HOLO_F_NMSE_DEVICE))
+        return fail(HOLO_EINVAL, "holo_gs_iterate_noalloc writes NMSE values to device memory only "
+                                 "(HOLO_F_NMSE_DEVICE)");
+    if (!pow2_in_range(nx) || !pow2_in_range(ny))
+        return fail(HOLO_EUNSUPPORTED, "nx, ny must be powers of two in [16, 2048]");
+    if (precision != HOLO_FP32) return fail(HOLO_EUNSUPPORTED, "holo_gs_iterate computes in FP32 only");
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    holo_status st;
+    if (!init_phasor && (st = check_lut(lut, device))) return st;
+    GsArgs a{target, nx, ny, n_iter, init_phasor ? nullptr : lut, init_phasor ? 0 : *cursor, init_phasor,
+             field, codes, nmse_per_iter, err_per_iter, nmse_final2, recon, flags};
+    const LaunchCfg cfg = plan_get(PLAN_GS, nx, ny, 1);
+    const GsLayout L = gs_layout(a, cfg);
+    if (L.bytes > kNoAllocScratch)
+        return fail(HOLO_EUNSUPPORTED, "holo_gs_iterate_noalloc: %lldx%lld with %d iterations needs %zu bytes of "
+                                       "scratch, more than the fixed %zu", (long long)nx, (long long)ny, n_iter,
+                    L.bytes, kNoAllocScratch);
+    hipStream_t s = (hipStream_t)hip_stream;
+    NoAllocDevice d;
+    if ((st = noalloc_device(device, s, &d))) return st;
+    struct Suppress {
+        Suppress() { t_prof_suppress = true; }
+        ~Suppress() { t_prof_suppress = false; }
+    } no_events;   // kernel timing would create events: not recorded here
+    char* b = d.scratch;
+    if (!a.init) {
+        hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, (uint64_t*)(b + L.o_cur), lut_wrap(a.lut, a.cursor));
+        HIP_TRY(hipGetLastError());
+    }
+    if ((st = gs_enqueue(a, s, cfg, d.tw + (nx - 16), d.tw + (ny - 16), b, L))) return st;
+    if (codes && nmse_final2) {
+        if ((st = copy_out(nmse_final2, (double*)(b + L.o_f2), 2, flags, s))) return st;
+    }
+    if ((st = copy_out(nmse_per_iter, (double*)(b + L.o_nm), n_iter, flags, s))) return st;
+    if ((st = copy_out(err_per_iter, (double*)(b + L.o_er), n_iter, flags, s))) return st;
     if (!init_phasor) *cursor += (uint64_t)nx * (uint64_t)ny;
     return HOLO_OK;
 }
