@@ -100,8 +100,10 @@ def test_ospr_small_cases(holo, orc, nx, ny, nsf, n_lut, cursor):
     _ospr_case(holo, orc, nx, ny, nsf, n_lut, cursor, t)
 
 
-@pytest.mark.parametrize("n_lut", [2 ** 16, 10007])
+@pytest.mark.parametrize("n_lut", [2 ** 16, 10007, 2 ** 20, 1024 * 1024 * 24])
 def test_ospr_1024_full_size(holo, orc, n_lut):
+    # the benchmark's frame; 2^20 and the non-repeating table (every pixel of
+    # every sub-frame its own entry) reach the largest pool offsets
     t = synth.blob_target(1024, 1024, synth.SEED_OSPR_1024)
     _, _, ties = _ospr_case(holo, orc, 1024, 1024, 24, n_lut, 0, t, want_recon=True)
     assert ties < 24 * 1024 * 1024 * 1e-3
@@ -187,22 +189,87 @@ def _gs_case(holo, orc, nx, ny, n_iter, n_lut, seed):
     return t, r, ref
 
 
-def test_gs_512_50_iterations(holo, orc):
-    # 512x512, 50 iterations, 4096-entry LUT seed, 8 levels at the end.  The
-    # FP32 trajectory drifts from the FP64 one by ~1e-4 in relative L2 after
-    # 50 iterations, so the 8-level codes are compared as a mismatch fraction
-    # (pixels near a decision boundary may flip) while the replay NMSE of the
-    # GPU's own codes is checked exactly against the oracle's reconstruction.
-    t, r, ref = _gs_case(holo, orc, 512, 512, 50, 4096, synth.SEED_GS_512)
-    codes = r["codes"].cpu().numpy()
-    mism = float(np.mean(codes != ref["codes"]))
-    print(f"8-level code mismatch after 50 iterations: {mism:.2e}")
-    assert mism < 1e-2, mism
-    np.testing.assert_allclose(r["nmse_final2"], ref["nmse_final2"], rtol=1e-2)
-    own = orc.reconstruct(codes[None], 8, 512, 512, 1)
-    np.testing.assert_allclose(r["nmse_final2"], orc.nmse_pair(own, t), rtol=NMSE_RTOL)
-    fld = r["field"].cpu().numpy()
-    assert _rel_l2(fld, ref["field"]) < 1e-2
+# Error model of a 50-iteration GS trajectory.  GS is sensitive to its
+# starting point: the FP64 oracle itself, with its seed phases perturbed by
+# GS_EPS = 2^-22 (about the relative rounding error of one FP32 transform of
+# 1024 points, log2(N)/2 * 2^-24), ends 50 iterations later with replay fields
+# 0.5-1% (512^2) and 2.5-3.5% (1024^2) apart in relative L2, as many 8-level
+# codes changed, and per-iteration NMSE up to ~3e-4 relative apart; an
+# independent FP32 FFT (pocketfft) lands in the same range.  An FP32 run rounds
+# at every iteration, not once, so its trajectory cannot match the FP64 one to
+# 1e-4 after many iterations, whatever its arithmetic.  The bars therefore are:
+#   * iterations 1..10 from the LUT seed, where the spread is still below 3e-5:
+#     NMSE 1e-4 and amplitude error 1e-3 relative;
+#   * every later iteration checked from the GPU's own state: the oracle
+#     restarts from the GPU's field every 10 iterations and both run 10 more
+#     (NMSE 1e-4, amplitude error 1e-3) -- this checks each iteration's
+#     arithmetic independently of the trajectory's sensitivity;
+#   * the free 50-iteration run against the FP64 envelope measured here (two
+#     perturbation seeds): field and code mismatch within 2x, per-iteration
+#     NMSE within 5x (the envelope perturbs once, the GPU every iteration);
+#   * the replay NMSE of the GPU's own codes against the oracle's replay of
+#     those codes: 1e-4 (exact given the codes).
+GS_EPS = 2.0 ** -22
+GS_WINDOW = 10
+
+
+def _gs_envelope(orc, t, init, ref, n_iter, seeds=(100, 101)):
+    env = {"field": 0.0, "codes": 0.0, "nmse": 0.0}
+    for sd in seeds:
+        rng = np.random.default_rng(sd)
+        p = init * np.exp(1j * GS_EPS * rng.standard_normal(init.shape))
+        r = orc.gs(t, n_iter, p)
+        env["field"] = max(env["field"], _rel_l2(r["field"], ref["field"]))
+        env["codes"] = max(env["codes"], float(np.mean(r["codes"] != ref["codes"])))
+        env["nmse"] = max(env["nmse"], float(np.max(np.abs(r["nmse"] - ref["nmse"]) / ref["nmse"])))
+    return env
+
+
+@pytest.mark.parametrize("n,plan", [(512, None), (1024, [4, 1, 0, 0, 0, 0, 8]), (1024, [0, 0, 0, 0, -1, 0, 16])])
+def test_gs_50_iterations(holo, orc, n, plan):
+    # n^2, 50 iterations, 4096-entry LUT seed, 8 levels at the end; 1024^2
+    # under the benchmark's tuned plan and with 16 points per thread
+    n_iter = 50
+    if plan is not None:
+        holo.plan_set(holo.PLAN_GS, n, n, 1, plan)
+    try:
+        print(f"gs {n}x{n} x{n_iter} plan {plan}", flush=True)
+        t = synth.blob_target(n, n, synth.SEED_GS_512)
+        tt = torch.from_numpy(t).cuda()
+        lut = holo.Lut(4096, 1)
+        init = orc.lut_phasor_field(orc.lut_phases(4096, 1), 4096, 0, 0, n, n)
+        r = holo.gs_iterate(tt, n_iter, lut, 0, want_err=True)
+        ref = orc.gs(t, n_iter, init)
+        assert r["cursor"] == n * n
+        head = slice(0, GS_WINDOW)
+        np.testing.assert_allclose(r["nmse"][head], ref["nmse"][head], rtol=1e-4)
+        np.testing.assert_allclose(r["err"][head], ref["err"][head], rtol=1e-3)
+        # windows from the GPU's own state
+        f = holo.gs_iterate(tt, GS_WINDOW, lut, 0)["field"]
+        for k0 in range(GS_WINDOW, n_iter, GS_WINDOW):
+            print(f"gs {n}x{n} window from iteration {k0}", flush=True)
+            state = f.cpu().numpy().astype(np.complex128)
+            w = holo.gs_iterate(tt, GS_WINDOW, None, 0, init_phasor=f.clone(), want_err=True)
+            wr = orc.gs(t, GS_WINDOW, state)
+            np.testing.assert_allclose(w["nmse"], wr["nmse"], rtol=1e-4)
+            np.testing.assert_allclose(w["err"], wr["err"], rtol=1e-3)
+            f = w["field"]
+        # the free run against the FP64 envelope
+        env = _gs_envelope(orc, t, init, ref, n_iter)
+        fld = _rel_l2(r["field"].cpu().numpy(), ref["field"])
+        codes = r["codes"].cpu().numpy()
+        mism = float(np.mean(codes != ref["codes"]))
+        dn = float(np.max(np.abs(r["nmse"] - ref["nmse"]) / ref["nmse"]))
+        print(f"gs {n}x{n}: field {fld:.2e} (envelope {env['field']:.2e}), codes {mism:.2e} "
+              f"({env['codes']:.2e}), NMSE {dn:.2e} ({env['nmse']:.2e})", flush=True)
+        assert fld < 2 * env["field"]
+        assert mism < 2 * env["codes"]
+        assert dn < 5 * env["nmse"]
+        own = orc.reconstruct(codes[None], 8, n, n, 1)
+        np.testing.assert_allclose(r["nmse_final2"], orc.nmse_pair(own, t), rtol=NMSE_RTOL)
+    finally:
+        if plan is not None:
+            holo.plan_set(holo.PLAN_GS, n, n, 1, holo.DEFAULT_PLAN)
 
 
 def test_gs_quantiser_exact_after_one_iteration(holo, orc):
