@@ -57,14 +57,18 @@ def blob_target(nx: int, ny: int, seed: int, n_blobs: int = 20, n_rects: int = 1
       rect: x0 = floor(u*nx), y0 = floor(u*ny), w = floor((0.05+0.25u)*nx),
             h = floor((0.05+0.25u)*ny), a = 0.2 + 0.8u (clipped, no wrap)."""
     st = _Stream(seed)
-    yy, xx = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    xs = np.arange(nx, dtype=np.float64)
+    ys = np.arange(ny, dtype=np.float64)
     s = np.zeros((ny, nx), dtype=np.float64)
     for _ in range(n_blobs):
         cx = st.u() * nx
         cy = st.u() * ny
         sig = (0.01 + 0.09 * st.u()) * nx
         a = 0.2 + 0.8 * st.u()
-        s += a * np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2) / (2.0 * sig * sig))
+        # the Gaussian is separable: exp(-(dx^2 + dy^2)/2s^2) = gy(y) * gx(x)
+        gx = np.exp(-((xs - cx) ** 2) / (2.0 * sig * sig))
+        gy = a * np.exp(-((ys - cy) ** 2) / (2.0 * sig * sig))
+        s += np.multiply.outer(gy, gx)
     for _ in range(n_rects):
         x0 = int(st.u() * nx)
         y0 = int(st.u() * ny)

@@ -223,3 +223,36 @@ def test_seed_comparison_runs(holo):
             assert r["iters"] == 1 or run["nmse"][r["iters"] - 2] > r["goal_nmse"]
         else:
             assert np.all(run["nmse"] > r["goal_nmse"])
+
+
+def test_trained_seed_against_untrained_and_lut(holo):
+    """End to end: train on seeded targets with LUT-seeded GS-50 labels, then
+    on held-out targets count the GS iterations each seed needs to reach the
+    NMSE that LUT-seeded GS reaches after 50 iterations (the LUT seed needs 50
+    by definition).  Asserted: the training loss falls on the training set;
+    both network seeds reach the goal on every held-out target within 100
+    iterations and end 50 iterations below the LUT seed's NMSE; the books
+    agree with the per-iteration NMSE.  The learned gain over the untrained
+    network is reported, not asserted (at 1024^2 and 10k targets it is about
+    one iteration in 45)."""
+    from paper_2004_04049_amd import seed
+    n = 256
+    train = [torch.from_numpy(synth.blob_target(n, n, synth.SEED_CNN_TRAIN0 + i)).cuda() for i in range(48)]
+    held = [torch.from_numpy(synth.blob_target(n, n, synth.SEED_CNN_HELDOUT0 + i)).cuda() for i in range(6)]
+    lut = holo.Lut(4096, 1)
+    labels = seed.gs_labels(train, lut, 50)
+    net = holo.Cnn(seed=1)
+    before = np.mean([net.loss_grad(t, q)[0] for t, q in zip(train[:16], labels[:16])])
+    hist = seed.train(net, train, labels, 3, 1e-3, batch=4)
+    after = np.mean([net.loss_grad(t, q)[0] for t, q in zip(train[:16], labels[:16])])
+    trained = seed.compare(net, held, lut, 50, 100)
+    untrained = seed.compare(holo.Cnn(seed=1), held, lut, 50, 100)
+    print(f"loss {before:.5f} -> {after:.5f} (epochs {hist['epoch_loss']}); iterations to the LUT GS-50 NMSE: "
+          f"trained {trained['iters_mean']}, untrained {untrained['iters_mean']}, LUT 50; NMSE ratio at 50: "
+          f"{trained['nmse_ratio_at_ref_mean']:.4f} / {untrained['nmse_ratio_at_ref_mean']:.4f}")
+    assert after < before
+    for res in (trained, untrained):
+        assert res["reached"] == len(held)
+        assert res["nmse_ratio_at_ref_mean"] < 1.0
+        for r in res["rows"]:
+            assert r["t_cnn_s"] is not None and r["t_infer_s"] > 0
