@@ -36,7 +36,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--lut", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extras", action="store_true", help="skip GS and the LUT sweep")
+    ap.add_argument("--no-extras", action="store_true", help="skip every leg after the headline")
+    ap.add_argument("--legs", default="batched,gs,lut_sweep,phase_sources,ospr_variants,cnn_seed",
+                    help="comma list of the legs to run after the headline")
     ap.add_argument("--cnn-held", type=int, default=100, help="learned-seed held-out targets (1024^2)")
     ap.add_argument("--plan", default=None,
                     help="OSPR launch plan 'cols,rows,ksplit,recon_cols,pad,chunk[,pts]' to use instead of autotuning")
@@ -228,12 +230,16 @@ def main():
         def leg(name, f):
             print(f"bench: {name}", file=sys.stderr, flush=True)   # progress (stdout keeps the one JSON line)
             out[name] = f()
-        leg("batched", lambda: bench_batched(h, synth, torch, dev))
-        leg("gs", lambda: bench_gs(h, synth, torch, dev))
-        leg("lut_sweep", lambda: bench_lut_sweep(h, synth, torch, dev, target, nx, ny, n_sf))
-        leg("phase_sources", lambda: bench_phase_sources(h, synth, torch, dev, target, nx, ny, n_sf))
-        leg("ospr_variants", lambda: bench_ospr_variants(h, synth, torch, dev, target, nx, ny, n_sf, lut))
-        leg("cnn_seed", lambda: bench_cnn(h, synth, torch, dev, args))
+        legs = {
+            "batched": lambda: bench_batched(h, synth, torch, dev),
+            "gs": lambda: bench_gs(h, synth, torch, dev),
+            "lut_sweep": lambda: bench_lut_sweep(h, synth, torch, dev, target, nx, ny, n_sf),
+            "phase_sources": lambda: bench_phase_sources(h, synth, torch, dev, target, nx, ny, n_sf),
+            "ospr_variants": lambda: bench_ospr_variants(h, synth, torch, dev, target, nx, ny, n_sf, lut),
+            "cnn_seed": lambda: bench_cnn(h, synth, torch, dev, args),
+        }
+        for name in [x for x in args.legs.split(",") if x]:
+            leg(name, legs[name])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(synth, nx, ny, n_lut)
     if args.calib:
@@ -514,7 +520,7 @@ def cpu_model():
 
 def cpu_baseline(synth, nx, ny, n_lut):
     """The FP64 oracle, as it stands, on a bounded sample of the workload: the
-    same target, LUT and frame size, 4 frames of 24 sub-frames on all host
+    same target, LUT and frame size, 12 frames of 24 sub-frames on all host
     threads, and one frame on one thread; beside it, as context only, the
     transforms alone (torch.fft on the CPU, complex64, all threads)."""
     import oracle
@@ -532,7 +538,7 @@ def cpu_baseline(synth, nx, ny, n_lut):
         return time.perf_counter() - t0
 
     threads = oracle.num_threads()
-    frames = 4
+    frames = 12
     dt = run(frames)
     oracle.set_threads(1)
     dt1 = run(1)
