@@ -301,6 +301,22 @@ def bench_batched(h, synth, torch, dev):
                             "nmse_rel_mean": float(np.mean(nrel)), "nmse_rel_max": float(np.max(nrel)),
                             "ibar_rel_l2_mean": float(np.mean(irel)), "ibar_rel_l2_max": float(np.max(irel))}
         res[name] = r
+    # the same 64 frames as 64 single-frame calls in batch order on one stream
+    # (cursor chained), against the one graph launch over four branches
+    bits1 = [torch.empty((k, n * n // 32), dtype=torch.int32, device=dev) for n, k in layout]
+    nm1 = torch.zeros(2, dtype=torch.float64, device=dev)
+
+    def sequential(c):
+        for f in range(64):
+            _, _, c = h.ospr_generate(targets[f], nsfs[f], lut, c, bits=bits1[f], want_nmse=False, nmse_out=nm1)
+        return c
+    c = sequential(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        c = sequential(c)
+    torch.cuda.synchronize()
+    res["fp32_sequential_ms_per_batch"] = round(1e3 * (time.perf_counter() - t0) / 5, 3)
     return res
 
 
