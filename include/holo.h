@@ -61,12 +61,13 @@ enum {
 
 /* Arithmetic of the transform stages.
  *   HOLO_FP32  radix stages in FP32 on the vector ALUs.
- *   HOLO_BF16, HOLO_FP16  every radix-R stage of every transform as a small
- *              DFT-matrix product on the matrix cores: data rounded once per
- *              stage to BF16 (8 significant bits) or FP16 (11), DFT matrix
- *              split into two operand-format terms (hi + lo), FP32
- *              accumulation; inter-stage twiddles, pointwise steps and all
- *              sums stay FP32/FP64.  Sides of 256 and more only.  Results are
+ *   HOLO_BF16, HOLO_FP16  the 16-point DFTs of every radix-16 stage of
+ *              every transform as DFT-matrix products on the matrix cores:
+ *              data rounded once per radix-16 stage to BF16 (8 significant
+ *              bits) or FP16 (11), DFT matrix split into two operand-format
+ *              terms (hi + lo), FP32 accumulation; inter-stage twiddles, the
+ *              last radix-2/4/8 stage, pointwise steps and all sums stay
+ *              FP32/FP64.  Sides of 256 and more only.  Results are
  *              not bit-exact: binarisation flips pixels whose Re H is within
  *              the rounding error of 0.
  * Entry points that take a precision return HOLO_EUNSUPPORTED for BF16/FP16

@@ -1,30 +1,27 @@
-// mfma_dft.hpp -- DFT stages as small DFT-matrix products on gfx950 matrix
+// mfma_dft.hpp -- radix-16 DFTs of the register FFT engine on gfx950 matrix
 // cores (BF16 or FP16 operands, FP32 accumulation).
 //
-// Same contract as fft_stages in fft_engine.hpp (thread t of a length-N
-// transform holds element t + T*m in slot m on entry and on exit, T = N/16),
-// same Stockham factorisation (radix 16 while 16 divides, then one radix
-// 2/4/8 stage), same inter-stage twiddles W_{Ns*R}^{(j mod Ns)*r} from the
-// FP32 table, applied on the vector ALUs in FP32.  What changes is the R-point
-// DFT itself: the T threads' butterfly sets ("vectors" of 16 points, 16/R
-// butterflies of R points) are taken 32 at a time as one operand of
-// v_mfma_f32_32x32x16_{bf16,f16}, with the DFT matrix as the other:
+// The transform is fft_stages of fft_engine.hpp -- same slot contract (thread
+// t of a length-N transform holds element t + T*m in slot m on entry and on
+// exit, T = N/16), same Stockham factorisation (radix 16 while 16 divides,
+// then one radix-2/4/8 stage), same FP32 inter-stage twiddles and LDS
+// exchanges -- with one change: the 16-point DFT of each radix-16 butterfly is
+// a DFT-matrix product on the matrix cores instead of butterflies on the
+// vector ALUs.  A wave's 64 threads are 64 vectors of 16 points; per group of
+// 32 vectors v_mfma_f32_32x32x16_{bf16,f16} computes
 //
-//   Y[v][k'] = sum_k X[v][k] W[k][k'],  W = blockdiag(W_R, ..., W_R) (16x16),
-//   W_R[r][q] = exp(SIGN*2*pi*i*r*q/R) / R,
+//   D = W^T X^T,  W[r][q] = exp(SIGN*2*pi*i*r*q/16) / 16,
 //
-// as two real products per K block (Re X and Im X against [[Re W, Im W],
-// [-Im W, Re W]]), 32 output columns = 16 real parts then 16 imaginary
-// parts.  W is split W = W_hi + W_lo (W_hi = rn(W), W_lo = rn(W - W_hi) in the
-// operand format, from FP64 values generated on the device), so each product
-// is X*W_hi + X*W_lo accumulated in FP32:
-// four MFMAs per 32 vectors.  The data are rounded to the operand format once
-// per stage (after the FP32 twiddle).  The 1/R per stage keeps FP16 operands
-// in range and is undone exactly (x N, a power of two) on exit.
-//
-// Stages run LDS -> registers -> MFMA -> LDS; the engine writes the slot data
-// to LDS on entry and reads it back on exit.  Every lane of the block takes
-// part (blockDim a multiple of 64; a wave's 64 threads are its 64 vectors).
+// as real products (Re X and Im X against the real and imaginary parts of the
+// coefficients), the 32 rows of D being the real and imaginary part of each
+// output in turn.  W is split W = W_hi + W_lo (W_hi = rn(W), W_lo = rn(W -
+// W_hi) in the operand format, from FP64 values generated on the device), so
+// each product is X*W_hi + X*W_lo accumulated in FP32: four MFMAs per 32
+// vectors.  The data are rounded to the operand format once per radix-16
+// stage (after the FP32 twiddle); the last radix-2/4/8 stage stays FP32.  The
+// 1/16 per stage keeps FP16 operands in range and is undone exactly (x 16^s)
+// after the transform.  The data stay in registers: operand and result layouts
+// are matched to the threads' own vectors with lane swaps (below).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -33,7 +30,6 @@
 namespace holo {
 
 typedef float mf32x16 __attribute__((ext_vector_type(16)));
-typedef float mf32x8 __attribute__((ext_vector_type(8)));
 
 template <int PREC>
 struct MfmaOp;
@@ -42,7 +38,12 @@ struct MfmaOp;
 template <>
 struct MfmaOp<1> {
     typedef __bf16 v8 __attribute__((ext_vector_type(8)));
-    static __device__ __forceinline__ v8 cvt(mf32x8 x) { return __builtin_convertvector(x, v8); }
+    // two values rounded to nearest even, the first in bits 0..15
+    static __device__ __forceinline__ uint32_t pack(float a, float b)
+    {
+        const __bf16 x = (__bf16)a, y = (__bf16)b;
+        return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
+    }
     static __device__ __forceinline__ mf32x16 mma(v8 a, v8 b, mf32x16 c)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -53,28 +54,15 @@ struct MfmaOp<1> {
 template <>
 struct MfmaOp<2> {
     typedef _Float16 v8 __attribute__((ext_vector_type(8)));
-    static __device__ __forceinline__ v8 cvt(mf32x8 x) { return __builtin_convertvector(x, v8); }
+    static __device__ __forceinline__ uint32_t pack(float a, float b)
+    {
+        const _Float16 x = (_Float16)a, y = (_Float16)b;
+        return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
+    }
     static __device__ __forceinline__ mf32x16 mma(v8 a, v8 b, mf32x16 c)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
     }
-};
-
-// Thread layouts of the kernels, as seen by the engine: slot index t of block
-// thread `tid`, and the LDS element (float2) index of padded position p of
-// that thread's transform, base(tid) + p * S.
-template <int N>
-struct RowsOf {   // one transform per T consecutive threads, one padded LDS row each
-    static constexpr int T = N / kP;
-    static constexpr int S = 1;
-    __device__ __forceinline__ int t(int tid) const { return tid & (T - 1); }
-    __device__ __forceinline__ int base(int tid) const { return (tid / T) * PadLen<N>::v; }
-};
-template <int N, int C>
-struct ColsOf {   // C interleaved transforms: thread (c, t) = c + C*t
-    static constexpr int S = C;
-    __device__ __forceinline__ int t(int tid) const { return tid / C; }
-    __device__ __forceinline__ int base(int tid) const { return tid & (C - 1); }
 };
 
 // DFT-matrix operands, generated once per device in FP64 (launch_dft_operand_gen):
@@ -83,143 +71,99 @@ struct ColsOf {   // C interleaved transforms: thread (c, t) = c + C*t
 // values as one 16-byte word: uint4 index ((ri*2 + si)*4 + part)*64 + l.
 // Row o = l & 31 of W^T is output o >> 1, real part (o even) or imaginary
 // part (o odd); column k = 8*(l >> 5) + e is input point k.
-template <int PREC, int R, int SIGN>
-__device__ __forceinline__ void load_operand(const uint4* __restrict__ op, int lane, typename MfmaOp<PREC>::v8 (&a)[4])
+// Scalar reinterpretation by value.  (Reinterpreting an element of an
+// ext_vector value in place with __builtin_bit_cast reads element 0 whatever
+// the index, with this compiler, so elements are copied out first.)
+__device__ __forceinline__ uint32_t f2u(float f) { return __builtin_bit_cast(uint32_t, f); }
+__device__ __forceinline__ float u2f(uint32_t u) { return __builtin_bit_cast(float, u); }
+
+// Register reinterpretation of a whole vector (same size), by value.
+template <typename To, typename From>
+__device__ __forceinline__ To vcast(From x)
 {
-    constexpr int ri = R == 16 ? 3 : R == 8 ? 2 : R == 4 ? 1 : 0;
-    const uint4* p = op + ((ri * 2 + (SIGN > 0 ? 1 : 0)) * 4) * 64 + lane;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] = __builtin_bit_cast(typename MfmaOp<PREC>::v8, p[q * 64]);
+    static_assert(sizeof(To) == sizeof(From), "same size");
+    To r;
+    __builtin_memcpy(&r, &x, sizeof(To));
+    return r;
 }
 
-// The DFT-matrix product runs transposed, D = W^T X^T: the A operand holds
-// the 32 output rows of W^T (real and imaginary part of each output, in
-// turn), the B operand 32 vectors (lane l32 of each half-wave holds points
-// 8*half..+7 of vector l32), and registers 2p, 2p+1 of the result hold, for
-// the lane's vector, the real and imaginary part of output
-// 4*(p>>1) + 2*half + (p&1).  So every LDS access of a lane is a per-lane base
-// plus a compile-time offset, and outputs leave as complex pairs straight from
-// adjacent accumulator registers.  The
-// padded positions (one spare slot per 16, as in the register engine) keep
-// the strided accesses on distinct banks; T = N/16 is a multiple of 16, so
-// pad(x + 16m) = pad(x) + 17m splits every address that way.
-template <int N, int SIGN, int PREC, typename Lay, bool WAVE_LOCAL = false>
-__device__ __forceinline__ void fft_stages_mfma(float2 (&v)[kP], float2* lds, const Lay& lay,
-                                                const float2* __restrict__ tw, const uint4* __restrict__ dftop)
+// v_permlane32_swap of (a, b): lanes 32..63 of a trade places with lanes 0..31
+// of b (lanes 0..31 of a and 32..63 of b stay).
+__device__ __forceinline__ void swap_halves(uint32_t& a, uint32_t& b)
 {
-    using M = MfmaOp<PREC>;
-    constexpr int T = N / kP;
-    static_assert(T % 16 == 0, "matrix-core stages need N >= 256");
-    constexpr int T17 = T / 16 * 17;
-    constexpr int L = ilog2<N>::v;
-    constexpr int NS16 = L / 4;
-    constexpr int REM = L % 4;
-    constexpr int NSTAGE = NS16 + (REM ? 1 : 0);
-    constexpr int S = Lay::S;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, half = lane >> 5, l32 = lane & 31;
-    const int wbase = tid - lane;
-    const auto rtw = make_rsrc(tw, (uint32_t)(N * sizeof(float2)));
-
-    {
-        const int b = lay.base(tid) + lds_pad(lay.t(tid)) * S;
-#pragma unroll
-        for (int m = 0; m < kP; ++m) lds[b + m * T17 * S] = v[m];
-    }
-    exchange_sync<WAVE_LOCAL>();
-
-    int tt[2], bs[2];
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-        const int vt = wbase + 32 * g + l32;
-        tt[g] = lay.t(vt);
-        bs[g] = lay.base(vt);
-    }
-    int Ns = 1;
-#pragma unroll
-    for (int s = 0; s < NSTAGE; ++s) {
-        const int R = (s < NS16) ? 16 : (1 << REM);
-        // B operands: points k = 8*half + e of the wave's 64 vectors, FP32
-        // twiddle W_{Ns R}^{(j mod Ns) r} first (butterfly j = tt + b*T reads
-        // element j + r*N/R)
-        typename M::v8 xr[2], xi[2];
-        mf32x8 fr, fi;
-        const int bh = R == 16 ? 0 : 8 * half / R;   // butterfly offset of this half
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-            const int lb = bs[g] + (lds_pad(tt[g]) + (R == 16 ? 8 * half * T17 : bh * T17)) * S;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int off = R == 16 ? e * T17 : ((e / R) * T + (e % R) * (N / R)) / 16 * 17;
-                float2 x = lds[lb + off * S];
-                if (Ns > 1) {
-                    const int r = R == 16 ? 8 * half + e : e % R;
-                    const int j = tt[g] + (bh + (R == 16 ? 0 : e / R)) * T;
-                    const float2 w = buf_ld2(rtw, (uint32_t)((j & (Ns - 1)) * (N / (Ns * R)) * r) * 8u, 0);
-                    x = SIGN < 0 ? cmul(x, w) : cmulc(x, w);
-                }
-                fr[e] = x.x;
-                fi[e] = x.y;
-            }
-            xr[g] = M::cvt(fr);
-            xi[g] = M::cvt(fi);
-        }
-        exchange_sync<WAVE_LOCAL>();
-        typename M::v8 a[4];
-        if (R == 16) load_operand<PREC, 16, SIGN>(dftop, lane, a);
-        else load_operand<PREC, (1 << (REM ? REM : 1)), SIGN>(dftop, lane, a);
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-            mf32x16 acc = {};
-            acc = M::mma(a[0], xr[g], acc);
-            acc = M::mma(a[1], xr[g], acc);
-            acc = M::mma(a[2], xi[g], acc);
-            acc = M::mma(a[3], xi[g], acc);
-            // output ko = 4*(p>>1) + 2*half + (p&1) of butterfly j = tt + (ko/R)*T
-            // goes to Stockham position (j/Ns)*Ns*R + (j mod Ns) + (ko mod R)*Ns
-            int sb;
-            if (Ns == 1) {   // first stage, R = 16: 16*tt + ko, padded 17*tt + ko
-                sb = bs[g] + (17 * tt[g] + 2 * half) * S;
-            } else if (R == 16) {
-                const int j = tt[g];
-                sb = bs[g] + (lds_pad((j / Ns) * 16 * Ns + (j & (Ns - 1))) + 2 * half * (Ns / 16) * 17) * S;
-            } else {         // last stage, j < Ns: position j + q*Ns
-                sb = bs[g] + (lds_pad(tt[g]) + ((2 * half / R) * T + (2 * half % R) * Ns) / 16 * 17) * S;
-            }
-#pragma unroll
-            for (int p = 0; p < 8; ++p) {
-                const int kc = 4 * (p >> 1) + (p & 1);
-                const int off = Ns == 1 ? kc
-                                : R == 16 ? kc * (Ns / 16) * 17
-                                          : ((kc / R) * T + (kc % R) * Ns) / 16 * 17;
-                lds[sb + off * S] = make_float2(acc[2 * p], acc[2 * p + 1]);
-            }
-        }
-        exchange_sync<WAVE_LOCAL>();
-        Ns *= R;
-    }
-    {
-        const float sc = (float)N;   // undoes the 1/R of every stage (exact)
-        const int b = lay.base(tid) + lds_pad(lay.t(tid)) * S;
-#pragma unroll
-        for (int m = 0; m < kP; ++m) {
-            const float2 x = lds[b + m * T17 * S];
-            v[m] = make_float2(x.x * sc, x.y * sc);
-        }
-    }
-    exchange_sync<WAVE_LOCAL>();
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
 }
 
-// One transform through the FP32 register engine (PREC 0) or the matrix
-// cores (PREC 1 = BF16, 2 = FP16).  `addr` is the calling thread's LDS
-// addressing for the register engine; `lay` the block's layout for the
-// matrix-core engine.
-template <int N, int SIGN, int PREC, bool WAVE_LOCAL = false, typename Addr, typename Lay>
-__device__ __forceinline__ void fft_any(float2 (&v)[kP], int t, float2* lds, Addr addr, const Lay& lay,
+template <int SIGN, int PREC>
+struct Dft16Mfma {
+    typedef typename MfmaOp<PREC>::v8 V;
+    const uint4* dftop;   // operand table (the W_16/16 operand is read per call: 4 KiB, cache-resident)
+    __device__ __forceinline__ void operator()(float2 (&u)[16]) const
+    {
+        using M = MfmaOp<PREC>;
+        // DFT-matrix operand (the table layout above, radix 16): Re-coefficient
+        // hi, lo; Im-coefficient hi, lo
+        const uint4* op = dftop + ((3 * 2 + (SIGN > 0 ? 1 : 0)) * 4) * 64 + (threadIdx.x & 63);
+        const V a0 = vcast<V>(op[0]), a1 = vcast<V>(op[64]), a2 = vcast<V>(op[128]), a3 = vcast<V>(op[192]);
+        // the lane's points in the operand format, two per register (point 2d
+        // in the low half), then halves traded with lane l ^ 32
+        uint32_t r0[4], r1[4], i0[4], i1[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            r0[d] = M::pack(u[2 * d].x, u[2 * d + 1].x);
+            i0[d] = M::pack(u[2 * d].y, u[2 * d + 1].y);
+            r1[d] = M::pack(u[8 + 2 * d].x, u[9 + 2 * d].x);
+            i1[d] = M::pack(u[8 + 2 * d].y, u[9 + 2 * d].y);
+            swap_halves(r0[d], r1[d]);
+            swap_halves(i0[d], i1[d]);
+        }
+        const V b0r = vcast<V>(u32x4_t{r0[0], r0[1], r0[2], r0[3]});
+        const V b0i = vcast<V>(u32x4_t{i0[0], i0[1], i0[2], i0[3]});
+        const V b1r = vcast<V>(u32x4_t{r1[0], r1[1], r1[2], r1[3]});
+        const V b1i = vcast<V>(u32x4_t{i1[0], i1[1], i1[2], i1[3]});
+        mf32x16 acc0 = {}, acc1 = {};
+        acc0 = M::mma(a0, b0r, acc0);
+        acc0 = M::mma(a1, b0r, acc0);
+        acc0 = M::mma(a2, b0i, acc0);
+        acc0 = M::mma(a3, b0i, acc0);
+        acc1 = M::mma(a0, b1r, acc1);
+        acc1 = M::mma(a1, b1r, acc1);
+        acc1 = M::mma(a2, b1i, acc1);
+        acc1 = M::mma(a3, b1i, acc1);
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const int k = 4 * (p >> 1) + (p & 1);
+            uint32_t x0 = f2u(acc0[2 * p]), x1 = f2u(acc1[2 * p]);
+            uint32_t y0 = f2u(acc0[2 * p + 1]), y1 = f2u(acc1[2 * p + 1]);
+            swap_halves(x0, x1);
+            swap_halves(y0, y1);
+            u[k] = make_float2(u2f(x0), u2f(y0));
+            u[k + 2] = make_float2(u2f(x1), u2f(y1));
+        }
+    }
+};
+
+// One transform through the FP32 register engine (PREC 0) or with its radix-16
+// DFTs on the matrix cores (PREC 1 = BF16, 2 = FP16; the inter-stage twiddles
+// and the last radix-2/4/8 stage stay FP32 on the vector ALUs).  `addr` is the
+// calling thread's LDS addressing.  With PREC > 0 every lane of each wave must
+// take part (blocks of whole waves, no divergence around the call).
+template <int N, int SIGN, int PREC, bool WAVE_LOCAL = false, typename Addr>
+__device__ __forceinline__ void fft_any(float2 (&v)[kP], int t, float2* lds, Addr addr,
                                         const float2* __restrict__ tw, const uint4* __restrict__ dftop)
 {
-    if constexpr (PREC == 0) fft_stages<N, SIGN, Addr, WAVE_LOCAL>(v, t, lds, addr, tw);
-    else fft_stages_mfma<N, SIGN, PREC, Lay, WAVE_LOCAL>(v, lds, lay, tw, dftop);
+    if constexpr (PREC == 0) {
+        fft_stages<N, SIGN, Addr, WAVE_LOCAL>(v, t, lds, addr, tw);
+    } else {
+        const Dft16Mfma<SIGN, PREC> d16{dftop};
+        fft_stages<N, SIGN, Addr, WAVE_LOCAL, kP, Dft16Mfma<SIGN, PREC>>(v, t, lds, addr, tw, d16);
+        // undo the 1/16 of every radix-16 stage (exact)
+        constexpr float sc = (float)(1 << (4 * (ilog2<N>::v / 4)));
+#pragma unroll
+        for (int m = 0; m < kP; ++m) v[m] = make_float2(v[m].x * sc, v[m].y * sc);
+    }
 }
 
 }  // namespace holo

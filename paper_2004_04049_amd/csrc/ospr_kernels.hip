@@ -62,7 +62,7 @@ namespace holo {
 #define HOLO_SWITCH_C(c, ...)                                                \
     switch (c) {                                                             \
         case 2: { constexpr int C_ = P_ ? 8 : 2; __VA_ARGS__; } break;       \
-        case 4: { constexpr int C_ = P_ ? 8 : 4; __VA_ARGS__; } break;       \
+        case 4: { constexpr int C_ = 4; __VA_ARGS__; } break;                \
         case 8: { constexpr int C_ = 8; __VA_ARGS__; } break;                \
         case 16: { constexpr int C_ = P_ ? 8 : 16; __VA_ARGS__; } break;     \
         default: return hipErrorInvalidValue;                                \
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(P ? 256 : 1024) void k_fft_rows(const float2* __res
     const float2* src = in + y * N;
 #pragma unroll
     for (int m = 0; m < kP; ++m) v[m] = src[t + T * m];
-    fft_any<N, SIGN, P, (N / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<N>::v}, RowsOf<N>{}, tw, dftop);
+    fft_any<N, SIGN, P, (N / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<N>::v}, tw, dftop);
     float2* dst = out + y * N;
 #pragma unroll
     for (int m = 0; m < kP; ++m) dst[t + T * m] = v[m];
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(C * (N / kP)) void k_fft_cols(const float2* __restr
     float2 v[kP];
 #pragma unroll
     for (int m = 0; m < kP; ++m) v[m] = ld_off(in + x0 + m * mstride, toff);
-    fft_any<N, SIGN, P>(v, t, lds, ColAddr<C>{c}, ColsOf<N, C>{}, tw, dftop);
+    fft_any<N, SIGN, P>(v, t, lds, ColAddr<C>{c}, tw, dftop);
 #pragma unroll
     for (int m = 0; m < kP; ++m) st_off(out + x0 + m * mstride, toff, make_float2(v[m].x * scale, v[m].y * scale));
 }
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(C * (N / kP)) void k_fft_cols(const float2* __restr
 template <typename K>
 static void allow_lds(K kernel, size_t bytes)
 {
-    if (bytes > 64 * 1024) hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (bytes > 64 * 1024) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int ny, int sign,
@@ -243,11 +243,14 @@ hipError_t launch_fft2(const float2* in, float2* tmp, float2* out, int nx, int n
         });
     }
     {
-        const int C = cfg.prec ? 8 : col_block_cols(ny, nx, 1, cfg.cols_per_block, 2);
+        // matrix-core columns: 8 per block (4 at 2048, within 128 registers a thread)
+        const int C = cfg.prec ? (ny >= 2048 ? 4 : 8) : col_block_cols(ny, nx, 1, cfg.cols_per_block, 2);
         const float scale = (float)(1.0 / sqrt((double)nx * (double)ny));
         HOLO_SWITCH_NP(ny, cfg.prec, HOLO_SWITCH_C(C, {
             constexpr int T = N_ / kP;
-            if (C_ * T <= 1024) {
+            if constexpr (C_ * T > (P_ ? 512 : 1024)) {
+                return hipErrorInvalidValue;
+            } else {
                 size_t lds = (size_t)C_ * PadLen<N_>::v * sizeof(float2);
                 if (sign < 0) {
                     allow_lds(k_fft_cols<N_, -1, C_, P_>, lds);
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(P ? 256 : 512) void k_ospr_rows(const float* __rest
         phase_slots<kP>(src, pos0, (uint32_t)T, t, rs, v, lt);
 #pragma unroll
         for (int m = 0; m < kP; ++m) v[m] = make_float2(a[m] * v[m].x, a[m] * v[m].y);
-        fft_any<NX, 1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, RowsOf<NX>{}, tw, dftop);
+        fft_any<NX, 1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, tw, dftop);
         const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
 #pragma unroll
         for (int m = 0; m < kP; ++m) buf_st2(ro, ooff, (uint32_t)(m * T * 8), v[m]);
@@ -415,7 +418,7 @@ __global__ __launch_bounds__(P ? 256 : 512) void k_ospr_rows_h(const float* __re
             // R(x, y) + conj R(-x, -y)
             v[m] = make_float2(fmaf(a[m], v[m].x, bm * wm.x), fmaf(a[m], v[m].y, -bm * wm.y));
         }
-        fft_any<NX, 1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, RowsOf<NX>{}, tw, dftop);
+        fft_any<NX, 1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, tw, dftop);
         if (yr < nh) {
             const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
 #pragma unroll
@@ -462,7 +465,9 @@ hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, con
 // mirror row ny - y = (T - t) + T*(15 - m) (also for t = 0, where slot 8 is row
 // ny/2) and conjugates; rows 0 and ny/2 are real up to rounding, and their real
 // parts are taken.  The C/2 lanes of a row segment are adjacent in the wave,
-// so two ballots give the row's C bits.
+// so two ballots give the row's C bits.  Four waves per SIMD (what the LDS
+// tile allows): the matrix-core form would otherwise take 148 registers and
+// run three.
 // -------------------------------------------------------------------------
 // Bits 0..7 of x moved to the even positions 0, 2, .., 14.
 __device__ __forceinline__ uint32_t spread_bits8(uint32_t x)
@@ -473,7 +478,7 @@ __device__ __forceinline__ uint32_t spread_bits8(uint32_t x)
 }
 
 template <int NY, int C, int P>
-__global__ __launch_bounds__((C / 2) * (NY / kP)) void k_ospr_cols2(const float2* __restrict__ x1, int nx,
+__global__ __launch_bounds__((C / 2) * (NY / kP)) __attribute__((amdgpu_waves_per_eu(P && NY <= 256 ? 3 : 4))) void k_ospr_cols2(const float2* __restrict__ x1, int nx,
                                                                    uint32_t* __restrict__ bits,
                                                                    float2* __restrict__ x2,
                                                                    const float2* __restrict__ tw, int pitch,
@@ -506,7 +511,7 @@ __global__ __launch_bounds__((C / 2) * (NY / kP)) void k_ospr_cols2(const float2
             v[kP / 2] = make_float2(cd.x, cd.z);
         }
     }
-    fft_any<NY, 1, P>(v, t, lds, ColAddr<CP>{q}, ColsOf<NY, CP>{}, tw, dftop);
+    fft_any<NY, 1, P>(v, t, lds, ColAddr<CP>{q}, tw, dftop);
 
     // nearest of {+1, -1}: bit = (Re h < 0); Re h = 0 -> +1.  The CP lanes of
     // a row give the even columns' bits (ballot of .x) and the odd columns'
@@ -527,7 +532,7 @@ __global__ __launch_bounds__((C / 2) * (NY / kP)) void k_ospr_cols2(const float2
         }
         v[m] = make_float2(na ? -1.0f : 1.0f, nb ? -1.0f : 1.0f);
     }
-    fft_any<NY, -1, P>(v, t, lds, ColAddr<CP>{q}, ColsOf<NY, CP>{}, tw, dftop);
+    fft_any<NY, -1, P>(v, t, lds, ColAddr<CP>{q}, tw, dftop);
 
     // separation: rows v <= NY/2 (slots m < 8, and m = 8 for t = 0) need Z at
     // -v, which lies in slots 8..15, or slot 0 for v = 0
@@ -556,14 +561,14 @@ hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t
     // engine's column layout wants.  FP32: 8-column tiles (4 transforms per
     // block) unless planned; measured at 1024^2, 24 sub-frames: 50.3 us
     // against 55.2 us for 16-column tiles
-    const int C = cfg.prec ? 16 : cfg.cols_per_block > 0 ? col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8) : 8;
+    const int C = cfg.prec ? 8 : cfg.cols_per_block > 0 ? col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8) : 8;
     HOLO_SWITCH_NP(ny, cfg.prec, {
         constexpr int T = N_ / kP;
         if constexpr (P_ != 0) {
-            if (8 * T <= 1024) {
-                size_t lds = (size_t)8 * PadLen<N_>::v * sizeof(float2);
-                allow_lds(k_ospr_cols2<N_, 16, P_>, lds);
-                hipLaunchKernelGGL((k_ospr_cols2<N_, 16, P_>), dim3((nx / 16) * n_sf), dim3(8 * T), lds, s, x1, nx,
+            if (4 * T <= 1024) {
+                size_t lds = (size_t)4 * PadLen<N_>::v * sizeof(float2);
+                allow_lds(k_ospr_cols2<N_, 8, P_>, lds);
+                hipLaunchKernelGGL((k_ospr_cols2<N_, 8, P_>), dim3((nx / 8) * n_sf), dim3(4 * T), lds, s, x1, nx,
                                    bits, x2, tw_y, row_pitch(nx, cfg), DFTOP(cfg));
             }
         } else {
@@ -619,7 +624,7 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols_pair(const float2* 
     float2 v[kP];
 #pragma unroll
     for (int m = 0; m < kP; ++m) v[m] = buf_ld2(rin, voff, m * mst);
-    fft_any<NY, 1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
+    fft_any<NY, 1, P>(v, t, lds, ColAddr<C>{c}, tw, dftop);
 
     // nearest of {+1, -1} for Re H (sub-frame 2j) and Im H (sub-frame 2j+1)
     const auto rb_re = make_rsrc(bits + (size_t)(2 * j) * (npix / 32), (uint32_t)(npix / 8));
@@ -642,7 +647,7 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols_pair(const float2* 
         }
         v[m] = make_float2(nre ? -1.0f : 1.0f, nim ? -1.0f : 1.0f);
     }
-    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
+    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, tw, dftop);
 
     // mirror rows through LDS (plain [row][C] layout; the engine is done with it)
     __syncthreads();
@@ -695,7 +700,7 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols_l8(const float2* __
     float2 v[kP];
 #pragma unroll
     for (int m = 0; m < kP; ++m) v[m] = buf_ld2(rin, voff, m * mst);
-    fft_any<NY, 1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
+    fft_any<NY, 1, P>(v, t, lds, ColAddr<C>{c}, tw, dftop);
     const auto rc = make_rsrc(codes + (size_t)k * npix, (uint32_t)npix);
     const uint32_t coff = (uint32_t)t * (uint32_t)nx + (uint32_t)(x0 + c);
 #pragma unroll
@@ -704,7 +709,7 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_ospr_cols_l8(const float2* __
         __builtin_amdgcn_raw_buffer_store_b8((unsigned char)q, rc, coff, (uint32_t)(m * T * nx), 0);
         v[m] = level8_phasor(q);
     }
-    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
+    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, tw, dftop);
     const auto rout = make_rsrc(x2 + (size_t)k * plane, (uint32_t)(plane * 8));
 #pragma unroll
     for (int m = 0; m < kP; ++m) buf_st2(rout, voff, m * mst, v[m]);
@@ -768,7 +773,7 @@ __global__ __launch_bounds__(C * (NY / kP)) void k_recon_cols(const void* __rest
 #pragma unroll
         for (int m = 0; m < kP; ++m) v[m] = level8_phasor(cd[(size_t)(t + T * m) * nx + x]);
     }
-    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, ColsOf<NY, C>{}, tw, dftop);
+    fft_any<NY, -1, P>(v, t, lds, ColAddr<C>{c}, tw, dftop);
     const int vmax = levels == 2 ? NY / 2 : NY - 1;
     float2* dst = x2 + (size_t)k * (vmax + 1) * pitch;
 #pragma unroll
@@ -836,7 +841,7 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(P
         float2 v[kP];
 #pragma unroll
         for (int m = 0; m < kP; ++m) v[m] = buf_ld2(rx, roff, (uint32_t)(m * T * 8));
-        fft_any<NX, -1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, RowsOf<NX>{}, tw, dftop);
+        fft_any<NX, -1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, tw, dftop);
         if (valid) {
 #pragma unroll
             for (int m = 0; m < kP; ++m) acc[m] = fmaf(v[m].x, v[m].x, fmaf(v[m].y, v[m].y, acc[m]));

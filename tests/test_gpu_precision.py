@@ -1,13 +1,13 @@
 """BF16 / FP16 matrix-core DFT stages against the FP64 oracle.
 
-Error model: every stage rounds its input to the operand format once
+Error model: every radix-16 stage rounds its input to the operand format once
 (round to nearest, relative error at most u per real component, RMS below
 u/sqrt(3); u = 2^-8 for BF16 with 8 significant bits, 2^-11 for FP16 with
-11); the split DFT matrix (hi + lo) and the FP32 accumulation add O(u^2).  The
-stages are (scaled) unitary, so independent stage errors add in quadrature:
-the relative L2 error of a 2D transform with S stages in all is below
-u * sqrt(S / 3) (a stage-by-stage emulation with round-to-nearest gives 0.74
-of that for both formats).  Bound used: u * sqrt(S).
+11); the split DFT matrix (hi + lo), the FP32 accumulation and the FP32 last
+radix-2/4/8 stage add O(u^2).  The stages are (scaled) unitary, so
+independent stage errors add in quadrature: the relative L2 error of a 2D
+transform with S radix-16 stages in all is below u * sqrt(S / 3).  Bound
+used: u * sqrt(S).
 
 Binarisation flips a pixel when the error of Re H exceeds |Re H|; with Re H
 roughly Gaussian that is a fraction ~ sqrt(2/pi) * (relative error of H) of
@@ -37,8 +37,8 @@ def holo():
 
 
 def _stages(n):
-    l2 = int(math.log2(n))
-    return l2 // 4 + (1 if l2 % 4 else 0)
+    """Radix-16 stages of a length-n transform (the ones that round)."""
+    return int(math.log2(n)) // 4
 
 
 def _rel_l2(a, b):
