@@ -190,19 +190,10 @@ __device__ __forceinline__ void apply_twiddles(float2 (&u)[R], const float2* __r
     }
 }
 
-// The 16-point DFT of a radix-16 stage on the vector ALUs: the default of
-// fft_stages.  Another functor with the same contract (natural order in and
-// out, kernel exp(SIGN*2*pi*i*q*r/16), unscaled or scaled by a constant the
-// caller undoes) may replace it.
-template <int SIGN>
-struct Dft16Valu {
-    __device__ __forceinline__ void operator()(float2 (&u)[16]) const { dft_small<16, SIGN>(u); }
-};
-
 // One radix-R stage on butterfly b of thread t (slots b + r*P/R).
-template <int N, int R, int SIGN, int P = kP, typename D16 = Dft16Valu<SIGN>>
+template <int N, int R, int SIGN, int P = kP>
 __device__ __forceinline__ void stage_butterfly(float2 (&v)[P], int t, int b, int Ns,
-                                                const float2* __restrict__ tw, const D16& d16 = D16{})
+                                                const float2* __restrict__ tw)
 {
     constexpr int T = N / P;
     constexpr int nb = P / R;
@@ -211,8 +202,7 @@ __device__ __forceinline__ void stage_butterfly(float2 (&v)[P], int t, int b, in
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[b + r * nb];
     if (Ns > 1) apply_twiddles<R, SIGN>(u, tw, (j & (Ns - 1)) * (N / (Ns * R)));
-    if constexpr (R == 16) d16(u);
-    else dft_small<R, SIGN>(u);
+    dft_small<R, SIGN>(u);
 #pragma unroll
     for (int r = 0; r < R; ++r) v[b + r * nb] = u[r];
 }
@@ -240,9 +230,9 @@ __device__ __forceinline__ void exchange_sync()
     }
 }
 
-template <int N, int SIGN, typename Addr, bool WAVE_LOCAL = false, int P = kP, typename D16 = Dft16Valu<SIGN>>
+template <int N, int SIGN, typename Addr, bool WAVE_LOCAL = false, int P = kP>
 __device__ __forceinline__ void fft_stages(float2 (&v)[P], int t, float2* lds, Addr addr,
-                                           const float2* __restrict__ tw, const D16& d16 = D16{})
+                                           const float2* __restrict__ tw)
 {
     static_assert(P == 4 || P == 8 || P == 16, "points per thread");
     constexpr int T = N / P;
@@ -260,7 +250,7 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[P], int t, float2* lds, A
         const int nb = P / R;
 #pragma unroll
         for (int b = 0; b < nb; ++b) {
-            if (R == 16) stage_butterfly<N, 16, SIGN, P, D16>(v, t, b, Ns, tw, d16);
+            if (R == 16) stage_butterfly<N, 16, SIGN, P>(v, t, b, Ns, tw);
             else if (R == 8) stage_butterfly<N, 8, SIGN, P>(v, t, b, Ns, tw);
             else if (R == 4) stage_butterfly<N, 4, SIGN, P>(v, t, b, Ns, tw);
             else stage_butterfly<N, 2, SIGN, P>(v, t, b, Ns, tw);

@@ -201,7 +201,7 @@ holo_status get_dftop(int device, int prec, hipStream_t s, const void** out)
         return HOLO_OK;
     }
     void* t = nullptr;
-    if (hipMalloc(&t, 4 * 2 * 4 * 64 * 8 * sizeof(uint16_t)) != hipSuccess)
+    if (hipMalloc(&t, kDftOpElems * sizeof(uint16_t)) != hipSuccess)
         return fail(HOLO_ENOMEM, "DFT operand table");
     HIP_TRY(launch_dft_operand_gen((uint16_t*)t, prec, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -38,8 +38,10 @@ int col_block_cols(int n, int ncols, int nbatch, int planned, int cmin);
 // FP64 twiddle generation on the device: tw[k] = fp32(exp(-2*pi*i*k/n)).
 hipError_t launch_twiddle_gen(float2* tw, int n, hipStream_t s);
 
-// DFT-matrix operand table of the matrix-core stages, 32 KiB: prec 1 (BF16)
-// or 2 (FP16), FP64 evaluation on the device.
+// DFT-matrix operand table of the matrix-core radix-16 DFTs (kDftOpElems
+// 16-bit values, 8 KiB): prec 1 (BF16) or 2 (FP16), FP64 evaluation on the
+// device.
+constexpr int kDftOpElems = 2 * 4 * 64 * 8;
 hipError_t launch_dft_operand_gen(uint16_t* out, int prec, hipStream_t s);
 
 // Plain unitary 2D transform (Eq. (1) for sign < 0, Eq. (2) for sign > 0):

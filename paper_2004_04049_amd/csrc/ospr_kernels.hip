@@ -130,38 +130,37 @@ hipError_t launch_twiddle_gen(float2* tw, int n, hipStream_t s)
 }
 
 // -------------------------------------------------------------------------
-// DFT-matrix operands of the matrix-core stages (layout in mfma_dft.hpp):
-// W_R[r][q] = exp(sign*2*pi*i*r*q/R)/R evaluated in FP64 (sincospi: exact at
-// multiples of pi/2), each coefficient split hi = rn(w), lo = rn(w - hi) in the
-// operand format.  One thread per (radix, sign, part, lane, element).
+// DFT-matrix operands of the matrix-core radix-16 DFTs (layout in
+// mfma_dft.hpp): W[r][q] = exp(sign*2*pi*i*r*q/16) * sc evaluated in FP64
+// (sincospi: exact at multiples of pi/2), each coefficient split hi = rn(w),
+// lo = rn(w - hi) in the operand format.  sc = 1/16 for FP16 (keeps the data
+// of chained stages in FP16's range; undone exactly after the transform), 1
+// for BF16 (FP32's exponent range).  One thread per (sign, part, lane,
+// element).
 // -------------------------------------------------------------------------
 __global__ void k_dft_operand_gen(uint16_t* __restrict__ out, int prec)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;   // < 4*2*4*64*8
-    if (idx >= 4 * 2 * 4 * 64 * 8) return;
-    const int e = idx & 7, lane = (idx >> 3) & 63, part = (idx >> 9) & 3, si = (idx >> 11) & 1, ri = idx >> 12;
-    const int R = 2 << ri;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= kDftOpElems) return;
+    const int e = idx & 7, lane = (idx >> 3) & 63, part = (idx >> 9) & 3, si = (idx >> 11) & 1;
     const int half = lane >> 5, l32 = lane & 31;
     const int ko = l32 >> 1;
     const bool im_out = (l32 & 1) != 0;
     const int k = 8 * half + e;
-    double wr = 0.0, wi = 0.0;
-    if (k / R == ko / R) {
-        double sn, cs;
-        sincospi(2.0 * (double)(((k % R) * (ko % R)) % R) / (double)R, &sn, &cs);
-        wr = cs / R;
-        wi = (si ? sn : -sn) / R;
-    }
+    const double sc = prec == 2 ? 1.0 / 16.0 : 1.0;
+    double sn, cs;
+    sincospi(2.0 * (double)((k * ko) % 16) / 16.0, &sn, &cs);
+    const double wr = cs * sc, wi = (si ? sn : -sn) * sc;
     // coefficient of Re X[k] (parts 0, 1) and of Im X[k] (parts 2, 3)
     const double w = part < 2 ? (im_out ? wi : wr) : (im_out ? wr : -wi);
     uint16_t bits;
     if (prec == 1) {
-        const __bf16 hi = (__bf16)(float)w;
-        const __bf16 lo = (__bf16)(float)(w - (double)(float)hi);
+        const __bf16 hi = (__bf16)w;
+        const __bf16 lo = (__bf16)(w - (double)hi);
         bits = __builtin_bit_cast(uint16_t, (part & 1) ? lo : hi);
     } else {
-        const _Float16 hi = (_Float16)(float)w;
-        const _Float16 lo = (_Float16)(float)(w - (double)(float)hi);
+        const _Float16 hi = (_Float16)w;
+        const _Float16 lo = (_Float16)(w - (double)hi);
         bits = __builtin_bit_cast(uint16_t, (part & 1) ? lo : hi);
     }
     out[idx] = bits;
@@ -169,7 +168,7 @@ __global__ void k_dft_operand_gen(uint16_t* __restrict__ out, int prec)
 
 hipError_t launch_dft_operand_gen(uint16_t* out, int prec, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dft_operand_gen, dim3(4 * 2 * 4 * 64 * 8 / 256), dim3(256), 0, s, out, prec);
+    hipLaunchKernelGGL(k_dft_operand_gen, dim3(kDftOpElems / 256), dim3(256), 0, s, out, prec);
     return hipGetLastError();
 }
 
@@ -365,7 +364,7 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
 // -------------------------------------------------------------------------
 
 template <int NX, int P>
-__global__ __launch_bounds__(P ? 256 : 512) void k_ospr_rows_h(const float* __restrict__ target, int ny, int n_sf,
+__global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(3))) void k_ospr_rows_h(const float* __restrict__ target, int ny, int n_sf,
                                                                 int spb, PhaseSrc src, uint64_t c0,
                                                                 const uint64_t* __restrict__ c0_base,
                                                                 float2* __restrict__ x1, const float2* __restrict__ tw,
@@ -478,7 +477,7 @@ __device__ __forceinline__ uint32_t spread_bits8(uint32_t x)
 }
 
 template <int NY, int C, int P>
-__global__ __launch_bounds__((C / 2) * (NY / kP)) __attribute__((amdgpu_waves_per_eu(P && NY <= 256 ? 3 : 4))) void k_ospr_cols2(const float2* __restrict__ x1, int nx,
+__global__ __launch_bounds__((C / 2) * (NY / kP)) __attribute__((amdgpu_waves_per_eu(4))) void k_ospr_cols2(const float2* __restrict__ x1, int nx,
                                                                    uint32_t* __restrict__ bits,
                                                                    float2* __restrict__ x2,
                                                                    const float2* __restrict__ tw, int pitch,
@@ -808,7 +807,7 @@ hipError_t launch_recon_cols(const void* holo, int levels, int nx, int ny, int n
 // this row stands for (itself and, for the half spectrum, its point mirror).
 // -------------------------------------------------------------------------
 template <int NX, int P>
-__global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(P ? 1 : 4))) void k_recon_rows(const float2* __restrict__ x2, int ny, int n_sf, int half,
+__global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(4))) void k_recon_rows(const float2* __restrict__ x2, int ny, int n_sf, int half,
                                                      const float* __restrict__ target, float* __restrict__ recon,
                                                      double* __restrict__ partials, const float2* __restrict__ tw,
                                                      float inv_scale, int pitch, const uint4* __restrict__ dftop)
