@@ -355,8 +355,8 @@ HOLO_API holo_status holo_phase_mask(const holo_lut* lut, uint64_t cursor, int64
 
 /* ---------------------------------------------------------------------------
  * Launch plans and the autotuner (implementation choices, not part of the
- * method: every plan computes the same holograms, except that the GS points
- * per thread change the FP32 factorisation and so the rounding).
+ * method: every plan computes the same holograms, except that the points per
+ * thread change the FP32 factorisation and so the rounding).
  * A plan is seven ints {cols, rows, ksplit, recon_cols, pad, chunk, pts}:
  * column-tile width of the generation column pass (OSPR: 8 or 16; GS: 2, 4, 8
  * or 16), row transforms per block of the row pass, sub-frame groups per
@@ -365,17 +365,26 @@ HOLO_API holo_status holo_phase_mask(const holo_lut* lut, uint64_t cursor, int64
  * four); extra elements per row of the library's internal fields (-1:
  * heuristic); OSPR sub-frames generated per chunk (0: all; a chunk's
  * intermediate planes are reused, so they can stay in the last-level cache);
- * and points per thread of the GS transforms (4, 8 or 16; 0: heuristic, more
- * threads per transform when a single field offers few transforms; the
- * heuristic and the autotuner use 8 or 16 only, as 4 rounds more often).  Plans
- * are keyed by kind (0 = OSPR, 1 = GS), nx, ny and n_sf (ignored for GS).
+ * and points per thread, i.e. the radix factorisation of the transforms: GS
+ * passes 4, 8 or 16 (0: heuristic, more threads per transform when a single
+ * field offers few transforms; the heuristic and the autotuner use 8 or 16
+ * only, as 4 rounds more often); OSPR row, column and reconstruction-row
+ * passes all 16 (radix-16 stages, then one radix-2/4/8 stage) or all 8
+ * (radix-8 stages, then one radix-2/4 stage), or 0: 8 for the row pass and
+ * for transforms of up to 512 points, 16 for longer column and
+ * reconstruction transforms (FP32 only: the BF16/FP16 forms take 16;
+ * 2048-point columns at 8 points per thread use 8-column tiles).  Plans are keyed by kind (0 = OSPR, 1 = GS), nx, ny and n_sf
+ * (ignored for GS).
  * holo_autotune_ospr / holo_autotune_gs time candidate plans on the caller's
  * inputs (coordinate descent, after a warm-up of the default plan; a
- * candidate's time is the fastest of three batches of `reps` runs; about
- * 40 candidates for OSPR, so 20-run batches of a 0.12 ms frame take well under
+ * candidate's time is the fastest of three batches of `reps` runs;
+ * 41 candidates for OSPR, so 20-run batches of a 0.12 ms frame take well under
  * a second) and keep the fastest
  * whose holograms (bits / codes) equal those of the default plan exactly and
  * whose NMSE agrees to 1e-6 relative (FP32 summation order of the average);
+ * OSPR candidates with other points per thread than the default (0, 16
+ * and 8 are searched jointly with the tile width and chunking) are kept when
+ * at most 1e-5 of the bits differ and the NMSE agrees to 1e-6 relative;
  * GS points-per-thread candidates are kept when codes differ on at most 1e-3
  * of the pixels and the per-iteration NMSE agrees to 1e-5 relative after four
  * iterations.  `chosen` (int[7] or NULL) receives the plan.  scratch_bits: device

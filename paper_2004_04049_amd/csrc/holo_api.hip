@@ -1353,15 +1353,25 @@ holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t ny, int3
     for (int i = 0; i < 200; ++i)
         if ((st = run(best))) return st;
     if ((st = time_runs(s, reps, [&] { return run(best); }, &best_ms))) return st;
-    // coordinate descent over each kernel's shape; a candidate counts only if
-    // it reproduces the reference holograms bit for bit; its NMSE may differ
-    // by the FP32 summation order of the average
+    // coordinate descent over each kernel's shape; a candidate with the
+    // reference's points per thread counts only if it reproduces the reference
+    // holograms bit for bit; one with other points per thread (another radix
+    // factorisation) rounds differently, and may flip pixels whose Re h is
+    // within that rounding of 0: at most 1e-5 of the bits; either way the NMSE
+    // must agree to 1e-6 relative (FP32 summation order)
+    const int ref_pts = best.pts;
     auto try_plan = [&](const LaunchCfg& c) {
         double ms = 0.0;
-        if (run(c) != HOLO_OK) return;
+        if (run(c) != HOLO_OK) {
+            g_err.clear();
+            return;
+        }
         if (ospr_run(device, target, nx, ny, n_sf, lut, 0, scratch_bits, nullptr, nm, 0, s, c)) return;
         if (hipMemcpy(bits.data(), scratch_bits, nwords * 4, hipMemcpyDeviceToHost) != hipSuccess) return;
-        if (bits != ref_bits || std::fabs(nm[0] - ref_nm[0]) > 1e-6 * std::fabs(ref_nm[0]) ||
+        size_t flips = 0;
+        for (size_t w = 0; w < nwords; ++w) flips += (size_t)__builtin_popcount(bits[w] ^ ref_bits[w]);
+        const size_t allowed = c.pts == ref_pts ? 0 : (size_t)(1e-5 * 32.0 * (double)nwords);
+        if (flips > allowed || std::fabs(nm[0] - ref_nm[0]) > 1e-6 * std::fabs(ref_nm[0]) ||
             std::fabs(nm[1] - ref_nm[1]) > 1e-6 * std::fabs(ref_nm[1]))
             return;
         if (time_runs(s, reps, [&] { return run(c); }, &ms)) return;
@@ -1370,18 +1380,24 @@ holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t ny, int3
             best = c;
         }
     };
-    // column-tile width and chunking interact (tile lines vs cache residency):
-    // search them jointly, then the remaining shapes one at a time
+    // radix factorisation (points per thread of the row, column and
+    // reconstruction passes: the per-pass default, all 16 -- 1024 = 16*16*4 --
+    // or all 8 -- 8*8*8*2), column-tile width and chunking interact
+    // (registers and waves, tile lines, cache residency): search them jointly,
+    // then the remaining shapes one at a time
+    const int pts_opts[] = {0, 16, 8};
     const int cols_opts[] = {8, 16};
     const int chunk_opts[] = {0, 4, 6, 8, 12};
     const LaunchCfg base = best;
-    for (int ci : cols_opts)
-        for (int ch : chunk_opts) {
-            LaunchCfg c = base;
-            c.cols_per_block = ci;
-            c.chunk = ch;
-            try_plan(c);
-        }
+    for (int pt : pts_opts)
+        for (int ci : cols_opts)
+            for (int ch : chunk_opts) {
+                LaunchCfg c = base;
+                c.pts = pt;
+                c.cols_per_block = ci;
+                c.chunk = ch;
+                try_plan(c);
+            }
     const int rows_opts[] = {1, 2, 4, 8};
     const int ks_opts[] = {1, 2, 4, 8};
     const int pad_opts[] = {0, 16, 64};
@@ -1505,11 +1521,18 @@ holo_status holo_autotune_gs(const float* target, int64_t nx, int64_t ny, const 
     return HOLO_OK;
 }
 
+// Points per thread of a plan: GS 0, 4, 8 or 16; OSPR 0, 8 or 16.
+holo_status plan_check_pts(int kind, int pts)
+{
+    if (kind == PLAN_GS ? (pts != 0 && pts != 4 && pts != 8 && pts != 16) : (pts != 0 && pts != 8 && pts != 16))
+        return fail(HOLO_EINVAL, "points per thread must be 0, %s8 or 16 (got %d)", kind == PLAN_GS ? "4, " : "", pts);
+    return HOLO_OK;
+}
+
 holo_status holo_plan_set(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, const int32_t* cfg)
 {
     if ((kind != 0 && kind != 1) || !cfg) return fail(HOLO_EINVAL, "kind must be 0 (OSPR) or 1 (GS), cfg set");
-    if (cfg[6] != 0 && cfg[6] != 4 && cfg[6] != 8 && cfg[6] != 16)
-        return fail(HOLO_EINVAL, "points per thread must be 0, 4, 8 or 16 (got %d)", cfg[6]);
+    if (holo_status st = plan_check_pts(kind, cfg[6])) return st;
     LaunchCfg c;
     c.cols_per_block = cfg[0];
     c.rows_per_block = cfg[1];
@@ -1576,6 +1599,8 @@ holo_status holo_plan_load(const char* path)
         if (std::sscanf(txt.c_str() + pos,
                         "{\"kind\": %d, \"nx\": %lld, \"ny\": %lld, \"n_sf\": %d, \"cfg\": [%d, %d, %d, %d, %d, %d, %d]}",
                         &kind, &nx, &ny, &sf, &c0, &c1, &c2, &c3, &c4, &c5, &c6) == 11) {
+            if (kind != PLAN_OSPR && kind != PLAN_GS) return fail(HOLO_EINVAL, "plan kind %d in %s", kind, path);
+            if (holo_status st = plan_check_pts(kind, c6)) return st;
             LaunchCfg c;
             c.cols_per_block = c0;
             c.rows_per_block = c1;

@@ -17,7 +17,7 @@ struct LaunchCfg {
     int recon_cols_per_block = 0;  // C of the reconstruction column pass
     int pad = -1;                  // extra elements per row of internal fields (-1 = heuristic)
     int chunk = 0;                 // OSPR sub-frames per generation chunk (0 = all at once)
-    int pts = 0;                   // points per thread of the GS passes: 4, 8 or 16 (0 = heuristic)
+    int pts = 0;                   // points per thread: GS passes 4, 8 or 16; OSPR K1-K3 8 or 16 (FP32; 0 = per-pass heuristic)
     int prec = 0;                  // DFT stages: 0 FP32 registers, 1 BF16 MFMA, 2 FP16 MFMA (sizes >= 256)
     const void* dftop = nullptr;   // DFT-matrix operand table of `prec` (launch_dft_operand_gen)
 };

@@ -244,17 +244,23 @@ __device__ __forceinline__ void fft_stages_mc(float2 (&v)[kP], int t, float2* ld
     }
 }
 
-// One transform through the FP32 register engine (PREC 0) or with its radix-16
-// DFTs on the matrix cores (PREC 1 = BF16, 2 = FP16; the inter-stage twiddles
-// and the last radix-2/4/8 stage stay FP32 on the vector ALUs).  `addr` is the
-// calling thread's LDS addressing.  With PREC > 0 every lane of each wave must
-// take part (blocks of whole waves, no divergence around the call).
-template <int N, int SIGN, int PREC, bool WAVE_LOCAL = false, typename Addr>
-__device__ __forceinline__ void fft_any(float2 (&v)[kP], int t, float2* lds, Addr addr,
+// One transform through the FP32 register engine (PREC 0, PT = 4, 8 or 16
+// points per thread) or with its radix-16 DFTs on the matrix cores (PREC 1 =
+// BF16, 2 = FP16, PT = 16; the inter-stage twiddles and the last radix-2/4/8
+// stage stay FP32 on the vector ALUs).  `addr` is the calling thread's LDS
+// addressing (padded as the engine with PT points per thread pads).  With
+// PREC > 0 every lane of each wave must take part (blocks of whole waves, no
+// divergence around the call).
+template <int N, int SIGN, int PREC, bool WAVE_LOCAL = false, int PT = kP, typename Addr>
+__device__ __forceinline__ void fft_any(float2 (&v)[PT], int t, float2* lds, Addr addr,
                                         const float2* __restrict__ tw, const uint4* __restrict__ dftop)
 {
-    if constexpr (PREC == 0) fft_stages<N, SIGN, Addr, WAVE_LOCAL>(v, t, lds, addr, tw);
-    else fft_stages_mc<N, SIGN, PREC, Addr, WAVE_LOCAL>(v, t, lds, addr, tw, dftop);
+    if constexpr (PREC == 0) {
+        fft_stages<N, SIGN, Addr, WAVE_LOCAL, PT>(v, t, lds, addr, tw);
+    } else {
+        static_assert(PT == kP, "the matrix-core transforms take 16 points per thread");
+        fft_stages_mc<N, SIGN, PREC, Addr, WAVE_LOCAL>(v, t, lds, addr, tw, dftop);
+    }
 }
 
 }  // namespace holo

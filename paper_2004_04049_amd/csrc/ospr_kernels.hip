@@ -56,9 +56,34 @@ namespace holo {
         return hipErrorInvalidValue;                                            \
     }
 
+// Points per thread PT_ of the OSPR row pass, column pass and reconstruction
+// row pass: 16 (radix-16 stages, then one radix-2/4/8 stage) or, in FP32, 8
+// (radix-8 stages, then one radix-2/4 stage).  The matrix-core forms take 16
+// points per thread.
+#define HOLO_SWITCH_PT(pt, ...)                                              \
+    if ((pt) == 8) {                                                         \
+        constexpr int PT_ = P_ ? kP : 8;                                     \
+        __VA_ARGS__;                                                         \
+    } else {                                                                 \
+        constexpr int PT_ = kP;                                              \
+        __VA_ARGS__;                                                         \
+    }
+// The plan's points per thread (8 or 16 for all three passes), or else per
+// pass (0 = generation rows, 1 = generation columns, 2 = reconstruction rows)
+// and transform length n: 8 for the generation rows and for lengths up to
+// 512, 16 above (FP32, 24 sub-frames, 1024^2: rows 40.1 against 41.5 us,
+// columns 57.0 against 53.6, reconstruction 42.5 against 36.4; 512^2: 16.8 /
+// 18.6 / 22.2 against 20.9 / 20.9 / 26.2 us).
+static int plan_pts(const LaunchCfg& c, int pass, int n)
+{
+    if (c.prec != 0) return kP;
+    if (c.pts == 8 || c.pts == kP) return c.pts;
+    return (pass == 0 || n <= 512) ? 8 : kP;
+}
+
 // Column-tile width C (columns transformed side by side by one block).
-// Matrix-core variants (P_ != 0) exist for C = 8 only (the launchers pick
-// C = 8 for them), so every other case maps to that instantiation.
+// Matrix-core variants (P_ != 0) exist for C = 8 (and 4, for the 2048-point
+// plain column transform) only, so the other cases map to C = 8.
 #define HOLO_SWITCH_C(c, ...)                                                \
     switch (c) {                                                             \
         case 2: { constexpr int C_ = P_ ? 8 : 2; __VA_ARGS__; } break;       \
@@ -80,9 +105,9 @@ struct RowAddrR {
     __device__ __forceinline__ int operator()(int p) const { return base + p; }
 };
 
-static int row_block_rows(int n, int nrows, int planned, int prec = 0)
+static int row_block_rows(int n, int nrows, int planned, int prec = 0, int pt = kP)
 {
-    const int T = n / kP;
+    const int T = n / pt;
     int rows = planned > 0 ? planned : (256 / T > 0 ? 256 / T : 1);
     if (prec && rows * T < 64) rows = 64 / T;   // matrix cores: whole waves
     if (prec && rows * T > 256) rows = 256 / T; // ... and at most 256 threads (register budget)
@@ -355,7 +380,9 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
 // half plane of ny/2 + 1 rows, pitch as x1) and the column pass rebuilds the
 // others.  Each thread draws its pixels (x, y) and their mirrors (-x, -y):
 // for x = t + T*m the mirror column is t' + T*m' with t' = (T - t) mod T and
-// m' = 15 - m (t > 0) or (16 - m) mod 16 (t = 0), i.e. slot m' of a thread t'.
+// m' = PT - 1 - m (t > 0) or (PT - m) mod PT (t = 0), i.e. slot m' of a thread
+// t' (PT points per thread, T = nx/PT; PT = 8 or 16 in FP32, 16 with the
+// matrix cores).
 // A block serves `spb` consecutive sub-frames of its rows, so each thread
 // loads its target values once for all of them (the target does not stay in
 // L2 between sub-frames of a whole-frame launch).
@@ -363,7 +390,7 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
 // the last row block repeat row ny/2 and are not stored.
 // -------------------------------------------------------------------------
 
-template <int NX, int P>
+template <int NX, int P, int PT>
 __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(3))) void k_ospr_rows_h(const float* __restrict__ target, int ny, int n_sf,
                                                                 int spb, PhaseSrc src, uint64_t c0,
                                                                 const uint64_t* __restrict__ c0_base,
@@ -371,7 +398,7 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(3
                                                                 int pitch, const uint4* __restrict__ dftop)
 {
     extern __shared__ float2 lds[];
-    constexpr int T = NX / kP;
+    constexpr int T = NX / PT;
     const int rows = blockDim.x / T;
     const int row = threadIdx.x / T, t = threadIdx.x % T;
     const int nh = ny / 2 + 1;
@@ -385,15 +412,15 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(3
     const auto rt = make_rsrc(target, (uint32_t)(npix * 4));
     const uint32_t toff0 = ((uint32_t)y * NX + (uint32_t)t) * 4u;
     const uint32_t toff1 = ((uint32_t)ym * NX + (uint32_t)tm) * 4u;
-    float a[kP], b[kP];
+    float a[PT], b[PT];
 #pragma unroll
-    for (int m = 0; m < kP; ++m) {
+    for (int m = 0; m < PT; ++m) {
         a[m] = buf_ld1(rt, toff0, (uint32_t)(m * T * 4));
         b[m] = buf_ld1(rt, toff1, (uint32_t)(m * T * 4));
     }
     uint32_t* lt = nullptr;
     if (phase_uses_lds(src)) {
-        lt = (uint32_t*)(lds + rows * PadLen<NX>::v);
+        lt = (uint32_t*)(lds + rows * PadLenP<NX, PT>::v);
         phase_stage(src, (uint32_t)T, lt);
     }
     const bool mseq = src.kind == SRC_MSEQ;
@@ -406,22 +433,22 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(3
         const uint64_t pos1 = pool_pos(src, c0, c0_base, (uint64_t)k * npix + (uint64_t)ym * NX + (uint64_t)tm);
         const uint32_t rs0 = mseq ? src.rows[(size_t)k * ny + y] : 0u;
         const uint32_t rs1 = mseq ? src.rows[(size_t)k * ny + ym] : 0u;
-        float2 v[kP], w[kP];
-        phase_slots<kP>(src, pos0, (uint32_t)T, t, rs0, v, lt);
-        phase_slots<kP>(src, pos1, (uint32_t)T, tm, rs1, w, lt);
+        float2 v[PT], w[PT];
+        phase_slots<PT>(src, pos0, (uint32_t)T, t, rs0, v, lt);
+        phase_slots<PT>(src, pos1, (uint32_t)T, tm, rs1, w, lt);
 #pragma unroll
-        for (int m = 0; m < kP; ++m) {
-            const int mi = 15 - m, mz = (16 - m) & 15;
+        for (int m = 0; m < PT; ++m) {
+            const int mi = PT - 1 - m, mz = (PT - m) & (PT - 1);
             const float bm = t0 ? b[mz] : b[mi];
             const float2 wm = t0 ? w[mz] : w[mi];
             // R(x, y) + conj R(-x, -y)
             v[m] = make_float2(fmaf(a[m], v[m].x, bm * wm.x), fmaf(a[m], v[m].y, -bm * wm.y));
         }
-        fft_any<NX, 1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{row * PadLen<NX>::v}, tw, dftop);
+        fft_any<NX, 1, P, (NX / PT <= 64), PT>(v, t, lds, RowAddrR{row * PadLenP<NX, PT>::v}, tw, dftop);
         if (yr < nh) {
             const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
 #pragma unroll
-            for (int m = 0; m < kP; ++m) buf_st2(ro, ooff, (uint32_t)(m * T * 8), v[m]);
+            for (int m = 0; m < PT; ++m) buf_st2(ro, ooff, (uint32_t)(m * T * 8), v[m]);
         }
     }
 }
@@ -430,19 +457,20 @@ hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, con
                               const uint64_t* c0_base, float2* x1, const float2* tw_x, const LaunchCfg& cfg,
                               hipStream_t s)
 {
-    int rows = row_block_rows(nx, ny, cfg.rows_per_block, cfg.prec);
-    while (rows > 1 && rows * (nx / kP) > 512) rows >>= 1;   // the FP32 kernel's launch bound
+    const int pt = plan_pts(cfg, 0, nx);
+    int rows = row_block_rows(nx, ny, cfg.rows_per_block, cfg.prec, pt);
+    while (rows > 1 && rows * (nx / pt) > 512) rows >>= 1;   // the FP32 kernel's launch bound
     const int row_blocks = (ny / 2 + 1 + rows - 1) / rows;
     const int spb = rows_sf_per_block(row_blocks, n_sf);
     const int sf_blocks = (n_sf + spb - 1) / spb;
-    HOLO_SWITCH_NP(nx, cfg.prec, {
-        constexpr int T = N_ / kP;
-        size_t lds = (size_t)rows * PadLen<N_>::v * sizeof(float2) +
+    HOLO_SWITCH_NP(nx, cfg.prec, HOLO_SWITCH_PT(pt, {
+        constexpr int T = N_ / PT_;
+        size_t lds = (size_t)rows * PadLenP<N_, PT_>::v * sizeof(float2) +
                      (src.kind == SRC_MSEQ || src.kind == SRC_CODES8 ? kPhaseLdsWords * sizeof(uint32_t) : 0);
-        allow_lds(k_ospr_rows_h<N_, P_>, lds);
-        hipLaunchKernelGGL((k_ospr_rows_h<N_, P_>), dim3(row_blocks * sf_blocks), dim3(rows * T), lds, s, target, ny,
-                           n_sf, spb, src, c0, c0_base, x1, tw_x, row_pitch(nx, cfg), DFTOP(cfg));
-    });
+        allow_lds(k_ospr_rows_h<N_, P_, PT_>, lds);
+        hipLaunchKernelGGL((k_ospr_rows_h<N_, P_, PT_>), dim3(row_blocks * sf_blocks), dim3(rows * T), lds, s, target,
+                           ny, n_sf, spb, src, c0, c0_base, x1, tw_x, row_pitch(nx, cfg), DFTOP(cfg));
+    }));
     return hipGetLastError();
 }
 
@@ -458,11 +486,11 @@ hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, con
 // Z = F{B_a + i B_b}, separated as F_a(v) = (Z(v) + conj Z(-v))/2,
 // F_b(v) = (Z(v) - conj Z(-v))/(2i) (as in the pair variant below).  Signs and
 // spectra differ from per-column transforms by rounding only.
-// Grid: (nx / C) * n_sf blocks of (C/2) * (ny/16) threads; thread (q, t) owns
-// columns x0 + 2q and x0 + 2q + 1 (one 16-byte load and one 16-byte store per
-// row), rows t + T*m.  Slots m < 8 load row y = t + T*m; slot m >= 8 loads the
-// mirror row ny - y = (T - t) + T*(15 - m) (also for t = 0, where slot 8 is row
-// ny/2) and conjugates; rows 0 and ny/2 are real up to rounding, and their real
+// Grid: (nx / C) * n_sf blocks of (C/2) * (ny/PT) threads (PT points per
+// thread); thread (q, t) owns columns x0 + 2q and x0 + 2q + 1 (one 16-byte
+// load and one 16-byte store per row), rows t + T*m.  Slots m < PT/2 load row
+// y = t + T*m; slot m >= PT/2 loads the mirror row ny - y = (T - t) +
+// T*(PT - 1 - m) (also for t = 0, where slot PT/2 is row ny/2) and conjugates; rows 0 and ny/2 are real up to rounding, and their real
 // parts are taken.  The C/2 lanes of a row segment are adjacent in the wave,
 // so two ballots give the row's C bits.  Four waves per SIMD (what the LDS
 // tile allows): the matrix-core form would otherwise take 148 registers and
@@ -476,8 +504,8 @@ __device__ __forceinline__ uint32_t spread_bits8(uint32_t x)
     return (x | (x << 1)) & 0x5555u;
 }
 
-template <int NY, int C, int P>
-__global__ __launch_bounds__((C / 2) * (NY / kP)) __attribute__((amdgpu_waves_per_eu(4))) void k_ospr_cols2(const float2* __restrict__ x1, int nx,
+template <int NY, int C, int P, int PT>
+__global__ __launch_bounds__((C / 2) * (NY / PT)) __attribute__((amdgpu_waves_per_eu(4))) void k_ospr_cols2(const float2* __restrict__ x1, int nx,
                                                                    uint32_t* __restrict__ bits,
                                                                    float2* __restrict__ x2,
                                                                    const float2* __restrict__ tw, int pitch,
@@ -485,7 +513,7 @@ __global__ __launch_bounds__((C / 2) * (NY / kP)) __attribute__((amdgpu_waves_pe
 {
     extern __shared__ float2 lds[];
     constexpr int CP = C / 2;
-    constexpr int T = NY / kP;
+    constexpr int T = NY / PT;
     const int q = threadIdx.x % CP, t = threadIdx.x / CP;
     const int lane = threadIdx.x & 63;
     const int ncb = nx / C;
@@ -498,19 +526,19 @@ __global__ __launch_bounds__((C / 2) * (NY / kP)) __attribute__((amdgpu_waves_pe
     const uint32_t moff = ((uint32_t)(T - t) * (uint32_t)pitch + (uint32_t)(x0 + 2 * q)) * 8u;
     const uint32_t mst = (uint32_t)T * (uint32_t)pitch * 8u;
     const auto rin = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
-    float2 v[kP];
+    float2 v[PT];
 #pragma unroll
-    for (int m = 0; m < kP / 2; ++m) {
+    for (int m = 0; m < PT / 2; ++m) {
         const float4 ab = buf_ld4(rin, voff, m * mst);               // X_a = (x, y), X_b = (z, w) at row y
         v[m] = make_float2(ab.x - ab.w, ab.y + ab.z);                // X_a + i X_b
-        const float4 cd = buf_ld4(rin, moff, (kP / 2 - 1 - m) * mst); // slot m + 8: row ny - y = (T - t) + T*(7 - m)
-        v[m + kP / 2] = make_float2(cd.x + cd.w, cd.z - cd.y);       // conj X_a + i conj X_b
+        const float4 cd = buf_ld4(rin, moff, (PT / 2 - 1 - m) * mst); // slot m + PT/2: row ny - y = (T - t) + T*(PT/2 - 1 - m)
+        v[m + PT / 2] = make_float2(cd.x + cd.w, cd.z - cd.y);       // conj X_a + i conj X_b
         if (m == 0 && t == 0) {                                      // rows 0 and ny/2
             v[0] = make_float2(ab.x, ab.z);
-            v[kP / 2] = make_float2(cd.x, cd.z);
+            v[PT / 2] = make_float2(cd.x, cd.z);
         }
     }
-    fft_any<NY, 1, P>(v, t, lds, ColAddr<CP>{q}, tw, dftop);
+    fft_any<NY, 1, P, false, PT>(v, t, lds, ColAddr<CP>{q}, tw, dftop);
 
     // nearest of {+1, -1}: bit = (Re h < 0); Re h = 0 -> +1.  The CP lanes of
     // a row give the even columns' bits (ballot of .x) and the odd columns'
@@ -520,7 +548,7 @@ __global__ __launch_bounds__((C / 2) * (NY / kP)) __attribute__((amdgpu_waves_pe
     const uint32_t bst = (uint32_t)T * (uint32_t)nx / 8u;
     const int g0 = lane & ~(CP - 1);
 #pragma unroll
-    for (int m = 0; m < kP; ++m) {
+    for (int m = 0; m < PT; ++m) {
         const bool na = v[m].x < 0.0f, nb = v[m].y < 0.0f;
         const uint64_t ma = __ballot(na), mb = __ballot(nb);
         if (q == 0) {
@@ -531,21 +559,21 @@ __global__ __launch_bounds__((C / 2) * (NY / kP)) __attribute__((amdgpu_waves_pe
         }
         v[m] = make_float2(na ? -1.0f : 1.0f, nb ? -1.0f : 1.0f);
     }
-    fft_any<NY, -1, P>(v, t, lds, ColAddr<CP>{q}, tw, dftop);
+    fft_any<NY, -1, P, false, PT>(v, t, lds, ColAddr<CP>{q}, tw, dftop);
 
-    // separation: rows v <= NY/2 (slots m < 8, and m = 8 for t = 0) need Z at
-    // -v, which lies in slots 8..15, or slot 0 for v = 0
+    // separation: rows v <= NY/2 (slots m < PT/2, and m = PT/2 for t = 0) need
+    // Z at -v, which lies in slots PT/2..PT-1, or slot 0 for v = 0
     __syncthreads();
 #pragma unroll
-    for (int m = kP / 2; m < kP; ++m) lds[(t + T * m) * CP + q] = v[m];
+    for (int m = PT / 2; m < PT; ++m) lds[(t + T * m) * CP + q] = v[m];
     if (t == 0) lds[q] = v[0];
     __syncthreads();
     // one 16-byte store per row: F_a = (Z + conj Zm) / 2, F_b = (Z - conj Zm) / (2i)
     const size_t hplane = (size_t)(NY / 2 + 1) * pitch;
     const auto rout = make_rsrc(x2 + (size_t)k * hplane, (uint32_t)(hplane * 8));
 #pragma unroll
-    for (int m = 0; m <= kP / 2; ++m) {
-        if (m == kP / 2 && t != 0) break;
+    for (int m = 0; m <= PT / 2; ++m) {
+        if (m == PT / 2 && t != 0) break;
         const float2 z = v[m];
         const float2 zm = lds[((NY - (t + T * m)) & (NY - 1)) * CP + q];
         buf_st4z(rout, voff + (uint32_t)m * mst,
@@ -556,31 +584,32 @@ __global__ __launch_bounds__((C / 2) * (NY / kP)) __attribute__((amdgpu_waves_pe
 hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
                             const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
 {
-    // matrix cores: 16-column tiles, i.e. 8 transforms per block, as the
-    // engine's column layout wants.  FP32: 8-column tiles (4 transforms per
-    // block) unless planned; measured at 1024^2, 24 sub-frames: 50.3 us
-    // against 55.2 us for 16-column tiles
-    const int C = cfg.prec ? 8 : cfg.cols_per_block > 0 ? col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8) : 8;
-    HOLO_SWITCH_NP(ny, cfg.prec, {
-        constexpr int T = N_ / kP;
+    // 8-column tiles (4 column pairs per block) unless planned; measured at
+    // 1024^2, 24 sub-frames (FP32): 50.3 us against 55.2 us for 16-column
+    // tiles.  The matrix-core forms use 8-column tiles.
+    const int pt = plan_pts(cfg, 1, ny);
+    int C = cfg.prec ? 8 : cfg.cols_per_block > 0 ? col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8) : 8;
+    if ((C / 2) * (ny / pt) > 1024) C = 8;   // 2048-point columns at 8 points per thread
+    HOLO_SWITCH_NP(ny, cfg.prec, HOLO_SWITCH_PT(pt, {
+        constexpr int T = N_ / PT_;
         if constexpr (P_ != 0) {
-            if (4 * T <= 1024) {
-                size_t lds = (size_t)4 * PadLen<N_>::v * sizeof(float2);
-                allow_lds(k_ospr_cols2<N_, 8, P_>, lds);
-                hipLaunchKernelGGL((k_ospr_cols2<N_, 8, P_>), dim3((nx / 8) * n_sf), dim3(4 * T), lds, s, x1, nx,
-                                   bits, x2, tw_y, row_pitch(nx, cfg), DFTOP(cfg));
-            }
+            size_t lds = (size_t)4 * PadLen<N_>::v * sizeof(float2);
+            allow_lds(k_ospr_cols2<N_, 8, P_, kP>, lds);
+            hipLaunchKernelGGL((k_ospr_cols2<N_, 8, P_, kP>), dim3((nx / 8) * n_sf), dim3(4 * T), lds, s, x1, nx,
+                               bits, x2, tw_y, row_pitch(nx, cfg), DFTOP(cfg));
         } else {
             HOLO_SWITCH_C816(C, {
-                if ((C_ / 2) * T <= 1024) {
-                    size_t lds = (size_t)(C_ / 2) * PadLen<N_>::v * sizeof(float2);
-                    allow_lds(k_ospr_cols2<N_, C_, 0>, lds);
-                    hipLaunchKernelGGL((k_ospr_cols2<N_, C_, 0>), dim3((nx / C_) * n_sf), dim3((C_ / 2) * T), lds, s,
-                                       x1, nx, bits, x2, tw_y, row_pitch(nx, cfg), nullptr);
+                if constexpr ((C_ / 2) * T > 1024) {
+                    return hipErrorInvalidValue;   // not reached: C is reduced above
+                } else {
+                    size_t lds = (size_t)(C_ / 2) * PadLenP<N_, PT_>::v * sizeof(float2);
+                    allow_lds(k_ospr_cols2<N_, C_, 0, PT_>, lds);
+                    hipLaunchKernelGGL((k_ospr_cols2<N_, C_, 0, PT_>), dim3((nx / C_) * n_sf), dim3((C_ / 2) * T), lds,
+                                       s, x1, nx, bits, x2, tw_y, row_pitch(nx, cfg), nullptr);
                 }
             });
         }
-    });
+    }));
     return hipGetLastError();
 }
 
@@ -806,22 +835,22 @@ hipError_t launch_recon_cols(const void* holo, int levels, int nx, int ny, int n
 // partials[v*5 + {0..4}] = {S_II, S_IT, S_ITs, S_TT, S_TsTs} over the pixels
 // this row stands for (itself and, for the half spectrum, its point mirror).
 // -------------------------------------------------------------------------
-template <int NX, int P>
+template <int NX, int P, int PT>
 __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(4))) void k_recon_rows(const float2* __restrict__ x2, int ny, int n_sf, int half,
                                                      const float* __restrict__ target, float* __restrict__ recon,
                                                      double* __restrict__ partials, const float2* __restrict__ tw,
                                                      float inv_scale, int pitch, const uint4* __restrict__ dftop)
 {
     extern __shared__ float2 lds[];
-    constexpr int T = NX / kP;
+    constexpr int T = NX / PT;
     const int G = blockDim.x / T;
     const int g = threadIdx.x / T, t = threadIdx.x % T;
     const int v_row = blockIdx.x;
     const int nrows_spec = half ? (ny / 2 + 1) : ny;
     const size_t sf_stride = (size_t)nrows_spec * pitch;
-    float acc[kP];
+    float acc[PT];
 #pragma unroll
-    for (int m = 0; m < kP; ++m) acc[m] = 0.0f;
+    for (int m = 0; m < PT; ++m) acc[m] = 0.0f;
     const int rounds = (n_sf + G - 1) / G;
     // one descriptor per round, based at the round's first spectrum (64-bit
     // pointer arithmetic) and covering the round's min(G, n_sf - r*G) spectra,
@@ -837,13 +866,13 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(4
         const bool valid = k < n_sf;
         const int in_round = n_sf - r * G < G ? n_sf - r * G : G;
         const auto rx = make_rsrc(x2 + (size_t)r * G * sf_stride, (uint32_t)in_round * kst);
-        float2 v[kP];
+        float2 v[PT];
 #pragma unroll
-        for (int m = 0; m < kP; ++m) v[m] = buf_ld2(rx, roff, (uint32_t)(m * T * 8));
-        fft_any<NX, -1, P, (NX / kP <= 64)>(v, t, lds, RowAddrR{g * PadLen<NX>::v}, tw, dftop);
+        for (int m = 0; m < PT; ++m) v[m] = buf_ld2(rx, roff, (uint32_t)(m * T * 8));
+        fft_any<NX, -1, P, (NX / PT <= 64), PT>(v, t, lds, RowAddrR{g * PadLenP<NX, PT>::v}, tw, dftop);
         if (valid) {
 #pragma unroll
-            for (int m = 0; m < kP; ++m) acc[m] = fmaf(v[m].x, v[m].x, fmaf(v[m].y, v[m].y, acc[m]));
+            for (int m = 0; m < PT; ++m) acc[m] = fmaf(v[m].x, v[m].x, fmaf(v[m].y, v[m].y, acc[m]));
         }
     }
     // combine the G groups' sums (group order fixed); the groups' transforms
@@ -852,11 +881,11 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(4
     if (G > 1) {
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < kP; ++m) ldsf[g * NX + t + T * m] = acc[m];
+        for (int m = 0; m < PT; ++m) ldsf[g * NX + t + T * m] = acc[m];
         __syncthreads();
         if (g == 0) {
 #pragma unroll
-            for (int m = 0; m < kP; ++m) {
+            for (int m = 0; m < PT; ++m) {
                 float s = ldsf[t + T * m];
                 for (int gg = 1; gg < G; ++gg) s += ldsf[gg * NX + t + T * m];
                 acc[m] = s;
@@ -871,7 +900,7 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(4
         const float* trow = target + (size_t)v_row * NX;
         const float* mrow = target + (size_t)vm * NX;
 #pragma unroll
-        for (int m = 0; m < kP; ++m) {
+        for (int m = 0; m < PT; ++m) {
             const int u = t + T * m;
             const int um = (NX - u) & (NX - 1);
             const double ib = (double)(acc[m] * inv_scale);
@@ -907,22 +936,23 @@ hipError_t launch_recon_rows(const float2* x2, int nx, int ny, int n_sf, bool ha
                              hipStream_t s)
 {
     const int nrows_spec = half ? ny / 2 + 1 : ny;
-    HOLO_SWITCH_NP(nx, cfg.prec, {
-        constexpr int T = N_ / kP;
+    const int pt = plan_pts(cfg, 2, nx);
+    HOLO_SWITCH_NP(nx, cfg.prec, HOLO_SWITCH_PT(pt, {
+        constexpr int T = N_ / PT_;
         int G = cfg.ksplit > 0 ? cfg.ksplit : 4;
         while (G > 1 && (G * T > 512 || G > n_sf)) G >>= 1;
         // matrix cores: whole waves (groups past n_sf transform zeros and add
         // nothing), at most 256 threads
         if (P_ && G * T > 256) G = 256 / T;
         if (P_ && G * T < 64) G = 64 / T;
-        size_t fft_lds = (size_t)G * PadLen<N_>::v * sizeof(float2);
+        size_t fft_lds = (size_t)G * PadLenP<N_, PT_>::v * sizeof(float2);
         size_t red_lds = (size_t)5 * (G * T / 64 + 1) * sizeof(double);
         size_t lds = fft_lds > red_lds ? fft_lds : red_lds;
         const float inv_scale = (float)(1.0 / ((double)n_sf * (double)nx * (double)ny));
-        allow_lds(k_recon_rows<N_, P_>, lds);
-        hipLaunchKernelGGL((k_recon_rows<N_, P_>), dim3(nrows_spec), dim3(G * T), lds, s, x2, ny, n_sf, half ? 1 : 0,
-                           target, recon, partials, tw_x, inv_scale, row_pitch(nx, cfg), DFTOP(cfg));
-    });
+        allow_lds(k_recon_rows<N_, P_, PT_>, lds);
+        hipLaunchKernelGGL((k_recon_rows<N_, P_, PT_>), dim3(nrows_spec), dim3(G * T), lds, s, x2, ny, n_sf,
+                           half ? 1 : 0, target, recon, partials, tw_x, inv_scale, row_pitch(nx, cfg), DFTOP(cfg));
+    }));
     return hipGetLastError();
 }
 

@@ -89,3 +89,33 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.holo_phase_mask(fake, 0, 64, 64, 1, None, None) == h.HOLO_EINVAL
     assert lib.holo_phase_mask(fake, 0, 64, 64, 0, fake, None) == h.HOLO_EINVAL
     assert lib.holo_phase_mask(fake, 0, 100, 64, 1, fake, None) == h.HOLO_EUNSUPPORTED
+
+
+def test_plan_points_per_thread_rules(lib, tmp_path):
+    """OSPR plans take 8 or 16 points per thread (0: heuristic), GS plans also
+    4; plan_set and plan_load refuse the others."""
+    import paper_2004_04049_amd as h
+    try:
+        h.plan_set(h.PLAN_OSPR, 256, 128, 4, [0, 0, 0, 0, -1, 0, 8])
+        assert h.plan_get(h.PLAN_OSPR, 256, 128, 4)[6] == 8
+        with pytest.raises(h.HoloError) as e:
+            h.plan_set(h.PLAN_OSPR, 256, 128, 4, [0, 0, 0, 0, -1, 0, 4])
+        assert e.value.status == h.HOLO_EINVAL
+        h.plan_set(h.PLAN_GS, 256, 128, 1, [0, 0, 0, 0, -1, 0, 4])
+        with pytest.raises(h.HoloError):
+            h.plan_set(h.PLAN_GS, 256, 128, 1, [0, 0, 0, 0, -1, 0, 12])
+        bad = tmp_path / "plans.json"
+        bad.write_text('[{"kind": 0, "nx": 64, "ny": 64, "n_sf": 2, "cfg": [0, 0, 0, 0, -1, 0, 4]}]')
+        with pytest.raises(h.HoloError):
+            h.plan_load(str(bad))
+        bad.write_text('[{"kind": 3, "nx": 64, "ny": 64, "n_sf": 2, "cfg": [0, 0, 0, 0, -1, 0, 8]}]')
+        with pytest.raises(h.HoloError):
+            h.plan_load(str(bad))
+        good = tmp_path / "good.json"
+        h.plan_save(str(good))
+        h.plan_set(h.PLAN_OSPR, 256, 128, 4, h.DEFAULT_PLAN)
+        h.plan_load(str(good))
+        assert h.plan_get(h.PLAN_OSPR, 256, 128, 4)[6] == 8
+    finally:
+        h.plan_set(h.PLAN_OSPR, 256, 128, 4, h.DEFAULT_PLAN)
+        h.plan_set(h.PLAN_GS, 256, 128, 1, h.DEFAULT_PLAN)

@@ -148,6 +148,30 @@ def test_ospr_2048_tall_and_wide(holo, orc):
     _ospr_case(holo, orc, 128, 2048, 3, 10007, 11, t)
 
 
+@pytest.mark.parametrize("pts", [8, 16])
+@pytest.mark.parametrize("nx,ny,nsf,n_lut,cursor,plan", [
+    (16, 16, 3, 17, 5, [0, 0, 0, 0, -1, 0]),
+    (128, 32, 5, 10007, 123456789012, [0, 0, 0, 0, -1, 0]),
+    (256, 256, 6, 10007, 3, [8, 2, 2, 0, 16, 0]),
+    (512, 1024, 4, 65537, 17, [16, 1, 4, 0, 16, 3]),   # chunks of 3 over 4 sub-frames
+    (1024, 1024, 24, 65536, 0, [8, 1, 0, 0, 16, 0]),   # the benchmark frame
+    (2048, 128, 3, 10007, 11, [8, 1, 2, 0, 16, 0]),
+    (128, 2048, 3, 10007, 11, [16, 1, 2, 0, 16, 0]),   # 2048-point columns: 8 points -> 8-column tiles
+])
+def test_ospr_points_per_thread(holo, orc, nx, ny, nsf, n_lut, cursor, plan, pts):
+    """Both radix factorisations of the row, column and reconstruction passes
+    (8 points per thread: radix-8 stages, then one radix-2/4 stage; 16:
+    radix-16 stages, then one radix-2/4/8 stage) for all three passes, as a
+    plan selects them (the default mixes them per pass), against the oracle
+    with the same bars."""
+    t = synth.blob_target(nx, ny, 7)
+    holo.plan_set(holo.PLAN_OSPR, nx, ny, nsf, plan + [pts])
+    try:
+        _ospr_case(holo, orc, nx, ny, nsf, n_lut, cursor, t)
+    finally:
+        holo.plan_set(holo.PLAN_OSPR, nx, ny, nsf, holo.DEFAULT_PLAN)
+
+
 def test_ospr_cursor_chaining_bit_exact(holo):
     t = torch.from_numpy(synth.blob_target(256, 256, 3)).cuda()
     lut = holo.Lut(10007, 1)
@@ -418,14 +442,27 @@ def test_launch_plans_give_identical_holograms(holo, plan):
     np.testing.assert_allclose(nm1, nm0, rtol=1e-6)
 
 
-def test_batched_equals_sequential_calls(holo, orc):
+@pytest.mark.parametrize("pts", [0, 8, 16])
+def test_batched_equals_sequential_calls(holo, orc, pts):
     # a seeded batch of uneven frames in one (graph-replayed) call equals one
     # holo_ospr_generate call per frame with the cursor chained in batch order
+    # (with the default plans, and with every frame's plan at 8 or at 16
+    # points per thread)
     layout = synth.batch_layout(10, synth.SEED_BATCH, sizes=(64, 128, 256, 512), n_sf_range=(3, 9))
     targets = [torch.from_numpy(synth.blob_target(n, n, synth.SEED_BATCH_TARGET0 + f)).cuda()
                for f, (n, _) in enumerate(layout)]
     nsfs = [k for _, k in layout]
     lut = holo.Lut(10007, 1)
+    for n, k in layout:
+        holo.plan_set(holo.PLAN_OSPR, n, n, k, [0, 0, 0, 0, -1, 0, pts])
+    try:
+        _batched_vs_sequential(holo, orc, layout, targets, nsfs, lut)
+    finally:
+        for n, k in layout:
+            holo.plan_set(holo.PLAN_OSPR, n, n, k, holo.DEFAULT_PLAN)
+
+
+def _batched_vs_sequential(holo, orc, layout, targets, nsfs, lut):
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         for rep, cursor in enumerate((123, 10 ** 12 + 7, 5)):
