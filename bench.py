@@ -254,7 +254,8 @@ def main():
 def bench_batched(h, synth, torch, dev):
     """64 frames, sizes uniform over {256, 512, 1024, 2048}^2, n_sf uniform in
     8..24 (seed 14), targets seeds 1000+f, LUT 10007 chained across frames, one
-    graph launch per batch; DFT stages in FP32, then BF16 and FP16 on the
+    graph launch per batch, one autotuned plan per size; DFT stages in FP32,
+    then BF16 and FP16 on the
     matrix cores, each reported against the FP32 run of the same batch (bit
     mismatch, NMSE and replay-intensity differences per frame)."""
     layout = synth.batch_layout(64, synth.SEED_BATCH)
@@ -262,12 +263,21 @@ def bench_batched(h, synth, torch, dev):
                for f, (n, _) in enumerate(layout)]
     nsfs = [k for _, k in layout]
     lut = h.Lut(10007, synth.SEED_LUT)
+    # one autotuned plan per frame size (on the batch's first frame of that
+    # size, at 16 sub-frames), stored for every sub-frame count of the size;
+    # outside the timed region
+    plans = {}
+    for n in sorted({m for m, _ in layout}):
+        f = next(i for i, (m, _) in enumerate(layout) if m == n)
+        plans[str(n)] = h.autotune_ospr(targets[f], 16, lut, reps=10)
+        h.plan_set(h.PLAN_OSPR, n, n, 0, plans[str(n)])
     pxsf = sum(n * n * k for n, k in layout)
     canon = sum(n * n * (k * 32.125 + 8) for n, k in layout)
     design = sum(sum(ospr_design_bytes(n, n, k, 10007).values()) for n, k in layout)
     res = {"frames": 64, "px_subframes": pxsf, "canonical_GB": round(canon / 1e9, 3),
            "design_GB": round(design / 1e9, 3),
-           "sizes": {str(s_): sum(1 for n, _ in layout if n == s_) for s_ in (256, 512, 1024, 2048)}}
+           "sizes": {str(s_): sum(1 for n, _ in layout if n == s_) for s_ in (256, 512, 1024, 2048)},
+           "plans": plans}
     ref = None
     for prec, name in ((h.FP32, "fp32"), (h.BF16, "bf16"), (h.FP16, "fp16")):
         nm = torch.zeros((64, 2), dtype=torch.float64, device=dev)

@@ -373,8 +373,10 @@ HOLO_API holo_status holo_phase_mask(const holo_lut* lut, uint64_t cursor, int64
  * (radix-8 stages, then one radix-2/4 stage), or 0: 8 for the row pass and
  * for transforms of up to 512 points, 16 for longer column and
  * reconstruction transforms (FP32 only: the BF16/FP16 forms take 16;
- * 2048-point columns at 8 points per thread use 8-column tiles).  Plans are keyed by kind (0 = OSPR, 1 = GS), nx, ny and n_sf
- * (ignored for GS).
+ * 2048-point columns at 8 points per thread use 8-column tiles).  Plans
+ * are keyed by kind (0 = OSPR, 1 = GS), nx, ny and n_sf (ignored for GS); an
+ * OSPR plan set with n_sf = 0 serves every sub-frame count of that size that
+ * has no plan of its own (holo_plan_get reports the plan a call would use).
  * holo_autotune_ospr / holo_autotune_gs time candidate plans on the caller's
  * inputs (coordinate descent, after a warm-up of the default plan; a
  * candidate's time is the fastest of three batches of `reps` runs;

@@ -364,10 +364,13 @@ struct PlanKey {
 std::mutex g_plan_mu;
 std::map<PlanKey, LaunchCfg> g_plans;
 
+// The plan of (kind, nx, ny, n_sf); for OSPR without one of its own, the
+// size's plan stored under n_sf = 0 (every sub-frame count); else defaults.
 LaunchCfg plan_get(int kind, int64_t nx, int64_t ny, int n_sf)
 {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     auto it = g_plans.find(PlanKey{kind, nx, ny, kind == PLAN_GS ? 1 : n_sf});
+    if (it == g_plans.end() && kind == PLAN_OSPR) it = g_plans.find(PlanKey{kind, nx, ny, 0});
     return it == g_plans.end() ? LaunchCfg{} : it->second;
 }
 
@@ -1532,6 +1535,7 @@ holo_status plan_check_pts(int kind, int pts)
 holo_status holo_plan_set(int32_t kind, int64_t nx, int64_t ny, int32_t n_sf, const int32_t* cfg)
 {
     if ((kind != 0 && kind != 1) || !cfg) return fail(HOLO_EINVAL, "kind must be 0 (OSPR) or 1 (GS), cfg set");
+    if (n_sf < 0) return fail(HOLO_EINVAL, "n_sf must be >= 0 (0: every sub-frame count)");
     if (holo_status st = plan_check_pts(kind, cfg[6])) return st;
     LaunchCfg c;
     c.cols_per_block = cfg[0];

@@ -119,3 +119,20 @@ def test_plan_points_per_thread_rules(lib, tmp_path):
     finally:
         h.plan_set(h.PLAN_OSPR, 256, 128, 4, h.DEFAULT_PLAN)
         h.plan_set(h.PLAN_GS, 256, 128, 1, h.DEFAULT_PLAN)
+
+
+def test_plan_for_every_subframe_count(lib):
+    """An OSPR plan stored under n_sf = 0 serves the size's sub-frame counts
+    that have no plan of their own; GS plans ignore n_sf."""
+    import paper_2004_04049_amd as h
+    try:
+        h.plan_set(h.PLAN_OSPR, 512, 256, 0, [8, 2, 4, 0, 16, 0, 8])
+        h.plan_set(h.PLAN_OSPR, 512, 256, 7, [16, 1, 2, 0, 0, 3, 16])
+        assert h.plan_get(h.PLAN_OSPR, 512, 256, 5) == [8, 2, 4, 0, 16, 0, 8]
+        assert h.plan_get(h.PLAN_OSPR, 512, 256, 7) == [16, 1, 2, 0, 0, 3, 16]
+        assert h.plan_get(h.PLAN_OSPR, 256, 512, 5) == h.DEFAULT_PLAN
+        with pytest.raises(h.HoloError):
+            h.plan_set(h.PLAN_OSPR, 512, 256, -1, h.DEFAULT_PLAN)
+    finally:
+        h.plan_set(h.PLAN_OSPR, 512, 256, 0, h.DEFAULT_PLAN)
+        h.plan_set(h.PLAN_OSPR, 512, 256, 7, h.DEFAULT_PLAN)

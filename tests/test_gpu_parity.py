@@ -442,23 +442,24 @@ def test_launch_plans_give_identical_holograms(holo, plan):
     np.testing.assert_allclose(nm1, nm0, rtol=1e-6)
 
 
-@pytest.mark.parametrize("pts", [0, 8, 16])
-def test_batched_equals_sequential_calls(holo, orc, pts):
+@pytest.mark.parametrize("pts,per_size", [(0, False), (8, False), (16, False), (8, True)])
+def test_batched_equals_sequential_calls(holo, orc, pts, per_size):
     # a seeded batch of uneven frames in one (graph-replayed) call equals one
     # holo_ospr_generate call per frame with the cursor chained in batch order
-    # (with the default plans, and with every frame's plan at 8 or at 16
-    # points per thread)
+    # (with the default plans, with every frame's plan at 8 or at 16 points
+    # per thread, and with one plan per size stored for every sub-frame count)
     layout = synth.batch_layout(10, synth.SEED_BATCH, sizes=(64, 128, 256, 512), n_sf_range=(3, 9))
     targets = [torch.from_numpy(synth.blob_target(n, n, synth.SEED_BATCH_TARGET0 + f)).cuda()
                for f, (n, _) in enumerate(layout)]
     nsfs = [k for _, k in layout]
     lut = holo.Lut(10007, 1)
-    for n, k in layout:
-        holo.plan_set(holo.PLAN_OSPR, n, n, k, [0, 0, 0, 0, -1, 0, pts])
+    keys = sorted({(n, 0) for n, _ in layout}) if per_size else layout
+    for n, k in keys:
+        holo.plan_set(holo.PLAN_OSPR, n, n, k, [8, 2, 2, 0, 16, 2, pts] if per_size else [0, 0, 0, 0, -1, 0, pts])
     try:
         _batched_vs_sequential(holo, orc, layout, targets, nsfs, lut)
     finally:
-        for n, k in layout:
+        for n, k in keys:
             holo.plan_set(holo.PLAN_OSPR, n, n, k, holo.DEFAULT_PLAN)
 
 
