@@ -1278,7 +1278,7 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
                                        (uintptr_t)c.cols_per_block, (uintptr_t)c.rows_per_block,
                                        (uintptr_t)c.ksplit, (uintptr_t)c.recon_cols_per_block,
                                        (uintptr_t)(intptr_t)c.pad, (uintptr_t)(intptr_t)c.chunk,
-                                       (uintptr_t)c.prec});
+                                       (uintptr_t)c.pts, (uintptr_t)c.prec});
         }
         hipGraphExec_t exec = nullptr;
         {

@@ -463,6 +463,32 @@ def test_batched_equals_sequential_calls(holo, orc, pts, per_size):
             holo.plan_set(holo.PLAN_OSPR, n, n, k, holo.DEFAULT_PLAN)
 
 
+def test_batched_graph_follows_plan_changes(holo):
+    # the same tensors through the batched call before and after a plan
+    # change that only switches the points per thread: the second call must
+    # run the new plan (its own graph), as the single-frame calls do
+    layout = [(256, 5), (512, 3)]
+    targets = [torch.from_numpy(synth.blob_target(n, n, 60 + f)).cuda() for f, (n, _) in enumerate(layout)]
+    nsfs = [k for _, k in layout]
+    lut = holo.Lut(10007, 1)
+    s = torch.cuda.Stream()
+    try:
+        with torch.cuda.stream(s):
+            for pts in (16, 8, 16):
+                for n, k in layout:
+                    holo.plan_set(holo.PLAN_OSPR, n, n, k, [0, 0, 0, 0, -1, 0, pts])
+                bits, nm, _ = holo.ospr_generate_batched(targets, nsfs, lut, 11)
+                c = 11
+                for f, (t, k) in enumerate(zip(targets, nsfs)):
+                    b1, nm1, c = holo.ospr_generate(t, k, lut, c)
+                    assert torch.equal(bits[f], b1), (pts, f)
+                    np.testing.assert_array_equal(nm[f], nm1)
+        torch.cuda.synchronize()
+    finally:
+        for n, k in layout:
+            holo.plan_set(holo.PLAN_OSPR, n, n, k, holo.DEFAULT_PLAN)
+
+
 def _batched_vs_sequential(holo, orc, layout, targets, nsfs, lut):
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
