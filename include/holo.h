@@ -270,12 +270,19 @@ HOLO_API holo_status holo_reconstruct_nmse(const void* holo, int32_t levels, int
  *             them is a device pointer owned by the caller
  *   nmse_out  [n_frames][2] {NMSE, NMSE_sym} per frame, host (complete on
  *             return) or device with HOLO_F_NMSE_DEVICE, or NULL
- * The device work of a batch is captured once into a HIP graph whose frames
- * run on four concurrent branches (longest frames first) and replayed with
- * one graph launch per call while the frame list, plans and buffers are
+ * The device work of a batch is captured once into a HIP graph and replayed
+ * with one graph launch per call while the frame list, plans and buffers are
  * unchanged; the moving cursor is read from device memory, so replays need
- * no re-capture.  On the legacy default stream, or while kernel timing is on,
- * the frames are launched directly instead.
+ * no re-capture.  In the graph, binary frames drawn from the table, code or
+ * PRNG sources are grouped: frames of one size and launch plan run each pass
+ * (row pass, column pass, reconstruction, NMSE) as one launch over up to
+ * 64 MiB of half planes, every frame with planes of its own (the workspace
+ * then holds about 8 bytes per pixel and sub-frame of the batch, plus the
+ * frame table that lives with the graph); other frames run their own
+ * launches.  Units run on four concurrent branches, longest first.  Results
+ * equal the single-frame calls bit for bit either way.  On the legacy default
+ * stream, or while kernel timing is on, the frames are launched one by one
+ * directly instead.
  * Errors: HOLO_EINVAL (null frames/cursor/target/bits, n_sf < 1, n_frames out
  * of range), HOLO_EUNSUPPORTED (sizes, precision not built).
  * ------------------------------------------------------------------------- */

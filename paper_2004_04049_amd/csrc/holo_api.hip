@@ -513,8 +513,29 @@ struct GraphKey {
 };
 std::mutex g_graph_mu;
 std::map<GraphKey, hipGraphExec_t> g_graphs;
+std::map<GraphKey, void*> g_graph_bufs;   // device tables a graph's kernels read, freed with the graph
 std::vector<GraphKey> g_graph_order;
 bool g_use_graphs = true;
+
+// Keeps at most 32 graphs: the oldest is destroyed (after stream s drains),
+// with its device table.  Called with g_graph_mu held.
+void graph_trim_locked(hipStream_t s)
+{
+    if (g_graph_order.size() <= 32) return;
+    const GraphKey k0 = g_graph_order.front();
+    g_graph_order.erase(g_graph_order.begin());
+    auto old = g_graphs.find(k0);
+    if (old != g_graphs.end()) {
+        (void)hipStreamSynchronize(s);
+        (void)hipGraphExecDestroy(old->second);
+        g_graphs.erase(old);
+    }
+    auto ob = g_graph_bufs.find(k0);
+    if (ob != g_graph_bufs.end()) {
+        (void)hipFree(ob->second);
+        g_graph_bufs.erase(ob);
+    }
+}
 
 // Scratch of one GS call, carved from one buffer.
 struct GsLayout {
@@ -646,15 +667,7 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
             std::lock_guard<std::mutex> lk(g_graph_mu);
             g_graphs[key] = exec;
             g_graph_order.push_back(key);
-            if (g_graph_order.size() > 32) {
-                auto old = g_graphs.find(g_graph_order.front());
-                if (old != g_graphs.end()) {
-                    (void)hipStreamSynchronize(s);
-                    (void)hipGraphExecDestroy(old->second);
-                    g_graphs.erase(old);
-                }
-                g_graph_order.erase(g_graph_order.begin());
-            }
+            graph_trim_locked(s);
         }
         DEBUG_FAIL_CHECK("graph");
         HIP_TRY(hipGraphLaunch(exec, s));
@@ -1203,28 +1216,88 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
         off[f] = total;
         total += (uint64_t)ospr_fields(fr.n_sf, mode) * (uint64_t)fr.nx * (uint64_t)fr.ny;
     }
-    // frames to branches: longest first onto the least-loaded branch
-    const int nb = n_frames < kBranches ? n_frames : kBranches;
-    std::vector<int> order(n_frames), branch(n_frames);
-    for (int f = 0; f < n_frames; ++f) order[f] = f;
-    std::sort(order.begin(), order.end(), [&](int a, int b2) {
-        const double wa = (double)frames[a].n_sf * frames[a].nx * frames[a].ny;
-        const double wb = (double)frames[b2].n_sf * frames[b2].nx * frames[b2].ny;
-        return wa != wb ? wa > wb : a < b2;
-    });
+    bool prof_on;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        prof_on = g_prof_on;
+    }
+    const bool use_graph = g_use_graphs && !prof_on && s != nullptr;
+    // Graph replays of binary frames drawn from a pool without per-row states
+    // run grouped: frames of one size and launch shape share one launch per
+    // pass (K1..K4), each frame with its own planes (no chunking).  Otherwise
+    // each frame runs its own launches (chunked, branch-local planes).
+    const bool grouped = use_graph && mode == OSPR_BINARY && lut->kind != SRC_MSEQ;
+    std::vector<std::vector<int>> units;   // frames launched together
+    if (grouped) {
+        std::map<std::vector<int>, int> gid;
+        for (int f = 0; f < n_frames; ++f) {
+            const holo_frame& fr = frames[f];
+            const LaunchCfg& c = cfg[f];
+            const std::vector<int> k = {(int)fr.nx, (int)fr.ny, c.cols_per_block, c.rows_per_block, c.ksplit,
+                                        c.pad, c.pts, recon_rows_groups((int)fr.nx, fr.n_sf, c)};
+            auto it = gid.find(k);
+            if (it == gid.end()) {
+                it = gid.emplace(k, (int)units.size()).first;
+                units.emplace_back();
+            }
+            units[it->second].push_back(f);
+        }
+        // groups are split (frames in order) so that a unit's half planes
+        // stay within 64 MiB -- the four branches' row-pass output then fits
+        // the last-level cache until the column pass reads it -- and within
+        // an eighth of the batch's work (balanced branches)
+        double all = 0.0;
+        for (int f = 0; f < n_frames; ++f) all += (double)frames[f].n_sf * frames[f].nx * frames[f].ny;
+        const double cap = std::min(all / (2.0 * kBranches), (double)(64u << 20) / 4.0);
+        std::vector<std::vector<int>> split;
+        for (const auto& g : units) {
+            split.emplace_back();
+            double w = 0.0;
+            for (int f : g) {
+                const double wf = (double)frames[f].n_sf * frames[f].nx * frames[f].ny;
+                if (!split.back().empty() && w + wf > cap) {
+                    split.emplace_back();
+                    w = 0.0;
+                }
+                split.back().push_back(f);
+                w += wf;
+            }
+        }
+        units.swap(split);
+    } else {
+        for (int f = 0; f < n_frames; ++f) units.push_back({f});
+    }
+    // units to branches: longest first onto the least-loaded branch
+    const int nu = (int)units.size();
+    const int nb = nu < kBranches ? nu : kBranches;
+    std::vector<double> work(nu, 0.0);
+    for (int u = 0; u < nu; ++u)
+        for (int f : units[u]) work[u] += (double)frames[f].n_sf * frames[f].nx * frames[f].ny;
+    std::vector<int> order(nu), branch(nu);
+    for (int u = 0; u < nu; ++u) order[u] = u;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return work[x] != work[y] ? work[x] > work[y] : x < y; });
     std::vector<double> load(nb, 0.0);
     std::vector<size_t> bbytes(nb, 0);
-    for (int f : order) {
-        int b = 0;
+    for (int u : order) {
+        int bi = 0;
         for (int i = 1; i < nb; ++i)
-            if (load[i] < load[b]) b = i;
-        branch[f] = b;
-        load[b] += (double)frames[f].n_sf * frames[f].nx * frames[f].ny;
-        if (lay[f].bytes > bbytes[b]) bbytes[b] = lay[f].bytes;
+            if (load[i] < load[bi]) bi = i;
+        branch[u] = bi;
+        load[bi] += work[u];
+        if (!grouped && lay[units[u][0]].bytes > bbytes[bi]) bbytes[bi] = lay[units[u][0]].bytes;
     }
     Carver cv;
-    std::vector<size_t> o_branch(nb);
-    for (int b = 0; b < nb; ++b) o_branch[b] = cv.take(bbytes[b]);
+    std::vector<size_t> o_branch(nb), o_x1(n_frames), o_x2(n_frames), o_part(n_frames);
+    if (grouped) {
+        for (int f = 0; f < n_frames; ++f) {
+            const size_t plane = (size_t)(frames[f].ny / 2 + 1) * (size_t)row_pitch((int)frames[f].nx, cfg[f]);
+            o_x1[f] = cv.take(sizeof(float2) * plane * (size_t)frames[f].n_sf);
+            o_x2[f] = cv.take(sizeof(float2) * plane * (size_t)frames[f].n_sf);
+            o_part[f] = cv.take(sizeof(double) * 5 * (size_t)(frames[f].ny / 2 + 1));
+        }
+    } else {
+        for (int i = 0; i < nb; ++i) o_branch[i] = cv.take(bbytes[i]);
+    }
     const size_t o_base = cv.take(sizeof(uint64_t));
     const size_t o_nm = cv.take(sizeof(double) * 2 * n_frames);
     // twiddle tables first: they synchronise, which capture forbids
@@ -1242,34 +1315,65 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
     uint64_t* dbase = (uint64_t*)(b + o_base);
     double* nm = (double*)(b + o_nm);
 
+    // grouped: the frame table, unit by unit (each unit's entries contiguous)
+    std::vector<GroupFrame> table;
+    std::vector<int> ustart(nu, 0);
+    if (grouped) {
+        for (int u = 0; u < nu; ++u) {
+            ustart[u] = (int)table.size();
+            for (int f : units[u]) {
+                const holo_frame& fr = frames[f];
+                GroupFrame g{};
+                g.target = fr.target;
+                g.x1 = (float2*)(b + o_x1[f]);
+                g.bits = (uint32_t*)fr.holo_bits;
+                g.x2 = (float2*)(b + o_x2[f]);
+                g.recon = fr.recon;
+                g.part = (double*)(b + o_part[f]);
+                g.nm = nm + 2 * f;
+                g.c0 = lut_wrap(lut, off[f]);
+                g.inv_scale = (float)(1.0 / ((double)fr.n_sf * (double)fr.nx * (double)fr.ny));
+                g.n_sf = fr.n_sf;
+                ospr_rows_h_shape((int)fr.nx, (int)fr.ny, fr.n_sf, cfg[f], &g.k1_blocks, &g.spb);
+                g.k2_tiles = ospr_cols_tiles((int)fr.nx, (int)fr.ny, fr.n_sf, cfg[f]);
+                table.push_back(g);
+            }
+        }
+    }
+
     // the only per-call value inside the graph: the pool start, in device memory
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, dbase, lut_wrap(lut, *cursor));
     HIP_TRY(hipGetLastError());
 
-    auto enqueue_all = [&](bool branches, BatchSync* bs) -> holo_status {
-        for (int f = 0; f < n_frames; ++f) {
+    auto enqueue_all = [&](bool branches, BatchSync* bs, const GroupFrame* dtab) -> holo_status {
+        for (int u = 0; u < nu; ++u) {
+            hipStream_t fs = branches ? bs->br[branch[u]] : s;
+            if (grouped) {
+                const int f0 = units[u][0];
+                const PhaseSrc src = make_src(lut, nullptr);
+                LAUNCH("ospr_group", fs,
+                       launch_ospr_group(dtab + ustart[u], &table[ustart[u]], (int)units[u].size(), (int)frames[f0].nx,
+                                         (int)frames[f0].ny, src, dbase, tw[(int)frames[f0].nx],
+                                         tw[(int)frames[f0].ny], cfg[f0], fs));
+                continue;
+            }
+            const int f = units[u][0];
             const holo_frame& fr = frames[f];
-            hipStream_t fs = branches ? bs->br[branch[f]] : s;
             holo_status e = ospr_enqueue(fr.target, fr.nx, fr.ny, fr.n_sf, lut, lut_wrap(lut, off[f]), dbase,
                                          fr.holo_bits, fr.recon, nm + 2 * f, tw[(int)fr.nx], tw[(int)fr.ny],
-                                         b + o_branch[branch[f]], lay[f], fs, cfg[f], mode);
+                                         b + o_branch[branch[u]], lay[f], fs, cfg[f], mode);
             if (e) return e;
         }
         return HOLO_OK;
     };
-    bool prof_on;
-    {
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        prof_on = g_prof_on;
-    }
-    if (!g_use_graphs || prof_on || s == nullptr) {
-        if ((st = enqueue_all(false, nullptr))) return st;
+    if (!use_graph) {
+        if ((st = enqueue_all(false, nullptr, nullptr))) return st;
     } else {
         BatchSync* bs = nullptr;
         if ((st = get_batch_sync(device, &bs))) return st;
         GraphKey key;
         key.k = {(uintptr_t)0xBA7C, (uintptr_t)device, (uintptr_t)s, (uintptr_t)ws, (uintptr_t)lut->id,
-                 (uintptr_t)n_frames, (uintptr_t)mode};
+                 (uintptr_t)n_frames, (uintptr_t)mode, (uintptr_t)grouped};
         for (int f = 0; f < n_frames; ++f) {
             const holo_frame& fr = frames[f];
             const LaunchCfg& c = cfg[f];
@@ -1287,12 +1391,27 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
             if (it != g_graphs.end()) exec = it->second;
         }
         if (!exec) {
+            // the frame table lives with the graph (device memory written once)
+            GroupFrame* dtab = nullptr;
+            if (grouped) {
+                if (hipMalloc((void**)&dtab, sizeof(GroupFrame) * table.size()) != hipSuccess)
+                    return fail(HOLO_ENOMEM, "batch frame table (%zu frames)", table.size());
+                hipError_t me = hipMemcpy(dtab, table.data(), sizeof(GroupFrame) * table.size(), hipMemcpyHostToDevice);
+                if (me != hipSuccess) {
+                    (void)hipFree(dtab);
+                    return fail(HOLO_EDEVICE, "batch frame table: %s", hipGetErrorString(me));
+                }
+            }
             hipGraph_t graph = nullptr;
-            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t be = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (be != hipSuccess) {
+                if (dtab) (void)hipFree(dtab);
+                return fail(HOLO_EDEVICE, "batch graph capture: %s", hipGetErrorString(be));
+            }
             holo_status est = HOLO_OK;
             hipError_t he = hipEventRecord(bs->fork, s);
             for (int i = 0; i < nb && he == hipSuccess; ++i) he = hipStreamWaitEvent(bs->br[i], bs->fork, 0);
-            if (he == hipSuccess) est = enqueue_all(true, bs);
+            if (he == hipSuccess) est = enqueue_all(true, bs, dtab);
             for (int i = 0; i < nb && he == hipSuccess; ++i) {
                 he = hipEventRecord(bs->join[i], bs->br[i]);
                 if (he == hipSuccess) he = hipStreamWaitEvent(s, bs->join[i], 0);
@@ -1300,25 +1419,22 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
             hipError_t ce = hipStreamEndCapture(s, &graph);
             if (est || he != hipSuccess || ce != hipSuccess) {
                 if (graph) (void)hipGraphDestroy(graph);
+                if (dtab) (void)hipFree(dtab);
                 if (est) return est;
                 return fail(HOLO_EDEVICE, "batch graph capture: %s",
                             hipGetErrorString(he != hipSuccess ? he : ce));
             }
             hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
-            if (ie != hipSuccess) return fail(HOLO_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(ie));
+            if (ie != hipSuccess) {
+                if (dtab) (void)hipFree(dtab);
+                return fail(HOLO_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(ie));
+            }
             std::lock_guard<std::mutex> lk(g_graph_mu);
             g_graphs[key] = exec;
+            if (dtab) g_graph_bufs[key] = dtab;
             g_graph_order.push_back(key);
-            if (g_graph_order.size() > 32) {
-                auto old = g_graphs.find(g_graph_order.front());
-                if (old != g_graphs.end()) {
-                    (void)hipStreamSynchronize(s);
-                    (void)hipGraphExecDestroy(old->second);
-                    g_graphs.erase(old);
-                }
-                g_graph_order.erase(g_graph_order.begin());
-            }
+            graph_trim_locked(s);
         }
         DEBUG_FAIL_CHECK("graph");
         HIP_TRY(hipGraphLaunch(exec, s));
@@ -1920,6 +2036,8 @@ void holo_shutdown(void)
         std::lock_guard<std::mutex> gl(g_graph_mu);
         for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
         g_graphs.clear();
+        for (auto& kv : g_graph_bufs) (void)hipFree(kv.second);
+        g_graph_bufs.clear();
         g_graph_order.clear();
     }
     (void)hipSetDevice(cur);

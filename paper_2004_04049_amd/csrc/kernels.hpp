@@ -22,6 +22,27 @@ struct LaunchCfg {
     const void* dftop = nullptr;   // DFT-matrix operand table of `prec` (launch_dft_operand_gen)
 };
 
+// Grouped binary OSPR frames: frames of one size and launch shape run each of
+// K1..K4 as one launch, blockIdx.y selecting the frame (its table entry) and
+// blocks past the frame's own count returning at once.  Every frame keeps the
+// shapes (and so the arithmetic) of its single-frame launch; all its
+// sub-frames are generated at once (no chunking).
+struct GroupFrame {
+    const float* target;
+    float2* x1;            // n_sf half planes
+    uint32_t* bits;        // n_sf * nx * ny / 32 words
+    float2* x2;            // n_sf half spectra
+    float* recon;          // nx * ny, or null
+    double* part;          // 5 per spectrum row
+    double* nm;            // {NMSE, NMSE_sym}
+    uint64_t c0;           // pool offset of the frame (reduced)
+    float inv_scale;       // 1 / (n_sf * nx * ny)
+    int n_sf;
+    int spb;               // K1: sub-frames per block
+    int k1_blocks;         // K1 blocks of the frame
+    int k2_tiles;          // K2 column tiles of the frame
+};
+
 // Row pitch (complex elements) of the library's internal [rows][nx] fields:
 // power-of-two row strides make column passes hit few memory channels, so a
 // small pad is added (planned, or 16 elements for nx >= 256).
@@ -61,9 +82,12 @@ hipError_t launch_ospr_rows(const float* target, int nx, int ny, int n_sf, const
 // OSPR K1 for binary frames: the Hermitian part of R (whose
 // inverse transform is Re H), inverse row transform of rows 0..ny/2 only,
 // written as half planes of ny/2 + 1 rows (stride (ny/2 + 1) * pitch).
+// gtab (device memory): a grouped launch of `ngroup` frames whose grid row
+// holds `grid_x` blocks (the largest frame's count); the per-frame arguments
+// above are then taken from the table.
 hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, const PhaseSrc& src, uint64_t c0,
                               const uint64_t* c0_base, float2* x1, const float2* tw_x, const LaunchCfg& cfg,
-                              hipStream_t s);
+                              hipStream_t s, const GroupFrame* gtab = nullptr, int ngroup = 1, int grid_x = 0);
 
 // M-sequence source: Galois state of the first pixel of every (sub-frame,
 // row) of a launch, rows[k*ny + y]; aux = x^(2^j) for j < 31, then S_0.
@@ -77,7 +101,8 @@ hipError_t launch_phase_mask(const PhaseSrc& src, uint64_t c0, int nx, int ny, i
 // of the +-1 column, half spectrum (rows 0..ny/2) out; x1 holds the half
 // planes of launch_ospr_rows_h.
 hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
-                            const float2* tw_y, const LaunchCfg& cfg, hipStream_t s);
+                            const float2* tw_y, const LaunchCfg& cfg, hipStream_t s, const GroupFrame* gtab = nullptr,
+                            int ngroup = 1, int grid_x = 0);
 // K2 variants: mode OSPR_PAIRS writes sub-frames 2j (Re H) and 2j+1 (Im H) of
 // each of the n_fields fields (bits, half spectra); mode OSPR_LEVELS8 writes
 // 8-level codes (uint8 [n_fields][ny*nx]) and full column spectra.
@@ -92,9 +117,20 @@ hipError_t launch_recon_cols(const void* holo, int levels, int nx, int ny, int n
 // half: x2 holds rows 0..ny/2 of a Hermitian-symmetric spectrum.
 hipError_t launch_recon_rows(const float2* x2, int nx, int ny, int n_sf, bool half, const float* target,
                              float* recon, double* partials, const float2* tw_x, const LaunchCfg& cfg,
-                             hipStream_t s);
+                             hipStream_t s, const GroupFrame* gtab = nullptr, int ngroup = 1);
 // K4: deterministic reduction of `nrows` x 5 partials -> {NMSE, NMSE_sym}.
 hipError_t launch_nmse_finalize(const double* partials, int nrows, double* out2, hipStream_t s);
+
+// Single-frame launch shapes, for building a group: K1 blocks and sub-frames
+// per block; K2 tiles; K3 sub-frame groups per block.
+void ospr_rows_h_shape(int nx, int ny, int n_sf, const LaunchCfg& cfg, int* blocks, int* spb);
+int ospr_cols_tiles(int nx, int ny, int n_sf, const LaunchCfg& cfg);
+int recon_rows_groups(int nx, int n_sf, const LaunchCfg& cfg);
+// K1..K4 of the `n` frames of table `tab` (device memory; the host copy
+// `host` gives the grid), all of size nx x ny with launch shapes `cfg`.
+hipError_t launch_ospr_group(const GroupFrame* tab, const GroupFrame* host, int n, int nx, int ny,
+                             const PhaseSrc& src, const uint64_t* c0_base, const float2* tw_x, const float2* tw_y,
+                             const LaunchCfg& cfg, hipStream_t s);
 
 // Gerchberg-Saxton passes.
 enum GsRowMode { GS_INIT = 0, GS_ITER = 1, GS_FINAL = 2 };

@@ -395,8 +395,18 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(3
                                                                 int spb, PhaseSrc src, uint64_t c0,
                                                                 const uint64_t* __restrict__ c0_base,
                                                                 float2* __restrict__ x1, const float2* __restrict__ tw,
-                                                                int pitch, const uint4* __restrict__ dftop)
+                                                                int pitch, const uint4* __restrict__ dftop,
+                                                                const GroupFrame* __restrict__ gtab)
 {
+    if (gtab) {   // grouped launch: this frame's arguments
+        const GroupFrame& gf = gtab[blockIdx.y];
+        if ((int)blockIdx.x >= gf.k1_blocks) return;
+        target = gf.target;
+        n_sf = gf.n_sf;
+        spb = gf.spb;
+        c0 = gf.c0;
+        x1 = gf.x1;
+    }
     extern __shared__ float2 lds[];
     constexpr int T = NX / PT;
     const int rows = blockDim.x / T;
@@ -453,23 +463,37 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(3
     }
 }
 
-hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, const PhaseSrc& src, uint64_t c0,
-                              const uint64_t* c0_base, float2* x1, const float2* tw_x, const LaunchCfg& cfg,
-                              hipStream_t s)
+static int rows_h_rows(int nx, int ny, const LaunchCfg& cfg, int pt)
 {
-    const int pt = plan_pts(cfg, 0, nx);
     int rows = row_block_rows(nx, ny, cfg.rows_per_block, cfg.prec, pt);
     while (rows > 1 && rows * (nx / pt) > 512) rows >>= 1;   // the FP32 kernel's launch bound
+    return rows;
+}
+
+void ospr_rows_h_shape(int nx, int ny, int n_sf, const LaunchCfg& cfg, int* blocks, int* spb)
+{
+    const int rows = rows_h_rows(nx, ny, cfg, plan_pts(cfg, 0, nx));
     const int row_blocks = (ny / 2 + 1 + rows - 1) / rows;
-    const int spb = rows_sf_per_block(row_blocks, n_sf);
-    const int sf_blocks = (n_sf + spb - 1) / spb;
+    *spb = rows_sf_per_block(row_blocks, n_sf);
+    *blocks = row_blocks * ((n_sf + *spb - 1) / *spb);
+}
+
+hipError_t launch_ospr_rows_h(const float* target, int nx, int ny, int n_sf, const PhaseSrc& src, uint64_t c0,
+                              const uint64_t* c0_base, float2* x1, const float2* tw_x, const LaunchCfg& cfg,
+                              hipStream_t s, const GroupFrame* gtab, int ngroup, int grid_x)
+{
+    const int pt = plan_pts(cfg, 0, nx);
+    const int rows = rows_h_rows(nx, ny, cfg, pt);
+    int blocks, spb;
+    ospr_rows_h_shape(nx, ny, n_sf, cfg, &blocks, &spb);
+    const dim3 grid(gtab ? grid_x : blocks, gtab ? ngroup : 1);
     HOLO_SWITCH_NP(nx, cfg.prec, HOLO_SWITCH_PT(pt, {
         constexpr int T = N_ / PT_;
         size_t lds = (size_t)rows * PadLenP<N_, PT_>::v * sizeof(float2) +
                      (src.kind == SRC_MSEQ || src.kind == SRC_CODES8 ? kPhaseLdsWords * sizeof(uint32_t) : 0);
         allow_lds(k_ospr_rows_h<N_, P_, PT_>, lds);
-        hipLaunchKernelGGL((k_ospr_rows_h<N_, P_, PT_>), dim3(row_blocks * sf_blocks), dim3(rows * T), lds, s, target,
-                           ny, n_sf, spb, src, c0, c0_base, x1, tw_x, row_pitch(nx, cfg), DFTOP(cfg));
+        hipLaunchKernelGGL((k_ospr_rows_h<N_, P_, PT_>), grid, dim3(rows * T), lds, s, target, ny, n_sf, spb, src, c0,
+                           c0_base, x1, tw_x, row_pitch(nx, cfg), DFTOP(cfg), gtab);
     }));
     return hipGetLastError();
 }
@@ -509,7 +533,8 @@ __global__ __launch_bounds__((C / 2) * (NY / PT)) __attribute__((amdgpu_waves_pe
                                                                    uint32_t* __restrict__ bits,
                                                                    float2* __restrict__ x2,
                                                                    const float2* __restrict__ tw, int pitch,
-                                                                   const uint4* __restrict__ dftop)
+                                                                   const uint4* __restrict__ dftop,
+                                                                   const GroupFrame* __restrict__ gtab)
 {
     extern __shared__ float2 lds[];
     constexpr int CP = C / 2;
@@ -518,6 +543,13 @@ __global__ __launch_bounds__((C / 2) * (NY / PT)) __attribute__((amdgpu_waves_pe
     const int lane = threadIdx.x & 63;
     const int ncb = nx / C;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (gtab) {   // grouped launch: this frame's arguments
+        const GroupFrame& gf = gtab[blockIdx.y];
+        if (tile >= gf.k2_tiles) return;
+        x1 = gf.x1;
+        bits = gf.bits;
+        x2 = gf.x2;
+    }
     const int k = tile / ncb;
     const int x0 = (tile - k * ncb) * C;
     const size_t npix = (size_t)nx * NY;
@@ -581,22 +613,35 @@ __global__ __launch_bounds__((C / 2) * (NY / PT)) __attribute__((amdgpu_waves_pe
     }
 }
 
-hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
-                            const float2* tw_y, const LaunchCfg& cfg, hipStream_t s)
+// Column-tile width of K2: 8 columns (4 column pairs per block) unless
+// planned; measured at 1024^2, 24 sub-frames (FP32): 50.3 us against 55.2 us
+// for 16-column tiles.  The matrix-core forms use 8-column tiles.
+static int ospr_cols_width(int nx, int ny, int n_sf, const LaunchCfg& cfg, int pt)
 {
-    // 8-column tiles (4 column pairs per block) unless planned; measured at
-    // 1024^2, 24 sub-frames (FP32): 50.3 us against 55.2 us for 16-column
-    // tiles.  The matrix-core forms use 8-column tiles.
-    const int pt = plan_pts(cfg, 1, ny);
     int C = cfg.prec ? 8 : cfg.cols_per_block > 0 ? col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8) : 8;
     if ((C / 2) * (ny / pt) > 1024) C = 8;   // 2048-point columns at 8 points per thread
+    return C;
+}
+
+int ospr_cols_tiles(int nx, int ny, int n_sf, const LaunchCfg& cfg)
+{
+    return (nx / ospr_cols_width(nx, ny, n_sf, cfg, plan_pts(cfg, 1, ny))) * n_sf;
+}
+
+hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t* bits, float2* x2,
+                            const float2* tw_y, const LaunchCfg& cfg, hipStream_t s, const GroupFrame* gtab,
+                            int ngroup, int grid_x)
+{
+    const int pt = plan_pts(cfg, 1, ny);
+    const int C = ospr_cols_width(nx, ny, n_sf, cfg, pt);
     HOLO_SWITCH_NP(ny, cfg.prec, HOLO_SWITCH_PT(pt, {
         constexpr int T = N_ / PT_;
         if constexpr (P_ != 0) {
             size_t lds = (size_t)4 * PadLen<N_>::v * sizeof(float2);
             allow_lds(k_ospr_cols2<N_, 8, P_, kP>, lds);
-            hipLaunchKernelGGL((k_ospr_cols2<N_, 8, P_, kP>), dim3((nx / 8) * n_sf), dim3(4 * T), lds, s, x1, nx,
-                               bits, x2, tw_y, row_pitch(nx, cfg), DFTOP(cfg));
+            const dim3 grid(gtab ? grid_x : (nx / 8) * n_sf, gtab ? ngroup : 1);
+            hipLaunchKernelGGL((k_ospr_cols2<N_, 8, P_, kP>), grid, dim3(4 * T), lds, s, x1, nx, bits, x2, tw_y,
+                               row_pitch(nx, cfg), DFTOP(cfg), gtab);
         } else {
             HOLO_SWITCH_C816(C, {
                 if constexpr ((C_ / 2) * T > 1024) {
@@ -604,8 +649,9 @@ hipError_t launch_ospr_cols(const float2* x1, int nx, int ny, int n_sf, uint32_t
                 } else {
                     size_t lds = (size_t)(C_ / 2) * PadLenP<N_, PT_>::v * sizeof(float2);
                     allow_lds(k_ospr_cols2<N_, C_, 0, PT_>, lds);
-                    hipLaunchKernelGGL((k_ospr_cols2<N_, C_, 0, PT_>), dim3((nx / C_) * n_sf), dim3((C_ / 2) * T), lds,
-                                       s, x1, nx, bits, x2, tw_y, row_pitch(nx, cfg), nullptr);
+                    const dim3 grid(gtab ? grid_x : (nx / C_) * n_sf, gtab ? ngroup : 1);
+                    hipLaunchKernelGGL((k_ospr_cols2<N_, C_, 0, PT_>), grid, dim3((C_ / 2) * T), lds, s, x1, nx, bits,
+                                       x2, tw_y, row_pitch(nx, cfg), nullptr, gtab);
                 }
             });
         }
@@ -839,8 +885,18 @@ template <int NX, int P, int PT>
 __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(4))) void k_recon_rows(const float2* __restrict__ x2, int ny, int n_sf, int half,
                                                      const float* __restrict__ target, float* __restrict__ recon,
                                                      double* __restrict__ partials, const float2* __restrict__ tw,
-                                                     float inv_scale, int pitch, const uint4* __restrict__ dftop)
+                                                     float inv_scale, int pitch, const uint4* __restrict__ dftop,
+                                                     const GroupFrame* __restrict__ gtab)
 {
+    if (gtab) {   // grouped launch: this frame's arguments (half spectra)
+        const GroupFrame& gf = gtab[blockIdx.y];
+        x2 = gf.x2;
+        n_sf = gf.n_sf;
+        target = gf.target;
+        recon = gf.recon;
+        partials = gf.part;
+        inv_scale = gf.inv_scale;
+    }
     extern __shared__ float2 lds[];
     constexpr int T = NX / PT;
     const int G = blockDim.x / T;
@@ -931,27 +987,35 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(4
         for (int i = 0; i < 5; ++i) partials[(size_t)v_row * 5 + i] = tot[i];
 }
 
+int recon_rows_groups(int nx, int n_sf, const LaunchCfg& cfg)
+{
+    const int T = nx / plan_pts(cfg, 2, nx);
+    int G = cfg.ksplit > 0 ? cfg.ksplit : 4;
+    while (G > 1 && (G * T > 512 || G > n_sf)) G >>= 1;
+    // matrix cores: whole waves (groups past n_sf transform zeros and add
+    // nothing), at most 256 threads
+    if (cfg.prec && G * T > 256) G = 256 / T;
+    if (cfg.prec && G * T < 64) G = 64 / T;
+    return G;
+}
+
 hipError_t launch_recon_rows(const float2* x2, int nx, int ny, int n_sf, bool half, const float* target,
                              float* recon, double* partials, const float2* tw_x, const LaunchCfg& cfg,
-                             hipStream_t s)
+                             hipStream_t s, const GroupFrame* gtab, int ngroup)
 {
     const int nrows_spec = half ? ny / 2 + 1 : ny;
     const int pt = plan_pts(cfg, 2, nx);
+    const int G = recon_rows_groups(nx, n_sf, cfg);
     HOLO_SWITCH_NP(nx, cfg.prec, HOLO_SWITCH_PT(pt, {
         constexpr int T = N_ / PT_;
-        int G = cfg.ksplit > 0 ? cfg.ksplit : 4;
-        while (G > 1 && (G * T > 512 || G > n_sf)) G >>= 1;
-        // matrix cores: whole waves (groups past n_sf transform zeros and add
-        // nothing), at most 256 threads
-        if (P_ && G * T > 256) G = 256 / T;
-        if (P_ && G * T < 64) G = 64 / T;
         size_t fft_lds = (size_t)G * PadLenP<N_, PT_>::v * sizeof(float2);
         size_t red_lds = (size_t)5 * (G * T / 64 + 1) * sizeof(double);
         size_t lds = fft_lds > red_lds ? fft_lds : red_lds;
         const float inv_scale = (float)(1.0 / ((double)n_sf * (double)nx * (double)ny));
         allow_lds(k_recon_rows<N_, P_, PT_>, lds);
-        hipLaunchKernelGGL((k_recon_rows<N_, P_, PT_>), dim3(nrows_spec), dim3(G * T), lds, s, x2, ny, n_sf,
-                           half ? 1 : 0, target, recon, partials, tw_x, inv_scale, row_pitch(nx, cfg), DFTOP(cfg));
+        hipLaunchKernelGGL((k_recon_rows<N_, P_, PT_>), dim3(nrows_spec, gtab ? ngroup : 1), dim3(G * T), lds, s, x2,
+                           ny, n_sf, half ? 1 : 0, target, recon, partials, tw_x, inv_scale, row_pitch(nx, cfg),
+                           DFTOP(cfg), gtab);
     }));
     return hipGetLastError();
 }
@@ -963,8 +1027,12 @@ hipError_t launch_recon_rows(const float2* x2, int nx, int ny, int n_sf, bool ha
 // barriers (6.3 against 7.0 us for a 256-thread block at 513 rows).
 // -------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_nmse_finalize(const double* __restrict__ partials, int nrows,
-                                                       double* __restrict__ out2)
+                                                       double* __restrict__ out2, const GroupFrame* __restrict__ gtab)
 {
+    if (gtab) {   // grouped launch: one block per frame
+        partials = gtab[blockIdx.x].part;
+        out2 = gtab[blockIdx.x].nm;
+    }
     double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int r = threadIdx.x; r < nrows; r += 64)
         for (int i = 0; i < 5; ++i) a[i] += partials[(size_t)r * 5 + i];
@@ -979,7 +1047,27 @@ __global__ __launch_bounds__(64) void k_nmse_finalize(const double* __restrict__
 
 hipError_t launch_nmse_finalize(const double* partials, int nrows, double* out2, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_nmse_finalize, dim3(1), dim3(64), 0, s, partials, nrows, out2);
+    hipLaunchKernelGGL(k_nmse_finalize, dim3(1), dim3(64), 0, s, partials, nrows, out2, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_ospr_group(const GroupFrame* tab, const GroupFrame* host, int n, int nx, int ny,
+                             const PhaseSrc& src, const uint64_t* c0_base, const float2* tw_x, const float2* tw_y,
+                             const LaunchCfg& cfg, hipStream_t s)
+{
+    int k1 = 0, k2 = 0;
+    for (int f = 0; f < n; ++f) {
+        k1 = host[f].k1_blocks > k1 ? host[f].k1_blocks : k1;
+        k2 = host[f].k2_tiles > k2 ? host[f].k2_tiles : k2;
+    }
+    // the shape arguments of the first frame stand for all (equal by grouping)
+    const int ns = host[0].n_sf;
+    hipError_t e = launch_ospr_rows_h(nullptr, nx, ny, ns, src, 0, c0_base, nullptr, tw_x, cfg, s, tab, n, k1);
+    if (e != hipSuccess) return e;
+    if ((e = launch_ospr_cols(nullptr, nx, ny, ns, nullptr, nullptr, tw_y, cfg, s, tab, n, k2)) != hipSuccess) return e;
+    if ((e = launch_recon_rows(nullptr, nx, ny, ns, true, nullptr, nullptr, nullptr, tw_x, cfg, s, tab, n)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_nmse_finalize, dim3(n), dim3(64), 0, s, nullptr, ny / 2 + 1, nullptr, tab);
     return hipGetLastError();
 }
 

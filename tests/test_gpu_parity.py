@@ -463,6 +463,35 @@ def test_batched_equals_sequential_calls(holo, orc, pts, per_size):
             holo.plan_set(holo.PLAN_OSPR, n, n, k, holo.DEFAULT_PLAN)
 
 
+def test_batched_grouped_ragged_frames(holo, orc):
+    # many frames of one size with different sub-frame counts (ragged block
+    # counts within one grouped launch), replay images on some frames only;
+    # equal to single-frame calls, and one frame against the oracle
+    nsfs = [1, 7, 3, 12, 2, 9, 5, 1, 4, 11, 6, 8]
+    n = 128
+    targets = [torch.from_numpy(synth.blob_target(n, n, 400 + f)).cuda() for f in range(len(nsfs))]
+    recons = [torch.empty((n, n), dtype=torch.float32, device="cuda") if f % 3 == 0 else None
+              for f in range(len(nsfs))]
+    lut = holo.Lut(10007, 1)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        bits, nm, cur = holo.ospr_generate_batched(targets, nsfs, lut, 77, recons=recons)
+        c = 77
+        for f, (t, k) in enumerate(zip(targets, nsfs)):
+            r1 = torch.empty_like(t) if recons[f] is not None else None
+            b1, nm1, c = holo.ospr_generate(t, k, lut, c, recon=r1)
+            assert torch.equal(bits[f], b1), f
+            np.testing.assert_array_equal(nm[f], nm1)
+            if r1 is not None:
+                assert torch.equal(recons[f], r1), f
+        assert cur == c
+    torch.cuda.synchronize()
+    f = 3
+    ref = orc.ospr(targets[f].cpu().numpy(), nsfs[f], orc.lut_phases(10007, 1), 10007, 77 + n * n * sum(nsfs[:f]))
+    _check_bits(holo, orc, bits[f], ref, n * n)
+    np.testing.assert_allclose(nm[f], ref["nmse2"], rtol=NMSE_RTOL)
+
+
 def test_batched_graph_follows_plan_changes(holo):
     # the same tensors through the batched call before and after a plan
     # change that only switches the points per thread: the second call must
