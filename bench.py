@@ -327,6 +327,20 @@ def bench_batched(h, synth, torch, dev):
         c = sequential(c)
     torch.cuda.synchronize()
     res["fp32_sequential_ms_per_batch"] = round(1e3 * (time.perf_counter() - t0) / 5, 3)
+    # batches of 64 small frames of one size (n_sf 8..24 from the same layout
+    # draw), where the grouped launches replace per-frame launch latency
+    small = {}
+    for n in (64, 256):
+        tg = [torch.from_numpy(synth.blob_target(n, n, synth.SEED_BATCH_TARGET0 + f)).to(dev) for f in range(64)]
+        bs, _, c = h.ospr_generate_batched(tg, nsfs, lut, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            bs, _, c = h.ospr_generate_batched(tg, nsfs, lut, c, bits=bs)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 10
+        small[f"64x{n}^2"] = {"ms_per_batch": round(1e3 * dt, 3), "px_subframes_per_s": round(n * n * sum(nsfs) / dt, 1)}
+    res["fp32_small_frames"] = small
     return res
 
 
