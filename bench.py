@@ -334,11 +334,13 @@ def bench_batched(h, synth, torch, dev):
         tg = [torch.from_numpy(synth.blob_target(n, n, synth.SEED_BATCH_TARGET0 + f)).to(dev) for f in range(64)]
         bs, _, c = h.ospr_generate_batched(tg, nsfs, lut, 0)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(10):
-            bs, _, c = h.ospr_generate_batched(tg, nsfs, lut, c, bits=bs)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 10
+        dt = float("inf")   # best of three 10-call loops (one-off runtime stalls of tens of ms occur)
+        for _ in range(3):
+            t0 = time.perf_counter()
+            for _ in range(10):
+                bs, _, c = h.ospr_generate_batched(tg, nsfs, lut, c, bits=bs)
+            torch.cuda.synchronize()
+            dt = min(dt, (time.perf_counter() - t0) / 10)
         small[f"64x{n}^2"] = {"ms_per_batch": round(1e3 * dt, 3), "px_subframes_per_s": round(n * n * sum(nsfs) / dt, 1)}
     res["fp32_small_frames"] = small
     return res
