@@ -288,11 +288,13 @@ def bench_batched(h, synth, torch, dev):
         out_nm = nm.cpu().numpy().copy()
         out_rec = [r.clone() for r in recons]
         reps = 5
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            bits, _, c = h.ospr_generate_batched(targets, nsfs, lut, c, bits=bits, nmse_out=nm, precision=prec)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
+        dt = float("inf")   # best of three loops (one-off runtime stalls of tens of ms occur)
+        for _ in range(3):
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                bits, _, c = h.ospr_generate_batched(targets, nsfs, lut, c, bits=bits, nmse_out=nm, precision=prec)
+            torch.cuda.synchronize()
+            dt = min(dt, (time.perf_counter() - t0) / reps)
         r = {"ms_per_batch": round(1e3 * dt, 3), "px_subframes_per_s": round(pxsf / dt, 1),
              "hbm_frac": round(design / dt / 1e9 / HBM_PEAK_GBS, 4),
              "canonical_frac": round(canon / dt / 1e9 / HBM_PEAK_GBS, 4), "nmse_mean": float(out_nm[:, 0].mean())}
