@@ -215,6 +215,44 @@ HOLO_API holo_status holo_gs_iterate(const float* target, int64_t nx, int64_t ny
                                      void* hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * holo_gs_iterate_batched -- holo_gs_iterate (Section 2) on n_frames frames of
+ * one size at once, each exactly as a holo_gs_iterate call computes it, with
+ * the pool cursor continuing from frame to frame in array order: a
+ * pool-seeded frame starts at *cursor + N * (pool-seeded frames before it),
+ * and *cursor advances by N per pool-seeded frame.  Every pass of every
+ * iteration is one launch over all frames (blockIdx.y selects the frame):
+ * GS iterations of one frame are sequential, and one 512^2 or 1024^2 frame
+ * leaves most of the GPU waiting on the dependent stages of its passes;
+ * independent frames fill it.
+ *   frames         host array of n_frames (1..256) descriptors; device
+ *                  pointers as holo_gs_iterate's: target, init_phasor (NULL:
+ *                  pool seed), field, codes, recon (each may be NULL except
+ *                  target; recon needs the frame's codes)
+ *   nmse_per_iter, err_per_iter  [n_frames][n_iter] or NULL
+ *   nmse_final2    [n_frames][2] or NULL (needs codes on every frame)
+ *                  (host, or device with HOLO_F_NMSE_DEVICE)
+ * The work is captured into a HIP graph and replayed while frames, buffers
+ * and plan are unchanged (launched directly on the legacy default stream or
+ * while kernel timing is on).  FP32 only.
+ * Errors: HOLO_EINVAL (null frames/cursor/target, n_frames or n_iter out of
+ * range, recon or nmse_final2 without codes, null lut with a pool-seeded
+ * frame), HOLO_EUNSUPPORTED (sizes; the M-sequence source, whose per-row
+ * states this call does not prepare).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    const float* target;       /* device float[ny][nx]                   */
+    const float* init_phasor;  /* device float2[ny][nx], or NULL (pool)  */
+    float* field;              /* device float2[ny][nx] out, or NULL     */
+    uint8_t* codes;            /* device uint8[ny][nx] out, or NULL      */
+    float* recon;              /* device float[ny][nx] out, or NULL      */
+} holo_gs_frame;
+
+HOLO_API holo_status holo_gs_iterate_batched(const holo_gs_frame* frames, int32_t n_frames, int64_t nx, int64_t ny,
+                                             int32_t n_iter, const holo_lut* lut, uint64_t* cursor,
+                                             double* nmse_per_iter, double* err_per_iter, double* nmse_final2,
+                                             uint32_t flags, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
  * holo_gs_iterate_noalloc -- holo_gs_iterate for callers that cannot allocate
  * device memory: code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc.  Same arguments, computation and results as

@@ -45,6 +45,7 @@ SIGNATURES = {
                                _U32, _P]),
     "holo_gs_iterate_noalloc": (_I32, [_P, _I64, _I64, _I32, _P, C.POINTER(_U64), _P, _P, _P, _P, _P, _P, _P,
                                        _I32, _U32, _P]),
+    "holo_gs_iterate_batched": (_I32, [_P, _I32, _I64, _I64, _I32, _P, C.POINTER(_U64), _P, _P, _P, _U32, _P]),
     "holo_reconstruct_nmse": (_I32, [_P, _I32, _I64, _I64, _I32, _P, _P, _P, _U32, _P]),
     "holo_fft2": (_I32, [_P, _P, _I64, _I64, _I32, _I32, _P]),
     "holo_phase_mask": (_I32, [_P, _U64, _I64, _I64, _I32, _P, _P]),
@@ -77,6 +78,12 @@ class HoloFrame(C.Structure):
     """holo_frame: one frame of a batched OSPR call (device pointers)."""
     _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("n_sf", C.c_int32), ("target", C.c_void_p),
                 ("holo_bits", C.c_void_p), ("recon", C.c_void_p)]
+
+
+class HoloGsFrame(C.Structure):
+    """holo_gs_frame: one frame of a batched GS call (device pointers)."""
+    _fields_ = [("target", C.c_void_p), ("init_phasor", C.c_void_p), ("field", C.c_void_p), ("codes", C.c_void_p),
+                ("recon", C.c_void_p)]
 
 
 class HoloError(RuntimeError):
@@ -282,6 +289,48 @@ def gs_iterate(target, n_iter: int, lut: Lut | None, cursor: int, init_phasor=No
         fin.ctypes.data_as(C.c_void_p) if fin is not None else None,
         _ptr(recon), FP32, 0, _stream(stream)))
     return {"nmse": nm, "err": er, "nmse_final2": fin, "field": field, "codes": codes, "cursor": int(cur.value)}
+
+
+def gs_iterate_batched(targets, n_iter: int, lut: Lut | None, cursor: int, init_phasors=None, fields=None,
+                       codes=None, recons=None, want_nmse=True, want_err=False, want_final=False, stream=None):
+    """holo_gs_iterate_batched: frames of one size.  targets: list of cuda
+    float32 [ny, nx]; init_phasors/fields: lists of complex64 [ny, nx] or
+    None entries; codes: list of uint8 [ny, nx] (allocated when want_final or
+    recons ask for them); recons: list of float32 [ny, nx] or None entries.
+    Returns dict(nmse [n, n_iter], err [n, n_iter], nmse_final2 [n, 2],
+    fields, codes, cursor)."""
+    import numpy as np
+    n = len(targets)
+    ny, nx = targets[0].shape
+    pick = lambda xs, i: xs[i] if xs is not None else None
+    fields = [pick(fields, i) if pick(fields, i) is not None else
+              torch.empty((ny, nx), dtype=torch.complex64, device=targets[0].device) for i in range(n)]
+    need_codes = want_final or (recons is not None and any(r is not None for r in recons))
+    if codes is None and need_codes:
+        codes = [torch.empty((ny, nx), dtype=torch.uint8, device=targets[0].device) for _ in range(n)]
+    arr = (HoloGsFrame * n)()
+    for i in range(n):
+        t = targets[i]
+        _dev(t, torch.float32, (ny, nx), "target")
+        ip, c, r = pick(init_phasors, i), pick(codes, i), pick(recons, i)
+        if ip is not None:
+            _dev(ip, torch.complex64, (ny, nx), "init_phasor")
+        _dev(fields[i], torch.complex64, (ny, nx), "field")
+        if c is not None:
+            _dev(c, torch.uint8, (ny, nx), "codes")
+        if r is not None:
+            _dev(r, torch.float32, (ny, nx), "recon")
+        arr[i] = HoloGsFrame(t.data_ptr(), ip.data_ptr() if ip is not None else None, fields[i].data_ptr(),
+                             c.data_ptr() if c is not None else None, r.data_ptr() if r is not None else None)
+    nm = np.zeros((n, n_iter)) if want_nmse else None
+    er = np.zeros((n, n_iter)) if want_err else None
+    fin = np.zeros((n, 2)) if want_final else None
+    cur = C.c_uint64(cursor)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
+    _check(lib().holo_gs_iterate_batched(C.cast(arr, C.c_void_p), n, nx, ny, n_iter,
+                                         lut.handle if lut is not None else None, C.byref(cur), ptr(nm), ptr(er),
+                                         ptr(fin), 0, _stream(stream)))
+    return {"nmse": nm, "err": er, "nmse_final2": fin, "fields": fields, "codes": codes, "cursor": int(cur.value)}
 
 
 def gs_iterate_noalloc(target, n_iter: int, lut: Lut | None, cursor: int, init_phasor=None, field=None,

@@ -81,8 +81,18 @@ __global__ __launch_bounds__(P == 16 ? 256 : 512) void k_gs_rows(const float* __
                                                   const float2* __restrict__ init, float2* __restrict__ state,
                                                   float2* __restrict__ field_out, double* __restrict__ partials,
                                                   const GsConsts* __restrict__ consts, const float2* __restrict__ tw,
-                                                  int pitch)
+                                                  int pitch, const GsFrame* __restrict__ gtab, int part_off)
 {
+    if (gtab) {   // grouped launch: this frame's arguments
+        const GsFrame& gf = gtab[blockIdx.y];
+        target = gf.target;
+        c0 = gf.c0;
+        init = gf.init;
+        state = gf.state;
+        field_out = gf.field;
+        partials = (MODE == GS_INIT ? gf.pinit : gf.piter) + part_off;
+        consts = gf.consts;
+    }
     extern __shared__ float2 lds[];
     constexpr int T = NX / P;
     const int rows = blockDim.x / T;
@@ -203,7 +213,7 @@ static int gs_points(int n, int ntrans, int planned)
 hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const PhaseSrc& src, uint64_t c0,
                           const uint64_t* c0_base, const float2* init, float2* state, float2* field_out,
                           double* partials, const GsConsts* consts, const float2* tw_x,
-                          const LaunchCfg& cfg, hipStream_t s)
+                          const LaunchCfg& cfg, hipStream_t s, const GsFrame* gtab, int ngroup, int part_off)
 {
     const int P = gs_points(nx, ny, cfg.pts);
     const int T = nx / P;
@@ -224,19 +234,19 @@ hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const P
             size_t lds = fft_lds > red_lds ? fft_lds : red_lds;
             if (mode == GS_INIT) {
                 allow_lds_g(k_gs_rows<N_, GS_INIT, P_>, lds);
-                hipLaunchKernelGGL((k_gs_rows<N_, GS_INIT, P_>), dim3(ny / rows), dim3(rows * T), lds, s, target,
-                                   ny, src, c0, c0_base, init, state, field_out, partials, consts, tw_x,
-                                   row_pitch(nx, cfg));
+                hipLaunchKernelGGL((k_gs_rows<N_, GS_INIT, P_>), dim3(ny / rows, ngroup), dim3(rows * T), lds, s,
+                                   target, ny, src, c0, c0_base, init, state, field_out, partials, consts, tw_x,
+                                   row_pitch(nx, cfg), gtab, part_off);
             } else if (mode == GS_ITER) {
                 allow_lds_g(k_gs_rows<N_, GS_ITER, P_>, lds);
-                hipLaunchKernelGGL((k_gs_rows<N_, GS_ITER, P_>), dim3(ny / rows), dim3(rows * T), lds, s, target,
-                                   ny, src, c0, c0_base, init, state, field_out, partials, consts, tw_x,
-                                   row_pitch(nx, cfg));
+                hipLaunchKernelGGL((k_gs_rows<N_, GS_ITER, P_>), dim3(ny / rows, ngroup), dim3(rows * T), lds, s,
+                                   target, ny, src, c0, c0_base, init, state, field_out, partials, consts, tw_x,
+                                   row_pitch(nx, cfg), gtab, part_off);
             } else {
                 allow_lds_g(k_gs_rows<N_, GS_FINAL, P_>, lds);
-                hipLaunchKernelGGL((k_gs_rows<N_, GS_FINAL, P_>), dim3(ny / rows), dim3(rows * T), lds, s, target,
-                                   ny, src, c0, c0_base, init, state, field_out, partials, consts, tw_x,
-                                   row_pitch(nx, cfg));
+                hipLaunchKernelGGL((k_gs_rows<N_, GS_FINAL, P_>), dim3(ny / rows, ngroup), dim3(rows * T), lds, s,
+                                   target, ny, src, c0, c0_base, init, state, field_out, partials, consts, tw_x,
+                                   row_pitch(nx, cfg), gtab, part_off);
             }
         }
     }));
@@ -249,8 +259,12 @@ hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const P
 template <int NY, int C, int P>
 __global__ __launch_bounds__(C * (NY / P)) void k_gs_cols(float2* __restrict__ state, int nx,
                                                           uint8_t* __restrict__ codes, const float2* __restrict__ tw,
-                                                          int pitch)
+                                                          int pitch, const GsFrame* __restrict__ gtab)
 {
+    if (gtab) {   // grouped launch: this frame's field (and codes, when asked)
+        state = gtab[blockIdx.y].state;
+        codes = codes ? gtab[blockIdx.y].codes : nullptr;
+    }
     extern __shared__ float2 lds[];
     constexpr int T = NY / P;
     const int c = threadIdx.x % C, t = threadIdx.x / C;
@@ -283,7 +297,7 @@ __global__ __launch_bounds__(C * (NY / P)) void k_gs_cols(float2* __restrict__ s
 }
 
 hipError_t launch_gs_cols(float2* state, int nx, int ny, uint8_t* codes, const float2* tw_y,
-                          const LaunchCfg& cfg, hipStream_t s)
+                          const LaunchCfg& cfg, hipStream_t s, const GsFrame* gtab, int ngroup)
 {
     const int P = gs_points(ny, nx, cfg.pts);
     const int T = ny / P;
@@ -303,8 +317,8 @@ hipError_t launch_gs_cols(float2* state, int nx, int ny, uint8_t* codes, const f
             if (N_ >= P_ && C_ * (N_ / P_) <= 1024) {                                                         \
                 size_t lds = (size_t)C_ * PadLenP<N_, P_>::v * sizeof(float2);                               \
                 allow_lds_g(k_gs_cols<N_, C_, P_>, lds);                                                      \
-                hipLaunchKernelGGL((k_gs_cols<N_, C_, P_>), dim3(nx / C_), dim3(C_ * T), lds, s, state, nx,   \
-                                   codes, tw_y, row_pitch(nx, cfg));                                          \
+                hipLaunchKernelGGL((k_gs_cols<N_, C_, P_>), dim3(nx / C_, ngroup), dim3(C_ * T), lds, s,      \
+                                   state, nx, codes, tw_y, row_pitch(nx, cfg), gtab);                         \
             }                                                                                                 \
         }));                                                                                                  \
     } break;
@@ -325,8 +339,12 @@ hipError_t launch_gs_cols(float2* state, int nx, int ny, uint8_t* codes, const f
 // replay energy (Parseval).
 // -------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_gs_consts(const double* __restrict__ part, int ny, int nx,
-                                                   GsConsts* __restrict__ consts)
+                                                   GsConsts* __restrict__ consts, const GsFrame* __restrict__ gtab)
 {
+    if (gtab) {   // grouped launch: one block per frame
+        part = gtab[blockIdx.x].pinit;
+        consts = gtab[blockIdx.x].consts;
+    }
     __shared__ double red[2 * 8];
     double a[2] = {0.0, 0.0}, out[2];
     for (int r = threadIdx.x; r < ny; r += 256) {
@@ -341,17 +359,25 @@ __global__ __launch_bounds__(256) void k_gs_consts(const double* __restrict__ pa
     }
 }
 
-hipError_t launch_gs_consts(const double* init_partials, int ny, int nx, GsConsts* consts, hipStream_t s)
+hipError_t launch_gs_consts(const double* init_partials, int ny, int nx, GsConsts* consts, hipStream_t s,
+                            const GsFrame* gtab, int ngroup)
 {
-    hipLaunchKernelGGL(k_gs_consts, dim3(1), dim3(256), 0, s, init_partials, ny, nx, consts);
+    hipLaunchKernelGGL(k_gs_consts, dim3(gtab ? ngroup : 1), dim3(256), 0, s, init_partials, ny, nx, consts, gtab);
     return hipGetLastError();
 }
 
 // One block per iteration: NMSE_i = 1 - S_IT^2 / (S_II * S_TT), E_i.
 __global__ __launch_bounds__(256) void k_gs_finalize(const double* __restrict__ part, int ny,
                                                      const GsConsts* __restrict__ consts, double* __restrict__ nmse,
-                                                     double* __restrict__ err)
+                                                     double* __restrict__ err, const GsFrame* __restrict__ gtab)
 {
+    if (gtab) {   // grouped launch: blockIdx.y selects the frame
+        const GsFrame& gf = gtab[blockIdx.y];
+        part = gf.piter;
+        consts = gf.consts;
+        nmse = gf.nmse;
+        err = gf.err;
+    }
     __shared__ double red[3 * 8];
     const int it = blockIdx.x;
     const double* p = part + (size_t)it * ny * 3;
@@ -367,9 +393,10 @@ __global__ __launch_bounds__(256) void k_gs_finalize(const double* __restrict__ 
 }
 
 hipError_t launch_gs_finalize(const double* partials, int n_iter, int ny, const GsConsts* consts,
-                              double* nmse_out, double* err_out, hipStream_t s)
+                              double* nmse_out, double* err_out, hipStream_t s, const GsFrame* gtab, int ngroup)
 {
-    hipLaunchKernelGGL(k_gs_finalize, dim3(n_iter), dim3(256), 0, s, partials, ny, consts, nmse_out, err_out);
+    hipLaunchKernelGGL(k_gs_finalize, dim3(n_iter, gtab ? ngroup : 1), dim3(256), 0, s, partials, ny, consts, nmse_out,
+                       err_out, gtab);
     return hipGetLastError();
 }
 

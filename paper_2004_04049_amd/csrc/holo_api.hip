@@ -682,6 +682,49 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
 
 
 // ---------------------------------------------------------------------------
+// Batched GS: frames of one size iterate together, every pass one launch over
+// the frame table (device memory: owned by the captured graph, or by the call
+// when launched directly).
+// ---------------------------------------------------------------------------
+holo_status gs_enqueue_group(const GsFrame* dtab, const std::vector<GsFrame>& tab,
+                             const std::vector<GsArgs>& args, const std::vector<GsLayout>& L,
+                             const std::vector<size_t>& o_frame, double* f2, int nx, int ny, int n_iter,
+                             const PhaseSrc& src, const uint64_t* dcur, const float2* tw_x, const float2* tw_y,
+                             char* b, const LaunchCfg& cfg, hipStream_t s)
+{
+    const int F = (int)tab.size();
+    bool any_codes = false;
+    for (const GsFrame& g : tab) any_codes = any_codes || g.codes;
+    LAUNCH("gs_rows", s, launch_gs_rows(GS_INIT, nullptr, nx, ny, src, 0, dcur, nullptr, nullptr, nullptr, nullptr,
+                                        nullptr, tw_x, cfg, s, dtab, F, 0));
+    LAUNCH("gs_consts", s, launch_gs_consts(nullptr, ny, nx, nullptr, s, dtab, F));
+    for (int it = 0; it < n_iter; ++it) {
+        const bool last = it == n_iter - 1;
+        // any non-null codes argument asks the grouped pass for every frame's
+        // codes (frames without a codes buffer skip them)
+        uint8_t* want = (last && any_codes) ? reinterpret_cast<uint8_t*>(b) : nullptr;
+        LAUNCH("gs_cols", s, launch_gs_cols(nullptr, nx, ny, want, tw_y, cfg, s, dtab, F));
+        LAUNCH("gs_rows", s, launch_gs_rows(last ? GS_FINAL : GS_ITER, nullptr, nx, ny, src, 0, nullptr, nullptr,
+                                            nullptr, nullptr, nullptr, nullptr, tw_x, cfg, s, dtab, F,
+                                            it * 3 * ny));
+    }
+    LAUNCH("gs_finalize", s, launch_gs_finalize(nullptr, n_iter, ny, nullptr, nullptr, nullptr, s, dtab, F));
+    // the 8-level replay, frame by frame
+    for (int f = 0; f < F; ++f) {
+        const GsArgs& a = args[f];
+        if (!a.codes || (!f2 && !a.recon)) continue;
+        char* bf = b + o_frame[f];
+        float2* x2 = (float2*)(bf + L[f].o_x2);
+        double* p5 = (double*)(bf + L[f].o_p5);
+        double* out2 = f2 ? f2 + 2 * f : (double*)(bf + L[f].o_f2);
+        LAUNCH("recon_cols", s, launch_recon_cols(a.codes, 8, nx, ny, 1, x2, tw_y, cfg, s));
+        LAUNCH("recon_rows", s, launch_recon_rows(x2, nx, ny, 1, false, a.target, a.recon, p5, tw_x, cfg, s));
+        LAUNCH("nmse_finalize", s, launch_nmse_finalize(p5, ny, out2, s));
+    }
+    return HOLO_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Allocation-free GS (holo_gs_iterate_noalloc): the call's scratch lives in a
 // fixed device array of kNoAllocScratch bytes and its twiddle tables in a
 // fixed device table, both static members of the library's code object (each
@@ -1077,6 +1120,167 @@ holo_status holo_gs_iterate(const float* target, int64_t nx, int64_t ny, int32_t
     const LaunchCfg cfg = plan_get(PLAN_GS, nx, ny, 1);
     if ((st = gs_run(device, a, (hipStream_t)hip_stream, cfg))) return st;
     if (!init_phasor) *cursor += (uint64_t)nx * (uint64_t)ny;
+    return HOLO_OK;
+}
+
+holo_status holo_gs_iterate_batched(const holo_gs_frame* frames, int32_t n_frames, int64_t nx, int64_t ny,
+                                    int32_t n_iter, const holo_lut* lut, uint64_t* cursor, double* nmse_per_iter,
+                                    double* err_per_iter, double* nmse_final2, uint32_t flags, void* hip_stream)
+{
+    if (!frames || !cursor) return fail(HOLO_EINVAL, "frames and cursor are required");
+    if (n_frames < 1 || n_frames > 256) return fail(HOLO_EINVAL, "n_frames must be in [1, 256] (got %d)", n_frames);
+    if (n_iter < 1) return fail(HOLO_EINVAL, "n_iter must be >= 1 (got %d)", n_iter);
+    if (!pow2_in_range(nx) || !pow2_in_range(ny))
+        return fail(HOLO_EUNSUPPORTED, "nx, ny must be powers of two in [16, 2048]");
+    int n_pool = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const holo_gs_frame& fr = frames[f];
+        if (!fr.target) return fail(HOLO_EINVAL, "frame %d: target is required", f);
+        if (fr.recon && !fr.codes) return fail(HOLO_EINVAL, "frame %d: recon needs codes", f);
+        if (nmse_final2 && !fr.codes) return fail(HOLO_EINVAL, "frame %d: nmse_final2 needs codes", f);
+        if (!fr.init_phasor) ++n_pool;
+    }
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    holo_status st;
+    if (n_pool) {
+        if ((st = check_lut(lut, device))) return st;
+        if (lut->kind == SRC_MSEQ)
+            return fail(HOLO_EUNSUPPORTED, "holo_gs_iterate_batched: the M-sequence source is not supported");
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    const LaunchCfg cfg = plan_get(PLAN_GS, nx, ny, 1);
+    const float2 *tw_x, *tw_y;
+    if ((st = get_twiddles(device, (int)nx, s, &tw_x))) return st;
+    if ((st = get_twiddles(device, (int)ny, s, &tw_y))) return st;
+    // per-frame layouts (as holo_gs_iterate's), one after another
+    std::vector<GsArgs> args(n_frames);
+    std::vector<GsLayout> L(n_frames);
+    std::vector<size_t> o_frame(n_frames);
+    Carver cv;
+    for (int f = 0; f < n_frames; ++f) {
+        const holo_gs_frame& fr = frames[f];
+        args[f] = GsArgs{fr.target, nx, ny, n_iter, fr.init_phasor ? nullptr : lut, 0, fr.init_phasor, fr.field,
+                         fr.codes, nullptr, nullptr, nullptr, fr.recon, flags};
+        L[f] = gs_layout(args[f], cfg);
+        o_frame[f] = cv.take(L[f].bytes);
+    }
+    const size_t o_cur = cv.take(sizeof(uint64_t));
+    const size_t o_nm = cv.take(sizeof(double) * (size_t)n_frames * n_iter);
+    const size_t o_er = cv.take(sizeof(double) * (size_t)n_frames * n_iter);
+    const size_t o_f2 = cv.take(sizeof(double) * 2 * (size_t)n_frames);
+    void* ws;
+    if ((st = get_workspace(device, s, cv.off, &ws))) return st;
+    char* b = (char*)ws;
+    uint64_t* dcur = (uint64_t*)(b + o_cur);
+    double* nm = (double*)(b + o_nm);
+    double* er = (double*)(b + o_er);
+    double* f2 = nmse_final2 ? (double*)(b + o_f2) : nullptr;
+    std::vector<GsFrame> tab(n_frames);
+    uint64_t pool_off = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const holo_gs_frame& fr = frames[f];
+        char* bf = b + o_frame[f];
+        GsFrame& g = tab[f];
+        g.target = fr.target;
+        g.init = (const float2*)fr.init_phasor;
+        g.state = (float2*)(bf + L[f].o_state);
+        g.field = fr.field ? (float2*)fr.field : (float2*)(bf + L[f].o_field);
+        g.codes = fr.codes;
+        g.pinit = (double*)(bf + L[f].o_pinit);
+        g.piter = (double*)(bf + L[f].o_piter);
+        g.consts = (GsConsts*)(bf + L[f].o_consts);
+        g.nmse = nm + (size_t)f * n_iter;
+        g.err = er + (size_t)f * n_iter;
+        g.c0 = fr.init_phasor ? 0 : lut_wrap(lut, pool_off);
+        if (!fr.init_phasor) pool_off += (uint64_t)nx * (uint64_t)ny;
+    }
+    PhaseSrc src{};
+    src.n = 1;
+    if (n_pool) {
+        src = make_src(lut, nullptr);
+        hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, dcur, lut_wrap(lut, *cursor));
+        HIP_TRY(hipGetLastError());
+    }
+    auto enqueue = [&](const GsFrame* dtab) {
+        return gs_enqueue_group(dtab, tab, args, L, o_frame, f2, (int)nx, (int)ny, n_iter, src, dcur, tw_x, tw_y, b,
+                                cfg, s);
+    };
+    auto new_table = [&](GsFrame** out) -> holo_status {
+        if (hipMalloc((void**)out, sizeof(GsFrame) * tab.size()) != hipSuccess)
+            return fail(HOLO_ENOMEM, "GS frame table (%zu frames)", tab.size());
+        hipError_t me = hipMemcpy(*out, tab.data(), sizeof(GsFrame) * tab.size(), hipMemcpyHostToDevice);
+        if (me != hipSuccess) {
+            (void)hipFree(*out);
+            return fail(HOLO_EDEVICE, "GS frame table: %s", hipGetErrorString(me));
+        }
+        return HOLO_OK;
+    };
+    bool prof_on;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        prof_on = g_prof_on;
+    }
+    if (!g_use_graphs || prof_on || s == nullptr) {
+        GsFrame* dtab = nullptr;
+        if ((st = new_table(&dtab))) return st;
+        st = enqueue(dtab);
+        hipError_t se = hipStreamSynchronize(s);   // the table is read by the launches above
+        (void)hipFree(dtab);
+        if (st) return st;
+        if (se != hipSuccess) return fail(HOLO_EDEVICE, "batched GS: %s", hipGetErrorString(se));
+    } else {
+        GraphKey key;
+        key.k = {(uintptr_t)0x65B7, (uintptr_t)device, (uintptr_t)s, (uintptr_t)ws, (uintptr_t)nx, (uintptr_t)ny,
+                 (uintptr_t)n_iter, (uintptr_t)(n_pool ? lut->id : 0), (uintptr_t)(f2 != nullptr),
+                 (uintptr_t)cfg.cols_per_block, (uintptr_t)cfg.rows_per_block, (uintptr_t)(intptr_t)cfg.pad,
+                 (uintptr_t)cfg.pts, (uintptr_t)n_frames};
+        for (int f = 0; f < n_frames; ++f)
+            key.k.insert(key.k.end(), {(uintptr_t)frames[f].target, (uintptr_t)frames[f].init_phasor,
+                                       (uintptr_t)frames[f].field, (uintptr_t)frames[f].codes,
+                                       (uintptr_t)frames[f].recon});
+        hipGraphExec_t exec = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_graph_mu);
+            auto it = g_graphs.find(key);
+            if (it != g_graphs.end()) exec = it->second;
+        }
+        if (!exec) {
+            GsFrame* dtab = nullptr;
+            if ((st = new_table(&dtab))) return st;
+            hipGraph_t graph = nullptr;
+            hipError_t be = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (be != hipSuccess) {
+                (void)hipFree(dtab);
+                return fail(HOLO_EDEVICE, "batched GS graph capture: %s", hipGetErrorString(be));
+            }
+            holo_status est = enqueue(dtab);
+            hipError_t ce = hipStreamEndCapture(s, &graph);
+            if (est || ce != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                (void)hipFree(dtab);
+                if (est) return est;
+                return fail(HOLO_EDEVICE, "batched GS graph capture: %s", hipGetErrorString(ce));
+            }
+            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) {
+                (void)hipFree(dtab);
+                return fail(HOLO_EDEVICE, "batched GS graph instantiate: %s", hipGetErrorString(ie));
+            }
+            std::lock_guard<std::mutex> lk(g_graph_mu);
+            g_graphs[key] = exec;
+            g_graph_bufs[key] = dtab;
+            g_graph_order.push_back(key);
+            graph_trim_locked(s);
+        }
+        DEBUG_FAIL_CHECK("graph");
+        HIP_TRY(hipGraphLaunch(exec, s));
+    }
+    if (f2 && (st = copy_out(nmse_final2, f2, 2 * (size_t)n_frames, flags, s))) return st;
+    if ((st = copy_out(nmse_per_iter, nm, (size_t)n_frames * n_iter, flags, s))) return st;
+    if ((st = copy_out(err_per_iter, er, (size_t)n_frames * n_iter, flags, s))) return st;
+    *cursor += (uint64_t)n_pool * (uint64_t)nx * (uint64_t)ny;
     return HOLO_OK;
 }
 

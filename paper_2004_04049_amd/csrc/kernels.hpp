@@ -137,15 +137,37 @@ enum GsRowMode { GS_INIT = 0, GS_ITER = 1, GS_FINAL = 2 };
 struct GsConsts {
     double sum_t2, sum_t4, te_scale;
 };
-// GS_INIT reads the pool at c0 + *c0_base (c0_base may be NULL).
+// One frame of a grouped GS launch (frames of one size iterate together,
+// blockIdx.y -- blockIdx.x for the one-block-per-frame kernels -- selecting
+// the frame); the per-frame arguments of the launchers below come from here.
+struct GsFrame {
+    const float* target;
+    const float2* init;    // caller seed phasors, or null (pool seed)
+    float2* state;         // [ny][pitch] working field
+    float2* field;         // unitary replay field out [ny][nx]
+    uint8_t* codes;        // 8-level codes out, or null
+    double* pinit;         // [ny][2] INIT partials
+    double* piter;         // [n_iter][ny][3] iteration partials
+    GsConsts* consts;
+    double* nmse;          // [n_iter], or null
+    double* err;           // [n_iter], or null
+    uint64_t c0;           // pool offset of the frame (reduced)
+};
+// GS_INIT reads the pool at c0 + *c0_base (c0_base may be NULL).  gtab: a
+// grouped launch of `ngroup` frames; `part_off` then offsets the frame's
+// partials (iteration it: it * 3 * ny).
 hipError_t launch_gs_rows(int mode, const float* target, int nx, int ny, const PhaseSrc& src, uint64_t c0,
                           const uint64_t* c0_base, const float2* init, float2* state, float2* field_out,
                           double* partials, const GsConsts* consts, const float2* tw_x,
-                          const LaunchCfg& cfg, hipStream_t s);
+                          const LaunchCfg& cfg, hipStream_t s, const GsFrame* gtab = nullptr, int ngroup = 1,
+                          int part_off = 0);
+// gtab: grouped launch; with it, codes != null asks for every frame's codes.
 hipError_t launch_gs_cols(float2* state, int nx, int ny, uint8_t* codes, const float2* tw_y,
-                          const LaunchCfg& cfg, hipStream_t s);
-hipError_t launch_gs_consts(const double* init_partials, int ny, int nx, GsConsts* consts, hipStream_t s);
+                          const LaunchCfg& cfg, hipStream_t s, const GsFrame* gtab = nullptr, int ngroup = 1);
+hipError_t launch_gs_consts(const double* init_partials, int ny, int nx, GsConsts* consts, hipStream_t s,
+                            const GsFrame* gtab = nullptr, int ngroup = 1);
 hipError_t launch_gs_finalize(const double* partials, int n_iter, int ny, const GsConsts* consts,
-                              double* nmse_out, double* err_out, hipStream_t s);
+                              double* nmse_out, double* err_out, hipStream_t s, const GsFrame* gtab = nullptr,
+                              int ngroup = 1);
 
 }  // namespace holo

@@ -136,3 +136,22 @@ def test_plan_for_every_subframe_count(lib):
     finally:
         h.plan_set(h.PLAN_OSPR, 512, 256, 0, h.DEFAULT_PLAN)
         h.plan_set(h.PLAN_OSPR, 512, 256, 7, h.DEFAULT_PLAN)
+
+
+def test_batched_gs_invalid_arguments(lib):
+    import paper_2004_04049_amd as h
+    cur = C.c_uint64(0)
+    fake = C.c_void_p(16)
+    fr = (h.HoloGsFrame * 2)()
+    fr[0] = h.HoloGsFrame(16, None, None, None, None)
+    fr[1] = h.HoloGsFrame(None, None, None, None, None)
+    arr = C.cast(fr, C.c_void_p)
+    assert lib.holo_gs_iterate_batched(None, 1, 64, 64, 3, fake, C.byref(cur), None, None, None, 0, None) == h.HOLO_EINVAL
+    assert lib.holo_gs_iterate_batched(arr, 0, 64, 64, 3, fake, C.byref(cur), None, None, None, 0, None) == h.HOLO_EINVAL
+    assert lib.holo_gs_iterate_batched(arr, 1, 64, 64, 0, fake, C.byref(cur), None, None, None, 0, None) == h.HOLO_EINVAL
+    assert lib.holo_gs_iterate_batched(arr, 2, 64, 64, 3, fake, C.byref(cur), None, None, None, 0, None) == h.HOLO_EINVAL
+    assert b"frame 1" in lib.holo_last_error()
+    fr[1] = h.HoloGsFrame(16, None, None, None, 16)     # recon without codes
+    assert lib.holo_gs_iterate_batched(arr, 2, 64, 64, 3, fake, C.byref(cur), None, None, None, 0, None) == h.HOLO_EINVAL
+    assert lib.holo_gs_iterate_batched(arr, 1, 100, 64, 3, fake, C.byref(cur), None, None, None, 0, None) == \
+        h.HOLO_EUNSUPPORTED
