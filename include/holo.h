@@ -314,10 +314,9 @@ HOLO_API holo_status holo_reconstruct_nmse(const void* holo, int32_t levels, int
  * no re-capture.  In the graph, binary frames drawn from the table, code or
  * PRNG sources are grouped: frames of one size and launch plan run each pass
  * (row pass, column pass, reconstruction, NMSE) as one launch over up to
- * 64 MiB of half planes, every frame with planes of its own (the workspace
- * then holds about 8 bytes per pixel and sub-frame of the batch, plus the
- * frame table that lives with the graph); other frames run their own
- * launches.  Units run on four concurrent branches, longest first.  Results
+ * 64 MiB of half planes, every frame with planes of its own within its
+ * unit, the units of a branch reusing one region (plus a frame table that
+ * lives with the graph); other frames run their own launches.  Units run on four concurrent branches, longest first.  Results
  * equal the single-frame calls bit for bit either way.  On the legacy default
  * stream, or while kernel timing is on, the frames are launched one by one
  * directly instead.

@@ -1493,12 +1493,27 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
     Carver cv;
     std::vector<size_t> o_branch(nb), o_x1(n_frames), o_x2(n_frames), o_part(n_frames);
     if (grouped) {
-        for (int f = 0; f < n_frames; ++f) {
-            const size_t plane = (size_t)(frames[f].ny / 2 + 1) * (size_t)row_pitch((int)frames[f].nx, cfg[f]);
-            o_x1[f] = cv.take(sizeof(float2) * plane * (size_t)frames[f].n_sf);
-            o_x2[f] = cv.take(sizeof(float2) * plane * (size_t)frames[f].n_sf);
-            o_part[f] = cv.take(sizeof(double) * 5 * (size_t)(frames[f].ny / 2 + 1));
+        // a unit's frames get planes of their own, at offsets within the unit;
+        // the units of one branch run one after another and reuse one region
+        // (sized for the branch's largest unit), which also keeps a branch's
+        // planes warm in the last-level cache from one unit to the next
+        for (int u = 0; u < nu; ++u) {
+            Carver cu;
+            for (int f : units[u]) {
+                const size_t plane = (size_t)(frames[f].ny / 2 + 1) * (size_t)row_pitch((int)frames[f].nx, cfg[f]);
+                o_x1[f] = cu.take(sizeof(float2) * plane * (size_t)frames[f].n_sf);
+                o_x2[f] = cu.take(sizeof(float2) * plane * (size_t)frames[f].n_sf);
+                o_part[f] = cu.take(sizeof(double) * 5 * (size_t)(frames[f].ny / 2 + 1));
+            }
+            bbytes[branch[u]] = std::max(bbytes[branch[u]], cu.off);
         }
+        for (int i = 0; i < nb; ++i) o_branch[i] = cv.take(bbytes[i]);
+        for (int u = 0; u < nu; ++u)
+            for (int f : units[u]) {
+                o_x1[f] += o_branch[branch[u]];
+                o_x2[f] += o_branch[branch[u]];
+                o_part[f] += o_branch[branch[u]];
+            }
     } else {
         for (int i = 0; i < nb; ++i) o_branch[i] = cv.take(bbytes[i]);
     }
