@@ -122,6 +122,23 @@ def measured_traffic(kernel, workload, sf_per_launch):
         return None
 
 
+def measured_batch_traffic(prec, design_bytes):
+    """HBM bytes per call of the 64-frame batch (one precision) from the
+    committed rocprofv3 --pmc summary, if it was taken on the current kernel
+    sources and the same batch layout; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        with open(p) as f:
+            e = json.load(f).get("batched_64frames", {}).get(prec)
+        if not e or e.get("source_hash") != source_hash() or e.get("design_bytes") != int(design_bytes):
+            return None
+        return e
+    except Exception:
+        return None
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -298,6 +315,12 @@ def bench_batched(h, synth, torch, dev):
         r = {"ms_per_batch": round(1e3 * dt, 3), "px_subframes_per_s": round(pxsf / dt, 1),
              "hbm_frac": round(design / dt / 1e9 / HBM_PEAK_GBS, 4),
              "canonical_frac": round(canon / dt / 1e9 / HBM_PEAK_GBS, 4), "nmse_mean": float(out_nm[:, 0].mean())}
+        tr = measured_batch_traffic(name, design)
+        if tr:   # measured bytes per batch (profiled plans) over this run's batch time
+            r["traffic"] = tr["bytes_per_batch"]
+            r["traffic_frac"] = round(tr["bytes_per_batch"] / dt / 1e9 / HBM_PEAK_GBS, 4)
+            r["traffic_vs_design"] = round(tr["bytes_per_batch"] / design, 4)
+            r["traffic_plans_match"] = tr.get("plans") == plans
         if ref is None:
             ref = (out_bits, out_nm, out_rec)
         else:

@@ -80,3 +80,33 @@ def test_design_bytes_half_planes():
         rec = json.load(f)
     e = rec["ospr_1024x1024_sf24_lut65536"]["ospr_cols"]
     assert abs(e["bytes_per_launch"] / db["ospr_cols"] - 1) <= bench.TRAFFIC_MARGIN
+
+
+def test_measured_batch_traffic_gating(tmp_path, monkeypatch):
+    (tmp_path / "profiles").mkdir()
+    h = bench.source_hash()
+    rec = {"batched_64frames": {"fp32": {"bytes_per_batch": 7, "fetch_bytes": 4, "write_bytes": 3,
+                                         "design_bytes": 100, "plans": {}, "source_hash": h, "frames": 64}}}
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_hash", lambda: h)
+    assert bench.measured_batch_traffic("fp32", 100)["bytes_per_batch"] == 7
+    assert bench.measured_batch_traffic("fp32", 101) is None           # another batch layout
+    assert bench.measured_batch_traffic("bf16", 100) is None           # not profiled
+    monkeypatch.setattr(bench, "source_hash", lambda: "0" * 16)        # sources changed
+    assert bench.measured_batch_traffic("fp32", 100) is None
+
+
+def test_committed_batch_traffic_matches_the_benchmark_batch():
+    # the committed batch record was taken on the benchmark's 64-frame layout
+    import synth
+    design = sum(sum(bench.ospr_design_bytes(n, n, k, 10007).values())
+                 for n, k in synth.batch_layout(64, synth.SEED_BATCH))
+    with open(bench.os.path.join(bench.ROOT, "profiles", "traffic.json")) as f:
+        rec = json.load(f)["batched_64frames"]
+    assert set(rec) == {"fp32", "bf16", "fp16"}
+    for e in rec.values():
+        assert e["design_bytes"] == int(design) and e["frames"] == 64
+        assert abs(e["bytes_per_batch"] - e["fetch_bytes"] - e["write_bytes"]) <= 1
+        # measured bytes within 10% of the design bytes (row pitch, re-reads)
+        assert 1.0 <= e["bytes_per_batch"] / design < 1.1
