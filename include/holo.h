@@ -414,9 +414,9 @@ HOLO_API holo_status holo_phase_mask(const holo_lut* lut, uint64_t cursor, int64
  * field offers few transforms; the heuristic and the autotuner use 8 or 16
  * only, as 4 rounds more often); OSPR row, column and reconstruction-row
  * passes all 16 (radix-16 stages, then one radix-2/4/8 stage) or all 8
- * (radix-8 stages, then one radix-2/4 stage), or 0: 8 for the row pass and
- * for transforms of up to 512 points, 16 for longer column and
- * reconstruction transforms (FP32 only: the BF16/FP16 forms take 16;
+ * (radix-8 stages, then one radix-2/4 stage), or 0: 8 for the row pass,
+ * for column transforms of up to 1024 points and for reconstruction
+ * transforms of up to 512, 16 for longer ones (FP32 only: the BF16/FP16 forms take 16;
  * 2048-point columns at 8 points per thread use 8-column tiles).  Plans
  * are keyed by kind (0 = OSPR, 1 = GS), nx, ny and n_sf (ignored for GS); an
  * OSPR plan set with n_sf = 0 serves every sub-frame count of that size that

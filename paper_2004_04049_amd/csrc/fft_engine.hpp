@@ -140,45 +140,51 @@ struct PadLenP { static constexpr int v = N + N / P; };
 // the two chained transforms; 2048-point columns need 1024 to hold 8 columns.
 __host__ __device__ constexpr int col_bound(int n) { return n >= 2048 ? 1024 : 512; }
 
-// One transform of length N on T = N/16 threads.  `v` holds slot m = element
-// t + T*m on entry and on exit.  LDS addressing is abstracted by `addr(e)` so
-// row (one transform per LDS row) and column (C interleaved transforms) layouts
-// share the engine.  `tw` is the FP32 table W_N^k; SIGN = -1 for Eq. (1),
-// +1 for Eq. (2).  Contains __syncthreads(): every thread of the block must
-// call it the same number of times.
 // u[r] *= W^(step*r) for r = 1..R-1 (conjugated for the inverse kernel),
-// where W^k = tw[k] = exp(-2*pi*i*k/N).  Radix 16 loads W^s, W^2s, W^3s and
+// where W^k = tw[k] = exp(-2*pi*i*k/N).  Radix 16 reads W^s, W^2s, W^3s and
 // W^4s, W^8s, W^12s and forms the other nine as W^4as * W^bs (one FP32 product
-// of two correctly rounded table values); radix 8 loads four and forms three.
-// Fewer table loads keep register pressure and vector-memory traffic low.
+// of two correctly rounded table values); radix 8 reads four and forms three.
+// Fewer table reads keep register pressure and vector-memory traffic low.
+__host__ __device__ constexpr int tw_count(int R) { return R == 16 ? 6 : R == 8 ? 4 : R == 4 ? 3 : 1; }
+
+// The tw_count(R) table values of one butterfly with twiddle step `step`:
+// W^s, then W^2s, W^3s (radix >= 4), W^4s (radix >= 8), W^8s, W^12s (radix 16).
+template <int R>
+__device__ __forceinline__ void read_twiddles(float2* wl, const float2* __restrict__ tw, int step)
+{
+    wl[0] = tw[step];
+    if (R >= 4) {
+        wl[1] = tw[2 * step];
+        wl[2] = tw[3 * step];
+    }
+    if (R >= 8) wl[3] = tw[4 * step];
+    if (R == 16) {
+        wl[4] = tw[8 * step];
+        wl[5] = tw[12 * step];
+    }
+}
+
 template <int R, int SIGN>
-__device__ __forceinline__ void apply_twiddles(float2 (&u)[R], const float2* __restrict__ tw, int step)
+__device__ __forceinline__ void apply_read_twiddles(float2 (&u)[R], const float2* wl)
 {
     auto mul = [](float2 x, float2 w) { return SIGN < 0 ? cmul(x, w) : cmulc(x, w); };
     if (R == 2) {
-        u[1] = mul(u[1], tw[step]);
+        u[1] = mul(u[1], wl[0]);
     } else if (R == 4) {
-        const float2 w1 = tw[step], w2 = tw[2 * step], w3 = tw[3 * step];
-        u[1] = mul(u[1], w1);
-        u[2] = mul(u[2], w2);
-        u[3] = mul(u[3], w3);
+        u[1] = mul(u[1], wl[0]);
+        u[2] = mul(u[2], wl[1]);
+        u[3] = mul(u[3], wl[2]);
     } else if (R == 8) {
-        const float2 w1 = tw[step], w2 = tw[2 * step], w3 = tw[3 * step], w4 = tw[4 * step];
-        u[1] = mul(u[1], w1);
-        u[2] = mul(u[2], w2);
-        u[3] = mul(u[3], w3);
-        u[4] = mul(u[4], w4);
-        u[5] = mul(u[5], cmul(w4, w1));
-        u[6] = mul(u[6], cmul(w4, w2));
-        u[7] = mul(u[7], cmul(w4, w3));
+        u[1] = mul(u[1], wl[0]);
+        u[2] = mul(u[2], wl[1]);
+        u[3] = mul(u[3], wl[2]);
+        u[4] = mul(u[4], wl[3]);
+        u[5] = mul(u[5], cmul(wl[3], wl[0]));
+        u[6] = mul(u[6], cmul(wl[3], wl[1]));
+        u[7] = mul(u[7], cmul(wl[3], wl[2]));
     } else {
-        float2 wb[4], wa[4];
-        wb[1] = tw[step];
-        wb[2] = tw[2 * step];
-        wb[3] = tw[3 * step];
-        wa[1] = tw[4 * step];
-        wa[2] = tw[8 * step];
-        wa[3] = tw[12 * step];
+        const float2 wb[4] = {make_float2(1.0f, 0.0f), wl[0], wl[1], wl[2]};
+        const float2 wa[4] = {make_float2(1.0f, 0.0f), wl[3], wl[4], wl[5]};
 #pragma unroll
         for (int b = 1; b < 4; ++b) u[b] = mul(u[b], wb[b]);
 #pragma unroll
@@ -190,10 +196,74 @@ __device__ __forceinline__ void apply_twiddles(float2 (&u)[R], const float2* __r
     }
 }
 
+template <int R, int SIGN>
+__device__ __forceinline__ void apply_twiddles(float2 (&u)[R], const float2* __restrict__ tw, int step)
+{
+    float2 wl[tw_count(R)];
+    read_twiddles<R>(wl, tw, step);
+    apply_read_twiddles<R, SIGN>(u, wl);
+}
+
+// Stage shape of a length-N transform with P points per thread: radix-P
+// stages while P divides the remaining length, then one radix 2^REM stage.
+template <int N, int P>
+struct StageShape {
+    static constexpr int L = ilog2<N>::v;
+    static constexpr int LP = ilog2<P>::v;
+    static constexpr int NSP = L / LP;
+    static constexpr int REM = L % LP;
+    static constexpr int NSTAGE = NSP + (REM ? 1 : 0);
+    static constexpr int radix(int s) { return s < NSP ? P : (1 << REM); }
+    // table values a thread reads over stages 1..NSTAGE-1 (stage 0 has none)
+    static constexpr int tw_total()
+    {
+        int c = 0;
+        for (int s = 1; s < NSTAGE; ++s) c += (P / radix(s)) * tw_count(radix(s));
+        return c;
+    }
+};
+
+// The table twiddles of one thread's butterflies over a whole transform, read
+// once and kept in registers, for threads that run several transforms of the
+// same length and direction set (over sub-frames, or a forward transform and
+// its inverse): those transforms then wait on no table reads.  The products
+// formed from them are the ones the table path forms, so results are
+// bit-identical to it.
+template <int N, int P>
+struct TwRegs {
+    using S = StageShape<N, P>;
+    float2 w[S::tw_total() > 0 ? S::tw_total() : 1];
+    __device__ __forceinline__ void read(const float2* __restrict__ tw, int t)
+    {
+        constexpr int T = N / P;
+        int slot = 0, Ns = 1;
+#pragma unroll
+        for (int s = 0; s < S::NSTAGE; ++s) {
+            const int R = S::radix(s);
+            const int nb = P / R;
+            if (s > 0) {
+#pragma unroll
+                for (int b = 0; b < nb; ++b) {
+                    const int j = t + b * T;
+                    const int step = (j & (Ns - 1)) * (N / (Ns * R));
+                    float2* d = w + slot + b * tw_count(R);
+                    if (R == 16) read_twiddles<16>(d, tw, step);
+                    else if (R == 8) read_twiddles<8>(d, tw, step);
+                    else if (R == 4) read_twiddles<4>(d, tw, step);
+                    else read_twiddles<2>(d, tw, step);
+                }
+                slot += nb * tw_count(R);
+            }
+            Ns *= R;
+        }
+    }
+};
+
 // One radix-R stage on butterfly b of thread t (slots b + r*P/R).
+// `pre`, when given, holds this butterfly's table values (TwRegs).
 template <int N, int R, int SIGN, int P = kP>
 __device__ __forceinline__ void stage_butterfly(float2 (&v)[P], int t, int b, int Ns,
-                                                const float2* __restrict__ tw)
+                                                const float2* __restrict__ tw, const float2* pre = nullptr)
 {
     constexpr int T = N / P;
     constexpr int nb = P / R;
@@ -201,7 +271,10 @@ __device__ __forceinline__ void stage_butterfly(float2 (&v)[P], int t, int b, in
     float2 u[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[b + r * nb];
-    if (Ns > 1) apply_twiddles<R, SIGN>(u, tw, (j & (Ns - 1)) * (N / (Ns * R)));
+    if (Ns > 1) {
+        if (pre) apply_read_twiddles<R, SIGN>(u, pre);
+        else apply_twiddles<R, SIGN>(u, tw, (j & (Ns - 1)) * (N / (Ns * R)));
+    }
     dft_small<R, SIGN>(u);
 #pragma unroll
     for (int r = 0; r < R; ++r) v[b + r * nb] = u[r];
@@ -230,19 +303,18 @@ __device__ __forceinline__ void exchange_sync()
     }
 }
 
+// `pre` (optional): the thread's table twiddles read by TwRegs<N, P>::read.
 template <int N, int SIGN, typename Addr, bool WAVE_LOCAL = false, int P = kP>
 __device__ __forceinline__ void fft_stages(float2 (&v)[P], int t, float2* lds, Addr addr,
-                                           const float2* __restrict__ tw)
+                                           const float2* __restrict__ tw, const float2* pre = nullptr)
 {
     static_assert(P == 4 || P == 8 || P == 16, "points per thread");
     constexpr int T = N / P;
-    constexpr int L = ilog2<N>::v;
-    constexpr int LP = ilog2<P>::v;
-    constexpr int NSP = L / LP;          // radix-P stages
-    constexpr int REM = L % LP;          // bits left for the last small stage
-    constexpr int NSTAGE = NSP + (REM ? 1 : 0);
+    constexpr int NSP = StageShape<N, P>::NSP;        // radix-P stages
+    constexpr int REM = StageShape<N, P>::REM;        // bits left for the last small stage
+    constexpr int NSTAGE = StageShape<N, P>::NSTAGE;
     auto pad = [](int e) { return P == 16 ? lds_pad(e) : lds_pad_p<P>(e); };
-    int Ns = 1;
+    int Ns = 1, slot = 0;
 #pragma unroll
     for (int s = 0; s < NSTAGE; ++s) {
         const bool last = (s == NSTAGE - 1);
@@ -250,11 +322,13 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[P], int t, float2* lds, A
         const int nb = P / R;
 #pragma unroll
         for (int b = 0; b < nb; ++b) {
-            if (R == 16) stage_butterfly<N, 16, SIGN, P>(v, t, b, Ns, tw);
-            else if (R == 8) stage_butterfly<N, 8, SIGN, P>(v, t, b, Ns, tw);
-            else if (R == 4) stage_butterfly<N, 4, SIGN, P>(v, t, b, Ns, tw);
-            else stage_butterfly<N, 2, SIGN, P>(v, t, b, Ns, tw);
+            const float2* pb = (pre && s > 0) ? pre + slot + b * tw_count(R) : nullptr;
+            if (R == 16) stage_butterfly<N, 16, SIGN, P>(v, t, b, Ns, tw, pb);
+            else if (R == 8) stage_butterfly<N, 8, SIGN, P>(v, t, b, Ns, tw, pb);
+            else if (R == 4) stage_butterfly<N, 4, SIGN, P>(v, t, b, Ns, tw, pb);
+            else stage_butterfly<N, 2, SIGN, P>(v, t, b, Ns, tw, pb);
         }
+        if (s > 0) slot += nb * tw_count(R);
         if (!last) {
             // exchange: write outputs at their Stockham positions, read back the
             // t + T*m set for the next stage.  Addresses are padded indices

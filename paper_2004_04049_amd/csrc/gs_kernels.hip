@@ -149,7 +149,14 @@ __global__ __launch_bounds__(P == 16 ? 256 : 512) void k_gs_rows(const float* __
     const uint32_t soff = ((uint32_t)y * (uint32_t)pitch + (uint32_t)t) * 8u;
 #pragma unroll
     for (int m = 0; m < P; ++m) v[m] = buf_ld2(rs, soff, (uint32_t)(m * T * 8));
-    fft_stages<NX, -1, RowAddrG, (NX / P <= 64), P>(v, t, lds, RowAddrG{row * PadLenP<NX, P>::v}, tw);
+    // an iteration's forward and inverse row transforms share one read of
+    // the table twiddles (at 8 points per thread and up to 1024 points; at 16
+    // points the registers are spent, at 2048 the values would go to scratch)
+    constexpr bool kPre = MODE == GS_ITER && P == 8 && NX <= 1024;
+    TwRegs<NX, P> twr;
+    if constexpr (kPre) twr.read(tw, t);
+    const float2* pre = kPre ? twr.w : nullptr;
+    fft_stages<NX, -1, RowAddrG, (NX / P <= 64), P>(v, t, lds, RowAddrG{row * PadLenP<NX, P>::v}, tw, pre);
     // R' (unscaled) = sqrt(N) * R'_unitary; intensity in unitary units
     const float inv_n = 1.0f / (float)((size_t)NX * (size_t)ny);
     const float inv_sqrt_n = (float)(1.0 / sqrt((double)NX * (double)ny));
@@ -177,7 +184,7 @@ __global__ __launch_bounds__(P == 16 ? 256 : 512) void k_gs_rows(const float* __
             const float k = ta[m] * rsqrtf(m2);   // T / |R'|
             v[m] = m2 > 0.0f ? make_float2(k * v[m].x, k * v[m].y) : make_float2(ta[m], 0.0f);
         }
-        fft_stages<NX, 1, RowAddrG, (NX / P <= 64), P>(v, t, lds, RowAddrG{row * PadLenP<NX, P>::v}, tw);
+        fft_stages<NX, 1, RowAddrG, (NX / P <= 64), P>(v, t, lds, RowAddrG{row * PadLenP<NX, P>::v}, tw, pre);
 #pragma unroll
         for (int m = 0; m < P; ++m) buf_st2(rs, soff, (uint32_t)(m * T * 8), v[m]);
     }
@@ -277,7 +284,13 @@ __global__ __launch_bounds__(C * (NY / P)) void k_gs_cols(float2* __restrict__ s
     float2 v[P];
 #pragma unroll
     for (int m = 0; m < P; ++m) v[m] = buf_ld2(rs, toff, m * mst);
-    fft_stages<NY, 1, ColAddr<C>, false, P>(v, t, lds, ColAddr<C>{c}, tw);
+    // one read of the table twiddles for both transforms (at 8 points per
+    // thread and up to 1024 points, as in the rows pass)
+    constexpr bool kPre = P == 8 && NY <= 1024;
+    TwRegs<NY, P> twr;
+    if constexpr (kPre) twr.read(tw, t);
+    const float2* pre = kPre ? twr.w : nullptr;
+    fft_stages<NY, 1, ColAddr<C>, false, P>(v, t, lds, ColAddr<C>{c}, tw, pre);
     if (codes) {
         const auto rc = make_rsrc(codes, (uint32_t)((size_t)NY * nx));
         const uint32_t coff = (uint32_t)t * (uint32_t)nx + (uint32_t)(x0 + c);
@@ -291,7 +304,7 @@ __global__ __launch_bounds__(C * (NY / P)) void k_gs_cols(float2* __restrict__ s
         const float k = rsqrtf(m2);   // 1 / |H|
         v[m] = m2 > 0.0f ? make_float2(k * v[m].x, k * v[m].y) : make_float2(1.0f, 0.0f);
     }
-    fft_stages<NY, -1, ColAddr<C>, false, P>(v, t, lds, ColAddr<C>{c}, tw);
+    fft_stages<NY, -1, ColAddr<C>, false, P>(v, t, lds, ColAddr<C>{c}, tw, pre);
 #pragma unroll
     for (int m = 0; m < P; ++m) buf_st2(rs, toff, m * mst, v[m]);
 }

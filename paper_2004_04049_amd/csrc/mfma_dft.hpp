@@ -250,13 +250,15 @@ __device__ __forceinline__ void fft_stages_mc(float2 (&v)[kP], int t, float2* ld
 // stage stay FP32 on the vector ALUs).  `addr` is the calling thread's LDS
 // addressing (padded as the engine with PT points per thread pads).  With
 // PREC > 0 every lane of each wave must take part (blocks of whole waves, no
-// divergence around the call).
+// divergence around the call).  `pre` (FP32 only, optional): the thread's
+// table twiddles from TwRegs<N, PT>::read.
 template <int N, int SIGN, int PREC, bool WAVE_LOCAL = false, int PT = kP, typename Addr>
 __device__ __forceinline__ void fft_any(float2 (&v)[PT], int t, float2* lds, Addr addr,
-                                        const float2* __restrict__ tw, const uint4* __restrict__ dftop)
+                                        const float2* __restrict__ tw, const uint4* __restrict__ dftop,
+                                        const float2* pre = nullptr)
 {
     if constexpr (PREC == 0) {
-        fft_stages<N, SIGN, Addr, WAVE_LOCAL, PT>(v, t, lds, addr, tw);
+        fft_stages<N, SIGN, Addr, WAVE_LOCAL, PT>(v, t, lds, addr, tw, pre);
     } else {
         static_assert(PT == kP, "the matrix-core transforms take 16 points per thread");
         fft_stages_mc<N, SIGN, PREC, Addr, WAVE_LOCAL>(v, t, lds, addr, tw, dftop);

@@ -70,15 +70,15 @@ namespace holo {
     }
 // The plan's points per thread (8 or 16 for all three passes), or else per
 // pass (0 = generation rows, 1 = generation columns, 2 = reconstruction rows)
-// and transform length n: 8 for the generation rows and for lengths up to
-// 512, 16 above (FP32, 24 sub-frames, 1024^2: rows 40.1 against 41.5 us,
-// columns 57.0 against 53.6, reconstruction 42.5 against 36.4; 512^2: 16.8 /
-// 18.6 / 22.2 against 20.9 / 20.9 / 26.2 us).
+// and transform length n: 8 for the generation rows, for the generation
+// columns up to 1024 points and for the reconstruction rows up to 512; 16
+// above (FP32, 24 sub-frames, 1024^2: rows 34.5 against 36.4 us, columns 48.3
+// against 50.4, reconstruction 41.0 against 35.9).
 static int plan_pts(const LaunchCfg& c, int pass, int n)
 {
     if (c.prec != 0) return kP;
     if (c.pts == 8 || c.pts == kP) return c.pts;
-    return (pass == 0 || n <= 512) ? 8 : kP;
+    return (pass == 0 || n <= (pass == 1 ? 1024 : 512)) ? 8 : kP;
 }
 
 // Column-tile width C (columns transformed side by side by one block).
@@ -435,6 +435,11 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(3
     }
     const bool mseq = src.kind == SRC_MSEQ;
     const bool t0 = t == 0;
+    // FP32 at 8 points per thread: the row transforms' table twiddles are read
+    // once for all of the block's sub-frames (at 16 the registers are spent)
+    constexpr bool kPre = P == 0 && PT == 8 && NX <= 1024;
+    TwRegs<NX, PT> twr;
+    if constexpr (kPre) twr.read(tw, t);
     const size_t plane = (size_t)nh * pitch;
     const uint32_t ooff = ((uint32_t)y * (uint32_t)pitch + (uint32_t)t) * 8u;
     const int k_end = min(n_sf, (kb + 1) * spb);
@@ -454,7 +459,8 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(3
             // R(x, y) + conj R(-x, -y)
             v[m] = make_float2(fmaf(a[m], v[m].x, bm * wm.x), fmaf(a[m], v[m].y, -bm * wm.y));
         }
-        fft_any<NX, 1, P, (NX / PT <= 64), PT>(v, t, lds, RowAddrR{row * PadLenP<NX, PT>::v}, tw, dftop);
+        fft_any<NX, 1, P, (NX / PT <= 64), PT>(v, t, lds, RowAddrR{row * PadLenP<NX, PT>::v}, tw, dftop,
+                                               kPre ? twr.w : nullptr);
         if (yr < nh) {
             const auto ro = make_rsrc(x1 + (size_t)k * plane, (uint32_t)(plane * 8));
 #pragma unroll
@@ -570,7 +576,13 @@ __global__ __launch_bounds__((C / 2) * (NY / PT)) __attribute__((amdgpu_waves_pe
             v[PT / 2] = make_float2(cd.x, cd.z);
         }
     }
-    fft_any<NY, 1, P, false, PT>(v, t, lds, ColAddr<CP>{q}, tw, dftop);
+    // FP32 at 8 points per thread: one read of the table twiddles serves both
+    // transforms (at 16 the registers are spent)
+    constexpr bool kPre = P == 0 && PT == 8 && NY <= 1024;
+    TwRegs<NY, PT> twr;
+    if constexpr (kPre) twr.read(tw, t);
+    const float2* pre = kPre ? twr.w : nullptr;
+    fft_any<NY, 1, P, false, PT>(v, t, lds, ColAddr<CP>{q}, tw, dftop, pre);
 
     // nearest of {+1, -1}: bit = (Re h < 0); Re h = 0 -> +1.  The CP lanes of
     // a row give the even columns' bits (ballot of .x) and the odd columns'
@@ -591,7 +603,7 @@ __global__ __launch_bounds__((C / 2) * (NY / PT)) __attribute__((amdgpu_waves_pe
         }
         v[m] = make_float2(na ? -1.0f : 1.0f, nb ? -1.0f : 1.0f);
     }
-    fft_any<NY, -1, P, false, PT>(v, t, lds, ColAddr<CP>{q}, tw, dftop);
+    fft_any<NY, -1, P, false, PT>(v, t, lds, ColAddr<CP>{q}, tw, dftop, pre);
 
     // separation: rows v <= NY/2 (slots m < PT/2, and m = PT/2 for t = 0) need
     // Z at -v, which lies in slots PT/2..PT-1, or slot 0 for v = 0
@@ -917,6 +929,12 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(4
     // faster (35.8 against 37.2 us at 1024^2, 24 sub-frames, 4 groups)
     const uint32_t kst = (uint32_t)(sf_stride * 8);
     const uint32_t roff = ((uint32_t)v_row * (uint32_t)pitch + (uint32_t)t) * 8u + (uint32_t)g * kst;
+    // FP32 at 8 points per thread: the table twiddles read once for all rounds
+    // (up to 512 points; at 1024 the extra registers cost a block per CU, and
+    // the 513 blocks then take two rounds: 51 against 41 us)
+    constexpr bool kPre = P == 0 && PT == 8 && NX <= 512;
+    TwRegs<NX, PT> twr;
+    if constexpr (kPre) twr.read(tw, t);
     for (int r = 0; r < rounds; ++r) {
         const int k = r * G + g;
         const bool valid = k < n_sf;
@@ -925,7 +943,8 @@ __global__ __launch_bounds__(P ? 256 : 512) __attribute__((amdgpu_waves_per_eu(4
         float2 v[PT];
 #pragma unroll
         for (int m = 0; m < PT; ++m) v[m] = buf_ld2(rx, roff, (uint32_t)(m * T * 8));
-        fft_any<NX, -1, P, (NX / PT <= 64), PT>(v, t, lds, RowAddrR{g * PadLenP<NX, PT>::v}, tw, dftop);
+        fft_any<NX, -1, P, (NX / PT <= 64), PT>(v, t, lds, RowAddrR{g * PadLenP<NX, PT>::v}, tw, dftop,
+                                                kPre ? twr.w : nullptr);
         if (valid) {
 #pragma unroll
             for (int m = 0; m < PT; ++m) acc[m] = fmaf(v[m].x, v[m].x, fmaf(v[m].y, v[m].y, acc[m]));
