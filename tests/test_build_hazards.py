@@ -10,6 +10,10 @@ store unguarded, and on gfx950 such 16-byte stores were seen to lose data words
 16-byte store in the lane register.  This test compiles each source to AMD
 assembly with the library's own flags and checks both properties, so that a
 change of code or compiler that brings back the unguarded form fails here.
+
+The same assembly also shows each kernel's scratch (private segment) size:
+every kernel keeps its data in registers and LDS, so a nonzero size means a
+register array the compiler could not promote, or spills.
 """
 import concurrent.futures as cf
 import os
@@ -64,14 +68,48 @@ def _problems(lines):
     return bad
 
 
-@pytest.mark.skipif(not os.path.exists(holo_build.HIPCC) and shutil.which("hipcc") is None,
-                    reason="hipcc not available")
-def test_wide_buffer_stores_are_guarded(tmp_path):
+needs_hipcc = pytest.mark.skipif(not os.path.exists(holo_build.HIPCC) and shutil.which("hipcc") is None,
+                                 reason="hipcc not available")
+
+
+@pytest.fixture(scope="module")
+def kernel_asm(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("asm"))
     srcs = holo_build.sources()
     with cf.ThreadPoolExecutor(max_workers=min(len(srcs), 8)) as ex:
-        results = list(ex.map(lambda s: _asm(s, str(tmp_path)), srcs))
-    bad = {name: probs[:3] for name, lines in results if (probs := _problems(lines))}
+        return list(ex.map(lambda s: _asm(s, out), srcs))
+
+
+@needs_hipcc
+def test_wide_buffer_stores_are_guarded(kernel_asm):
+    bad = {name: probs[:3] for name, lines in kernel_asm if (probs := _problems(lines))}
     assert not bad, f"unguarded wide buffer stores: {bad}"
+
+
+def _scratch(lines):
+    """(kernel, private segment bytes) for every kernel descriptor."""
+    out, name = [], None
+    for line in lines:
+        t = line.split()
+        if len(t) == 2 and t[0] == ".amdhsa_kernel":
+            name = t[1]
+        elif len(t) == 2 and t[0] == ".amdhsa_private_segment_fixed_size":
+            out.append((name, int(t[1])))
+    return out
+
+
+@needs_hipcc
+def test_no_kernel_uses_scratch(kernel_asm):
+    sizes = [(src, k, n) for src, lines in kernel_asm for k, n in _scratch(lines)]
+    assert len(sizes) > 100   # every source's kernels were found
+    bad = [(src, k, n) for src, k, n in sizes if n != 0]
+    assert not bad, f"kernels with scratch: {bad[:5]}"
+
+
+def test_scratch_parser():
+    lines = ["\t.amdhsa_kernel _Z1kv", "\t\t.amdhsa_private_segment_fixed_size 152", "\t.end_amdhsa_kernel",
+             "\t.amdhsa_kernel _Z1jv", "\t\t.amdhsa_private_segment_fixed_size 0"]
+    assert _scratch(lines) == [("_Z1kv", 152), ("_Z1jv", 0)]
 
 
 def test_checker_flags_the_unguarded_forms():
