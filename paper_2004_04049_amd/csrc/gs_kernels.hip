@@ -40,7 +40,9 @@ struct RowAddrG {
 template <typename K>
 void allow_lds_g(K kernel, size_t bytes)
 {
-    if (bytes > 64 * 1024) hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    // a refusal shows up as the launch's own error
+    if (bytes > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 // Sum over the T threads of each row (rows are aligned groups of T lanes):

@@ -1931,7 +1931,6 @@ holo_status holo_plan_load(const char* path)
     std::fclose(f);
     // entries written by holo_plan_save: {"kind": K, "nx": X, "ny": Y, "n_sf": S, "cfg": [7 ints]}
     size_t pos = 0;
-    int loaded = 0;
     while ((pos = txt.find("{\"kind\"", pos)) != std::string::npos) {
         int kind, sf, c0, c1, c2, c3, c4, c5, c6;
         long long nx, ny;
@@ -1939,6 +1938,7 @@ holo_status holo_plan_load(const char* path)
                         "{\"kind\": %d, \"nx\": %lld, \"ny\": %lld, \"n_sf\": %d, \"cfg\": [%d, %d, %d, %d, %d, %d, %d]}",
                         &kind, &nx, &ny, &sf, &c0, &c1, &c2, &c3, &c4, &c5, &c6) == 11) {
             if (kind != PLAN_OSPR && kind != PLAN_GS) return fail(HOLO_EINVAL, "plan kind %d in %s", kind, path);
+            if (sf < 0) return fail(HOLO_EINVAL, "plan n_sf %d in %s (must be >= 0)", sf, path);
             if (holo_status st = plan_check_pts(kind, c6)) return st;
             LaunchCfg c;
             c.cols_per_block = c0;
@@ -1949,7 +1949,6 @@ holo_status holo_plan_load(const char* path)
             c.chunk = c5;
             c.pts = c6;
             plan_put(kind, nx, ny, sf, c);
-            ++loaded;
         } else {
             return fail(HOLO_EINVAL, "malformed plan entry in %s", path);
         }

@@ -626,8 +626,9 @@ __global__ __launch_bounds__((C / 2) * (NY / PT)) __attribute__((amdgpu_waves_pe
 }
 
 // Column-tile width of K2: 8 columns (4 column pairs per block) unless
-// planned; measured at 1024^2, 24 sub-frames (FP32): 50.3 us against 55.2 us
-// for 16-column tiles.  The matrix-core forms use 8-column tiles.
+// planned; measured at 1024^2, 24 sub-frames (FP32, 16 points per thread):
+// 50.3 us against 55.2 us for 16-column tiles.  The matrix-core forms use
+// 8-column tiles.
 static int ospr_cols_width(int nx, int ny, int n_sf, const LaunchCfg& cfg, int pt)
 {
     int C = cfg.prec ? 8 : cfg.cols_per_block > 0 ? col_block_cols(ny, nx, n_sf, cfg.cols_per_block, 8) : 8;

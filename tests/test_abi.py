@@ -111,6 +111,10 @@ def test_plan_points_per_thread_rules(lib, tmp_path):
         bad.write_text('[{"kind": 3, "nx": 64, "ny": 64, "n_sf": 2, "cfg": [0, 0, 0, 0, -1, 0, 8]}]')
         with pytest.raises(h.HoloError):
             h.plan_load(str(bad))
+        bad.write_text('[{"kind": 0, "nx": 64, "ny": 64, "n_sf": -1, "cfg": [0, 0, 0, 0, -1, 0, 8]}]')
+        with pytest.raises(h.HoloError) as e:   # as plan_set: n_sf >= 0
+            h.plan_load(str(bad))
+        assert e.value.status == h.HOLO_EINVAL
         good = tmp_path / "good.json"
         h.plan_save(str(good))
         h.plan_set(h.PLAN_OSPR, 256, 128, 4, h.DEFAULT_PLAN)
