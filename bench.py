@@ -408,7 +408,8 @@ def bench_gs(h, synth, torch, dev):
                 torch.cuda.synchronize()
                 best = min(best, (time.perf_counter() - t0) / runs)
             return best
-        cands = [plan, [8, 2, 0, 0, 16, 0, 16], [0, 0, 0, 0, -1, 0, 16], [4, 1, 0, 0, 64, 0, 8], [16, 2, 0, 0, 16, 0, 16]]
+        cands = [plan, [8, 2, 0, 0, 16, 0, 16], [0, 0, 0, 0, -1, 0, 16], [4, 1, 0, 0, 64, 0, 8], [16, 2, 0, 0, 16, 0, 16],
+                 [8, 2, 0, 0, 16, 0, 8], [16, 2, 0, 0, 16, 0, 8]]
         timed = []
         for c in cands:
             h.plan_set(h.PLAN_GS, n, n, 1, c)
