@@ -514,19 +514,29 @@ struct GraphKey {
 std::mutex g_graph_mu;
 std::map<GraphKey, hipGraphExec_t> g_graphs;
 std::map<GraphKey, void*> g_graph_bufs;   // device tables a graph's kernels read, freed with the graph
+std::map<GraphKey, hipStream_t> g_graph_streams;   // the stream each graph is launched on (part of its key)
 std::vector<GraphKey> g_graph_order;
 bool g_use_graphs = true;
 
-// Keeps at most 32 graphs: the oldest is destroyed (after stream s drains),
-// with its device table.  Called with g_graph_mu held.
-void graph_trim_locked(hipStream_t s)
+// Records a new graph for `key`, launched on stream s, and keeps at most 32:
+// the oldest is destroyed, with its device table, once its own stream has
+// drained (which may be another stream than s).  Called with g_graph_mu held.
+void graph_insert_locked(const GraphKey& key, hipGraphExec_t exec, void* dtab, hipStream_t s)
 {
+    g_graphs[key] = exec;
+    if (dtab) g_graph_bufs[key] = dtab;
+    g_graph_streams[key] = s;
+    g_graph_order.push_back(key);
     if (g_graph_order.size() <= 32) return;
     const GraphKey k0 = g_graph_order.front();
     g_graph_order.erase(g_graph_order.begin());
+    auto os = g_graph_streams.find(k0);
+    if (os != g_graph_streams.end()) {
+        (void)hipStreamSynchronize(os->second);
+        g_graph_streams.erase(os);
+    }
     auto old = g_graphs.find(k0);
     if (old != g_graphs.end()) {
-        (void)hipStreamSynchronize(s);
         (void)hipGraphExecDestroy(old->second);
         g_graphs.erase(old);
     }
@@ -665,9 +675,7 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
             (void)hipGraphDestroy(graph);
             if (ie != hipSuccess) return fail(HOLO_EDEVICE, "GS graph instantiate: %s", hipGetErrorString(ie));
             std::lock_guard<std::mutex> lk(g_graph_mu);
-            g_graphs[key] = exec;
-            g_graph_order.push_back(key);
-            graph_trim_locked(s);
+            graph_insert_locked(key, exec, nullptr, s);
         }
         DEBUG_FAIL_CHECK("graph");
         HIP_TRY(hipGraphLaunch(exec, s));
@@ -1269,10 +1277,7 @@ holo_status holo_gs_iterate_batched(const holo_gs_frame* frames, int32_t n_frame
                 return fail(HOLO_EDEVICE, "batched GS graph instantiate: %s", hipGetErrorString(ie));
             }
             std::lock_guard<std::mutex> lk(g_graph_mu);
-            g_graphs[key] = exec;
-            g_graph_bufs[key] = dtab;
-            g_graph_order.push_back(key);
-            graph_trim_locked(s);
+            graph_insert_locked(key, exec, dtab, s);
         }
         DEBUG_FAIL_CHECK("graph");
         HIP_TRY(hipGraphLaunch(exec, s));
@@ -1650,10 +1655,7 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
                 return fail(HOLO_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(ie));
             }
             std::lock_guard<std::mutex> lk(g_graph_mu);
-            g_graphs[key] = exec;
-            if (dtab) g_graph_bufs[key] = dtab;
-            g_graph_order.push_back(key);
-            graph_trim_locked(s);
+            graph_insert_locked(key, exec, dtab, s);
         }
         DEBUG_FAIL_CHECK("graph");
         HIP_TRY(hipGraphLaunch(exec, s));
@@ -2256,6 +2258,7 @@ void holo_shutdown(void)
         g_graphs.clear();
         for (auto& kv : g_graph_bufs) (void)hipFree(kv.second);
         g_graph_bufs.clear();
+        g_graph_streams.clear();
         g_graph_order.clear();
     }
     (void)hipSetDevice(cur);
