@@ -25,9 +25,15 @@
  *     except that host outputs (NMSE values) are complete on return, which
  *     synchronises the stream.  With HOLO_F_NMSE_DEVICE the NMSE pointers are
  *     device pointers written in stream order and nothing synchronises.
- *   - Calls made concurrently on different host threads are safe; calls that
- *     overlap on the same stream are ordered by it.  The library keeps one
- *     scratch workspace per (device, stream).
+ *   - Calls made concurrently on different host threads are safe with graph
+ *     replay off (holo_set_graphs(0)); calls that overlap on the same stream
+ *     are ordered by it.  The library keeps one scratch workspace per (device,
+ *     stream).  With graph replay on (the default), a call that captures a new
+ *     graph while another host thread launches work can have its capture
+ *     invalidated by the HIP runtime (stream capture is not isolated between
+ *     threads here); that call then returns HOLO_EDEVICE and enqueues nothing
+ *     further, and a retry replays or re-captures.  Cached graphs are replayed
+ *     and evicted safely from several threads and streams.
  *   - Every call returns a holo_status; no exception or abort crosses the ABI.
  *     holo_last_error() gives this thread's text for the last failure.
  *   - Environment switches, read at each use (so they may change between
@@ -436,7 +442,9 @@ HOLO_API holo_status holo_phase_mask(const holo_lut* lut, uint64_t cursor, int64
  * iterations.  `chosen` (int[7] or NULL) receives the plan.  scratch_bits: device
  * uint32[n_sf][nx*ny/32], overwritten.  holo_plan_save / holo_plan_load
  * write and read all plans as JSON.  holo_set_graphs(0) disables the HIP
- * graph replay of holo_gs_iterate (on by default).
+ * graph replay of holo_gs_iterate, holo_gs_iterate_batched and
+ * holo_ospr_generate_batched (on by default; at most 32 graphs are kept, the
+ * oldest destroyed once its own stream has drained).
  * ------------------------------------------------------------------------- */
 HOLO_API holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t ny, int32_t n_sf,
                                         const holo_lut* lut, uint32_t* scratch_bits, int32_t reps, int32_t* chosen,

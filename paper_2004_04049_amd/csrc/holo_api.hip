@@ -547,6 +547,39 @@ void graph_insert_locked(const GraphKey& key, hipGraphExec_t exec, void* dtab, h
     }
 }
 
+// Launches the cached graph for `key` on s, if there is one (*launched), with
+// the cache lock held so that no other thread's insertion evicts it between
+// the lookup and the launch.
+holo_status graph_launch_cached(const GraphKey& key, hipStream_t s, bool* launched)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    *launched = it != g_graphs.end();
+    if (!*launched) return HOLO_OK;
+    DEBUG_FAIL_CHECK("graph");
+    HIP_TRY(hipGraphLaunch(it->second, s));
+    return HOLO_OK;
+}
+
+// Caches a newly instantiated graph (with its device table) and launches it,
+// under the cache lock.  If another thread cached the same key meanwhile, its
+// graph is launched and the new one (never launched) is dropped.
+holo_status graph_insert_launch(const GraphKey& key, hipGraphExec_t exec, void* dtab, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) {
+        (void)hipGraphExecDestroy(exec);
+        if (dtab) (void)hipFree(dtab);
+        exec = it->second;
+    } else {
+        graph_insert_locked(key, exec, dtab, s);
+    }
+    DEBUG_FAIL_CHECK("graph");
+    HIP_TRY(hipGraphLaunch(exec, s));
+    return HOLO_OK;
+}
+
 // Scratch of one GS call, carved from one buffer.
 struct GsLayout {
     size_t o_state, o_field, o_pinit, o_piter, o_consts, o_nm, o_er, o_x2, o_p5, o_f2, o_rs, o_cur, bytes;
@@ -656,12 +689,9 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
                       (uintptr_t)cfg.recon_cols_per_block, (uintptr_t)(intptr_t)cfg.pad,
                       (uintptr_t)(intptr_t)cfg.chunk, (uintptr_t)cfg.pts}};
         hipGraphExec_t exec = nullptr;
-        {
-            std::lock_guard<std::mutex> lk(g_graph_mu);
-            auto it = g_graphs.find(key);
-            if (it != g_graphs.end()) exec = it->second;
-        }
-        if (!exec) {
+        bool launched = false;
+        if ((st = graph_launch_cached(key, s, &launched))) return st;
+        if (!launched) {
             hipGraph_t graph = nullptr;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             holo_status est = gs_enqueue(a, s, cfg, tw_x, tw_y, b, L);
@@ -674,11 +704,8 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
             hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             if (ie != hipSuccess) return fail(HOLO_EDEVICE, "GS graph instantiate: %s", hipGetErrorString(ie));
-            std::lock_guard<std::mutex> lk(g_graph_mu);
-            graph_insert_locked(key, exec, nullptr, s);
+            if ((st = graph_insert_launch(key, exec, nullptr, s))) return st;
         }
-        DEBUG_FAIL_CHECK("graph");
-        HIP_TRY(hipGraphLaunch(exec, s));
     }
     if (a.codes && a.final2) {
         if ((st = copy_out(a.final2, (double*)(b + L.o_f2), 2, a.flags, s))) return st;
@@ -1248,12 +1275,9 @@ holo_status holo_gs_iterate_batched(const holo_gs_frame* frames, int32_t n_frame
                                        (uintptr_t)frames[f].field, (uintptr_t)frames[f].codes,
                                        (uintptr_t)frames[f].recon});
         hipGraphExec_t exec = nullptr;
-        {
-            std::lock_guard<std::mutex> lk(g_graph_mu);
-            auto it = g_graphs.find(key);
-            if (it != g_graphs.end()) exec = it->second;
-        }
-        if (!exec) {
+        bool launched = false;
+        if ((st = graph_launch_cached(key, s, &launched))) return st;
+        if (!launched) {
             GsFrame* dtab = nullptr;
             if ((st = new_table(&dtab))) return st;
             hipGraph_t graph = nullptr;
@@ -1276,11 +1300,8 @@ holo_status holo_gs_iterate_batched(const holo_gs_frame* frames, int32_t n_frame
                 (void)hipFree(dtab);
                 return fail(HOLO_EDEVICE, "batched GS graph instantiate: %s", hipGetErrorString(ie));
             }
-            std::lock_guard<std::mutex> lk(g_graph_mu);
-            graph_insert_locked(key, exec, dtab, s);
+            if ((st = graph_insert_launch(key, exec, dtab, s))) return st;
         }
-        DEBUG_FAIL_CHECK("graph");
-        HIP_TRY(hipGraphLaunch(exec, s));
     }
     if (f2 && (st = copy_out(nmse_final2, f2, 2 * (size_t)n_frames, flags, s))) return st;
     if ((st = copy_out(nmse_per_iter, nm, (size_t)n_frames * n_iter, flags, s))) return st;
@@ -1609,12 +1630,9 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
                                        (uintptr_t)c.pts, (uintptr_t)c.prec});
         }
         hipGraphExec_t exec = nullptr;
-        {
-            std::lock_guard<std::mutex> lk(g_graph_mu);
-            auto it = g_graphs.find(key);
-            if (it != g_graphs.end()) exec = it->second;
-        }
-        if (!exec) {
+        bool launched = false;
+        if ((st = graph_launch_cached(key, s, &launched))) return st;
+        if (!launched) {
             // the frame table lives with the graph (device memory written once)
             GroupFrame* dtab = nullptr;
             if (grouped) {
@@ -1654,11 +1672,8 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
                 if (dtab) (void)hipFree(dtab);
                 return fail(HOLO_EDEVICE, "batch graph instantiate: %s", hipGetErrorString(ie));
             }
-            std::lock_guard<std::mutex> lk(g_graph_mu);
-            graph_insert_locked(key, exec, dtab, s);
+            if ((st = graph_insert_launch(key, exec, dtab, s))) return st;
         }
-        DEBUG_FAIL_CHECK("graph");
-        HIP_TRY(hipGraphLaunch(exec, s));
     }
     if ((st = copy_out(nmse_out, nm, 2 * (size_t)n_frames, flags, s))) return st;
     *cursor += total;

@@ -37,3 +37,56 @@ def test_graph_cache_eviction_across_streams():
         graphed = run(True)
         for k, a, b in zip(iters, direct, graphed):
             assert torch.equal(a, b), f"n_iter {k}"
+
+
+def test_concurrent_threads_with_direct_launches():
+    """Two host threads, each on its own stream (ctypes releases the GIL), with
+    graph replay off: the results equal those of one thread's calls.  (With
+    replay on, a capture in one thread can be invalidated by the other's
+    launches; that call then fails cleanly, which is not exercised here.)"""
+    import threading
+    import paper_2004_04049_amd as h
+    h.lib()
+    n = 64
+    dev = torch.device("cuda:0")
+    t = torch.from_numpy(synth.blob_target(n, n, synth.SEED_GS_512)).to(dev)
+    lut = h.Lut(4096, synth.SEED_LUT)
+    work = [list(range(1, 31)), list(range(31, 61))]   # 60 keys in all
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+
+    def run(graphs):
+        h.set_graphs(graphs)
+        outs = [[torch.empty((n, n), dtype=torch.complex64, device=dev) for _ in w] for w in work]
+        errs = []
+
+        def worker(j):
+            try:
+                for _ in range(2):   # the second round replays survivors, re-captures the evicted
+                    for i, k in enumerate(work[j]):
+                        h.gs_iterate(t, k, lut, 0, field=outs[j][i], want_nmse=False, want_final=False,
+                                     stream=streams[j])
+            except Exception as e:   # noqa: BLE001 (reported below)
+                errs.append(e)
+        try:
+            th = [threading.Thread(target=worker, args=(j,)) for j in range(2)]
+            for x in th:
+                x.start()
+            for x in th:
+                x.join()
+            torch.cuda.synchronize()
+        finally:
+            h.set_graphs(True)
+        assert not errs, errs
+        return [[o.cpu() for o in row] for row in outs]
+
+    threaded = run(False)
+    h.set_graphs(False)
+    try:   # the same calls from this thread alone
+        for j in range(2):
+            for k, ref in zip(work[j], threaded[j]):
+                f = torch.empty((n, n), dtype=torch.complex64, device=dev)
+                h.gs_iterate(t, k, lut, 0, field=f, want_nmse=False, want_final=False, stream=streams[j])
+                torch.cuda.synchronize()
+                assert torch.equal(f.cpu(), ref), f"thread {j} n_iter {k}"
+    finally:
+        h.set_graphs(True)
