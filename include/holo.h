@@ -25,15 +25,15 @@
  *     except that host outputs (NMSE values) are complete on return, which
  *     synchronises the stream.  With HOLO_F_NMSE_DEVICE the NMSE pointers are
  *     device pointers written in stream order and nothing synchronises.
- *   - Calls made concurrently on different host threads are safe with graph
- *     replay off (holo_set_graphs(0)); calls that overlap on the same stream
- *     are ordered by it.  The library keeps one scratch workspace per (device,
- *     stream).  With graph replay on (the default), a call that captures a new
- *     graph while another host thread launches work can have its capture
- *     invalidated by the HIP runtime (stream capture is not isolated between
- *     threads here); that call then returns HOLO_EDEVICE and enqueues nothing
- *     further, and a retry replays or re-captures.  Cached graphs are replayed
- *     and evicted safely from several threads and streams.
+ *   - Calls made concurrently on different host threads are safe; calls that
+ *     overlap on the same stream are ordered by it.  The library keeps one
+ *     scratch workspace per (device, stream).  While one call captures a new
+ *     HIP graph (graph replay on, the first call of a shape), the library's
+ *     other calls wait: the HIP runtime can invalidate a capture when another
+ *     thread launches or allocates meanwhile.  GPU work that the caller
+ *     enqueues from other threads through other libraries during such a
+ *     capture is not covered; a call whose capture was invalidated returns
+ *     HOLO_EDEVICE (holo_set_graphs(0) avoids captures altogether).
  *   - Every call returns a holo_status; no exception or abort crosses the ABI.
  *     holo_last_error() gives this thread's text for the last failure.
  *   - Environment switches, read at each use (so they may change between

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <atomic>
 #include <map>
+#include <shared_mutex>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -507,6 +508,54 @@ struct GsArgs {
 // buffer has to outlive the call).
 __global__ void k_set_u64(uint64_t* p, uint64_t v) { *p = v; }
 
+// Graph capture and the other threads' calls.  This HIP runtime can
+// invalidate a stream capture when another host thread launches work or
+// allocates meanwhile, whatever the capture mode, so the library's own calls
+// exclude each other from captures: every call that enqueues GPU work holds
+// g_call_mu shared (CallGuard, outermost call of a thread only), and a capture
+// holds it exclusively (CaptureSection, which first gives up this thread's
+// shared hold and takes it back afterwards).  Work that other code enqueues
+// meanwhile is outside this protection.
+std::shared_mutex g_call_mu;
+thread_local int t_call_depth = 0;
+thread_local bool t_capturing = false;
+
+struct CallGuard {
+    bool locked = false;
+    CallGuard()
+    {
+        if (t_call_depth++ == 0 && !t_capturing) {
+            g_call_mu.lock_shared();
+            locked = true;
+        }
+    }
+    ~CallGuard()
+    {
+        --t_call_depth;
+        if (locked) g_call_mu.unlock_shared();
+    }
+    CallGuard(const CallGuard&) = delete;
+    CallGuard& operator=(const CallGuard&) = delete;
+};
+
+struct CaptureSection {
+    bool had_shared;
+    CaptureSection() : had_shared(t_call_depth > 0 && !t_capturing)
+    {
+        if (had_shared) g_call_mu.unlock_shared();
+        g_call_mu.lock();
+        t_capturing = true;
+    }
+    ~CaptureSection()
+    {
+        t_capturing = false;
+        g_call_mu.unlock();
+        if (had_shared) g_call_mu.lock_shared();
+    }
+    CaptureSection(const CaptureSection&) = delete;
+    CaptureSection& operator=(const CaptureSection&) = delete;
+};
+
 struct GraphKey {
     std::vector<uintptr_t> k;
     bool operator<(const GraphKey& o) const { return k < o.k; }
@@ -692,6 +741,7 @@ holo_status gs_run(int device, const GsArgs& a, hipStream_t s, const LaunchCfg& 
         bool launched = false;
         if ((st = graph_launch_cached(key, s, &launched))) return st;
         if (!launched) {
+            CaptureSection capture_section;   // no other library call runs while capturing
             hipGraph_t graph = nullptr;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             holo_status est = gs_enqueue(a, s, cfg, tw_x, tw_y, b, L);
@@ -914,6 +964,7 @@ int32_t holo_version(void) { return 1; }
 
 holo_status holo_lut_from_phases(const double* phases, uint64_t n_lut, holo_lut** out)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!out) return fail(HOLO_EINVAL, "out is NULL");
     *out = nullptr;
     if (n_lut && !phases) return fail(HOLO_EINVAL, "phases is NULL");
@@ -932,6 +983,7 @@ holo_status holo_lut_from_phases(const double* phases, uint64_t n_lut, holo_lut*
 
 holo_status holo_lut_build(uint64_t n_lut, uint64_t seed, holo_lut** out)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!out) return fail(HOLO_EINVAL, "out is NULL");
     if (n_lut >= (1ull << 29)) return fail(HOLO_EUNSUPPORTED, "n_lut %llu >= 2^29", (unsigned long long)n_lut);
     std::vector<double> phi(n_lut);
@@ -946,6 +998,7 @@ holo_status holo_lut_build(uint64_t n_lut, uint64_t seed, holo_lut** out)
 
 holo_status holo_lut_build_codes(uint64_t n_lut, uint64_t seed, holo_lut** out)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!out) return fail(HOLO_EINVAL, "out is NULL");
     *out = nullptr;
     if (n_lut == 0) return fail(HOLO_EINVAL, "n_lut must be >= 1");
@@ -964,6 +1017,7 @@ holo_status holo_lut_build_codes(uint64_t n_lut, uint64_t seed, holo_lut** out)
 
 holo_status holo_lut_prng(uint64_t seed, holo_lut** out)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!out) return fail(HOLO_EINVAL, "out is NULL");
     *out = new_lut(SRC_PRNG, UINT64_MAX, 1u, seed);
     return *out ? HOLO_OK : HOLO_EDEVICE;
@@ -971,6 +1025,7 @@ holo_status holo_lut_prng(uint64_t seed, holo_lut** out)
 
 holo_status holo_lut_mseq(uint64_t seed, holo_lut** out)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!out) return fail(HOLO_EINVAL, "out is NULL");
     *out = nullptr;
     holo_lut* l = new_lut(SRC_MSEQ, kMseqM, kMseqM, seed);
@@ -1003,6 +1058,7 @@ int32_t holo_lut_kind(const holo_lut* lut) { return lut ? lut->kind : -1; }
 
 holo_status holo_lut_phases(const holo_lut* lut, double* out, uint64_t n)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!lut || (!out && n)) return fail(HOLO_EINVAL, "lut/out is NULL");
     if (lut->kind == SRC_PRNG || lut->kind == SRC_MSEQ)
         return fail(HOLO_EUNSUPPORTED, "this phase source keeps no table (holo_phase_mask gives its phasors)");
@@ -1020,6 +1076,7 @@ uint64_t holo_lut_size(const holo_lut* lut) { return lut ? lut->n_lut : 0; }
 
 void holo_lut_free(holo_lut* lut)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!lut) return;
     int cur = 0;
     (void)hipGetDevice(&cur);
@@ -1078,6 +1135,7 @@ holo_status holo_ospr_generate(const float* target, int64_t nx, int64_t ny, int3
                                uint64_t* cursor, void* holo_out, float* recon, double* nmse2,
                                int32_t precision, uint32_t flags, void* hip_stream)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!target || !cursor || !holo_out) return fail(HOLO_EINVAL, "target, cursor and holo_out are required");
     if (n_sf < 1) return fail(HOLO_EINVAL, "n_sf must be >= 1 (got %d)", n_sf);
     int mode = OSPR_BINARY;
@@ -1104,6 +1162,7 @@ holo_status holo_reconstruct_nmse(const void* holo, int32_t levels, int64_t nx, 
                                   const float* target, float* recon, double* nmse2, uint32_t flags,
                                   void* hip_stream)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!holo || !target) return fail(HOLO_EINVAL, "holo and target are required");
     if (levels != 2 && levels != 8) return fail(HOLO_EINVAL, "levels must be 2 or 8 (got %d)", levels);
     if (n_sf < 1) return fail(HOLO_EINVAL, "n_sf must be >= 1 (got %d)", n_sf);
@@ -1140,6 +1199,7 @@ holo_status holo_gs_iterate(const float* target, int64_t nx, int64_t ny, int32_t
                             double* nmse_per_iter, double* err_per_iter, double* nmse_final2, float* recon,
                             int32_t precision, uint32_t flags, void* hip_stream)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!target || !cursor) return fail(HOLO_EINVAL, "target and cursor are required");
     if (n_iter < 1) return fail(HOLO_EINVAL, "n_iter must be >= 1 (got %d)", n_iter);
     if ((nmse_final2 || recon) && !codes) return fail(HOLO_EINVAL, "nmse_final2/recon need codes");
@@ -1162,6 +1222,7 @@ holo_status holo_gs_iterate_batched(const holo_gs_frame* frames, int32_t n_frame
                                     int32_t n_iter, const holo_lut* lut, uint64_t* cursor, double* nmse_per_iter,
                                     double* err_per_iter, double* nmse_final2, uint32_t flags, void* hip_stream)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!frames || !cursor) return fail(HOLO_EINVAL, "frames and cursor are required");
     if (n_frames < 1 || n_frames > 256) return fail(HOLO_EINVAL, "n_frames must be in [1, 256] (got %d)", n_frames);
     if (n_iter < 1) return fail(HOLO_EINVAL, "n_iter must be >= 1 (got %d)", n_iter);
@@ -1278,6 +1339,7 @@ holo_status holo_gs_iterate_batched(const holo_gs_frame* frames, int32_t n_frame
         bool launched = false;
         if ((st = graph_launch_cached(key, s, &launched))) return st;
         if (!launched) {
+            CaptureSection capture_section;   // no other library call runs while capturing
             GsFrame* dtab = nullptr;
             if ((st = new_table(&dtab))) return st;
             hipGraph_t graph = nullptr;
@@ -1316,6 +1378,7 @@ holo_status holo_gs_iterate_noalloc(const float* target, int64_t nx, int64_t ny,
                                     double* nmse_final2, float* recon, int32_t precision, uint32_t flags,
                                     void* hip_stream)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!target || !cursor) return fail(HOLO_EINVAL, "target and cursor are required");
     if (n_iter < 1) return fail(HOLO_EINVAL, "n_iter must be >= 1 (got %d)", n_iter);
     if ((nmse_final2 || recon) && !codes) return fail(HOLO_EINVAL, "nmse_final2/recon need codes");
@@ -1362,6 +1425,7 @@ holo_status holo_gs_iterate_noalloc(const float* target, int64_t nx, int64_t ny,
 holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t ny, int32_t sign, int32_t precision,
                       void* hip_stream)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!in || !out) return fail(HOLO_EINVAL, "in and out are required");
     if (sign != 1 && sign != -1) return fail(HOLO_EINVAL, "sign must be +1 or -1");
     if (!pow2_in_range(nx) || !pow2_in_range(ny))
@@ -1387,6 +1451,7 @@ holo_status holo_fft2(const float* in, float* out, int64_t nx, int64_t ny, int32
 holo_status holo_phase_mask(const holo_lut* lut, uint64_t cursor, int64_t nx, int64_t ny, int32_t n_sf, float* out,
                             void* hip_stream)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!out) return fail(HOLO_EINVAL, "out is required");
     if (n_sf < 1) return fail(HOLO_EINVAL, "n_sf must be >= 1");
     if (!pow2_in_range(nx) || !pow2_in_range(ny))
@@ -1412,6 +1477,7 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
                                        uint64_t* cursor, double* nmse_out, int32_t precision, uint32_t flags,
                                        void* hip_stream)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!frames || !cursor) return fail(HOLO_EINVAL, "frames and cursor are required");
     if (n_frames < 1 || n_frames > 4096) return fail(HOLO_EINVAL, "n_frames must be in [1, 4096] (got %d)", n_frames);
     int mode = OSPR_BINARY;
@@ -1633,6 +1699,7 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
         bool launched = false;
         if ((st = graph_launch_cached(key, s, &launched))) return st;
         if (!launched) {
+            CaptureSection capture_section;   // no other library call runs while capturing
             // the frame table lives with the graph (device memory written once)
             GroupFrame* dtab = nullptr;
             if (grouped) {
@@ -1683,6 +1750,7 @@ holo_status holo_ospr_generate_batched(const holo_frame* frames, int32_t n_frame
 holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t ny, int32_t n_sf, const holo_lut* lut,
                                uint32_t* scratch_bits, int32_t reps, int32_t* chosen, void* hip_stream)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!target || !scratch_bits) return fail(HOLO_EINVAL, "target and scratch_bits are required");
     if (n_sf < 1 || reps < 1) return fail(HOLO_EINVAL, "n_sf and reps must be >= 1");
     if (!pow2_in_range(nx) || !pow2_in_range(ny))
@@ -1788,6 +1856,7 @@ holo_status holo_autotune_ospr(const float* target, int64_t nx, int64_t ny, int3
 holo_status holo_autotune_gs(const float* target, int64_t nx, int64_t ny, const holo_lut* lut, int32_t reps,
                              int32_t* chosen, void* hip_stream)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!target) return fail(HOLO_EINVAL, "target is required");
     if (reps < 1) return fail(HOLO_EINVAL, "reps must be >= 1");
     if (!pow2_in_range(nx) || !pow2_in_range(ny))
@@ -2044,6 +2113,7 @@ int32_t holo_cnn_nparams(void) { return CnnLayout().n; }
 
 holo_status holo_cnn_create(uint64_t seed, holo_cnn** out)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!out) return fail(HOLO_EINVAL, "out is NULL");
     *out = nullptr;
     holo_cnn* c = new holo_cnn();
@@ -2083,6 +2153,7 @@ holo_status holo_cnn_create(uint64_t seed, holo_cnn** out)
 
 holo_status holo_cnn_get_params(const holo_cnn* c, float* host_out, int32_t n)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!c || !host_out) return fail(HOLO_EINVAL, "network and out are required");
     if (n != c->lay.n) return fail(HOLO_EINVAL, "network has %d parameters, not %d", c->lay.n, n);
     HIP_TRY(hipDeviceSynchronize());
@@ -2092,6 +2163,7 @@ holo_status holo_cnn_get_params(const holo_cnn* c, float* host_out, int32_t n)
 
 holo_status holo_cnn_set_params(holo_cnn* c, const float* host_in, int32_t n)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!c || !host_in) return fail(HOLO_EINVAL, "network and parameters are required");
     if (n != c->lay.n) return fail(HOLO_EINVAL, "network has %d parameters, not %d", c->lay.n, n);
     HIP_TRY(hipDeviceSynchronize());
@@ -2104,6 +2176,7 @@ holo_status holo_cnn_set_params(holo_cnn* c, const float* host_in, int32_t n)
 holo_status holo_cnn_infer(holo_cnn* c, const float* target, int64_t nx, int64_t ny, float* phasor_out,
                            void* hip_stream)
 {
+    CallGuard call_guard;   // see g_call_mu
     holo_status st = cnn_check(c, nx, ny);
     if (st) return st;
     if (!target || !phasor_out) return fail(HOLO_EINVAL, "target and phasor_out are required");
@@ -2116,6 +2189,7 @@ holo_status holo_cnn_infer(holo_cnn* c, const float* target, int64_t nx, int64_t
 holo_status holo_cnn_loss_grad(holo_cnn* c, const float* target, const float* label, int64_t nx, int64_t ny,
                                double* loss_out, float* grad_out, void* hip_stream)
 {
+    CallGuard call_guard;   // see g_call_mu
     holo_status st = cnn_check(c, nx, ny);
     if (st) return st;
     if (!target || !label) return fail(HOLO_EINVAL, "target and label are required");
@@ -2138,6 +2212,7 @@ holo_status holo_cnn_loss_grad(holo_cnn* c, const float* target, const float* la
 holo_status holo_cnn_train_step(holo_cnn* c, const float* targets, const float* labels, int32_t batch, int64_t nx,
                                 int64_t ny, float lr, double* loss_out, void* hip_stream)
 {
+    CallGuard call_guard;   // see g_call_mu
     holo_status st = cnn_check(c, nx, ny);
     if (st) return st;
     if (!targets || !labels) return fail(HOLO_EINVAL, "targets and labels are required");
@@ -2165,6 +2240,7 @@ holo_status holo_cnn_train_step(holo_cnn* c, const float* targets, const float* 
 
 holo_status holo_cnn_save(const holo_cnn* c, const char* path)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!c || !path) return fail(HOLO_EINVAL, "network and path are required");
     const int n = c->lay.n;
     std::vector<float> buf((size_t)3 * n);
@@ -2184,6 +2260,7 @@ holo_status holo_cnn_save(const holo_cnn* c, const char* path)
 
 holo_status holo_cnn_load(const char* path, holo_cnn** out)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!path || !out) return fail(HOLO_EINVAL, "path and out are required");
     *out = nullptr;
     FILE* f = std::fopen(path, "rb");
@@ -2211,6 +2288,7 @@ holo_status holo_cnn_load(const char* path, holo_cnn** out)
 
 void holo_cnn_free(holo_cnn* c)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!c) return;
     (void)hipDeviceSynchronize();
     cnn_free_images(c);
@@ -2222,6 +2300,7 @@ void holo_cnn_free(holo_cnn* c)
 
 holo_status holo_prof_enable(int32_t on)
 {
+    CallGuard call_guard;   // see g_call_mu
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
     return HOLO_OK;
@@ -2229,6 +2308,7 @@ holo_status holo_prof_enable(int32_t on)
 
 holo_status holo_prof_read(const char* kernel, double* total_ms, int64_t* count)
 {
+    CallGuard call_guard;   // see g_call_mu
     if (!kernel || !total_ms || !count) return fail(HOLO_EINVAL, "kernel, total_ms and count are required");
     std::lock_guard<std::mutex> lk(g_prof_mu);
     prof_drain();
@@ -2240,6 +2320,7 @@ holo_status holo_prof_read(const char* kernel, double* total_ms, int64_t* count)
 
 void holo_prof_reset(void)
 {
+    CallGuard call_guard;   // see g_call_mu
     std::lock_guard<std::mutex> lk(g_prof_mu);
     prof_drain();
     g_prof_tot.clear();
@@ -2247,6 +2328,7 @@ void holo_prof_reset(void)
 
 void holo_shutdown(void)
 {
+    std::unique_lock<std::shared_mutex> calls(g_call_mu);   // no call in flight
     std::lock_guard<std::mutex> lk(g_mu);
     int cur = 0;
     (void)hipGetDevice(&cur);

@@ -39,11 +39,13 @@ def test_graph_cache_eviction_across_streams():
             assert torch.equal(a, b), f"n_iter {k}"
 
 
-def test_concurrent_threads_with_direct_launches():
-    """Two host threads, each on its own stream (ctypes releases the GIL), with
-    graph replay off: the results equal those of one thread's calls.  (With
-    replay on, a capture in one thread can be invalidated by the other's
-    launches; that call then fails cleanly, which is not exercised here.)"""
+@pytest.mark.parametrize("graphs", [False, True])
+def test_concurrent_threads(graphs):
+    """Two host threads, each on its own stream (ctypes releases the GIL),
+    with graph replay off and on: with it on, one thread captures new graphs
+    (the library keeps its other calls out of a capture) and evicts old ones
+    while the other looks its own up and launches it.  The results equal those
+    of one thread's direct calls."""
     import threading
     import paper_2004_04049_amd as h
     h.lib()
@@ -53,40 +55,33 @@ def test_concurrent_threads_with_direct_launches():
     lut = h.Lut(4096, synth.SEED_LUT)
     work = [list(range(1, 31)), list(range(31, 61))]   # 60 keys in all
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [[torch.empty((n, n), dtype=torch.complex64, device=dev) for _ in w] for w in work]
+    errs = []
 
-    def run(graphs):
-        h.set_graphs(graphs)
-        outs = [[torch.empty((n, n), dtype=torch.complex64, device=dev) for _ in w] for w in work]
-        errs = []
-
-        def worker(j):
-            try:
-                for _ in range(2):   # the second round replays survivors, re-captures the evicted
-                    for i, k in enumerate(work[j]):
-                        h.gs_iterate(t, k, lut, 0, field=outs[j][i], want_nmse=False, want_final=False,
-                                     stream=streams[j])
-            except Exception as e:   # noqa: BLE001 (reported below)
-                errs.append(e)
+    def worker(j):
         try:
-            th = [threading.Thread(target=worker, args=(j,)) for j in range(2)]
-            for x in th:
-                x.start()
-            for x in th:
-                x.join()
-            torch.cuda.synchronize()
-        finally:
-            h.set_graphs(True)
-        assert not errs, errs
-        return [[o.cpu() for o in row] for row in outs]
+            for _ in range(2):   # the second round replays survivors, re-captures the evicted
+                for i, k in enumerate(work[j]):
+                    h.gs_iterate(t, k, lut, 0, field=outs[j][i], want_nmse=False, want_final=False,
+                                 stream=streams[j])
+        except Exception as e:   # noqa: BLE001 (reported below)
+            errs.append(e)
 
-    threaded = run(False)
-    h.set_graphs(False)
-    try:   # the same calls from this thread alone
+    h.set_graphs(graphs)
+    try:
+        th = [threading.Thread(target=worker, args=(j,)) for j in range(2)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        torch.cuda.synchronize()
+        assert not errs, errs
+        h.set_graphs(False)   # the same calls from this thread alone
         for j in range(2):
-            for k, ref in zip(work[j], threaded[j]):
+            for k, got in zip(work[j], outs[j]):
                 f = torch.empty((n, n), dtype=torch.complex64, device=dev)
                 h.gs_iterate(t, k, lut, 0, field=f, want_nmse=False, want_final=False, stream=streams[j])
                 torch.cuda.synchronize()
-                assert torch.equal(f.cpu(), ref), f"thread {j} n_iter {k}"
+                assert torch.equal(f.cpu(), got.cpu()), f"thread {j} n_iter {k}"
     finally:
         h.set_graphs(True)
