@@ -85,3 +85,70 @@ def test_concurrent_threads(graphs):
                 assert torch.equal(f.cpu(), got.cpu()), f"thread {j} n_iter {k}"
     finally:
         h.set_graphs(True)
+
+
+def test_concurrent_threads_batched_entry_points():
+    """One thread captures and replays batched OSPR graphs while another does
+    the same with batched GS; both equal one thread's direct calls."""
+    import threading
+    import paper_2004_04049_amd as h
+    h.lib()
+    dev = torch.device("cuda:0")
+    lut = h.Lut(10007, synth.SEED_LUT)
+    layouts = [[(64, 2), (128, 3), (64, 4)], [(128, 2), (64, 3)], [(64, 1), (64, 2), (128, 2), (64, 3)],
+               [(128, 4)], [(64, 5), (128, 1)], [(128, 3), (128, 2), (64, 2)]]
+    o_targets = [[torch.from_numpy(synth.blob_target(n, n, 700 + 10 * i + f)).to(dev) for f, (n, _) in enumerate(lay)]
+                 for i, lay in enumerate(layouts)]
+    g_iters = list(range(1, 11))
+    g_targets = [torch.from_numpy(synth.blob_target(64, 64, 900 + f)).to(dev) for f in range(3)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+
+    def ospr_calls(out):
+        for _ in range(2):
+            for i, lay in enumerate(layouts):
+                nm = torch.zeros((len(lay), 2), dtype=torch.float64, device=dev)
+                bits, _, _ = h.ospr_generate_batched(o_targets[i], [k for _, k in lay], lut, 3 * i, nmse_out=nm,
+                                                     stream=streams[0])
+                out[i] = (bits, nm)
+
+    def gs_calls(out):
+        for _ in range(2):
+            for k in g_iters:
+                fl = [torch.empty((64, 64), dtype=torch.complex64, device=dev) for _ in g_targets]
+                h.gs_iterate_batched(g_targets, k, lut, 5 * k, fields=fl, want_nmse=False, stream=streams[1])
+                out[k] = fl
+
+    def snapshot(o_out, g_out):
+        torch.cuda.synchronize()
+        return ({i: ([b.cpu() for b in bits], nm.cpu()) for i, (bits, nm) in o_out.items()},
+                {k: [f.cpu() for f in fl] for k, fl in g_out.items()})
+
+    h.set_graphs(False)
+    try:
+        o_ref, g_ref = {}, {}
+        ospr_calls(o_ref)
+        gs_calls(g_ref)
+        o_ref, g_ref = snapshot(o_ref, g_ref)
+    finally:
+        h.set_graphs(True)
+    o_out, g_out, errs = {}, {}, []
+
+    def run(fn, out):
+        try:
+            fn(out)
+        except Exception as e:   # noqa: BLE001 (reported below)
+            errs.append(e)
+    th = [threading.Thread(target=run, args=(ospr_calls, o_out)), threading.Thread(target=run, args=(gs_calls, g_out))]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    assert not errs, errs
+    o_got, g_got = snapshot(o_out, g_out)
+    for i in o_ref:
+        for a, b in zip(o_ref[i][0], o_got[i][0]):
+            assert torch.equal(a, b), f"OSPR layout {i}: bits"
+        assert torch.equal(o_ref[i][1], o_got[i][1]), f"OSPR layout {i}: NMSE"
+    for k in g_ref:
+        for a, b in zip(g_ref[k], g_got[k]):
+            assert torch.equal(a, b), f"GS n_iter {k}"
